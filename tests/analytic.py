@@ -1,0 +1,37 @@
+"""Closed-form solutions used to pin the oracle (independent of it).
+
+One-sided Stefan problem (D_s = 0) of Sec. 4.2 of the paper, with the
+chemical potential playing the role of the temperature:
+  transcendental equation, Eq. (Cartesian_Transcendental):
+      alpha exp(alpha^2) erfc(alpha) + (mu_eq - mu_inf) / (dc sqrt(pi)) = 0
+  interface position, Eq. (x_i_Ds0):  x_i(t) = 2 alpha sqrt(D_l t)
+  liquid chemical potential, Eq. (Analytical_muL_Ds0):
+      mu_l(x, t) = mu_inf + (mu_eq - mu_inf) erfc(x / (2 sqrt(D_l t))) / erfc(alpha)
+"""
+import math
+
+import numpy as np
+from scipy.optimize import brentq
+from scipy.special import erfc
+
+
+def stefan_alpha(mu_eq: float, mu_inf: float, dc: float) -> float:
+    rhs = (mu_eq - mu_inf) / (dc * math.sqrt(math.pi))
+    f = lambda a: a * math.exp(a * a) * math.erfc(a) + rhs
+    return brentq(f, -5.0, 5.0, xtol=1e-15, rtol=1e-15)
+
+
+def stefan_front(alpha: float, D_l: float, t):
+    return 2.0 * alpha * np.sqrt(D_l * np.asarray(t, dtype=np.float64))
+
+
+def stefan_mu_liquid(x, t, alpha, D_l, mu_eq, mu_inf):
+    x = np.asarray(x, dtype=np.float64)
+    return mu_inf + (mu_eq - mu_inf) * erfc(x / (2.0 * math.sqrt(D_l * t))) / erfc(alpha)
+
+
+def front_position(phi):
+    """Interface position of a planar front with solid on the left and the
+    zero-flux wall at x = -1/2: -1/2 + mean over y of sum_x (1 - phi)."""
+    phi = np.asarray(phi)
+    return -0.5 + (1.0 - phi).sum(axis=-1).mean()

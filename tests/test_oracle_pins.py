@@ -1,0 +1,286 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each checks a printed value, a
+closed-form solution, a conservation law or a special case that reduces to a
+textbook problem.  The mutation tests (test_oracle_mutations.py) show that a
+plausible slip in the oracle breaks at least one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.integrate import quad
+from scipy.special import expit
+
+import workloads as wl
+from tests import analytic
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
+
+
+def golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+# --------------------------------------------------------------------------
+# Printed values: Stefan root, lambda*, Table 3
+
+
+def test_stefan_root_matches_printed():
+    g = golden()["stefan_dissolution"]
+    a = analytic.stefan_alpha(g["mu_eq"], g["mu_inf"], g["c_s_co"] - g["c_l_co"])
+    assert abs(a - g["alpha"]) < 0.6 * 10 ** (-g["printed_digits"])
+
+
+def test_lambda_star_matches_printed():
+    g = golden()["lambda_star_porous"]
+    lam = wl.lambda_star(g["D_l"], g["M_phi"], g["dc"])
+    assert round(lam) == g["lambda_star"]
+    assert abs(lam - 230.2115) < 1e-3
+
+
+def _tanh_phi(xi):
+    # (1 + tanh(2 xi)) / 2 written as the logistic function of 4 xi, which
+    # keeps full relative accuracy in both tails
+    return expit(4.0 * xi)
+
+
+def test_table3_integrals_by_quadrature():
+    ln2 = math.log(2.0)
+    dphi = lambda xi: 4.0 * _tanh_phi(xi) * (1.0 - _tanh_phi(xi))
+    I = quad(lambda x: dphi(x) ** 2, -20, 20, epsabs=1e-14, epsrel=1e-14)[0]
+    assert abs(I - 2.0 / 3.0) < 1e-12
+    # (h - a dphi)/q with h = q = phi, a = 1/4 reduces to phi
+    ratio = lambda x: (_tanh_phi(x) - 0.25 * dphi(x)) / _tanh_phi(x)
+    F_l = quad(lambda x: 1.0 - ratio(x), 0, 20, epsabs=1e-14)[0]
+    F_s = quad(lambda x: ratio(x), -20, 0, epsabs=1e-14)[0]
+    assert abs(F_l - ln2 / 4) < 1e-12 and abs(F_s - ln2 / 4) < 1e-12
+    p = lambda f: f * f * (3.0 - 2.0 * f)
+    Ft_l = quad(lambda x: 1.0 - p(_tanh_phi(x)) / _tanh_phi(x), 0, 20, epsabs=1e-14)[0]
+    Ft_s = quad(lambda x: p(_tanh_phi(x)) / _tanh_phi(x), -20, 0, epsabs=1e-14)[0]
+    assert abs(Ft_l - (ln2 - 1) / 4) < 1e-12 and abs(Ft_s - (ln2 + 1) / 4) < 1e-12
+    H_l = quad(lambda x: 1.0 - _tanh_phi(x), 0, 20, epsabs=1e-14)[0]
+    assert abs(H_l - ln2 / 4) < 1e-12
+    assert abs(wl.TABLE3_I - 2.0 / 3.0) < 1e-15
+    assert abs(wl.TABLE3_F - ln2 / 4) < 1e-15
+
+
+def test_table3_K_printed_vs_integrand():
+    """K printed as (31 - 30 ln2)/150 reproduces the printed lambda* = 230, but
+    quadrature of its defining integral gives 5/24 - ln2/4.  The printed value
+    is used (it is the one the paper's own lambda* follows)."""
+    ln2 = math.log(2.0)
+    pprime_dphi = lambda x: 6.0 * _tanh_phi(x) * (1 - _tanh_phi(x)) * 4.0 * _tanh_phi(x) * (1 - _tanh_phi(x))
+    inner = lambda x: quad(lambda s: _tanh_phi(s), 0.0, x, epsabs=1e-14)[0]
+    K = quad(lambda x: pprime_dphi(x) * inner(x), -12, 12, epsabs=1e-13, limit=200)[0]
+    assert abs(K - (5.0 / 24.0 - ln2 / 4.0)) < 1e-9
+    assert abs(wl.TABLE3_K - (31 - 30 * ln2) / 150) < 1e-15
+    assert abs(K - wl.TABLE3_K) > 0.03
+
+
+# --------------------------------------------------------------------------
+# Closed-form solutions
+
+
+def test_stefan_dissolution_front_and_profile(oracle_mod):
+    """Workload 0 (planar dissolution, D_s = 0, anti-trapping, lambda*)
+    against the one-sided Stefan solution of Sec. 4.2."""
+    p, phi0, c0, nsteps = wl.config0()
+    mu_inf = p["mu_eq"] + 0.0 - p["c_l_co"]
+    alpha = analytic.stefan_alpha(p["mu_eq"], mu_inf, p["c_s_co"] - p["c_l_co"])
+    assert abs(alpha - (-0.0586022)) < 1e-6
+    o = oracle_mod.Oracle(p).init(phi0, c0)
+    x0 = analytic.front_position(o.fields()[0][0])
+    assert abs(x0 - 100.0) < 1e-6
+    for t in (1000, 2000, 3000, 4000):
+        o.step(t - o.step_count)
+        phi, c, mu = o.fields()
+        dx = analytic.front_position(phi[0]) - x0
+        exact = analytic.stefan_front(alpha, p["D_l"], t)
+        assert abs(dx - exact) < 0.01 * abs(exact), (t, dx, exact)
+    x = np.arange(512) - 100.0
+    xi = analytic.stefan_front(alpha, p["D_l"], 4000)
+    m = x > xi + 5
+    mua = analytic.stefan_mu_liquid(x, 4000, alpha, p["D_l"], p["mu_eq"], mu_inf)
+    err = np.linalg.norm(mu[0, 0][m] - mua[m]) / np.linalg.norm(mua[m])
+    assert err < 2e-3
+    # solid keeps its coexistence composition (D_s = 0)
+    assert np.all(np.abs(c[0, :, :80] - p["c_s_co"]) < 1e-3)
+
+
+@pytest.mark.parametrize("counter_term", [0, 1])
+def test_circle_curvature_flow(oracle_mod, counter_term):
+    """lambda = 0: without the counter term the grain follows mean-curvature
+    flow R^2 = R0^2 - 2 M t (Eq. ModelA_EqPhi); with it the radius stays put
+    (Eq. ModelA_EqPhi_CounterTerm)."""
+    W, M = 6.0, 0.05
+    p = wl.base_params(shape=(1, 128, 128), bc=(0, 0, 0), counter_term=counter_term,
+                       lam=0.0, W=W)
+    phi0, c0 = wl.disc(128, 128, 30.0, W, 1.0, 0.1)
+    o = oracle_mod.Oracle(p).init(phi0, c0)
+    o.step(400)
+    A1 = (1 - o.fields()[0]).sum() / math.pi
+    o.step(1600)
+    A2 = (1 - o.fields()[0]).sum() / math.pi
+    rate = (A1 - A2) / 1600
+    if counter_term:
+        assert abs(A1 - A2) / A1 < 1e-8
+    else:
+        assert abs(rate / (2 * M) - 1.0) < 0.03, rate
+
+
+def test_ade_fourier_mode_decay(oracle_mod):
+    """phi = 1 everywhere: the c-LBE reduces to the textbook advection-free
+    diffusion LBM, so a Fourier mode of c decays as exp(-D_l k^2 t)."""
+    L = 128
+    p = wl.base_params(shape=(1, 4, L), bc=(0, 0, 0))
+    x = np.arange(L)
+    k = 2 * np.pi / L
+    phi0 = np.ones((1, 4, L))
+    c0 = p["c_l_co"] + 0.01 * np.broadcast_to(np.cos(k * x), (1, 4, L))
+    o = oracle_mod.Oracle(p).init(phi0, c0)
+    o.step(100)
+    amp = lambda: 2 * np.abs(np.fft.rfft(o.fields()[1][0, 0])[1]) / L
+    a0 = amp()
+    o.step(2000)
+    a1 = amp()
+    rate = -math.log(a1 / a0) / 2000
+    assert abs(rate / (p["D_l"] * k * k) - 1.0) < 2e-3, rate
+    assert np.max(np.abs(o.fields()[0] - 1.0)) < 1e-15
+
+
+# --------------------------------------------------------------------------
+# Conservation laws and special cases
+
+
+@pytest.mark.parametrize("lattice,shape,bc", [
+    (0, (1, 24, 40), (1, 0, 0)),
+    (0, (1, 24, 40), (1, 1, 0)),
+    (0, (1, 24, 40), (0, 0, 0)),
+    (1, (10, 12, 14), (1, 0, 1)),
+    (1, (10, 12, 14), (0, 0, 0)),
+])
+def test_solute_mass_conserved(oracle_mod, lattice, shape, bc):
+    """sum_k h^eq_k = c, sum_k H_k = 0 and streaming permutes populations, so
+    the total solute is conserved to round-off (Eq. Moment0_LBM_Concent)."""
+    p = wl.base_params(lattice=lattice, shape=shape, bc=bc)
+    phi0, c0 = wl.random_state_fields(shape, seed=3)
+    o = oracle_mod.Oracle(p).init(phi0, c0)
+    m0 = o.diagnostics()["total_mass"]
+    o.step(200)
+    m1 = o.diagnostics()["total_mass"]
+    assert abs(m1 - m0) / abs(m0) < 1e-12
+
+
+@pytest.mark.parametrize("lattice,shape", [(0, (1, 32, 32)), (1, (12, 12, 12))])
+def test_phase_conserved_without_coupling(oracle_mod, lattice, shape):
+    """lambda = 0 with the counter term: the phi equation is conservative
+    (Eq. ModelA_EqPhi_CounterTerm, divergence form), so sum phi is kept."""
+    p = wl.base_params(lattice=lattice, shape=shape, bc=(0, 0, 0), lam=0.0)
+    phi0, c0 = wl.random_state_fields(shape, seed=5)
+    o = oracle_mod.Oracle(p).init(phi0, c0)
+    s0 = o.diagnostics()["sum_phi"]
+    o.step(300)
+    s1 = o.diagnostics()["sum_phi"]
+    assert abs(s1 - s0) / s0 < 1e-12
+
+
+def test_pure_solid_is_stationary(oracle_mod):
+    """phi = 0, D_s = 0: no diffusion, no source; the state does not move."""
+    shape = (1, 16, 20)
+    p = wl.base_params(shape=shape, bc=(1, 0, 0))
+    phi0 = np.zeros(shape)
+    c0 = 1.0 + 0.1 * np.random.default_rng(0).standard_normal(shape)
+    o = oracle_mod.Oracle(p).init(phi0, c0)
+    g0, h0, f0 = o.state()
+    o.step(50)
+    g1, h1, f1 = o.state()
+    assert np.array_equal(g0, g1) and np.array_equal(h0, h1) and np.array_equal(f0, f1)
+
+
+@pytest.mark.parametrize("lattice", [0, 1])
+def test_gradient_exact_on_linear_field(oracle_mod, lattice):
+    """Directional derivatives (Eq. DerivDirec_Grad) combined by Eq. (Grad)
+    are exact for a linear field at interior nodes."""
+    shape = (1, 9, 11) if lattice == 0 else (7, 9, 11)
+    p = wl.base_params(lattice=lattice, shape=shape, bc=(1, 1, 1 if lattice else 0))
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    b = (0.013, -0.021, 0.017 if lattice else 0.0)
+    phi = 0.4 + b[0] * x + b[1] * y + b[2] * z
+    o = oracle_mod.Oracle(p).init(phi, np.zeros(shape))
+    g, n = o.gradient()
+    inner = (slice(1, -1) if lattice else slice(None), slice(1, -1), slice(1, -1))
+    for a in range(3):
+        assert np.max(np.abs(g[inner][..., a] - b[a])) < 1e-14
+    bn = np.array(b) / math.sqrt(sum(v * v for v in b) + p["eps_n"] ** 2)
+    assert np.max(np.abs(n[inner] - bn)) < 1e-12
+
+
+def test_planar_front_independent_of_y(oracle_mod):
+    """Workload 0 is one-dimensional: every y row evolves identically."""
+    p, phi0, c0, _ = wl.config0()
+    o = oracle_mod.Oracle(p).init(phi0, c0)
+    o.step(300)
+    phi, c, mu = o.fields()
+    for f in (phi, c, mu):
+        assert np.all(f[0] == f[0, :1])
+
+
+def test_counter_term_irrelevant_in_1d(oracle_mod):
+    """Sec. 4: in one dimension both phi equations give the same solution."""
+    xs = []
+    for ct in (0, 1):
+        p, phi0, c0, _ = wl.config0(counter_term=ct)
+        o = oracle_mod.Oracle(p).init(phi0, c0)
+        traj = []
+        for _ in range(10):
+            o.step(200)
+            traj.append(analytic.front_position(o.fields()[0][0]))
+        xs.append(np.array(traj))
+    # 0.025 cells: about 1% of the distance the front travels by t = 4000
+    assert np.max(np.abs(xs[0] - xs[1])) < 2.5e-2
+
+
+def test_flat_front_at_equilibrium_is_stationary(oracle_mod):
+    """c0 = c_co(phi0) puts mu = mu_eq everywhere: with the counter term a
+    flat front does not move, apart from the slow relaxation of the sampled
+    tanh profile to the discrete one (below 1e-2 cells and dying out, to
+    compare with the 2.3 cells an undersaturated liquid drives it in 4000
+    steps)."""
+    p = wl.base_params(shape=(1, 4, 256), bc=(1, 0, 0))
+    phi0, _ = wl.planar(256, 4, p["W"], 120.0, 1.0, 0.0)
+    c0 = p["c_l_co"] * phi0 + p["c_s_co"] * (1 - phi0)
+    o = oracle_mod.Oracle(p).init(phi0, c0)
+    xs = []
+    for _ in range(8):
+        o.step(1000)
+        xs.append(analytic.front_position(o.fields()[0][0]))
+    xs = np.array(xs)
+    drift = np.abs(np.diff(xs))
+    assert np.max(np.abs(xs - 120.0)) < 1e-2
+    assert np.all(np.diff(drift) < 0) and drift[-1] < 5e-4
+    assert np.max(np.abs(o.fields()[2] - p["mu_eq"])) < 1e-3
+
+
+def test_closed_box_reaches_equal_chemical_potentials(oracle_mod):
+    """A closed box relaxes to mu = mu_eq in both phases (abstract, Sec. 5):
+    liquid at c_l^co, solid at c_s^co, solid fraction by the lever rule."""
+    n = 24
+    p = wl.base_params(shape=(1, n, n), bc=(1, 1, 0), D_l=0.2)
+    phi0, _ = wl.disc(n, n, 7.0, p["W"], 1.0, 0.0)
+    c0 = p["c_s_co"] * (1 - phi0) + 0.05 * phi0
+    o = oracle_mod.Oracle(p).init(phi0, c0)
+    mtot = o.diagnostics()["total_mass"]
+    errs = []
+    for _ in range(6):
+        o.step(4000)
+        errs.append(np.max(np.abs(o.fields()[2] - p["mu_eq"])))
+    assert errs[-1] < 1e-4 and errs[-1] < errs[0]
+    phi, c, mu = o.fields()
+    dc = p["c_s_co"] - p["c_l_co"]
+    lever = (mtot / (n * n) - p["c_l_co"]) / dc
+    assert abs(o.diagnostics()["solid_fraction"] - lever) < 1e-3
