@@ -1,0 +1,157 @@
+/*
+ * gplbm — coupled phase-field / composition lattice-Boltzmann step of the
+ * grand-potential model of dissolution and precipitation (Boutin, Verdier &
+ * Cartalade, arXiv:2111.05960), on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Plain pointers and sizes only.  Every device pointer is a HIP
+ * device address on the device that was current when gplbm_create ran; the
+ * stream argument is a hipStream_t passed as void*.
+ *
+ * What one step computes (lattice units dx = dt = 1, xi_s^2 = 1/3):
+ *   - phi-LBE, Sec. 3.2: BGK collision with trapezoidal source,
+ *     Eq. (LBE_PhaseField_Eq), g^eq = w_k phi (Eq. Geq_Allen-Cahn_Eq-1),
+ *     sources Eqs. (TermG), (SourceG_ST), (SourceG_dw) / (SourceG_CT) with
+ *     S_phi of Eq. (SourceTerm_Coexistence), phi moment Eq. (Moment_Phi),
+ *     gradient by directional derivatives Eqs. (DerivDirec_Grad), (Grad);
+ *   - c-LBE, Sec. 3.3: Eqs. (LBE_Composition), (Heq_Composition),
+ *     (SourceTerm_LBE_h), c moment Eq. (Moment0_LBM_Concent), closure
+ *     Eqs. (PotChim_Equilibirum)-(Coexistence_Interpol), anti-trapping
+ *     current Eq. (Anti-trapping_Equilibrium) with dphi/dt by explicit Euler
+ *     (the c-LBE is solved after the phi-LBE).
+ * Readings where the paper is silent (shared with the CPU reference):
+ *   the phi moment uses the closed-form zeroth moment of this step's
+ *   source at the same node (G^st, plus G^dw without the counter term); the
+ *   normal is grad phi / sqrt(|grad phi|^2 + eps_n^2); walls are halfway
+ *   bounce-back with a mirror ghost for the gradient; the initial
+ *   populations are the equilibria shifted by the trapezoidal variable
+ *   change, without anti-trapping current.
+ *
+ * Ownership.  The caller owns every device buffer and the stream.  The
+ * library never allocates device memory: gplbm_state_bytes says how large a
+ * device buffer gplbm_create must borrow for the whole state (populations,
+ * phase field, reduction scratch).  The context (host memory) is owned by the
+ * library until gplbm_destroy.  Calls on one context are not thread safe.
+ *
+ * Errors.  Every int-returning call returns GPLBM_OK (0) or a negative code;
+ * gplbm_last_error gives the text of the last failure on a context.
+ */
+#ifndef GPLBM_H
+#define GPLBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define GPLBM_OK 0
+#define GPLBM_E_INVALID (-1)   /* bad parameter, null pointer, unsupported combination */
+#define GPLBM_E_SIZE (-2)      /* borrowed buffer too small */
+#define GPLBM_E_DEVICE (-3)    /* HIP runtime error (text in gplbm_last_error) */
+#define GPLBM_E_NONFINITE (-4) /* diagnostics found a non-finite phi or c */
+#define GPLBM_E_STATE (-5)     /* step / read before gplbm_init_fields */
+
+/* lattices (the same lattice serves both distributions) */
+#define GPLBM_D2Q9 0
+#define GPLBM_D3Q19 1
+
+/* boundary conditions per axis */
+#define GPLBM_PERIODIC 0
+#define GPLBM_ZERO_FLUX 1 /* halfway bounce-back, walls at -1/2 and n-1/2 */
+
+/* storage / arithmetic precision of the populations and of phi */
+#define GPLBM_FP64 0 /* everything in double */
+#define GPLBM_FP32 1 /* float storage and collision; moments and closure in double */
+
+/* kernel schedule */
+#define GPLBM_SCHED_AUTO 0  /* fused when the geometry allows it, else split */
+#define GPLBM_SCHED_SPLIT 1 /* two kernels per step */
+#define GPLBM_SCHED_FUSED 2 /* one kernel per step (tile halo recompute) */
+
+typedef struct gplbm_params {
+  int32_t lattice;       /* GPLBM_D2Q9 or GPLBM_D3Q19 */
+  int32_t nx, ny, nz;    /* nodes; nz = 1 for D2Q9; node i = x + nx*(y + ny*z) */
+  int32_t bc[3];         /* per axis x, y, z: GPLBM_PERIODIC or GPLBM_ZERO_FLUX */
+  int32_t precision;     /* GPLBM_FP64 or GPLBM_FP32 */
+  int32_t counter_term;  /* 1: counter term G^ct_k (Eq. ModelA_EqPhi_CounterTerm); 0: G^dw */
+  int32_t anti_trapping; /* 1: anti-trapping current in the h source */
+  int32_t schedule;      /* GPLBM_SCHED_* */
+  int32_t reserved;      /* must be 0 */
+  double W;              /* interface width */
+  double M_phi;          /* phase-field mobility; tau_g = 3 M_phi */
+  double lambda;         /* coupling constant */
+  double D_l, D_s;       /* diffusivities of liquid and solid */
+  double gamma;          /* relaxation control of the c-LBE; tau_h = 3 / gamma */
+  double a_at;           /* anti-trapping coefficient a (1/4 for D_s = 0) */
+  double c_s_co, c_l_co; /* coexistence compositions */
+  double mu_eq;          /* equilibrium chemical potential */
+  double eps_n;          /* regularisation of the normal */
+} gplbm_params;
+
+typedef struct gplbm_diag {
+  int64_t step;                /* time level n of the fields described */
+  double total_mass;           /* sum over nodes of c^n */
+  double solid_fraction;       /* mean of 1 - phi^n */
+  double solid_fraction_count; /* fraction of nodes with phi^n < 1/2 */
+  double sum_phi;              /* sum over nodes of phi^n */
+  double phi_min, phi_max;
+  int32_t nonfinite;           /* 1 if some phi^n or c^n is not finite */
+  int32_t reserved;
+} gplbm_diag;
+
+typedef struct gplbm_ctx gplbm_ctx;
+
+/* Bytes of device memory gplbm_create must borrow for these parameters.
+ * Returns GPLBM_E_INVALID for parameters gplbm_create would reject. */
+int gplbm_state_bytes(const gplbm_params* p, uint64_t* bytes);
+
+/* Bytes of one saved state (gplbm_save_state / gplbm_load_state). */
+int gplbm_checkpoint_bytes(const gplbm_params* p, uint64_t* bytes);
+
+/* Create a context on the current device.  dev_buf (device, >= bytes from
+ * gplbm_state_bytes, 256-byte aligned) is borrowed until gplbm_destroy.
+ * stream: hipStream_t (as void*), may be NULL for the null stream.
+ * Rejects M_phi <= 0, gamma <= 0, W <= 0, sizes < 1, nz != 1 for D2Q9. */
+int gplbm_create(const gplbm_params* p, void* dev_buf, uint64_t bytes, void* stream,
+                 gplbm_ctx** out);
+
+/* Change the stream later calls are ordered on. */
+int gplbm_set_stream(gplbm_ctx* ctx, void* stream);
+
+/* Initial condition (time 0) from phi0 and c0: device pointers to N doubles
+ * each (N = nx*ny*nz, x fastest).  Asynchronous on the context's stream. */
+int gplbm_init_fields(gplbm_ctx* ctx, const double* phi0, const double* c0);
+
+/* Advance nsteps >= 0 time steps.  Asynchronous on the context's stream. */
+int gplbm_step(gplbm_ctx* ctx, int64_t nsteps);
+
+/* Current time level n. */
+int64_t gplbm_step_count(const gplbm_ctx* ctx);
+
+/* phi^n, c^n and mu^n as doubles into device arrays of N entries each; a
+ * NULL pointer skips that field.  Asynchronous on the context's stream. */
+int gplbm_read_fields(gplbm_ctx* ctx, double* phi, double* c, double* mu);
+
+/* FP64 diagnostics of the current time level into host memory.  Reduced on
+ * the device in a fixed order (deterministic); synchronises the stream.
+ * Returns GPLBM_E_NONFINITE (with *out filled) if some phi or c is not
+ * finite. */
+int gplbm_diagnostics(gplbm_ctx* ctx, gplbm_diag* out);
+
+/* Copy the complete state (gplbm_checkpoint_bytes bytes) to / from device
+ * memory; together with the step count it determines every later step
+ * exactly.  Asynchronous on the context's stream. */
+int gplbm_save_state(gplbm_ctx* ctx, void* dev_dst);
+int gplbm_load_state(gplbm_ctx* ctx, const void* dev_src, int64_t step);
+
+/* Which schedule the context runs (GPLBM_SCHED_SPLIT or GPLBM_SCHED_FUSED). */
+int gplbm_schedule(const gplbm_ctx* ctx);
+
+const char* gplbm_last_error(const gplbm_ctx* ctx);
+void gplbm_destroy(gplbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,406 @@
+// C ABI of the coupled phi / c lattice-Boltzmann library (declarations and
+// contract in include/gplbm.h).
+//
+// Host side: validation, the carving of the borrowed device buffer, the
+// per-run constants, and the dispatch of the kernels over lattice and
+// precision.  No device allocation happens here.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "gplbm.h"
+#include "kernels_fused2d.h"
+#include "kernels_fused3d.h"
+#include "kernels_split.h"
+
+using namespace gplbm;
+
+struct gplbm_ctx {
+  gplbm_params p;
+  int Q;
+  int64_t N;
+  size_t elem;        // bytes per stored value
+  size_t pop_bytes;   // Q*N*elem rounded up
+  size_t phi_bytes;   // N*elem rounded up
+  char* G[2];
+  char* H[2];
+  char* PHI[2];
+  double* red;        // reduction scratch: kDiagBlocks*kDiagVals + kDiagVals
+  int cur;
+  int64_t step;
+  bool ready;
+  int sched;
+  hipStream_t stream;
+  int device;
+  std::string err;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int lattice_q(int lattice) { return lattice == GPLBM_D2Q9 ? 9 : 19; }
+
+// Returns an error text, or nullptr when the parameters are acceptable.
+const char* check_params(const gplbm_params* p) {
+  if (!p) return "null parameters";
+  if (p->lattice != GPLBM_D2Q9 && p->lattice != GPLBM_D3Q19) return "unknown lattice";
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return "grid sizes must be >= 1";
+  if (p->lattice == GPLBM_D2Q9 && p->nz != 1) return "D2Q9 needs nz == 1";
+  for (int a = 0; a < 3; ++a)
+    if (p->bc[a] != GPLBM_PERIODIC && p->bc[a] != GPLBM_ZERO_FLUX) return "unknown boundary";
+  if (p->precision != GPLBM_FP64 && p->precision != GPLBM_FP32) return "unknown precision";
+  if (p->schedule < GPLBM_SCHED_AUTO || p->schedule > GPLBM_SCHED_FUSED) return "unknown schedule";
+  if (p->reserved != 0) return "reserved field must be 0";
+  if (!(p->W > 0.0) || !std::isfinite(p->W)) return "W must be > 0";
+  if (!(p->M_phi > 0.0) || !std::isfinite(p->M_phi)) return "M_phi must be > 0 (omega_g in (0,2))";
+  if (!(p->gamma > 0.0) || !std::isfinite(p->gamma)) return "gamma must be > 0 (omega_h in (0,2))";
+  const double vals[] = {p->lambda, p->D_l, p->D_s, p->a_at, p->c_s_co, p->c_l_co, p->mu_eq, p->eps_n};
+  for (double v : vals)
+    if (!std::isfinite(v)) return "non-finite parameter";
+  const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+  if (N > (int64_t)1 << 40) return "grid too large";
+  return nullptr;
+}
+
+void layout(const gplbm_params* p, size_t* elem, size_t* pop, size_t* phi, size_t* total) {
+  const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+  *elem = p->precision == GPLBM_FP64 ? 8 : 4;
+  *pop = round_up((size_t)lattice_q(p->lattice) * N * *elem);
+  *phi = round_up((size_t)N * *elem);
+  const size_t red = round_up(sizeof(double) * (kDiagBlocks * kDiagVals + kDiagVals));
+  *total = 4 * *pop + 2 * *phi + red;
+}
+
+int fail(gplbm_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+int check_launch(gplbm_ctx* ctx, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return fail(ctx, GPLBM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return GPLBM_OK;
+}
+
+template <class C>
+Coef<C> make_coef(const gplbm_params& p, int Q, const double* w) {
+  Coef<C> K{};
+  const double dc = p.c_s_co - p.c_l_co;
+  K.omega_g = C(1.0 / (3.0 * p.M_phi + 0.5));
+  K.omega_h = C(1.0 / (3.0 / p.gamma + 0.5));
+  K.dc = C(dc);
+  K.kst = C(-((p.lambda * p.M_phi) / (p.W * p.W)));
+  K.k4w = C(4.0 / p.W);
+  K.kdw = C(-((8.0 * p.M_phi) / (p.W * p.W)));
+  K.jfac = C((p.a_at * p.W) * dc);
+  K.Dp = C(p.D_l - p.D_s);
+  K.Dl = C(p.D_l);
+  K.Ds = C(p.D_s);
+  K.gamma = C(p.gamma);
+  K.eps2 = C(p.eps_n * p.eps_n);
+  K.mueq_c = C(p.mu_eq);
+  K.cl = p.c_l_co;
+  K.cs = p.c_s_co;
+  K.mueq = p.mu_eq;
+  for (int k = 0; k < Q; ++k) K.gw[k] = C(p.gamma * w[k]);
+  K.counter_term = p.counter_term ? 1 : 0;
+  K.anti_trapping = p.anti_trapping ? 1 : 0;
+  return K;
+}
+
+Geo make_geo(const gplbm_params& p) {
+  Geo g;
+  g.nx = p.nx;
+  g.ny = p.ny;
+  g.nz = p.nz;
+  g.bcx = p.bc[0];
+  g.bcy = p.bc[1];
+  g.bcz = p.lattice == GPLBM_D2Q9 ? GPLBM_PERIODIC : p.bc[2];
+  g.N = (int64_t)p.nx * p.ny * p.nz;
+  return g;
+}
+
+// Typed operations for one lattice L and storage / arithmetic types S, C.
+template <class L, class S, class C>
+struct Ops {
+  static dim3 block() { return dim3(64, 4, 1); }
+  static dim3 grid(const gplbm_ctx* ctx) {
+    return dim3((ctx->p.nx + 63) / 64, (ctx->p.ny + 3) / 4, ctx->p.nz);
+  }
+  static Coef<C> coef(const gplbm_ctx* ctx) { return make_coef<C>(ctx->p, L::Q, L::w); }
+
+  static int init(gplbm_ctx* ctx, const double* phi0, const double* c0) {
+    const Geo g = make_geo(ctx->p);
+    const int a = ctx->cur;
+    hipLaunchKernelGGL((k_init<L, S, C>), grid(ctx), block(), 0, ctx->stream, g, coef(ctx), phi0,
+                       c0, (S*)ctx->G[a], (S*)ctx->H[a], (S*)ctx->PHI[a]);
+    return check_launch(ctx, "init");
+  }
+
+  static int step_split(gplbm_ctx* ctx, int64_t nsteps) {
+    const Geo g = make_geo(ctx->p);
+    const Coef<C> K = coef(ctx);
+    for (int64_t s = 0; s < nsteps; ++s) {
+      const int a = ctx->cur, b = 1 - a;
+      StepBufs<S> bufs{(const S*)ctx->G[a], (const S*)ctx->H[a], (const S*)ctx->PHI[a],
+                       (S*)ctx->H[b],       (S*)ctx->PHI[b],       (S*)ctx->G[b]};
+      hipLaunchKernelGGL((k_split_h<L, S, C>), grid(ctx), block(), 0, ctx->stream, g, K, bufs);
+      hipLaunchKernelGGL((k_split_g<L, S, C>), grid(ctx), block(), 0, ctx->stream, g, K, bufs);
+      int rc = check_launch(ctx, "split step");
+      if (rc) return rc;
+      ctx->cur = b;
+      ctx->step += 1;
+    }
+    return GPLBM_OK;
+  }
+
+  static int step_fused(gplbm_ctx* ctx, int64_t nsteps) {
+    const Geo g = make_geo(ctx->p);
+    const Coef<C> K = coef(ctx);
+    for (int64_t s = 0; s < nsteps; ++s) {
+      const int a = ctx->cur, b = 1 - a;
+      StepBufs<S> bufs{(const S*)ctx->G[a], (const S*)ctx->H[a], (const S*)ctx->PHI[a],
+                       (S*)ctx->H[b],       (S*)ctx->PHI[b],       (S*)ctx->G[b]};
+      int rc = FusedLaunch<L, S, C>::launch(g, K, bufs, ctx->stream);
+      if (rc) return fail(ctx, GPLBM_E_DEVICE, "fused step launch failed");
+      rc = check_launch(ctx, "fused step");
+      if (rc) return rc;
+      ctx->cur = b;
+      ctx->step += 1;
+    }
+    return GPLBM_OK;
+  }
+
+  static int fields(gplbm_ctx* ctx, double* phi, double* c, double* mu) {
+    const Geo g = make_geo(ctx->p);
+    const int a = ctx->cur;
+    hipLaunchKernelGGL((k_fields<L, S>), grid(ctx), block(), 0, ctx->stream, g, ctx->p.c_l_co,
+                       ctx->p.c_s_co, ctx->p.mu_eq, (const S*)ctx->H[a], (const S*)ctx->PHI[a],
+                       phi, c, mu);
+    return check_launch(ctx, "read fields");
+  }
+
+  static int diag(gplbm_ctx* ctx) {
+    const Geo g = make_geo(ctx->p);
+    const int a = ctx->cur;
+    double* part = ctx->red;
+    double* out = ctx->red + kDiagBlocks * kDiagVals;
+    hipLaunchKernelGGL((k_diag_partial<L, S>), dim3(kDiagBlocks), dim3(kDiagThreads), 0,
+                       ctx->stream, g, (const S*)ctx->H[a], (const S*)ctx->PHI[a], part);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagThreads), 0, ctx->stream,
+                       (const double*)part, kDiagBlocks, out);
+    return check_launch(ctx, "diagnostics");
+  }
+};
+
+template <template <class, class, class> class Fn, class... Args>
+int dispatch(gplbm_ctx* ctx, Args... args) {
+  if (ctx->p.lattice == GPLBM_D2Q9) {
+    if (ctx->p.precision == GPLBM_FP64) return Fn<D2Q9, double, double>::run(ctx, args...);
+    return Fn<D2Q9, float, float>::run(ctx, args...);
+  }
+  if (ctx->p.precision == GPLBM_FP64) return Fn<D3Q19, double, double>::run(ctx, args...);
+  return Fn<D3Q19, float, float>::run(ctx, args...);
+}
+
+template <class L, class S, class C>
+struct InitFn {
+  static int run(gplbm_ctx* c, const double* a, const double* b) { return Ops<L, S, C>::init(c, a, b); }
+};
+template <class L, class S, class C>
+struct StepFn {
+  static int run(gplbm_ctx* c, int64_t n) {
+    return c->sched == GPLBM_SCHED_FUSED ? Ops<L, S, C>::step_fused(c, n)
+                                         : Ops<L, S, C>::step_split(c, n);
+  }
+};
+template <class L, class S, class C>
+struct FieldsFn {
+  static int run(gplbm_ctx* c, double* a, double* b, double* d) { return Ops<L, S, C>::fields(c, a, b, d); }
+};
+template <class L, class S, class C>
+struct DiagFn {
+  static int run(gplbm_ctx* c) { return Ops<L, S, C>::diag(c); }
+};
+
+int choose_schedule(const gplbm_params& p) {
+  const bool fused_ok = p.lattice == GPLBM_D2Q9 ? fused2d_supported(p.nx, p.ny)
+                                               : fused3d_supported(p.nx, p.ny, p.nz, p.bc);
+  if (p.schedule == GPLBM_SCHED_SPLIT) return GPLBM_SCHED_SPLIT;
+  if (p.schedule == GPLBM_SCHED_FUSED) return fused_ok ? GPLBM_SCHED_FUSED : -1;
+  return fused_ok ? GPLBM_SCHED_FUSED : GPLBM_SCHED_SPLIT;
+}
+
+int use_device(gplbm_ctx* ctx) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(ctx, GPLBM_E_DEVICE, "hipGetDevice failed");
+  if (dev != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
+    return fail(ctx, GPLBM_E_DEVICE, "hipSetDevice failed");
+  return GPLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gplbm_state_bytes(const gplbm_params* p, uint64_t* bytes) {
+  if (check_params(p) || !bytes) return GPLBM_E_INVALID;
+  size_t elem, pop, phi, total;
+  layout(p, &elem, &pop, &phi, &total);
+  *bytes = total;
+  return GPLBM_OK;
+}
+
+int gplbm_checkpoint_bytes(const gplbm_params* p, uint64_t* bytes) {
+  if (check_params(p) || !bytes) return GPLBM_E_INVALID;
+  size_t elem, pop, phi, total;
+  layout(p, &elem, &pop, &phi, &total);
+  *bytes = 2 * pop + phi;
+  return GPLBM_OK;
+}
+
+int gplbm_create(const gplbm_params* p, void* dev_buf, uint64_t bytes, void* stream,
+                 gplbm_ctx** out) {
+  if (!out) return GPLBM_E_INVALID;
+  *out = nullptr;
+  if (check_params(p) || !dev_buf) return GPLBM_E_INVALID;
+  if (((uintptr_t)dev_buf) % kAlign) return GPLBM_E_INVALID;
+  size_t elem, pop, phi, total;
+  layout(p, &elem, &pop, &phi, &total);
+  if (bytes < total) return GPLBM_E_SIZE;
+  const int sched = choose_schedule(*p);
+  if (sched < 0) return GPLBM_E_INVALID;
+  gplbm_ctx* ctx = new gplbm_ctx();
+  ctx->p = *p;
+  if (ctx->p.lattice == GPLBM_D2Q9) ctx->p.bc[2] = GPLBM_PERIODIC;
+  ctx->Q = lattice_q(p->lattice);
+  ctx->N = (int64_t)p->nx * p->ny * p->nz;
+  ctx->elem = elem;
+  ctx->pop_bytes = pop;
+  ctx->phi_bytes = phi;
+  char* b = (char*)dev_buf;
+  ctx->G[0] = b;
+  ctx->G[1] = b + pop;
+  ctx->H[0] = b + 2 * pop;
+  ctx->H[1] = b + 3 * pop;
+  ctx->PHI[0] = b + 4 * pop;
+  ctx->PHI[1] = b + 4 * pop + phi;
+  ctx->red = (double*)(b + 4 * pop + 2 * phi);
+  ctx->cur = 0;
+  ctx->step = 0;
+  ctx->ready = false;
+  ctx->sched = sched;
+  ctx->stream = (hipStream_t)stream;
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    delete ctx;
+    return GPLBM_E_DEVICE;
+  }
+  *out = ctx;
+  return GPLBM_OK;
+}
+
+int gplbm_set_stream(gplbm_ctx* ctx, void* stream) {
+  if (!ctx) return GPLBM_E_INVALID;
+  ctx->stream = (hipStream_t)stream;
+  return GPLBM_OK;
+}
+
+int gplbm_init_fields(gplbm_ctx* ctx, const double* phi0, const double* c0) {
+  if (!ctx) return GPLBM_E_INVALID;
+  if (!phi0 || !c0) return fail(ctx, GPLBM_E_INVALID, "null field pointer");
+  if (int rc = use_device(ctx)) return rc;
+  ctx->cur = 0;
+  ctx->step = 0;
+  int rc = dispatch<InitFn>(ctx, phi0, c0);
+  ctx->ready = rc == GPLBM_OK;
+  return rc;
+}
+
+int gplbm_step(gplbm_ctx* ctx, int64_t nsteps) {
+  if (!ctx) return GPLBM_E_INVALID;
+  if (nsteps < 0) return fail(ctx, GPLBM_E_INVALID, "negative step count");
+  if (!ctx->ready) return fail(ctx, GPLBM_E_STATE, "step before init");
+  if (int rc = use_device(ctx)) return rc;
+  return dispatch<StepFn>(ctx, nsteps);
+}
+
+int64_t gplbm_step_count(const gplbm_ctx* ctx) { return ctx ? ctx->step : -1; }
+
+int gplbm_read_fields(gplbm_ctx* ctx, double* phi, double* c, double* mu) {
+  if (!ctx) return GPLBM_E_INVALID;
+  if (!ctx->ready) return fail(ctx, GPLBM_E_STATE, "read before init");
+  if (int rc = use_device(ctx)) return rc;
+  return dispatch<FieldsFn>(ctx, phi, c, mu);
+}
+
+int gplbm_diagnostics(gplbm_ctx* ctx, gplbm_diag* out) {
+  if (!ctx || !out) return GPLBM_E_INVALID;
+  if (!ctx->ready) return fail(ctx, GPLBM_E_STATE, "diagnostics before init");
+  if (int rc = use_device(ctx)) return rc;
+  int rc = dispatch<DiagFn>(ctx);
+  if (rc) return rc;
+  double v[kDiagVals];
+  hipError_t e = hipMemcpyAsync(v, ctx->red + kDiagBlocks * kDiagVals, sizeof(v),
+                                hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail(ctx, GPLBM_E_DEVICE, std::string("diagnostics copy: ") + hipGetErrorString(e));
+  out->step = ctx->step;
+  out->total_mass = v[0];
+  out->solid_fraction = v[1] / (double)ctx->N;
+  out->solid_fraction_count = v[2] / (double)ctx->N;
+  out->sum_phi = v[3];
+  out->phi_min = v[4];
+  out->phi_max = v[5];
+  out->nonfinite = v[6] != 0.0 ? 1 : 0;
+  out->reserved = 0;
+  if (out->nonfinite) return fail(ctx, GPLBM_E_NONFINITE, "non-finite phi or c");
+  return GPLBM_OK;
+}
+
+int gplbm_save_state(gplbm_ctx* ctx, void* dev_dst) {
+  if (!ctx || !dev_dst) return GPLBM_E_INVALID;
+  if (!ctx->ready) return fail(ctx, GPLBM_E_STATE, "save before init");
+  if (int rc = use_device(ctx)) return rc;
+  const int a = ctx->cur;
+  char* d = (char*)dev_dst;
+  hipError_t e = hipMemcpyAsync(d, ctx->G[a], ctx->pop_bytes, hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d + ctx->pop_bytes, ctx->H[a], ctx->pop_bytes, hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d + 2 * ctx->pop_bytes, ctx->PHI[a], ctx->phi_bytes, hipMemcpyDeviceToDevice,
+                       ctx->stream);
+  if (e != hipSuccess) return fail(ctx, GPLBM_E_DEVICE, std::string("save: ") + hipGetErrorString(e));
+  return GPLBM_OK;
+}
+
+int gplbm_load_state(gplbm_ctx* ctx, const void* dev_src, int64_t step) {
+  if (!ctx || !dev_src || step < 0) return GPLBM_E_INVALID;
+  if (int rc = use_device(ctx)) return rc;
+  const int a = ctx->cur;
+  const char* s = (const char*)dev_src;
+  hipError_t e = hipMemcpyAsync(ctx->G[a], s, ctx->pop_bytes, hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ctx->H[a], s + ctx->pop_bytes, ctx->pop_bytes, hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ctx->PHI[a], s + 2 * ctx->pop_bytes, ctx->phi_bytes, hipMemcpyDeviceToDevice,
+                       ctx->stream);
+  if (e != hipSuccess) return fail(ctx, GPLBM_E_DEVICE, std::string("load: ") + hipGetErrorString(e));
+  ctx->step = step;
+  ctx->ready = true;
+  return GPLBM_OK;
+}
+
+int gplbm_schedule(const gplbm_ctx* ctx) { return ctx ? ctx->sched : GPLBM_E_INVALID; }
+
+const char* gplbm_last_error(const gplbm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void gplbm_destroy(gplbm_ctx* ctx) { delete ctx; }
+
+}  // extern "C"

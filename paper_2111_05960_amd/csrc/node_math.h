@@ -1,0 +1,198 @@
+// Per-node arithmetic of the coupled step, shared by every kernel schedule.
+//
+// Each expression is written in the exact order in which it is evaluated
+// (the library is compiled with -ffp-contract=off), and moments are summed in
+// ascending population index.  Multiplications by a lattice-vector component
+// of 0 or +-1 are replaced by skipping or negating the operand, which is
+// exact.  With these rules the FP64 path is reproducible to the last bit
+// from the formulas alone.
+//
+//   closure           mu = mu_eq + (c - (c_l phi + c_s (1 - phi)))
+//                     Eqs. (PotChim_Equilibirum), (Coexistence_Interpol)
+//   gradient          grad = 3 sum_k w_k e_k d_k, d_k = (phi(x+e_k) - phi(x-e_k))/2
+//                     Eqs. (DerivDirec_Grad), (Grad)
+//   normal            n = grad / sqrt(|grad|^2 + eps_n^2)
+//   phi sources       G^st = kst S_phi, S_phi = 6 phi(1-phi) dc (mu - mu_eq),
+//                     kst = -lambda M / W^2               Eqs. (SourceG_ST), (SourceTerm_Coexistence)
+//                     G^ct_k = (4/W) phi(1-phi) e_k.n     Eq. (SourceG_CT)
+//                     G^dw = kdw 2 phi(1-phi)(1-2phi), kdw = -8 M / W^2   Eq. (SourceG_dw)
+//                     G_k = w_k (G^st + G^curv)           Eq. (TermG)
+//   g collision       g* = (g - omega_g ((g - w_k phi) + G_k/2)) + G_k
+//                     Eq. (LBE_PhaseField_Eq), omega_g = 1/(3 M + 1/2)
+//   h source          F = (mu (D_l - D_s)) grad + (a W dc) dphi/dt n,
+//                     H_k = (gamma w_k) e_k.F             Eq. (SourceTerm_LBE_h)
+//   h equilibrium     Lambda = (gamma D(phi)) mu, D = D_l phi + D_s (1-phi)
+//                     h^eq_rest = c - (1 - w_rest) Lambda, h^eq_k = w_k Lambda
+//                     Eq. (Heq_Composition)
+//   h collision       h* = (h - omega_h ((h - h^eq_k) + H_k/2)) + H_k
+//                     Eq. (LBE_Composition), omega_h = 1/(3/gamma + 1/2)
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lattice.h"
+
+namespace gplbm {
+
+// Per-run constants, computed once on the host in double and converted to
+// the arithmetic type C of the kernel.
+template <class C>
+struct Coef {
+  C omega_g, omega_h;  // BGK rates of the two LBEs
+  C dc;                // c_s^co - c_l^co
+  C kst;               // -lambda M / W^2
+  C k4w;               // 4 / W
+  C kdw;               // -8 M / W^2
+  C jfac;              // a W dc
+  C Dp;                // D_l - D_s
+  C Dl, Ds, gamma;
+  C eps2;              // eps_n^2
+  C mueq_c;            // mu_eq in C
+  double cl, cs, mueq; // closure constants (always double)
+  C gw[19];            // gamma w_k
+  int counter_term, anti_trapping;
+};
+
+__device__ __forceinline__ double closure(double cl, double cs, double mueq, double c,
+                                          double phi) {
+  double cco = (cl * phi) + (cs * (1.0 - phi));
+  return mueq + (c - cco);
+}
+
+// e_k . v with the zero components skipped and -1 as a negation.
+template <class L, class C>
+__device__ __forceinline__ C edot(int k, C v0, C v1, C v2) {
+  C r = C(0);
+  bool first = true;
+  if (L::ex[k] != 0) {
+    r = L::ex[k] > 0 ? v0 : -v0;
+    first = false;
+  }
+  if (L::ey[k] != 0) {
+    r = first ? (L::ey[k] > 0 ? v1 : -v1) : (L::ey[k] > 0 ? r + v1 : r - v1);
+    first = false;
+  }
+  if (L::D == 3 && L::ez[k] != 0) {
+    r = first ? (L::ez[k] > 0 ? v2 : -v2) : (L::ez[k] > 0 ? r + v2 : r - v2);
+  }
+  return r;
+}
+
+// Gradient and normal from an accessor phi_at(dx, dy, dz) returning the
+// phase field at x + (dx, dy, dz) (ghost rule already applied).
+template <class L, class C, class F>
+__device__ __forceinline__ void gradient_normal(const F& phi_at, C eps2, C g[3], C n[3]) {
+  C a0 = C(0), a1 = C(0), a2 = C(0);
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    if (k == L::REST) continue;
+    C d = C(0.5) * (phi_at(L::ex[k], L::ey[k], L::ez[k]) -
+                    phi_at(-L::ex[k], -L::ey[k], -L::ez[k]));
+    C wd = C(L::w[k]) * d;
+    if (L::ex[k] > 0) a0 = a0 + wd;
+    if (L::ex[k] < 0) a0 = a0 - wd;
+    if (L::ey[k] > 0) a1 = a1 + wd;
+    if (L::ey[k] < 0) a1 = a1 - wd;
+    if (L::D == 3) {
+      if (L::ez[k] > 0) a2 = a2 + wd;
+      if (L::ez[k] < 0) a2 = a2 - wd;
+    }
+  }
+  g[0] = C(3) * a0;
+  g[1] = C(3) * a1;
+  g[2] = C(3) * a2;
+  C nn = g[0] * g[0] + g[1] * g[1];
+  if (L::D == 3) nn = nn + g[2] * g[2];
+  C den = sqrt(nn + eps2);
+  n[0] = g[0] / den;
+  n[1] = g[1] / den;
+  n[2] = L::D == 3 ? g[2] / den : C(0);
+}
+
+// Zeroth moment of the phi source at a node (closed form): G^st, plus G^dw
+// without the counter term.
+template <class C>
+__device__ __forceinline__ C source_moment(const Coef<C>& K, C phi, C mu) {
+  C pp = phi * (C(1) - phi);
+  C pprime = C(6) * pp;
+  C Sphi = (pprime * K.dc) * (mu - K.mueq_c);
+  C Gst = K.kst * Sphi;
+  if (K.counter_term) return Gst;
+  C wdw = C(2) * (pp * (C(1) - C(2) * phi));
+  C Gdw = K.kdw * wdw;
+  return Gst + Gdw;
+}
+
+// Population sources G_k of the phi-LBE.
+template <class L, class C>
+__device__ __forceinline__ void phi_sources(const Coef<C>& K, C phi, C mu, const C n[3],
+                                            C G[L::Q]) {
+  C pp = phi * (C(1) - phi);
+  C pprime = C(6) * pp;
+  C Sphi = (pprime * K.dc) * (mu - K.mueq_c);
+  C Gst = K.kst * Sphi;
+  if (K.counter_term) {
+    C kphi = K.k4w * pp;
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+      if (k == L::REST)
+        G[k] = C(L::w[k]) * Gst;
+      else
+        G[k] = C(L::w[k]) * (Gst + kphi * edot<L, C>(k, n[0], n[1], n[2]));
+    }
+  } else {
+    C wdw = C(2) * (pp * (C(1) - C(2) * phi));
+    C Gdw = K.kdw * wdw;
+    C s = Gst + Gdw;
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) G[k] = C(L::w[k]) * s;
+  }
+}
+
+template <class L, class C>
+__device__ __forceinline__ C g_collide(const Coef<C>& K, int k, C g, C phi, C Gk) {
+  C t = (g - C(L::w[k]) * phi) + C(0.5) * Gk;
+  return (g - K.omega_g * t) + Gk;
+}
+
+// Flux F = (mu D') grad + j_at of the h source (j_at only when enabled).
+template <class L, class C>
+__device__ __forceinline__ void h_flux(const Coef<C>& K, C mu, const C g[3], const C n[3],
+                                       C dtphi, bool with_at, C F[3]) {
+  C md = mu * K.Dp;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    F[a] = md * g[a];
+    if (with_at) F[a] = F[a] + (K.jfac * dtphi) * n[a];
+  }
+}
+
+template <class C>
+__device__ __forceinline__ C h_lambda(const Coef<C>& K, C phi, C mu) {
+  C D = (K.Dl * phi) + (K.Ds * (C(1) - phi));
+  return (K.gamma * D) * mu;
+}
+
+template <class L, class C>
+__device__ __forceinline__ C h_eq(int k, C c, C lam) {
+  if (k == L::REST) return c - C(1.0 - L::w[k]) * lam;
+  return C(L::w[k]) * lam;
+}
+
+template <class L, class C>
+__device__ __forceinline__ C h_source(const Coef<C>& K, int k, const C F[3]) {
+  if (k == L::REST) return C(0);
+  return K.gw[k] * edot<L, C>(k, F[0], F[1], F[2]);
+}
+
+template <class L, class C>
+__device__ __forceinline__ C h_collide(const Coef<C>& K, int k, C h, C heq, C Hk) {
+  if (k == L::REST) {
+    C t = h - heq;
+    return h - K.omega_h * t;
+  }
+  C t = (h - heq) + C(0.5) * Hk;
+  return (h - K.omega_h * t) + Hk;
+}
+
+}  // namespace gplbm

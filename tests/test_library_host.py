@@ -1,0 +1,86 @@
+"""Host-side checks of the HIP library that need no GPU: it loads, exports
+every function include/gplbm.h declares, and validates parameters."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import workloads as wl
+from paper_2111_05960_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    with open(os.path.join(ROOT, "include", "gplbm.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gplbm_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2111_05960_amd import build
+    if build.stale():
+        build.build()
+    return B.load()
+
+
+def test_every_declared_function_is_exported(lib):
+    names = header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(B.SYMBOLS)
+
+
+def test_struct_sizes_match_header(lib):
+    assert ctypes.sizeof(B.gplbm_params) == 4 * 12 + 8 * 11
+    assert ctypes.sizeof(B.gplbm_diag) == 8 * 7 + 8
+
+
+def test_state_bytes_layout(lib):
+    p = wl.base_params(lattice=wl.D3Q19, shape=(16, 12, 10), bc=(0, 0, 0))
+    for prec, elem in (("fp64", 8), ("fp32", 4)):
+        cp = B.make_params(p, prec)
+        n = 16 * 12 * 10
+        rnd = lambda v: (v + 255) // 256 * 256
+        pop, phi = rnd(19 * n * elem), rnd(n * elem)
+        assert B.gplbm_checkpoint_bytes(cp) == 2 * pop + phi
+        assert B.gplbm_state_bytes(cp) >= 4 * pop + 2 * phi
+
+
+@pytest.mark.parametrize("field,value", [
+    ("M_phi", 0.0), ("M_phi", -1.0), ("gamma", 0.0), ("W", 0.0), ("nz", 2), ("nx", 0),
+    ("lattice", 7), ("precision", 9), ("schedule", 5), ("lam", float("nan")),
+])
+def test_invalid_parameters_rejected(lib, field, value):
+    p = wl.base_params()
+    cp = B.make_params(p)
+    setattr(cp, field, value)
+    with pytest.raises(B.GplbmError) as e:
+        B.gplbm_state_bytes(cp)
+    assert e.value.code == B.GPLBM_E_INVALID
+    # gplbm_create rejects the same parameters before touching the device
+    h = ctypes.c_void_p()
+    rc = lib.gplbm_create(ctypes.byref(cp), ctypes.c_void_p(256), 1 << 30, None, ctypes.byref(h))
+    assert rc == B.GPLBM_E_INVALID and not h.value
+
+
+def test_create_rejects_small_or_misaligned_buffer(lib):
+    cp = B.make_params(wl.base_params())
+    need = B.gplbm_state_bytes(cp)
+    h = ctypes.c_void_p()
+    assert lib.gplbm_create(ctypes.byref(cp), ctypes.c_void_p(4096), need - 1, None,
+                            ctypes.byref(h)) == B.GPLBM_E_SIZE
+    assert lib.gplbm_create(ctypes.byref(cp), ctypes.c_void_p(4096 + 8), need, None,
+                            ctypes.byref(h)) == B.GPLBM_E_INVALID
+    assert lib.gplbm_create(ctypes.byref(cp), None, need, None,
+                            ctypes.byref(h)) == B.GPLBM_E_INVALID
+
+
+def test_null_context_is_rejected(lib):
+    assert lib.gplbm_step(None, 1) == B.GPLBM_E_INVALID
+    assert lib.gplbm_init_fields(None, None, None) == B.GPLBM_E_INVALID
+    assert lib.gplbm_step_count(None) == -1
