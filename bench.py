@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Throughput of the coupled phi / c lattice-Boltzmann step on one MI355X.
+
+One "step" advances both distributions (phi-LBE and c-LBE) of every node by
+one time step through the C ABI (gplbm_step).  The headline workload is the
+3-D porous-medium dissolution on a 512^3 D3Q19 periodic grid (Gaussian random
+field, correlation length 8, porosity 0.40, W = 2.5, counter term and
+anti-trapping on) in FP64; inputs are generated on the host, copied to HBM and
+initialised before the timed region.
+
+Printed: one JSON line with MLUPS (million node updates per second), the
+HBM roofline of the step kernel (algorithmic bytes per launch over the mean
+launch time, measured with HIP events on the stream the library launches on),
+and the CPU oracle timed on a bounded crop of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--precision fp64|fp32]
+                    [--schedule auto|split|fused] [--workload NAME]
+                    [--no-cpu-baseline] [--variants]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def bytes_per_node_step(lattice_q: int, elem: int) -> int:
+    """Algorithmic bytes each node-step must move: read and write both
+    distributions once, and read and write the one carried phi field."""
+    return (4 * lattice_q + 2) * elem
+
+
+WORKLOADS = {
+    "porous3d_512_d3q19": dict(kind="porous3d", n=512, steps=5000),
+    "porous3d_256_d3q19": dict(kind="porous3d", n=256, steps=10000),
+    "grain2d_1024_d2q9": dict(kind="grain2d", n=1024, steps=20000),
+    "porous2d_512_d2q9": dict(kind="porous2d", n=512, steps=4000),
+}
+
+
+def make_workload(name):
+    import workloads as wl
+    w = WORKLOADS[name]
+    if w["kind"] == "porous3d":
+        p, phi0, c0 = wl.config_porous3d(w["n"])
+    elif w["kind"] == "grain2d":
+        p, phi0, c0, _ = wl.config1(n=w["n"])
+    else:
+        p, phi0, c0, _ = wl.config_porous2d(n=w["n"])
+    return p, phi0, c0
+
+
+def time_gpu(p, phi0, c0, precision, schedule, steps, warmup, log):
+    import torch
+    from paper_2111_05960_amd import Simulation
+
+    sim = Simulation(p, precision, schedule)
+    sim.init(phi0, c0)
+    torch.cuda.synchronize()
+    d0 = sim.diagnostics(allow_nonfinite=True)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    d1 = sim.diagnostics(allow_nonfinite=True)
+    N = sim.N
+    launches = 1 if sim.schedule == "fused" else 2
+    elem = 8 if precision == "fp64" else 4
+    balg = bytes_per_node_step(sim.Q, elem)
+    ms_step = ms / steps
+    res = dict(
+        mlups=N * steps / (ms * 1e-3) / 1e6, ms_per_step=ms_step, wall_s=wall,
+        schedule=sim.schedule, launches_per_step=launches, nodes=N, Q=sim.Q,
+        bytes_per_node_step=balg,
+        achieved_gbs=balg * N / (ms_step * 1e-3) / 1e9,
+        mass_drift_rel=abs(d1["total_mass"] - d0["total_mass"]) / abs(d0["total_mass"]),
+        nonfinite=d1["nonfinite"], solid_fraction=[d0["solid_fraction"], d1["solid_fraction"]],
+    )
+    log(f"gpu {precision} {sim.schedule}: {res['mlups']:.1f} MLUPS, {ms_step:.3f} ms/step, "
+        f"{res['achieved_gbs']:.0f} GB/s algorithmic, mass drift {res['mass_drift_rel']:.2e}")
+    del sim
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(p, phi0, c0, log, budget_s=12.0):
+    """The CPU oracle on a 128^3 (3-D) or 512^2 (2-D) crop of the same
+    workload with zero-flux faces, stepped until about budget_s seconds."""
+    import numpy as np
+    import oracle
+    import workloads as wl
+    oracle.build(force=False)
+    size = 128 if p["lattice"] == wl.D3Q19 else 512
+    q, a, b = wl.crop_zero_flux(p, phi0, c0, min(size, p["shape"][-1]))
+    o = oracle.Oracle(q).init(a, b)
+    n_nodes = int(np.prod(q["shape"]))
+    o.step(1)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        o.step(2)
+        steps += 2
+        dt = time.perf_counter() - t0
+        if dt >= budget_s:
+            break
+    mlups = n_nodes * steps / dt / 1e6
+    log(f"cpu oracle: {mlups:.2f} MLUPS on {oracle.threads()} threads ({steps} steps of {q['shape']})")
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{steps} FP64 steps of the {'x'.join(map(str, q['shape'][::-1]))} crop "
+                      f"[0,{q['shape'][-1]}) of the same workload, zero-flux faces, "
+                      f"{dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="porous3d_512_d3q19", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--schedule", default="auto", choices=["auto", "split", "fused"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", action="store_true",
+                    help="also time the other precision and schedule")
+    args = ap.parse_args()
+
+    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the step runs on a single MI355X and this build "
+              "has no multi-GPU path (see DESIGN.md for how it would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    t0 = time.perf_counter()
+    p, phi0, c0 = make_workload(args.workload)
+    log(f"workload {args.workload} generated in {time.perf_counter() - t0:.1f} s")
+
+    main_res = time_gpu(p, phi0, c0, args.precision, args.schedule, args.steps, args.warmup, log)
+    variants = []
+    if args.variants:
+        for prec in ("fp64", "fp32"):
+            for sch in ("split", "auto"):
+                if prec == args.precision and sch == args.schedule:
+                    continue
+                r = time_gpu(p, phi0, c0, prec, sch, args.steps, args.warmup, log)
+                variants.append(dict(precision=prec, **r))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(p, phi0, c0, log)
+
+    nz, ny, nx = p["shape"]
+    achieved = main_res["achieved_gbs"]
+    line = {
+        "metric": "MLUPS of coupled phi-mu LBM step + % HBM roofline; adjoint/forward cost ratio",
+        "value": round(main_res["mlups"], 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "lattice": "D3Q19" if p["lattice"] == 1 else "D2Q9",
+            "grid": [nx, ny, nz],
+            "bc": "periodic",
+            "precision": args.precision,
+            "schedule": main_res["schedule"],
+            "counter_term": p["counter_term"], "anti_trapping": p["anti_trapping"],
+            "W": p["W"], "M_phi": p["M_phi"], "lambda": round(p["lam"], 6), "D_l": p["D_l"],
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "kernel": "step (all launches of one time step)",
+            "bytes_per_node_step": main_res["bytes_per_node_step"],
+            "launches_per_step": main_res["launches_per_step"],
+        },
+        "cpu_baseline": cpu,
+        "checks": {"mass_drift_rel": main_res["mass_drift_rel"], "nonfinite": main_res["nonfinite"]},
+        "context": {"paper_v100_mlups_2d_1024sq_d2q9": 149.8},
+    }
+    if variants:
+        line["variants"] = variants
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
