@@ -1,15 +1,182 @@
-// Fused schedule for D2Q9 (one kernel per step): not yet available.
+// Fused schedule for D2Q9: one kernel per time step n -> n+1.
+//
+// A block owns an output tile T of (BX-2) x (BY-2) nodes and runs one thread
+// per node of T grown by one node on each side (T+1).  Every thread of T+1:
+//   - pulls h~^n (sum -> c^n, mu^n) and g~^{n+1} (kept in registers),
+//   - reads phi^n around itself from an LDS tile covering T+2 (gradient,
+//     normal, source moment), forms phi^{n+1} and writes it to an LDS tile,
+//   - runs the h collision of step n (anti-trapping current from
+//     phi^{n+1} - phi^n).
+// The post-collision h* of T+1 are then streamed inside the block: Q passes,
+// one per population in index order, each adding the population that arrives
+// at every node of T into an LDS accumulator, so that c^{n+1} is summed in the
+// same order as a pull would sum it.  Finally the threads of T run the g
+// collision of step n+1 (gradient of phi^{n+1} from the LDS tile) and write
+// g~*^{n+1}, h~*^n and phi^{n+1}.
+//
+// HBM traffic per node and step is the minimum: Q + Q reads, Q + Q writes,
+// one phi read and one phi write.  The halo ring is recomputed (its pulls hit
+// the L2), and tiles are assigned to blocks so that the tiles of one XCD form
+// a contiguous band of the grid (blocks go to the 8 XCDs round robin).
 #pragma once
 
 #include "kernels_split.h"
 
 namespace gplbm {
 
-inline bool fused2d_supported(int, int) { return false; }
+constexpr int kNumXcd = 8;
+
+// Map the hardware block id to a tile id so that each XCD receives a
+// contiguous range of tiles (block b runs on XCD b % 8).
+__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
+  const int r = b % kNumXcd, j = b / kNumXcd;
+  const int q = ntiles / kNumXcd, rem = ntiles % kNumXcd;
+  const int start = r * q + (r < rem ? r : rem);
+  return start + j;
+}
+
+__device__ __forceinline__ int wrap_coord(int u, int n) {
+  int v = u % n;
+  return v < 0 ? v + n : v;
+}
+
+template <int BX, int BY, class L, class S, class C>
+__global__ void __launch_bounds__(BX* BY) k_fused2d(Geo g, Coef<C> K, StepBufs<S> b, int tiles_x,
+                                                    int ntiles) {
+  constexpr int TX = BX - 2, TY = BY - 2;
+  constexpr int AX = BX + 2, AY = BY + 2;  // phi^n tile with a 2-node halo
+  __shared__ C phiA[AY][AX];
+  __shared__ C phiB[BY][BX];
+  __shared__ double acc[BY][BX];
+
+  const int tile = xcd_tile(blockIdx.x, ntiles);
+  const int X0 = (tile % tiles_x) * TX, Y0 = (tile / tiles_x) * TY;
+  const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
+
+  // phi^n on T+2 (periodic wrap, or clamp = mirror ghost at a wall)
+  for (int l = threadIdx.x; l < AX * AY; l += BX * BY) {
+    const int lx = l % AX, ly = l / AX;
+    int ux = X0 - 2 + lx, uy = Y0 - 2 + ly;
+    ux = g.bcx ? min(max(ux, 0), g.nx - 1) : wrap_coord(ux, g.nx);
+    uy = g.bcy ? min(max(uy, 0), g.ny - 1) : wrap_coord(uy, g.ny);
+    phiA[ly][lx] = C(b.PHI[node_index(g, ux, uy, 0)]);
+  }
+
+  const int ux = X0 - 1 + tx, uy = Y0 - 1 + ty;  // unwrapped node of this thread
+  const bool in_x = ux >= 0 && ux < g.nx, in_y = uy >= 0 && uy < g.ny;
+  const bool active = (in_x || !g.bcx) && (in_y || !g.bcy);
+  const bool out = in_x && in_y && tx >= 1 && tx <= TX && ty >= 1 && ty <= TY;
+  const int x = g.bcx ? ux : wrap_coord(ux, g.nx);
+  const int y = g.bcy ? uy : wrap_coord(uy, g.ny);
+  const int64_t i = active ? node_index(g, x, y, 0) : 0;
+  // neighbour offsets clamped at walls (mirror ghost of the gradient stencil)
+  const int xm = (g.bcx && ux == 0) ? 0 : -1, xp = (g.bcx && ux == g.nx - 1) ? 0 : 1;
+  const int ym = (g.bcy && uy == 0) ? 0 : -1, yp = (g.bcy && uy == g.ny - 1) ? 0 : 1;
+  __syncthreads();
+
+  C gn[L::Q];  // g~^{n+1}
+  C hs[L::Q];  // h~*^n
+  C phin_c = C(0);
+  if (active) {
+    C h[L::Q];
+    double c = 0.0;
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+      S v = pull<L>(g, b.H, k, x, y, 0, i);
+      h[k] = C(v);
+      c = k == 0 ? double(v) : c + double(v);
+    }
+    double sg = 0.0;
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+      S v = pull<L>(g, b.G, k, x, y, 0, i);
+      gn[k] = C(v);
+      sg = k == 0 ? double(v) : sg + double(v);
+    }
+    const C phi = phiA[ty + 1][tx + 1];
+    const C mu = C(closure(K.cl, K.cs, K.mueq, c, double(phi)));
+    auto at = [&](int dx, int dy, int) -> C {
+      const int ox = dx < 0 ? xm : (dx > 0 ? xp : 0);
+      const int oy = dy < 0 ? ym : (dy > 0 ? yp : 0);
+      return phiA[ty + 1 + oy][tx + 1 + ox];
+    };
+    C gr[3], n[3];
+    gradient_normal<L, C>(at, K.eps2, gr, n);
+    const C sbar = source_moment<C>(K, phi, mu);
+    const double phin = sg + 0.5 * double(sbar);
+    phin_c = C(phin);
+    const C dtphi = phin_c - phi;
+    C F[3];
+    h_flux<L, C>(K, mu, gr, n, dtphi, K.anti_trapping != 0, F);
+    const C lam = h_lambda<C>(K, phi, mu);
+    const C cc = C(c);
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k)
+      hs[k] = C(S(h_collide<L, C>(K, k, h[k], h_eq<L, C>(k, cc, lam), h_source<L, C>(K, k, F))));
+  }
+  phiB[ty][tx] = phin_c;
+  __syncthreads();
+
+  // streaming of h* inside the tile: pass k adds the population k arriving
+  // at every output node (from x - e_k, or bounced back at a wall)
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    if (active) {
+      const int tx2 = tx + L::ex[k], ty2 = ty + L::ey[k];
+      const int vx = ux + L::ex[k], vy = uy + L::ey[k];
+      const bool tgt_in = tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY && vx >= 0 &&
+                          vx < g.nx && vy >= 0 && vy < g.ny;
+      if (tgt_in) {
+        const double v = double(hs[k]);
+        if (k == 0) acc[ty2][tx2] = v;
+        else acc[ty2][tx2] = acc[ty2][tx2] + v;
+      }
+      // population k of this node bounced back: its source x - e_k is beyond a wall
+      if (out && k != 0) {
+        const bool wall = (g.bcx && (ux - L::ex[k] < 0 || ux - L::ex[k] >= g.nx)) ||
+                          (g.bcy && (uy - L::ey[k] < 0 || uy - L::ey[k] >= g.ny));
+        if (wall) acc[ty][tx] = acc[ty][tx] + double(hs[L::opp[k]]);
+      }
+    }
+    __syncthreads();
+  }
+
+  if (!out) return;
+  const double c1 = acc[ty][tx];
+  const C phi1 = phiB[ty][tx];
+  const C mu1 = C(closure(K.cl, K.cs, K.mueq, c1, double(phi1)));
+  auto at1 = [&](int dx, int dy, int) -> C {
+    const int ox = dx < 0 ? xm : (dx > 0 ? xp : 0);
+    const int oy = dy < 0 ? ym : (dy > 0 ? yp : 0);
+    return phiB[ty + oy][tx + ox];
+  };
+  C gr[3], n[3];
+  gradient_normal<L, C>(at1, K.eps2, gr, n);
+  C G[L::Q];
+  phi_sources<L, C>(K, phi1, mu1, n, G);
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    b.Gn[(int64_t)k * g.N + i] = S(g_collide<L, C>(K, k, gn[k], phi1, G[k]));
+    b.Hn[(int64_t)k * g.N + i] = S(hs[k]);
+  }
+  b.PHIn[i] = S(phi1);
+}
+
+constexpr int kF2BX = 64, kF2BY = 8;
+
+inline bool fused2d_supported(int, int) { return true; }
 
 template <class L, class S, class C>
-struct FusedLaunch {
-  static int launch(const Geo&, const Coef<C>&, const StepBufs<S>&, hipStream_t) { return -1; }
+struct Fused2D {
+  static int launch(const Geo& g, const Coef<C>& K, const StepBufs<S>& b, hipStream_t st) {
+    constexpr int BX = kF2BX, BY = kF2BY;
+    const int tiles_x = (g.nx + BX - 3) / (BX - 2);
+    const int tiles_y = (g.ny + BY - 3) / (BY - 2);
+    const int ntiles = tiles_x * tiles_y;
+    hipLaunchKernelGGL((k_fused2d<BX, BY, L, S, C>), dim3(ntiles), dim3(BX * BY), 0, st, g, K, b,
+                       tiles_x, ntiles);
+    return 0;
+  }
 };
 
 }  // namespace gplbm

@@ -49,12 +49,17 @@ CASES_2D = [
     ((1, 33, 70), (1, 1, 0), 0, 1),
     ((1, 24, 130), (0, 1, 0), 1, 0),
     ((1, 17, 9), (1, 1, 0), 0, 0),
+    ((1, 3, 5), (0, 0, 0), 1, 1),
+    ((1, 7, 200), (0, 1, 0), 0, 1),
 ]
 CASES_3D = [
     ((12, 10, 14), (0, 0, 0), 1, 1),
     ((9, 13, 70), (1, 0, 1), 1, 1),
     ((10, 11, 12), (1, 1, 1), 0, 1),
     ((8, 16, 66), (0, 1, 0), 1, 0),
+    ((70, 9, 13), (0, 0, 0), 1, 1),
+    ((3, 4, 5), (0, 0, 0), 0, 1),
+    ((33, 20, 130), (0, 0, 0), 1, 0),
 ]
 
 
@@ -138,12 +143,14 @@ def test_checkpoint_resume_is_bitwise(gp):
         assert np.array_equal(x, y)
 
 
-def test_tile_shape_and_schedule_invariance(gp):
+@pytest.mark.parametrize("shape", [(1, 70, 150), (40, 30, 70)])
+def test_tile_shape_and_schedule_invariance(gp, shape):
     """The fused and split schedules give identical bits."""
-    shape = (1, 70, 150)
-    p = wl.base_params(shape=shape, bc=(0, 0, 0))
+    lattice = wl.D2Q9 if shape[0] == 1 else wl.D3Q19
+    p = wl.base_params(lattice=lattice, shape=shape, bc=(0, 0, 0))
     phi0, c0 = wl.random_state_fields(shape, seed=9)
     a = gp.Simulation(p, "fp64", "split").init(phi0, c0).step(25)
-    b = gp.Simulation(p, "fp64", "auto").init(phi0, c0).step(25)
+    b = gp.Simulation(p, "fp64", "fused").init(phi0, c0).step(25)
+    assert b.schedule == "fused"
     for x, y in zip(a.fields(), b.fields()):
         assert np.array_equal(x, y)
