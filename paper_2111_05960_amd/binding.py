@@ -16,7 +16,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgplbm.so")
+LIB_PATH = os.environ.get("GPLBM_LIBRARY") or os.path.join(HERE, "libgplbm.so")
 
 GPLBM_OK = 0
 GPLBM_E_INVALID = -1

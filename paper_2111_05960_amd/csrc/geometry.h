@@ -1,8 +1,11 @@
 // Grid geometry, boundary rules and the buffers of the state.
 //
-// Layout in device memory: structure of arrays f[k][z][y][x], x fastest, one
-// array per population k, so a wavefront of 64 consecutive x reads 64
-// consecutive elements of each population.
+// Layout in device memory: plane-major structure of arrays f[z][k][y][x],
+// x fastest: each z-plane holds its Q population planes one after the other
+// (for D2Q9, nz = 1, this is f[k][y][x]).  A wavefront of 64 consecutive x
+// reads 64 consecutive elements of one population, and all Q populations of
+// a plane lie within Q * nx * ny elements of each other, so a kernel addresses
+// them from one per-plane base and a 32-bit offset.
 //
 // State invariant between steps (time level n):
 //   G   = g~*^n      post-collision phi populations, not yet streamed
@@ -52,15 +55,22 @@ __device__ __forceinline__ int stencil_axis(int c, int n, int bc) {
   return c;
 }
 
+// Element index of population k at node (x, y, z).
+template <class L>
+__device__ __forceinline__ int64_t pop_index(const Geo& g, int k, int x, int y, int z) {
+  const int64_t plane = (int64_t)g.nx * g.ny;
+  return ((int64_t)z * L::Q + k) * plane + (int64_t)y * g.nx + x;
+}
+
 // Pull of population k at (x, y, z) from a post-collision array f.
 template <class L, class S>
 __device__ __forceinline__ S pull(const Geo& g, const S* __restrict__ f, int k, int x, int y,
-                                  int z, int64_t i) {
+                                  int z) {
   int sx = x, sy = y, sz = z;
   bool in = pull_axis(sx, L::ex[k], g.nx, g.bcx) && pull_axis(sy, L::ey[k], g.ny, g.bcy);
   if (L::D == 3) in = in && pull_axis(sz, L::ez[k], g.nz, g.bcz);
-  if (!in) return f[(int64_t)L::opp[k] * g.N + i];
-  return f[(int64_t)k * g.N + node_index(g, sx, sy, sz)];
+  if (!in) return f[pop_index<L>(g, L::opp[k], x, y, z)];
+  return f[pop_index<L>(g, k, sx, sy, sz)];
 }
 
 }  // namespace gplbm

@@ -90,7 +90,7 @@ int check_launch(gplbm_ctx* ctx, const char* what) {
 }
 
 template <class C>
-Coef<C> make_coef(const gplbm_params& p, int Q, const double* w) {
+Coef<C> make_coef(const gplbm_params& p) {
   Coef<C> K{};
   const double dc = p.c_s_co - p.c_l_co;
   K.omega_g = C(1.0 / (3.0 * p.M_phi + 0.5));
@@ -109,7 +109,6 @@ Coef<C> make_coef(const gplbm_params& p, int Q, const double* w) {
   K.cl = p.c_l_co;
   K.cs = p.c_s_co;
   K.mueq = p.mu_eq;
-  for (int k = 0; k < Q; ++k) K.gw[k] = C(p.gamma * w[k]);
   K.counter_term = p.counter_term ? 1 : 0;
   K.anti_trapping = p.anti_trapping ? 1 : 0;
   return K;
@@ -134,7 +133,7 @@ struct Ops {
   static dim3 grid(const gplbm_ctx* ctx) {
     return dim3((ctx->p.nx + 63) / 64, (ctx->p.ny + 3) / 4, ctx->p.nz);
   }
-  static Coef<C> coef(const gplbm_ctx* ctx) { return make_coef<C>(ctx->p, L::Q, L::w); }
+  static Coef<C> coef(const gplbm_ctx* ctx) { return make_coef<C>(ctx->p); }
 
   static int init(gplbm_ctx* ctx, const double* phi0, const double* c0) {
     const Geo g = make_geo(ctx->p);

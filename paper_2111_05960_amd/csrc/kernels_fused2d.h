@@ -82,14 +82,14 @@ __global__ void __launch_bounds__(BX* BY) k_fused2d(Geo g, Coef<C> K, StepBufs<S
     double c = 0.0;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
-      S v = pull<L>(g, b.H, k, x, y, 0, i);
+      S v = pull<L>(g, b.H, k, x, y, 0);
       h[k] = C(v);
       c = k == 0 ? double(v) : c + double(v);
     }
     double sg = 0.0;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
-      S v = pull<L>(g, b.G, k, x, y, 0, i);
+      S v = pull<L>(g, b.G, k, x, y, 0);
       gn[k] = C(v);
       sg = k == 0 ? double(v) : sg + double(v);
     }
@@ -156,8 +156,8 @@ __global__ void __launch_bounds__(BX* BY) k_fused2d(Geo g, Coef<C> K, StepBufs<S
   phi_sources<L, C>(K, phi1, mu1, n, G);
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
-    b.Gn[(int64_t)k * g.N + i] = S(g_collide<L, C>(K, k, gn[k], phi1, G[k]));
-    b.Hn[(int64_t)k * g.N + i] = S(hs[k]);
+    b.Gn[pop_index<L>(g, k, x, y, 0)] = S(g_collide<L, C>(K, k, gn[k], phi1, G[k]));
+    b.Hn[pop_index<L>(g, k, x, y, 0)] = S(hs[k]);
   }
   b.PHIn[i] = S(phi1);
 }

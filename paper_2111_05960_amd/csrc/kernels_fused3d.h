@@ -4,8 +4,7 @@
 // ZC planes, and runs one thread per node of the tile grown by one node in x
 // and y (T+1).  It walks the planes p = z0-1 .. z1 (one halo plane below and
 // above the chunk).  At plane p every thread
-//   - pulls h~^n (-> c^n, mu^n) and g~^{n+1} (-> phi^{n+1}; the values stay in
-//     registers for the g collision one plane later),
+//   - pulls h~^n (-> c^n, mu^n) and g~^{n+1} (-> phi^{n+1}),
 //   - takes phi^n of planes p-1, p, p+1 from a 3-plane LDS ring (T+2 in x-y)
 //     for the gradient, writes phi^{n+1}(p) into a second ring,
 //   - runs the h collision of step n.
@@ -15,7 +14,14 @@
 // numbered by layers of e_z (+1, 0, -1), every node's c^{n+1} receives its
 // populations in index order across the three planes, the order of a pull.
 // After plane p, c^{n+1}(p-1) is complete and the threads of T run the g
-// collision of step n+1 at plane p-1.
+// collision of step n+1 at plane p-1, on the g~^{n+1} pulled one plane
+// earlier (kept in registers, or pulled again from the cache).
+//
+// Addressing: with the plane-major layout f[z][k][y][x] every population a
+// thread pulls lies in one of three plane groups (z-1, z, z+1).  Each group is
+// a buffer resource in scalar registers; the population plane k*nx*ny is the
+// uniform offset and the (x, y) source the per-lane offset, so a load costs no
+// vector address arithmetic.
 //
 // Only periodic domains take this path (a wall would bounce some +z
 // populations into a plane one step later than the index order allows); the
@@ -32,13 +38,59 @@ namespace gplbm {
 
 __device__ __forceinline__ int ring3(int q) { return (q + 6) % 3; }
 
+#ifndef GPLBM_F3_REPULL
+#define GPLBM_F3_REPULL 0
+#endif
+#ifndef GPLBM_F3_MINBLOCKS
+#define GPLBM_F3_MINBLOCKS 1
+#endif
+#ifndef GPLBM_F3_PREFETCH
+#define GPLBM_F3_PREFETCH 0
+#endif
+
+// Raw buffer access: a resource (base, byte range) held in scalar registers,
+// a 32-bit per-lane offset and a 32-bit uniform offset.  Offsets outside the
+// range read 0 and drop writes.
+constexpr int kBufferFlags = 0x00020000;  // gfx9 buffer descriptor, dword 3
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                           kBufferFlags);
+}
+
+template <class S>
+__device__ __forceinline__ S bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(S) == 8)
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  else
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+// non-temporal store (the written state is not read again in this step)
+template <class S>
+__device__ __forceinline__ void bstore_nt(S v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                          uint32_t soff) {
+  constexpr int kNT = 2;
+  if constexpr (sizeof(S) == 8) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, kNT);
+  } else {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b32(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(V, v), r, voff, soff, kNT);
+  }
+}
+
 template <int BX, int BY, int ZC, class S, class C>
-__global__ void __launch_bounds__(BX* BY) k_fused3d(Geo g, Coef<C> K, StepBufs<S> b, int tiles_x,
-                                                    int tiles_xy, int ntiles) {
+__global__ void __launch_bounds__(BX* BY, GPLBM_F3_MINBLOCKS)
+    k_fused3d(Geo g, Coef<C> K, StepBufs<S> b, int tiles_x, int tiles_xy, int ntiles) {
   using L = D3Q19;
   constexpr int Q = L::Q;
   constexpr int TX = BX - 2, TY = BY - 2;
   constexpr int AX = BX + 2, AY = BY + 2;
+  constexpr int NT = BX * BY;
+  constexpr int PHI_PER_THREAD = (AX * AY + NT - 1) / NT;
+  constexpr bool kCarry = GPLBM_F3_REPULL == 0;
+  constexpr int kPre = GPLBM_F3_PREFETCH;  // 0 none, 1 phi and h, 2 phi, h and g
   __shared__ C phiA[3][AY][AX];      // phi^n, planes p-1, p, p+1
   __shared__ C phiB[3][BY][BX];      // phi^{n+1}, planes p-2, p-1, p
   __shared__ double acc[3][BY][BX];  // c^{n+1} being accumulated
@@ -50,55 +102,114 @@ __global__ void __launch_bounds__(BX* BY) k_fused3d(Geo g, Coef<C> K, StepBufs<S
   const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int plane = nx * ny;
+  const uint32_t planeB = uint32_t(plane) * sizeof(S);      // one population plane
+  const int64_t groupB = int64_t(plane) * Q * sizeof(S);    // one z plane group
 
   const int ux = X0 - 1 + tx, uy = Y0 - 1 + ty;
   const bool out = ux < nx && uy < ny && tx >= 1 && tx <= TX && ty >= 1 && ty <= TY;
-  // wrapped neighbour coordinates along x and y (periodic)
   const int x = wrap_coord(ux, nx), y = wrap_coord(uy, ny);
   const int xo[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
   const int yo[3] = {(y == 0 ? ny - 1 : y - 1) * nx, y * nx, (y == ny - 1 ? 0 : y + 1) * nx};
+  // byte offset, inside a population plane, of the source x - e_k (by e_x, e_y)
+  uint32_t xyb[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xyb[a][c] = uint32_t(yo[a] + xo[c]) * sizeof(S);
+  const uint32_t selfB = xyb[1][1];
+  // phi^n tile positions this thread loads (T+2 in x-y)
+  uint32_t phi_off[PHI_PER_THREAD];
+#pragma unroll
+  for (int j = 0; j < PHI_PER_THREAD; ++j) {
+    const int l = min((int)threadIdx.x + j * NT, AX * AY - 1);
+    const int gx = wrap_coord(X0 - 2 + l % AX, nx), gy = wrap_coord(Y0 - 2 + l / AX, ny);
+    phi_off[j] = uint32_t(gy * nx + gx);
+  }
 
-  auto load_phiA = [&](int p) {
-    const int zp = wrap_coord(p, nz);
-    const S* src = b.PHI + (int64_t)zp * plane;
-    for (int l = threadIdx.x; l < AX * AY; l += BX * BY) {
-      const int lx = l % AX, ly = l / AX;
-      const int gx = wrap_coord(X0 - 2 + lx, nx), gy = wrap_coord(Y0 - 2 + ly, ny);
-      phiA[ring3(p)][ly][lx] = C(src[gy * nx + gx]);
+  auto fetch_phi = [&](int p, S v[PHI_PER_THREAD]) {
+    const S* src = b.PHI + (int64_t)wrap_coord(p, nz) * plane;
+#pragma unroll
+    for (int j = 0; j < PHI_PER_THREAD; ++j) v[j] = src[phi_off[j]];
+  };
+  auto store_phi = [&](int p, const S v[PHI_PER_THREAD]) {
+#pragma unroll
+    for (int j = 0; j < PHI_PER_THREAD; ++j) {
+      const int l = threadIdx.x + j * NT;
+      if (l < AX * AY) phiA[ring3(p)][l / AX][l % AX] = C(v[j]);
     }
   };
-
-  load_phiA(z0 - 2);
-  load_phiA(z0 - 1);
-
-  C g_old[Q];
+  // pulls of plane p: population k at (x, y, z_p) comes from plane group z_p - e_z
+  auto fetch_pop = [&](const S* base, int p, S v[Q]) {
+    const int zp = wrap_coord(p, nz);
+    const int zs[3] = {(zp == 0 ? nz - 1 : zp - 1), zp, (zp == nz - 1 ? 0 : zp + 1)};
+    __amdgpu_buffer_rsrc_t R[3];
 #pragma unroll
-  for (int k = 0; k < Q; ++k) g_old[k] = C(0);
+    for (int j = 0; j < 3; ++j)
+      R[j] = make_rsrc(reinterpret_cast<const char*>(base) + zs[j] * groupB, uint32_t(groupB));
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      v[k] = bload<S>(R[1 - L::ez[k]], xyb[1 - L::ey[k]][1 - L::ex[k]], k * planeB);
+  };
+
+  {
+    S v[PHI_PER_THREAD];
+    fetch_phi(z0 - 2, v);
+    store_phi(z0 - 2, v);
+    fetch_phi(z0 - 1, v);
+    store_phi(z0 - 1, v);
+  }
+  S phi_nx[PHI_PER_THREAD];   // phi^n of plane p+1 (prefetched)
+  S h_nx[Q], g_nx[Q];         // pulls of plane p (prefetched)
+  if constexpr (kPre >= 1) {
+    fetch_phi(z0, phi_nx);
+    fetch_pop(b.H, z0 - 1, h_nx);
+    if constexpr (kPre >= 2) fetch_pop(b.G, z0 - 1, g_nx);
+  }
+
+  C g_old[kCarry ? Q : 1];
+#pragma unroll
+  for (int k = 0; k < (kCarry ? Q : 1); ++k) g_old[k] = C(0);
 
   for (int p = z0 - 1; p <= z1; ++p) {
-    load_phiA(p + 1);
-    __syncthreads();
+    S hv[Q], gv[Q];
+    if constexpr (kPre >= 1) {
+      store_phi(p + 1, phi_nx);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) hv[k] = h_nx[k];
+      if constexpr (kPre >= 2) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) gv[k] = g_nx[k];
+      }
+      __syncthreads();
+      // next plane's loads are in flight while this plane is computed
+      if (p + 1 <= z1) {
+        fetch_phi(p + 2, phi_nx);
+        fetch_pop(b.H, p + 1, h_nx);
+        if constexpr (kPre >= 2) fetch_pop(b.G, p + 1, g_nx);
+      }
+      if constexpr (kPre < 2) fetch_pop(b.G, p, gv);
+    } else {
+      S v[PHI_PER_THREAD];
+      fetch_phi(p + 1, v);
+      store_phi(p + 1, v);
+      __syncthreads();
+      fetch_pop(b.H, p, hv);
+      fetch_pop(b.G, p, gv);
+    }
 
     const int zp = wrap_coord(p, nz);
-    const int zo[3] = {(zp == 0 ? nz - 1 : zp - 1), zp, (zp == nz - 1 ? 0 : zp + 1)};
-    const int node = zp * plane + y * nx + x;
-
-    // pulls: population k at (x,y,zp) comes from (x,y,zp) - e_k
-    C h[Q], g_new[Q];
+    C h[Q];
+    C g_new[kCarry ? Q : 1];
     double c = 0.0, sg = 0.0;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      const int src = zo[1 - L::ez[k]] * plane + yo[1 - L::ey[k]] + xo[1 - L::ex[k]];
-      const S hv = b.H[(int64_t)k * g.N + src];
-      h[k] = C(hv);
-      c = k == 0 ? double(hv) : c + double(hv);
+      h[k] = C(hv[k]);
+      c = k == 0 ? double(hv[k]) : c + double(hv[k]);
     }
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      const int src = zo[1 - L::ez[k]] * plane + yo[1 - L::ey[k]] + xo[1 - L::ex[k]];
-      const S gv = b.G[(int64_t)k * g.N + src];
-      g_new[k] = C(gv);
-      sg = k == 0 ? double(gv) : sg + double(gv);
+      if constexpr (kCarry) g_new[k] = C(gv[k]);
+      sg = k == 0 ? double(gv[k]) : sg + double(gv[k]);
     }
     const int sA = ring3(p);
     const C phi = phiA[sA][ty + 1][tx + 1];
@@ -124,9 +235,10 @@ __global__ void __launch_bounds__(BX* BY) k_fused3d(Geo g, Coef<C> K, StepBufs<S
 
     const bool own_p = p >= z0 && p < z1;
     if (out && own_p) {
+      const auto Hw = make_rsrc(reinterpret_cast<char*>(b.Hn) + zp * groupB, uint32_t(groupB));
 #pragma unroll
-      for (int k = 0; k < Q; ++k) b.Hn[(int64_t)k * g.N + node] = S(hs[k]);
-      b.PHIn[node] = S(phin_c);
+      for (int k = 0; k < Q; ++k) bstore_nt<S>(S(hs[k]), Hw, selfB, k * planeB);
+      __builtin_nontemporal_store(S(phin_c), &b.PHIn[(int64_t)zp * plane + y * nx + x]);
     }
 
     // in-block streaming of h* into the accumulator ring, 9 passes:
@@ -165,7 +277,6 @@ __global__ void __launch_bounds__(BX* BY) k_fused3d(Geo g, Coef<C> K, StepBufs<S
     // g collision of step n+1 at plane p-1
     if (out && dn_ok) {
       const int zq = wrap_coord(p - 1, nz);
-      const int qnode = zq * plane + y * nx + x;
       const int sB = ring3(p - 1);
       const double c1 = acc[sB][ty][tx];
       const C phi1 = phiB[sB][ty][tx];
@@ -177,19 +288,37 @@ __global__ void __launch_bounds__(BX* BY) k_fused3d(Geo g, Coef<C> K, StepBufs<S
       gradient_normal<L, C>(atB, K.eps2, gr1, n1);
       C G[Q];
       phi_sources<L, C>(K, phi1, mu1, n1, G);
+      S gq[kCarry ? 1 : Q];
+      if constexpr (!kCarry) fetch_pop(b.G, p - 1, gq);
+      const auto Gw = make_rsrc(reinterpret_cast<char*>(b.Gn) + zq * groupB, uint32_t(groupB));
 #pragma unroll
-      for (int k = 0; k < Q; ++k)
-        b.Gn[(int64_t)k * g.N + qnode] = S(g_collide<L, C>(K, k, g_old[k], phi1, G[k]));
+      for (int k = 0; k < Q; ++k) {
+        C gk;
+        if constexpr (kCarry)
+          gk = g_old[k];
+        else
+          gk = C(gq[k]);
+        bstore_nt<S>(S(g_collide<L, C>(K, k, gk, phi1, G[k])), Gw, selfB, k * planeB);
+      }
     }
+    if constexpr (kCarry) {
 #pragma unroll
-    for (int k = 0; k < Q; ++k) g_old[k] = g_new[k];
+      for (int k = 0; k < Q; ++k) g_old[k] = g_new[k];
+    }
   }
 }
 
-constexpr int kF3BX = 64, kF3BY = 8, kF3ZC = 32;
+#ifndef GPLBM_F3BX
+#define GPLBM_F3BX 64
+#define GPLBM_F3BY 8
+#define GPLBM_F3ZC 32
+#endif
+constexpr int kF3BX = GPLBM_F3BX, kF3BY = GPLBM_F3BY, kF3ZC = GPLBM_F3ZC;
 
+// 32-bit offsets inside a z plane group: Q * nx * ny * 8 bytes must fit.
 inline bool fused3d_supported(int nx, int ny, int nz, const int* bc) {
-  return bc[0] == 0 && bc[1] == 0 && bc[2] == 0 && (int64_t)nx * ny * nz < ((int64_t)1 << 31);
+  return bc[0] == 0 && bc[1] == 0 && bc[2] == 0 && (int64_t)nx * ny * 19 * 8 < ((int64_t)1 << 32) &&
+         (int64_t)nx * ny * nz < ((int64_t)1 << 31);
 }
 
 template <class S, class C>

@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(256) k_split_h(Geo g, Coef<C> K, StepBufs<S> b
   double c = 0.0;
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
-    S v = pull<L>(g, b.H, k, x, y, z, i);
+    S v = pull<L>(g, b.H, k, x, y, z);
     h[k] = C(v);
     c = k == 0 ? double(v) : c + double(v);
   }
@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(256) k_split_h(Geo g, Coef<C> K, StepBufs<S> b
   double sg = 0.0;
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
-    double v = double(pull<L>(g, b.G, k, x, y, z, i));
+    double v = double(pull<L>(g, b.G, k, x, y, z));
     sg = k == 0 ? v : sg + v;
   }
   const double phin = sg + 0.5 * double(sbar);
@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(256) k_split_h(Geo g, Coef<C> K, StepBufs<S> b
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
     C Hk = h_source<L, C>(K, k, F);
-    b.Hn[(int64_t)k * g.N + i] = S(h_collide<L, C>(K, k, h[k], h_eq<L, C>(k, cc, lam), Hk));
+    b.Hn[pop_index<L>(g, k, x, y, z)] = S(h_collide<L, C>(K, k, h[k], h_eq<L, C>(k, cc, lam), Hk));
   }
   b.PHIn[i] = S(phin);
 }
@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(256) k_split_g(Geo g, Coef<C> K, StepBufs<S> b
   double c = 0.0;
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
-    double v = double(pull<L>(g, (const S*)b.Hn, k, x, y, z, i));
+    double v = double(pull<L>(g, (const S*)b.Hn, k, x, y, z));
     c = k == 0 ? v : c + v;
   }
   const C phi = C(b.PHIn[i]);
@@ -111,8 +111,8 @@ __global__ void __launch_bounds__(256) k_split_g(Geo g, Coef<C> K, StepBufs<S> b
   phi_sources<L, C>(K, phi, mu, n, G);
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
-    C gk = C(pull<L>(g, b.G, k, x, y, z, i));
-    b.Gn[(int64_t)k * g.N + i] = S(g_collide<L, C>(K, k, gk, phi, G[k]));
+    C gk = C(pull<L>(g, b.G, k, x, y, z));
+    b.Gn[pop_index<L>(g, k, x, y, z)] = S(g_collide<L, C>(K, k, gk, phi, G[k]));
   }
 }
 
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(256) k_init(Geo g, Coef<C> K, const double* __
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
     C g0 = S(C(L::w[k]) * phi - C(0.5) * G0[k]);
-    G[(int64_t)k * g.N + i] = S(g_collide<L, C>(K, k, g0, phi, Gk[k]));
+    G[pop_index<L>(g, k, x, y, z)] = S(g_collide<L, C>(K, k, g0, phi, Gk[k]));
   }
   // h~^0 into the slots the first pull reads
 #pragma unroll
@@ -182,9 +182,9 @@ __global__ void __launch_bounds__(256) k_init(Geo g, Coef<C> K, const double* __
     bool in = pull_axis(dx, L::ex[k], g.nx, g.bcx) && pull_axis(dy, L::ey[k], g.ny, g.bcy);
     if (L::D == 3) in = in && pull_axis(dz, L::ez[k], g.nz, g.bcz);
     if (in)
-      H[(int64_t)k * g.N + node_index(g, dx, dy, dz)] = hs[k];
+      H[pop_index<L>(g, k, dx, dy, dz)] = hs[k];
     else
-      H[(int64_t)L::opp[k] * g.N + i] = hs[k];
+      H[pop_index<L>(g, L::opp[k], x, y, z)] = hs[k];
   }
   PHI[i] = S(phi);
 }
@@ -205,7 +205,7 @@ __global__ void __launch_bounds__(256) k_fields(Geo g, double cl, double cs, dou
   double c = 0.0;
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
-    double v = double(pull<L>(g, H, k, x, y, z, i));
+    double v = double(pull<L>(g, H, k, x, y, z));
     c = k == 0 ? v : c + v;
   }
   const double phi = double(PHI[i]);
@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag_partial(Geo g, const S* _
     double c = 0.0;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
-      double hv = double(pull<L>(g, H, k, x, y, z, i));
+      double hv = double(pull<L>(g, H, k, x, y, z));
       c = k == 0 ? hv : c + hv;
     }
     const double phi = double(PHI[i]);

@@ -49,7 +49,6 @@ struct Coef {
   C eps2;              // eps_n^2
   C mueq_c;            // mu_eq in C
   double cl, cs, mueq; // closure constants (always double)
-  C gw[19];            // gamma w_k
   int counter_term, anti_trapping;
 };
 
@@ -182,7 +181,7 @@ __device__ __forceinline__ C h_eq(int k, C c, C lam) {
 template <class L, class C>
 __device__ __forceinline__ C h_source(const Coef<C>& K, int k, const C F[3]) {
   if (k == L::REST) return C(0);
-  return K.gw[k] * edot<L, C>(k, F[0], F[1], F[2]);
+  return (K.gamma * C(L::w[k])) * edot<L, C>(k, F[0], F[1], F[2]);
 }
 
 template <class L, class C>
