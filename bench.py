@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+PROFILE_CMD = ""
 
 
 def bytes_per_node_step(lattice_q: int, elem: int) -> int:
@@ -99,6 +100,106 @@ def time_gpu(p, phi0, c0, precision, schedule, steps, warmup, log):
     return res
 
 
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources: a stored traffic measurement is only used
+    while the kernels it was taken on are unchanged."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2111_05960_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".h", ".hip")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_file(workload, precision, schedule):
+    return os.path.join(ROOT, "profiles", f"step_{schedule}_{workload}_{precision}_traffic.json")
+
+
+def stored_traffic(workload, precision, schedule):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary, or None when there is none for the current kernel sources."""
+    path = traffic_file(workload, precision, schedule)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    return t
+
+
+def calibration_copy(log, gib=4):
+    """A plain streaming kernel of known size (gib GiB read + gib GiB written,
+    one elementwise negation) whose counter readings scale FETCH_SIZE and
+    WRITE_SIZE to bytes."""
+    import torch
+    n = gib * (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    log(f"calibration stream: {gib} GiB read + {gib} GiB written")
+    del a, b
+    torch.cuda.empty_cache()
+
+
+def summarize_profile(kind, dbs, out, workload, precision, schedule):
+    """Turn rocprofv3 database(s) into the text/JSON summaries kept under
+    profiles/.  kind: 'trace' (kernel trace statistics) or 'traffic'
+    (FETCH_SIZE and WRITE_SIZE runs, scaled by the calibration copy)."""
+    import sqlite3
+
+    def rows(db, sql):
+        con = sqlite3.connect(db)
+        try:
+            return con.execute(sql).fetchall()
+        finally:
+            con.close()
+
+    cmdline = " ".join(sys.argv)
+    if kind == "trace":
+        lines = [f"# rocprofv3 --kernel-trace --stats summary",
+                 f"# profiled command: {PROFILE_CMD}", f"# summarised by: {cmdline}"]
+        lines.append(f"{'calls':>6} {'avg_ms':>10} {'total_ms':>10} {'pct':>6}  kernel")
+        # durations in the rocpd views are in microseconds
+        for name, calls, total, avg, pct in rows(dbs[0], "select name, total_calls, total_duration, average, percentage from top_kernels"):
+            lines.append(f"{calls:>6} {avg / 1e3:>10.3f} {total / 1e3:>10.3f} {pct:>6.2f}  {name}")
+        with open(out, "w") as f:
+            f.write("\n".join(lines) + "\n")
+        return
+    vals, sums = {}, {}
+    for db in dbs:
+        for kname, counter, n, avg, tot in rows(db, "select kernel_name, counter_name, count(*), avg(value), sum(value) from counters_collection group by kernel_name, counter_name"):
+            vals[(kname, counter)] = (n, avg)
+            sums[(kname, counter)] = tot
+    step = [k for k in vals if "k_fused" in k[0] or "k_split" in k[0]]
+    copy = [k for k in sums if "neg" in k[0].lower()]
+    fetch_copy = sum(v for k, v in sums.items() if k in copy and k[1] == "FETCH_SIZE")
+    write_copy = sum(v for k, v in sums.items() if k in copy and k[1] == "WRITE_SIZE")
+    gib4_kib = 4 * (1 << 20)
+    f_scale, w_scale = gib4_kib / fetch_copy, gib4_kib / write_copy
+    res = {"source_hash": kernel_source_hash(), "workload": workload, "precision": precision,
+           "schedule": schedule, "profiled_commands": PROFILE_CMD, "summarised_by": cmdline,
+           "calibration": {"copy_bytes_each_way": 4 << 30, "FETCH_SIZE_kib": fetch_copy,
+                           "WRITE_SIZE_kib": write_copy, "fetch_scale": f_scale,
+                           "write_scale": w_scale},
+           "kernels": {}}
+    total = 0.0
+    for kname in sorted({k[0] for k in step}):
+        fk = vals.get((kname, "FETCH_SIZE"), (0, 0.0))[1]
+        wk = vals.get((kname, "WRITE_SIZE"), (0, 0.0))[1]
+        rd, wr = fk * 1024 * f_scale, wk * 1024 * w_scale
+        res["kernels"][kname] = {"FETCH_SIZE_kib": fk, "WRITE_SIZE_kib": wk,
+                                 "read_bytes": rd, "write_bytes": wr}
+        total += rd + wr
+    res["bytes_per_step"] = total
+    with open(out, "w") as f:
+        json.dump(res, f, indent=1)
+
+
 def cpu_baseline(p, phi0, c0, log, budget_s=12.0):
     """The CPU oracle on a 128^3 (3-D) or 512^2 (2-D) crop of the same
     workload with zero-flux faces, stepped until about budget_s seconds."""
@@ -137,7 +238,21 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", action="store_true",
                     help="also time the other precision and schedule")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="run a 4 GiB device copy after the timed region (counter calibration)")
+    ap.add_argument("--summarize-profile", nargs="+", metavar="DB",
+                    help="write a profiles/ summary from rocprofv3 database(s) and exit")
+    ap.add_argument("--profile-kind", choices=["trace", "traffic"], default="trace")
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--profile-cmd", default="", help="rocprofv3 command(s) recorded in a summary")
     args = ap.parse_args()
+
+    if args.summarize_profile:
+        global PROFILE_CMD
+        PROFILE_CMD = args.profile_cmd
+        summarize_profile(args.profile_kind, args.summarize_profile, args.out, args.workload,
+                          args.precision, args.schedule)
+        return
 
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -166,9 +281,13 @@ def main():
                 r = time_gpu(p, phi0, c0, prec, sch, args.steps, args.warmup, log)
                 variants.append(dict(precision=prec, **r))
 
+    if args.calibration_copy:
+        calibration_copy(log)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p, phi0, c0, log)
+    traffic = stored_traffic(args.workload, args.precision, main_res["schedule"])
 
     nz, ny, nx = p["shape"]
     achieved = main_res["achieved_gbs"]
@@ -202,7 +321,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": None if traffic is None else round(traffic["bytes_per_step"] / 1e9, 3),
+            "traffic_unit": "GB per step (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_gb_per_step": round(main_res["bytes_per_node_step"] * main_res["nodes"] / 1e9, 3),
             "kernel": "step (all launches of one time step)",
             "bytes_per_node_step": main_res["bytes_per_node_step"],
             "launches_per_step": main_res["launches_per_step"],
