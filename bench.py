@@ -32,9 +32,14 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 PROFILE_CMD = ""
 
 
-def bytes_per_node_step(lattice_q: int, elem: int) -> int:
+def bytes_per_node_step(lattice_q: int, precision: str) -> int:
     """Algorithmic bytes each node-step must move: read and write both
-    distributions once, and read and write the one carried phi field."""
+    distributions once, and read and write the carried phi field (and, for the
+    16-bit deviation formats, the Lambda field their h references need)."""
+    if precision in ("fp16dev", "bf16dev"):
+        dist = (lattice_q - 1) * 2 + 4          # 16-bit moving + FP32 rest
+        return 2 * (2 * dist + 4 + 4)
+    elem = 8 if precision == "fp64" else 4
     return (4 * lattice_q + 2) * elem
 
 
@@ -82,8 +87,7 @@ def time_gpu(p, phi0, c0, precision, schedule, steps, warmup, log):
     d1 = sim.diagnostics(allow_nonfinite=True)
     N = sim.N
     launches = 1 if sim.schedule == "fused" else 2
-    elem = 8 if precision == "fp64" else 4
-    balg = bytes_per_node_step(sim.Q, elem)
+    balg = bytes_per_node_step(sim.Q, precision)
     ms_step = ms / steps
     res = dict(
         mlups=N * steps / (ms * 1e-3) / 1e6, ms_per_step=ms_step, wall_s=wall,
@@ -233,7 +237,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="porous3d_512_d3q19", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp16dev", "bf16dev"])
     ap.add_argument("--schedule", default="auto", choices=["auto", "split", "fused"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", action="store_true",
@@ -274,11 +278,13 @@ def main():
     main_res = time_gpu(p, phi0, c0, args.precision, args.schedule, args.steps, args.warmup, log)
     variants = []
     if args.variants:
-        for prec in ("fp64", "fp32"):
+        precs = ("fp64", "fp32") + (("fp16dev", "bf16dev") if p["lattice"] == 1 else ())
+        for prec in precs:
             for sch in ("split", "auto"):
                 if prec == args.precision and sch == args.schedule:
                     continue
                 r = time_gpu(p, phi0, c0, prec, sch, args.steps, args.warmup, log)
+                r["hbm_frac"] = round(r["achieved_gbs"] / HBM_PEAK_GBS, 4)
                 variants.append(dict(precision=prec, **r))
 
     if args.calibration_copy:
@@ -302,7 +308,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp16dev": "f16 storage / f32 math",
+                  "bf16dev": "bf16 storage / f32 math"}[args.precision],
         "data": "synthetic",
         "config": {
             "workload": args.workload,

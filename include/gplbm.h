@@ -63,6 +63,13 @@ extern "C" {
 /* storage / arithmetic precision of the populations and of phi */
 #define GPLBM_FP64 0 /* everything in double */
 #define GPLBM_FP32 1 /* float storage and collision; moments and closure in double */
+/* D3Q19 only: the 18 moving populations of g and h stored as 16-bit deviations
+ * from the writing node's equilibrium (w_k phi for g, w_k gamma D(phi) mu for
+ * h), rest populations, phi and gamma D(phi) mu as float; float collision,
+ * double moments and closure; solute mass balanced through the rest
+ * population.  FP16 deviations are scaled by 2^12, BF16 ones are not. */
+#define GPLBM_FP16_DEV 2
+#define GPLBM_BF16_DEV 3
 
 /* kernel schedule */
 #define GPLBM_SCHED_AUTO 0  /* fused when the geometry allows it, else split */
@@ -73,7 +80,7 @@ typedef struct gplbm_params {
   int32_t lattice;       /* GPLBM_D2Q9 or GPLBM_D3Q19 */
   int32_t nx, ny, nz;    /* nodes; nz = 1 for D2Q9; node i = x + nx*(y + ny*z) */
   int32_t bc[3];         /* per axis x, y, z: GPLBM_PERIODIC or GPLBM_ZERO_FLUX */
-  int32_t precision;     /* GPLBM_FP64 or GPLBM_FP32 */
+  int32_t precision;     /* GPLBM_FP64, GPLBM_FP32, GPLBM_FP16_DEV or GPLBM_BF16_DEV */
   int32_t counter_term;  /* 1: counter term G^ct_k (Eq. ModelA_EqPhi_CounterTerm); 0: G^dw */
   int32_t anti_trapping; /* 1: anti-trapping current in the h source */
   int32_t schedule;      /* GPLBM_SCHED_* */

@@ -27,10 +27,11 @@ GPLBM_E_STATE = -5
 
 GPLBM_D2Q9, GPLBM_D3Q19 = 0, 1
 GPLBM_PERIODIC, GPLBM_ZERO_FLUX = 0, 1
-GPLBM_FP64, GPLBM_FP32 = 0, 1
+GPLBM_FP64, GPLBM_FP32, GPLBM_FP16_DEV, GPLBM_BF16_DEV = 0, 1, 2, 3
 GPLBM_SCHED_AUTO, GPLBM_SCHED_SPLIT, GPLBM_SCHED_FUSED = 0, 1, 2
 
-PRECISIONS = {"fp64": GPLBM_FP64, "fp32": GPLBM_FP32}
+PRECISIONS = {"fp64": GPLBM_FP64, "fp32": GPLBM_FP32, "fp16dev": GPLBM_FP16_DEV,
+              "bf16dev": GPLBM_BF16_DEV}
 SCHEDULES = {"auto": GPLBM_SCHED_AUTO, "split": GPLBM_SCHED_SPLIT, "fused": GPLBM_SCHED_FUSED}
 
 # exported symbols of the C ABI (checked by the tests against the header)

@@ -12,6 +12,7 @@
 #include <string>
 
 #include "gplbm.h"
+#include "kernels_dev.h"
 #include "kernels_fused2d.h"
 #include "kernels_fused3d.h"
 #include "kernels_split.h"
@@ -22,12 +23,15 @@ struct gplbm_ctx {
   gplbm_params p;
   int Q;
   int64_t N;
-  size_t elem;        // bytes per stored value
-  size_t pop_bytes;   // Q*N*elem rounded up
+  size_t elem;        // bytes per stored phi value
+  size_t pop_bytes;   // one distribution (rounded up)
+  size_t mov_bytes;   // deviation formats: the 16-bit moving part of a distribution
   size_t phi_bytes;   // N*elem rounded up
+  size_t lam_bytes;   // deviation formats: the Lambda field
   char* G[2];
   char* H[2];
   char* PHI[2];
+  char* LAM[2];
   double* red;        // reduction scratch: kDiagBlocks*kDiagVals + kDiagVals
   int cur;
   int64_t step;
@@ -54,7 +58,9 @@ const char* check_params(const gplbm_params* p) {
   if (p->lattice == GPLBM_D2Q9 && p->nz != 1) return "D2Q9 needs nz == 1";
   for (int a = 0; a < 3; ++a)
     if (p->bc[a] != GPLBM_PERIODIC && p->bc[a] != GPLBM_ZERO_FLUX) return "unknown boundary";
-  if (p->precision != GPLBM_FP64 && p->precision != GPLBM_FP32) return "unknown precision";
+  if (p->precision < GPLBM_FP64 || p->precision > GPLBM_BF16_DEV) return "unknown precision";
+  if (p->precision >= GPLBM_FP16_DEV && p->lattice != GPLBM_D3Q19)
+    return "deviation storage is implemented for D3Q19";
   if (p->schedule < GPLBM_SCHED_AUTO || p->schedule > GPLBM_SCHED_FUSED) return "unknown schedule";
   if (p->reserved != 0) return "reserved field must be 0";
   if (!(p->W > 0.0) || !std::isfinite(p->W)) return "W must be > 0";
@@ -68,13 +74,30 @@ const char* check_params(const gplbm_params* p) {
   return nullptr;
 }
 
-void layout(const gplbm_params* p, size_t* elem, size_t* pop, size_t* phi, size_t* total) {
+struct Layout {
+  size_t elem, pop, mov, phi, lam, red, total, ckpt;
+};
+
+Layout layout(const gplbm_params* p) {
+  Layout l{};
   const int64_t N = (int64_t)p->nx * p->ny * p->nz;
-  *elem = p->precision == GPLBM_FP64 ? 8 : 4;
-  *pop = round_up((size_t)lattice_q(p->lattice) * N * *elem);
-  *phi = round_up((size_t)N * *elem);
-  const size_t red = round_up(sizeof(double) * (kDiagBlocks * kDiagVals + kDiagVals));
-  *total = 4 * *pop + 2 * *phi + red;
+  const int Q = lattice_q(p->lattice);
+  if (p->precision >= GPLBM_FP16_DEV) {
+    l.elem = 4;
+    l.mov = round_up((size_t)(Q - 1) * N * 2);
+    l.pop = l.mov + round_up((size_t)N * 4);
+    l.lam = round_up((size_t)N * 4);
+  } else {
+    l.elem = p->precision == GPLBM_FP64 ? 8 : 4;
+    l.mov = 0;
+    l.pop = round_up((size_t)Q * N * l.elem);
+    l.lam = 0;
+  }
+  l.phi = round_up((size_t)N * l.elem);
+  l.red = round_up(sizeof(double) * (kDiagBlocks * kDiagVals + kDiagVals));
+  l.total = 4 * l.pop + 2 * l.phi + 2 * l.lam + l.red;
+  l.ckpt = 2 * l.pop + l.phi + l.lam;
+  return l;
 }
 
 int fail(gplbm_ctx* ctx, int code, const std::string& msg) {
@@ -199,8 +222,80 @@ struct Ops {
   }
 };
 
+// Operations in the deviation storage formats (D3Q19 only).
+template <class Codec>
+struct DevOps {
+  static dim3 block() { return dim3(64, 4, 1); }
+  static dim3 grid(const gplbm_ctx* ctx) {
+    return dim3((ctx->p.nx + 63) / 64, (ctx->p.ny + 3) / 4, ctx->p.nz);
+  }
+  static DevState state(const gplbm_ctx* ctx, int a) {
+    DevState s;
+    s.G.mov = (uint16_t*)ctx->G[a];
+    s.G.rest = (float*)(ctx->G[a] + ctx->mov_bytes);
+    s.H.mov = (uint16_t*)ctx->H[a];
+    s.H.rest = (float*)(ctx->H[a] + ctx->mov_bytes);
+    s.PHI = (float*)ctx->PHI[a];
+    s.LAM = (float*)ctx->LAM[a];
+    return s;
+  }
+  static int init(gplbm_ctx* ctx, const double* phi0, const double* c0) {
+    const Geo g = make_geo(ctx->p);
+    const Coef<float> K = make_coef<float>(ctx->p);
+    const DevState s = state(ctx, ctx->cur);
+    hipLaunchKernelGGL(k_dev_init_fields, grid(ctx), block(), 0, ctx->stream, g, K, phi0, c0, s);
+    hipLaunchKernelGGL((k_dev_init<Codec>), grid(ctx), block(), 0, ctx->stream, g, K, c0, s);
+    return check_launch(ctx, "init");
+  }
+  static int step(gplbm_ctx* ctx, int64_t nsteps) {
+    const Geo g = make_geo(ctx->p);
+    const Coef<float> K = make_coef<float>(ctx->p);
+    for (int64_t n = 0; n < nsteps; ++n) {
+      const int a = ctx->cur, b = 1 - a;
+      const DevStep st{state(ctx, a), state(ctx, b)};
+      if (ctx->sched == GPLBM_SCHED_FUSED) {
+        DevFused3D<Codec>::launch(g, K, st, ctx->stream);
+      } else {
+        hipLaunchKernelGGL((k_dev_split_h<Codec>), grid(ctx), block(), 0, ctx->stream, g, K, st);
+        hipLaunchKernelGGL((k_dev_split_g<Codec>), grid(ctx), block(), 0, ctx->stream, g, K, st);
+      }
+      int rc = check_launch(ctx, "step");
+      if (rc) return rc;
+      ctx->cur = b;
+      ctx->step += 1;
+    }
+    return GPLBM_OK;
+  }
+  static int fields(gplbm_ctx* ctx, double* phi, double* c, double* mu) {
+    const Geo g = make_geo(ctx->p);
+    hipLaunchKernelGGL((k_dev_fields<Codec>), grid(ctx), block(), 0, ctx->stream, g, ctx->p.c_l_co,
+                       ctx->p.c_s_co, ctx->p.mu_eq, state(ctx, ctx->cur), phi, c, mu);
+    return check_launch(ctx, "read fields");
+  }
+  static int diag(gplbm_ctx* ctx) {
+    const Geo g = make_geo(ctx->p);
+    double* part = ctx->red;
+    double* out = ctx->red + kDiagBlocks * kDiagVals;
+    hipLaunchKernelGGL((k_dev_diag_partial<Codec>), dim3(kDiagBlocks), dim3(kDiagThreads), 0,
+                       ctx->stream, g, state(ctx, ctx->cur), part);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagThreads), 0, ctx->stream,
+                       (const double*)part, kDiagBlocks, out);
+    return check_launch(ctx, "diagnostics");
+  }
+};
+
+template <class Codec>
+struct DevAdapter {
+  static int init(gplbm_ctx* c, const double* a, const double* b) { return DevOps<Codec>::init(c, a, b); }
+  static int step(gplbm_ctx* c, int64_t n) { return DevOps<Codec>::step(c, n); }
+  static int fields(gplbm_ctx* c, double* a, double* b, double* d) { return DevOps<Codec>::fields(c, a, b, d); }
+  static int diag(gplbm_ctx* c) { return DevOps<Codec>::diag(c); }
+};
+
 template <template <class, class, class> class Fn, class... Args>
 int dispatch(gplbm_ctx* ctx, Args... args) {
+  if (ctx->p.precision == GPLBM_FP16_DEV) return Fn<DevAdapter<F16Codec>, void, void>::run(ctx, args...);
+  if (ctx->p.precision == GPLBM_BF16_DEV) return Fn<DevAdapter<BF16Codec>, void, void>::run(ctx, args...);
   if (ctx->p.lattice == GPLBM_D2Q9) {
     if (ctx->p.precision == GPLBM_FP64) return Fn<D2Q9, double, double>::run(ctx, args...);
     return Fn<D2Q9, float, float>::run(ctx, args...);
@@ -213,6 +308,10 @@ template <class L, class S, class C>
 struct InitFn {
   static int run(gplbm_ctx* c, const double* a, const double* b) { return Ops<L, S, C>::init(c, a, b); }
 };
+template <class A>
+struct InitFn<A, void, void> {
+  static int run(gplbm_ctx* c, const double* a, const double* b) { return A::init(c, a, b); }
+};
 template <class L, class S, class C>
 struct StepFn {
   static int run(gplbm_ctx* c, int64_t n) {
@@ -220,18 +319,31 @@ struct StepFn {
                                          : Ops<L, S, C>::step_split(c, n);
   }
 };
+template <class A>
+struct StepFn<A, void, void> {
+  static int run(gplbm_ctx* c, int64_t n) { return A::step(c, n); }
+};
 template <class L, class S, class C>
 struct FieldsFn {
   static int run(gplbm_ctx* c, double* a, double* b, double* d) { return Ops<L, S, C>::fields(c, a, b, d); }
+};
+template <class A>
+struct FieldsFn<A, void, void> {
+  static int run(gplbm_ctx* c, double* a, double* b, double* d) { return A::fields(c, a, b, d); }
 };
 template <class L, class S, class C>
 struct DiagFn {
   static int run(gplbm_ctx* c) { return Ops<L, S, C>::diag(c); }
 };
+template <class A>
+struct DiagFn<A, void, void> {
+  static int run(gplbm_ctx* c) { return A::diag(c); }
+};
 
 int choose_schedule(const gplbm_params& p) {
-  const bool fused_ok = p.lattice == GPLBM_D2Q9 ? fused2d_supported(p.nx, p.ny)
-                                               : fused3d_supported(p.nx, p.ny, p.nz, p.bc);
+  const bool fused_ok = p.precision >= GPLBM_FP16_DEV ? dev_fused_supported(p.nx, p.ny, p.nz, p.bc)
+                        : p.lattice == GPLBM_D2Q9    ? fused2d_supported(p.nx, p.ny)
+                                                     : fused3d_supported(p.nx, p.ny, p.nz, p.bc);
   if (p.schedule == GPLBM_SCHED_SPLIT) return GPLBM_SCHED_SPLIT;
   if (p.schedule == GPLBM_SCHED_FUSED) return fused_ok ? GPLBM_SCHED_FUSED : -1;
   return fused_ok ? GPLBM_SCHED_FUSED : GPLBM_SCHED_SPLIT;
@@ -251,17 +363,13 @@ extern "C" {
 
 int gplbm_state_bytes(const gplbm_params* p, uint64_t* bytes) {
   if (check_params(p) || !bytes) return GPLBM_E_INVALID;
-  size_t elem, pop, phi, total;
-  layout(p, &elem, &pop, &phi, &total);
-  *bytes = total;
+  *bytes = layout(p).total;
   return GPLBM_OK;
 }
 
 int gplbm_checkpoint_bytes(const gplbm_params* p, uint64_t* bytes) {
   if (check_params(p) || !bytes) return GPLBM_E_INVALID;
-  size_t elem, pop, phi, total;
-  layout(p, &elem, &pop, &phi, &total);
-  *bytes = 2 * pop + phi;
+  *bytes = layout(p).ckpt;
   return GPLBM_OK;
 }
 
@@ -271,9 +379,8 @@ int gplbm_create(const gplbm_params* p, void* dev_buf, uint64_t bytes, void* str
   *out = nullptr;
   if (check_params(p) || !dev_buf) return GPLBM_E_INVALID;
   if (((uintptr_t)dev_buf) % kAlign) return GPLBM_E_INVALID;
-  size_t elem, pop, phi, total;
-  layout(p, &elem, &pop, &phi, &total);
-  if (bytes < total) return GPLBM_E_SIZE;
+  const Layout lay = layout(p);
+  if (bytes < lay.total) return GPLBM_E_SIZE;
   const int sched = choose_schedule(*p);
   if (sched < 0) return GPLBM_E_INVALID;
   gplbm_ctx* ctx = new gplbm_ctx();
@@ -281,17 +388,22 @@ int gplbm_create(const gplbm_params* p, void* dev_buf, uint64_t bytes, void* str
   if (ctx->p.lattice == GPLBM_D2Q9) ctx->p.bc[2] = GPLBM_PERIODIC;
   ctx->Q = lattice_q(p->lattice);
   ctx->N = (int64_t)p->nx * p->ny * p->nz;
-  ctx->elem = elem;
-  ctx->pop_bytes = pop;
-  ctx->phi_bytes = phi;
+  ctx->elem = lay.elem;
+  ctx->pop_bytes = lay.pop;
+  ctx->mov_bytes = lay.mov;
+  ctx->phi_bytes = lay.phi;
+  ctx->lam_bytes = lay.lam;
   char* b = (char*)dev_buf;
+  const size_t pop = lay.pop, phi = lay.phi, lam = lay.lam;
   ctx->G[0] = b;
   ctx->G[1] = b + pop;
   ctx->H[0] = b + 2 * pop;
   ctx->H[1] = b + 3 * pop;
   ctx->PHI[0] = b + 4 * pop;
   ctx->PHI[1] = b + 4 * pop + phi;
-  ctx->red = (double*)(b + 4 * pop + 2 * phi);
+  ctx->LAM[0] = lam ? b + 4 * pop + 2 * phi : nullptr;
+  ctx->LAM[1] = lam ? b + 4 * pop + 2 * phi + lam : nullptr;
+  ctx->red = (double*)(b + 4 * pop + 2 * phi + 2 * lam);
   ctx->cur = 0;
   ctx->step = 0;
   ctx->ready = false;
@@ -375,6 +487,9 @@ int gplbm_save_state(gplbm_ctx* ctx, void* dev_dst) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(d + 2 * ctx->pop_bytes, ctx->PHI[a], ctx->phi_bytes, hipMemcpyDeviceToDevice,
                        ctx->stream);
+  if (e == hipSuccess && ctx->lam_bytes)
+    e = hipMemcpyAsync(d + 2 * ctx->pop_bytes + ctx->phi_bytes, ctx->LAM[a], ctx->lam_bytes,
+                       hipMemcpyDeviceToDevice, ctx->stream);
   if (e != hipSuccess) return fail(ctx, GPLBM_E_DEVICE, std::string("save: ") + hipGetErrorString(e));
   return GPLBM_OK;
 }
@@ -390,6 +505,9 @@ int gplbm_load_state(gplbm_ctx* ctx, const void* dev_src, int64_t step) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(ctx->PHI[a], s + 2 * ctx->pop_bytes, ctx->phi_bytes, hipMemcpyDeviceToDevice,
                        ctx->stream);
+  if (e == hipSuccess && ctx->lam_bytes)
+    e = hipMemcpyAsync(ctx->LAM[a], s + 2 * ctx->pop_bytes + ctx->phi_bytes, ctx->lam_bytes,
+                       hipMemcpyDeviceToDevice, ctx->stream);
   if (e != hipSuccess) return fail(ctx, GPLBM_E_DEVICE, std::string("load: ") + hipGetErrorString(e));
   ctx->step = step;
   ctx->ready = true;

@@ -1,0 +1,586 @@
+// Reduced-precision storage of the D3Q19 state: the 18 moving populations of
+// each distribution are stored as FP16 or BF16 deviations from the local
+// equilibrium of the node that wrote them, the rest populations, phi and
+// Lambda = gamma D(phi) mu as FP32.  Collision arithmetic is FP32; the moments
+// (c, phi) and the closure mu(c, phi) are FP64.
+//
+//   g: stored delta_k = S (g*_k - w_k phi(y))     (phi of the writing node y)
+//   h: stored delta_k = S (h*_k - w_k Lambda(y))  (Lambda of the writing node)
+// with S = 2^12 for FP16 (keeps the small deviations in the normal range) and
+// S = 1 for BF16; rounding is round-to-nearest-even.  A reader decodes
+// f = ref + delta / S with the reference of the source node, which is
+// available to it (phi and Lambda are fields of the state).
+//
+// Solute mass: the writer sets the rest population of h so that the decoded
+// populations it leaves behind sum exactly (in FP64, then one FP32 rounding)
+// to the c it received - the collision conserves c exactly in arithmetic, so
+// this only removes the rounding of the 16-bit encodings from the balance.
+//
+// Layout of one distribution: moving populations u16[z][m][y][x] (m = k for
+// k < 5, k - 1 after the rest vector), then the rest populations
+// f32[z][y][x].
+#pragma once
+
+#include "kernels_fused3d.h"
+
+namespace gplbm {
+
+struct F16Codec {
+  static constexpr float kScale = 4096.0f, kInv = 1.0f / 4096.0f;
+  __device__ static uint16_t enc(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
+  __device__ static float dec(uint16_t u) { return (float)__builtin_bit_cast(_Float16, u); }
+};
+struct BF16Codec {
+  static constexpr float kScale = 1.0f, kInv = 1.0f;
+  __device__ static uint16_t enc(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
+  __device__ static float dec(uint16_t u) { return (float)__builtin_bit_cast(__bf16, u); }
+};
+
+// one distribution in the deviation format
+struct DevDist {
+  uint16_t* mov;
+  float* rest;
+};
+struct DevState {
+  DevDist G, H;
+  float* PHI;
+  float* LAM;
+};
+struct DevStep {
+  DevState cur;  // G = g~*^n, H = h~*^{n-1}, PHI = phi^n, LAM = Lambda^{n-1}
+  DevState nxt;  // written: G = g~*^{n+1}, H = h~*^n, PHI = phi^{n+1}, LAM = Lambda^n
+};
+
+using LD = D3Q19;
+constexpr int kMov = 18;
+
+__device__ __forceinline__ constexpr int mslot(int k) { return k < LD::REST ? k : k - 1; }
+
+__device__ __forceinline__ int64_t mov_index(const Geo& g, int k, int x, int y, int z) {
+  const int64_t plane = (int64_t)g.nx * g.ny;
+  return ((int64_t)z * kMov + mslot(k)) * plane + (int64_t)y * g.nx + x;
+}
+
+template <class Codec>
+__device__ __forceinline__ float dev_decode(uint16_t raw, float ref) {
+  return ref + Codec::dec(raw) * Codec::kInv;
+}
+template <class Codec>
+__device__ __forceinline__ uint16_t dev_encode(float v, float ref) {
+  return Codec::enc((v - ref) * Codec::kScale);
+}
+
+// Pull of population k at (x, y, z) from a distribution in the deviation
+// format; ref is the field (phi for g, Lambda for h) of the source node.
+template <class Codec>
+__device__ __forceinline__ float pull_dev(const Geo& g, const DevDist& d, const float* reff, int k,
+                                          int x, int y, int z) {
+  if (k == LD::REST) return d.rest[node_index(g, x, y, z)];
+  int sx = x, sy = y, sz = z;
+  const bool in = pull_axis(sx, LD::ex[k], g.nx, g.bcx) && pull_axis(sy, LD::ey[k], g.ny, g.bcy) &&
+                  pull_axis(sz, LD::ez[k], g.nz, g.bcz);
+  const int kk = in ? k : LD::opp[k];
+  if (!in) sx = x, sy = y, sz = z;
+  const float ref = float(LD::w[kk]) * reff[node_index(g, sx, sy, sz)];
+  return dev_decode<Codec>(d.mov[mov_index(g, kk, sx, sy, sz)], ref);
+}
+
+// Encode the post-collision h of one node with the mass balance of the rest
+// population; hdec receives the decoded values (what readers will see).
+template <class Codec>
+__device__ __forceinline__ void encode_h(const float hs[19], float lam, double c_in,
+                                         uint16_t enc[19], float hdec[19]) {
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    if (k == LD::REST) continue;
+    const float ref = float(LD::w[k]) * lam;
+    enc[k] = dev_encode<Codec>(hs[k], ref);
+    hdec[k] = dev_decode<Codec>(enc[k], ref);
+    s = s + double(hdec[k]);
+  }
+  hdec[LD::REST] = float(c_in - s);
+}
+
+template <class Codec>
+__device__ __forceinline__ void encode_g(const float gs[19], float phi, uint16_t enc[19],
+                                         float gdec[19]) {
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    if (k == LD::REST) {
+      gdec[k] = gs[k];
+      continue;
+    }
+    const float ref = float(LD::w[k]) * phi;
+    enc[k] = dev_encode<Codec>(gs[k], ref);
+    gdec[k] = dev_decode<Codec>(enc[k], ref);
+  }
+}
+
+struct DevGlobalPhi {
+  const Geo& g;
+  const float* __restrict__ f;
+  int x, y, z;
+  __device__ float operator()(int dx, int dy, int dz) const {
+    return f[node_index(g, stencil_axis(x + dx, g.nx, g.bcx), stencil_axis(y + dy, g.ny, g.bcy),
+                        stencil_axis(z + dz, g.nz, g.bcz))];
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Initialisation: first Lambda^0 and phi^0 as FP32 fields, then the
+// populations (h~^0 scattered to the slots the first pull reads, encoded with
+// the reference of the slot's node).
+
+__global__ void __launch_bounds__(256) k_dev_init_fields(Geo g, Coef<float> K,
+                                                         const double* __restrict__ phi0,
+                                                         const double* __restrict__ c0,
+                                                         DevState s) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int64_t i = node_index(g, x, y, z);
+  const float phi = float(phi0[i]);
+  const float mu0 = float(closure(K.cl, K.cs, K.mueq, c0[i], double(phi)));
+  s.PHI[i] = phi;
+  s.LAM[i] = h_lambda<float>(K, phi, mu0);
+}
+
+template <class Codec>
+__global__ void __launch_bounds__(256) k_dev_init(Geo g, Coef<float> K,
+                                                  const double* __restrict__ c0, DevState s) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int64_t i = node_index(g, x, y, z);
+  const float phi = s.PHI[i];
+  const double cin = c0[i];
+  float gr[3], n[3];
+  gradient_normal<LD, float>(DevGlobalPhi{g, s.PHI, x, y, z}, K.eps2, gr, n);
+  const float mu0 = float(closure(K.cl, K.cs, K.mueq, cin, double(phi)));
+  float G0[19];
+  phi_sources<LD, float>(K, phi, mu0, n, G0);
+  float F[3];
+  h_flux<LD, float>(K, mu0, gr, n, 0.0f, false, F);
+  const float lam = s.LAM[i];
+  // h~^0, encoded for the slot (x - e_k, k) or (x, opp k) at a wall
+  double c = 0.0;
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    const float hv = h_eq<LD, float>(k, float(cin), lam) - 0.5f * h_source<LD, float>(K, k, F);
+    float dec;
+    if (k == LD::REST) {
+      s.H.rest[i] = hv;
+      dec = hv;
+    } else {
+      int dx = x, dy = y, dz = z;
+      const bool in = pull_axis(dx, LD::ex[k], g.nx, g.bcx) &&
+                      pull_axis(dy, LD::ey[k], g.ny, g.bcy) &&
+                      pull_axis(dz, LD::ez[k], g.nz, g.bcz);
+      const int kk = in ? k : LD::opp[k];
+      if (!in) dx = x, dy = y, dz = z;
+      const float ref = float(LD::w[kk]) * s.LAM[node_index(g, dx, dy, dz)];
+      const uint16_t e = dev_encode<Codec>(hv, ref);
+      s.H.mov[mov_index(g, kk, dx, dy, dz)] = e;
+      dec = dev_decode<Codec>(e, ref);
+    }
+    c = k == 0 ? double(dec) : c + double(dec);
+  }
+  // collision of g at time 0 with c^0 = sum of the decoded h~^0
+  const float mu = float(closure(K.cl, K.cs, K.mueq, c, double(phi)));
+  float Gk[19], gs[19];
+  phi_sources<LD, float>(K, phi, mu, n, Gk);
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    const float g0 = float(LD::w[k]) * phi - 0.5f * G0[k];
+    gs[k] = g_collide<LD, float>(K, k, g0, phi, Gk[k]);
+  }
+  uint16_t enc[19];
+  float gdec[19];
+  encode_g<Codec>(gs, phi, enc, gdec);
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    if (k == LD::REST)
+      s.G.rest[i] = gdec[k];
+    else
+      s.G.mov[mov_index(g, k, x, y, z)] = enc[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Split schedule in the deviation format (any boundaries).
+
+template <class Codec>
+__global__ void __launch_bounds__(256) k_dev_split_h(Geo g, Coef<float> K, DevStep b) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int64_t i = node_index(g, x, y, z);
+  float h[19];
+  double c = 0.0;
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    h[k] = pull_dev<Codec>(g, b.cur.H, b.cur.LAM, k, x, y, z);
+    c = k == 0 ? double(h[k]) : c + double(h[k]);
+  }
+  const float phi = b.cur.PHI[i];
+  const float mu = float(closure(K.cl, K.cs, K.mueq, c, double(phi)));
+  float gr[3], n[3];
+  gradient_normal<LD, float>(DevGlobalPhi{g, b.cur.PHI, x, y, z}, K.eps2, gr, n);
+  const float sbar = source_moment<float>(K, phi, mu);
+  double sg = 0.0;
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    const double v = double(pull_dev<Codec>(g, b.cur.G, b.cur.PHI, k, x, y, z));
+    sg = k == 0 ? v : sg + v;
+  }
+  const float phin = float(sg + 0.5 * double(sbar));
+  float F[3];
+  h_flux<LD, float>(K, mu, gr, n, phin - phi, K.anti_trapping != 0, F);
+  const float lam = h_lambda<float>(K, phi, mu);
+  const float cc = float(c);
+  float hs[19];
+#pragma unroll
+  for (int k = 0; k < 19; ++k)
+    hs[k] = h_collide<LD, float>(K, k, h[k], h_eq<LD, float>(k, cc, lam), h_source<LD, float>(K, k, F));
+  uint16_t enc[19];
+  float hdec[19];
+  encode_h<Codec>(hs, lam, c, enc, hdec);
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    if (k == LD::REST)
+      b.nxt.H.rest[i] = hdec[k];
+    else
+      b.nxt.H.mov[mov_index(g, k, x, y, z)] = enc[k];
+  }
+  b.nxt.LAM[i] = lam;
+  b.nxt.PHI[i] = phin;
+}
+
+template <class Codec>
+__global__ void __launch_bounds__(256) k_dev_split_g(Geo g, Coef<float> K, DevStep b) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int64_t i = node_index(g, x, y, z);
+  double c = 0.0;
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    const double v = double(pull_dev<Codec>(g, b.nxt.H, b.nxt.LAM, k, x, y, z));
+    c = k == 0 ? v : c + v;
+  }
+  const float phi = b.nxt.PHI[i];
+  const float mu = float(closure(K.cl, K.cs, K.mueq, c, double(phi)));
+  float gr[3], n[3];
+  gradient_normal<LD, float>(DevGlobalPhi{g, b.nxt.PHI, x, y, z}, K.eps2, gr, n);
+  float G[19], gs[19];
+  phi_sources<LD, float>(K, phi, mu, n, G);
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    const float gk = pull_dev<Codec>(g, b.cur.G, b.cur.PHI, k, x, y, z);
+    gs[k] = g_collide<LD, float>(K, k, gk, phi, G[k]);
+  }
+  uint16_t enc[19];
+  float gdec[19];
+  encode_g<Codec>(gs, phi, enc, gdec);
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    if (k == LD::REST)
+      b.nxt.G.rest[i] = gdec[k];
+    else
+      b.nxt.G.mov[mov_index(g, k, x, y, z)] = enc[k];
+  }
+}
+
+// read-out and diagnostics in the deviation format
+template <class Codec>
+__global__ void __launch_bounds__(256) k_dev_fields(Geo g, double cl, double cs, double mueq,
+                                                    DevState s, double* phi_out, double* c_out,
+                                                    double* mu_out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int64_t i = node_index(g, x, y, z);
+  double c = 0.0;
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    const double v = double(pull_dev<Codec>(g, s.H, s.LAM, k, x, y, z));
+    c = k == 0 ? v : c + v;
+  }
+  const double phi = double(s.PHI[i]);
+  if (phi_out) phi_out[i] = phi;
+  if (c_out) c_out[i] = c;
+  if (mu_out) mu_out[i] = closure(cl, cs, mueq, c, phi);
+}
+
+template <class Codec>
+__global__ void __launch_bounds__(kDiagThreads) k_dev_diag_partial(Geo g, DevState s,
+                                                                   double* __restrict__ part) {
+  __shared__ double red[kDiagVals][kDiagThreads];
+  double v[kDiagVals] = {0.0, 0.0, 0.0, 0.0, INFINITY, -INFINITY, 0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.N; i += stride) {
+    const int x = int(i % g.nx);
+    const int y = int((i / g.nx) % g.ny);
+    const int z = int(i / ((int64_t)g.nx * g.ny));
+    double c = 0.0;
+#pragma unroll
+    for (int k = 0; k < 19; ++k) {
+      const double hv = double(pull_dev<Codec>(g, s.H, s.LAM, k, x, y, z));
+      c = k == 0 ? hv : c + hv;
+    }
+    const double phi = double(s.PHI[i]);
+    v[0] = v[0] + c;
+    v[1] = v[1] + (1.0 - phi);
+    v[2] = v[2] + (phi < 0.5 ? 1.0 : 0.0);
+    v[3] = v[3] + phi;
+    v[4] = fmin(v[4], phi);
+    v[5] = fmax(v[5], phi);
+    if (!isfinite(c) || !isfinite(phi)) v[6] = 1.0;
+  }
+  for (int j = 0; j < kDiagVals; ++j) red[j][threadIdx.x] = v[j];
+  __syncthreads();
+  for (int s2 = kDiagThreads / 2; s2 > 0; s2 >>= 1) {
+    if ((int)threadIdx.x < s2) {
+      const int t = threadIdx.x;
+      red[0][t] = red[0][t] + red[0][t + s2];
+      red[1][t] = red[1][t] + red[1][t + s2];
+      red[2][t] = red[2][t] + red[2][t + s2];
+      red[3][t] = red[3][t] + red[3][t + s2];
+      red[4][t] = fmin(red[4][t], red[4][t + s2]);
+      red[5][t] = fmax(red[5][t], red[5][t + s2]);
+      red[6][t] = fmax(red[6][t], red[6][t + s2]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < kDiagVals) part[blockIdx.x * kDiagVals + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// ---------------------------------------------------------------------------
+// Fused z-marching schedule in the deviation format (periodic domains).  Same
+// structure as k_fused3d; in addition a 3-plane LDS ring holds Lambda^{n-1}
+// on T+2 for the h references, and the phi^n ring serves the g references.
+
+__device__ __forceinline__ uint16_t bload16(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(uint16_t, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore16_nt(uint16_t v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                            uint32_t soff) {
+  using V = decltype(__builtin_amdgcn_raw_buffer_load_b16(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(V, v), r, voff, soff, 2);
+}
+
+template <int BX, int BY, int ZC, class Codec>
+__global__ void __launch_bounds__(BX* BY) k_dev_fused3d(Geo g, Coef<float> K, DevStep b,
+                                                        int tiles_x, int tiles_xy, int ntiles) {
+  constexpr int Q = 19;
+  constexpr int TX = BX - 2, TY = BY - 2;
+  constexpr int AX = BX + 2, AY = BY + 2;
+  __shared__ float phiA[3][AY][AX];  // phi^n, planes p-1, p, p+1
+  __shared__ float lamA[3][AY][AX];  // Lambda^{n-1}, planes p-1, p, p+1
+  __shared__ float phiB[3][BY][BX];  // phi^{n+1}, planes p-2, p-1, p
+  __shared__ double acc[3][BY][BX];  // c^{n+1}
+
+  const int tile = xcd_tile(blockIdx.x, ntiles);
+  const int chunk = tile / tiles_xy, txy = tile % tiles_xy;
+  const int X0 = (txy % tiles_x) * TX, Y0 = (txy / tiles_x) * TY;
+  const int z0 = chunk * ZC, z1 = min(z0 + ZC, g.nz);
+  const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int plane = nx * ny;
+  const uint32_t planeB = uint32_t(plane) * 2u;            // one 16-bit population plane
+  const int64_t groupB = int64_t(plane) * kMov * 2;        // one z group of moving populations
+
+  const int ux = X0 - 1 + tx, uy = Y0 - 1 + ty;
+  const bool out = ux < nx && uy < ny && tx >= 1 && tx <= TX && ty >= 1 && ty <= TY;
+  const int x = wrap_coord(ux, nx), y = wrap_coord(uy, ny);
+  const int xo[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
+  const int yo[3] = {(y == 0 ? ny - 1 : y - 1) * nx, y * nx, (y == ny - 1 ? 0 : y + 1) * nx};
+  uint32_t xyb[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xyb[a][c] = uint32_t(yo[a] + xo[c]) * 2u;
+  const uint32_t selfB = xyb[1][1];
+  const int self_xy = y * nx + x;
+
+  auto load_tiles = [&](int p) {
+    const int64_t zoff = (int64_t)wrap_coord(p, nz) * plane;
+    for (int l = threadIdx.x; l < AX * AY; l += BX * BY) {
+      const int lx = l % AX, ly = l / AX;
+      const int gx = wrap_coord(X0 - 2 + lx, nx), gy = wrap_coord(Y0 - 2 + ly, ny);
+      phiA[ring3(p)][ly][lx] = b.cur.PHI[zoff + gy * nx + gx];
+      lamA[ring3(p)][ly][lx] = b.cur.LAM[zoff + gy * nx + gx];
+    }
+  };
+  load_tiles(z0 - 2);
+  load_tiles(z0 - 1);
+
+  float g_old[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) g_old[k] = 0.0f;
+
+  for (int p = z0 - 1; p <= z1; ++p) {
+    load_tiles(p + 1);
+    __syncthreads();
+
+    const int zp = wrap_coord(p, nz);
+    const int zo[3] = {(zp == 0 ? nz - 1 : zp - 1), zp, (zp == nz - 1 ? 0 : zp + 1)};
+    __amdgpu_buffer_rsrc_t Hz[3], Gz[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      Hz[j] = make_rsrc(reinterpret_cast<const char*>(b.cur.H.mov) + zo[j] * groupB, uint32_t(groupB));
+      Gz[j] = make_rsrc(reinterpret_cast<const char*>(b.cur.G.mov) + zo[j] * groupB, uint32_t(groupB));
+    }
+    const int64_t selfnode = (int64_t)zp * plane + self_xy;
+
+    // pulls, decoded with the reference of the source node (LDS tiles)
+    float h[Q], g_new[Q];
+    double c = 0.0, sg = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      float v;
+      if (k == LD::REST) {
+        v = b.cur.H.rest[selfnode];
+      } else {
+        const float ref = float(LD::w[k]) *
+                          lamA[ring3(p - LD::ez[k])][ty + 1 - LD::ey[k]][tx + 1 - LD::ex[k]];
+        v = dev_decode<Codec>(bload16(Hz[1 - LD::ez[k]], xyb[1 - LD::ey[k]][1 - LD::ex[k]],
+                                      mslot(k) * planeB), ref);
+      }
+      h[k] = v;
+      c = k == 0 ? double(v) : c + double(v);
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      float v;
+      if (k == LD::REST) {
+        v = b.cur.G.rest[selfnode];
+      } else {
+        const float ref = float(LD::w[k]) *
+                          phiA[ring3(p - LD::ez[k])][ty + 1 - LD::ey[k]][tx + 1 - LD::ex[k]];
+        v = dev_decode<Codec>(bload16(Gz[1 - LD::ez[k]], xyb[1 - LD::ey[k]][1 - LD::ex[k]],
+                                      mslot(k) * planeB), ref);
+      }
+      g_new[k] = v;
+      sg = k == 0 ? double(v) : sg + double(v);
+    }
+    const int sA = ring3(p);
+    const float phi = phiA[sA][ty + 1][tx + 1];
+    const float mu = float(closure(K.cl, K.cs, K.mueq, c, double(phi)));
+    auto atA = [&](int dx, int dy, int dz) -> float {
+      return phiA[ring3(p + dz)][ty + 1 + dy][tx + 1 + dx];
+    };
+    float gr[3], n[3];
+    gradient_normal<LD, float>(atA, K.eps2, gr, n);
+    const float sbar = source_moment<float>(K, phi, mu);
+    const float phin = float(sg + 0.5 * double(sbar));
+    phiB[sA][ty][tx] = phin;
+    float F[3];
+    h_flux<LD, float>(K, mu, gr, n, phin - phi, K.anti_trapping != 0, F);
+    const float lam = h_lambda<float>(K, phi, mu);
+    const float cc = float(c);
+    float hs[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      hs[k] = h_collide<LD, float>(K, k, h[k], h_eq<LD, float>(k, cc, lam),
+                                   h_source<LD, float>(K, k, F));
+    uint16_t enc[Q];
+    float hdec[Q];
+    encode_h<Codec>(hs, lam, c, enc, hdec);
+
+    const bool own_p = p >= z0 && p < z1;
+    if (out && own_p) {
+      const auto Hw = make_rsrc(reinterpret_cast<char*>(b.nxt.H.mov) + zp * groupB, uint32_t(groupB));
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+        if (k != LD::REST) bstore16_nt(enc[k], Hw, selfB, mslot(k) * planeB);
+      __builtin_nontemporal_store(hdec[LD::REST], &b.nxt.H.rest[selfnode]);
+      __builtin_nontemporal_store(lam, &b.nxt.LAM[selfnode]);
+      __builtin_nontemporal_store(phin, &b.nxt.PHI[selfnode]);
+    }
+
+    const bool up_ok = p + 1 >= z0 && p + 1 < z1, dn_ok = p - 1 >= z0 && p - 1 < z1;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      if (j < 5 && up_ok) {
+        const int k = j;
+        const int tx2 = tx + LD::ex[k], ty2 = ty + LD::ey[k];
+        if (tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
+          double& a = acc[ring3(p + 1)][ty2][tx2];
+          a = k == 0 ? double(hdec[k]) : a + double(hdec[k]);
+        }
+      }
+      if (own_p) {
+        const int k = 5 + j;
+        const int tx2 = tx + LD::ex[k], ty2 = ty + LD::ey[k];
+        if (tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
+          double& a = acc[sA][ty2][tx2];
+          a = a + double(hdec[k]);
+        }
+      }
+      if (j < 5 && dn_ok) {
+        const int k = 14 + j;
+        const int tx2 = tx + LD::ex[k], ty2 = ty + LD::ey[k];
+        if (tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
+          double& a = acc[ring3(p - 1)][ty2][tx2];
+          a = a + double(hdec[k]);
+        }
+      }
+      __syncthreads();
+    }
+
+    if (out && dn_ok) {
+      const int zq = zo[0];
+      const int sB = ring3(p - 1);
+      const double c1 = acc[sB][ty][tx];
+      const float phi1 = phiB[sB][ty][tx];
+      const float mu1 = float(closure(K.cl, K.cs, K.mueq, c1, double(phi1)));
+      auto atB = [&](int dx, int dy, int dz) -> float {
+        return phiB[ring3(p - 1 + dz)][ty + dy][tx + dx];
+      };
+      float gr1[3], n1[3];
+      gradient_normal<LD, float>(atB, K.eps2, gr1, n1);
+      float G[Q], gs[Q];
+      phi_sources<LD, float>(K, phi1, mu1, n1, G);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) gs[k] = g_collide<LD, float>(K, k, g_old[k], phi1, G[k]);
+      uint16_t genc[Q];
+      float gdec[Q];
+      encode_g<Codec>(gs, phi1, genc, gdec);
+      const auto Gw = make_rsrc(reinterpret_cast<char*>(b.nxt.G.mov) + zq * groupB, uint32_t(groupB));
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+        if (k != LD::REST) bstore16_nt(genc[k], Gw, selfB, mslot(k) * planeB);
+      __builtin_nontemporal_store(gdec[LD::REST], &b.nxt.G.rest[(int64_t)zq * plane + self_xy]);
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) g_old[k] = g_new[k];
+  }
+}
+
+template <class Codec>
+struct DevFused3D {
+  static void launch(const Geo& g, const Coef<float>& K, const DevStep& b, hipStream_t st) {
+    constexpr int BX = 64, BY = 8, ZC = 32;
+    const int tiles_x = (g.nx + BX - 3) / (BX - 2);
+    const int tiles_y = (g.ny + BY - 3) / (BY - 2);
+    const int chunks = (g.nz + ZC - 1) / ZC;
+    const int tiles_xy = tiles_x * tiles_y;
+    const int ntiles = tiles_xy * chunks;
+    hipLaunchKernelGGL((k_dev_fused3d<BX, BY, ZC, Codec>), dim3(ntiles), dim3(BX * BY), 0, st, g,
+                       K, b, tiles_x, tiles_xy, ntiles);
+  }
+};
+
+inline bool dev_fused_supported(int nx, int ny, int nz, const int* bc) {
+  return bc[0] == 0 && bc[1] == 0 && bc[2] == 0 && (int64_t)nx * ny * kMov * 2 < ((int64_t)1 << 31) &&
+         (int64_t)nx * ny * nz < ((int64_t)1 << 31);
+}
+
+}  // namespace gplbm
