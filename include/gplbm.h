@@ -133,6 +133,12 @@ int gplbm_init_fields(gplbm_ctx* ctx, const double* phi0, const double* c0);
 /* Advance nsteps >= 0 time steps.  Asynchronous on the context's stream. */
 int gplbm_step(gplbm_ctx* ctx, int64_t nsteps);
 
+/* One step from a saved state to another (both in the gplbm_save_state
+ * format, device, distinct); the context's own state and step count are left
+ * unchanged.  Lets a checkpointing driver rebuild a segment of states without
+ * copies.  Asynchronous on the context's stream. */
+int gplbm_step_to(gplbm_ctx* ctx, const void* src_state, void* dst_state);
+
 /* Current time level n. */
 int64_t gplbm_step_count(const gplbm_ctx* ctx);
 
@@ -151,6 +157,36 @@ int gplbm_diagnostics(gplbm_ctx* ctx, gplbm_diag* out);
  * exactly.  Asynchronous on the context's stream. */
 int gplbm_save_state(gplbm_ctx* ctx, void* dev_dst);
 int gplbm_load_state(gplbm_ctx* ctx, const void* dev_src, int64_t step);
+
+/* Adjoint (reverse mode) of gplbm_init_fields followed by K steps, for FP64
+ * contexts: gradients of a scalar objective J(phi^K, c^K) with respect to
+ * phi0, c0, lambda and D_l (gamma, M_phi, W and a_at held fixed; D' = D_l - D_s
+ * and D(phi) follow D_l).  It differentiates exactly the discrete map that
+ * gplbm_step computes (every operation of the collisions, sources, closure,
+ * normal, anti-trapping current, streaming and boundaries), at the forward
+ * values recomputed from saved states.  The caller drives the reverse sweep
+ * (e.g. with sqrt(K) checkpointing of gplbm_save_state snapshots).
+ *
+ * gplbm_adjoint_bytes: size of the FP64 device workspace (adjoint state,
+ *   intermediates, per-node parameter accumulators).
+ * gplbm_adjoint_begin: borrow the workspace (256-byte aligned) and seed the
+ *   adjoint of the state at time K from dJ/dphi^K and dJ/dc^K (device arrays of
+ *   N doubles; NULL means zero).  Zeroes the parameter accumulators.
+ * gplbm_adjoint_step: one reverse step from time n+1 to n; state_n and
+ *   state_np1 are the forward states at n and n+1 in the gplbm_save_state
+ *   format (device).  Asynchronous.
+ * gplbm_adjoint_finish: reverse of gplbm_init_fields at (phi0, c0) (device):
+ *   writes dJ/dphi0 and dJ/dc0 (device, N doubles) and dJ/dlambda, dJ/dD_l into
+ *   dJ_dparams (host, 2 doubles).  Parameter sums are reduced in a fixed
+ *   order.  Synchronises the stream.
+ * Return GPLBM_E_INVALID for non-FP64 contexts or null pointers,
+ * GPLBM_E_SIZE for a short workspace, GPLBM_E_STATE out of order. */
+int gplbm_adjoint_bytes(const gplbm_params* p, uint64_t* bytes);
+int gplbm_adjoint_begin(gplbm_ctx* ctx, void* work, uint64_t bytes, const double* phi_bar,
+                        const double* c_bar);
+int gplbm_adjoint_step(gplbm_ctx* ctx, const void* state_n, const void* state_np1);
+int gplbm_adjoint_finish(gplbm_ctx* ctx, const double* phi0, const double* c0, double* phi0_bar,
+                         double* c0_bar, double* dJ_dparams);
 
 /* Which schedule the context runs (GPLBM_SCHED_SPLIT or GPLBM_SCHED_FUSED). */
 int gplbm_schedule(const gplbm_ctx* ctx);

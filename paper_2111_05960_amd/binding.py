@@ -38,7 +38,8 @@ SCHEDULES = {"auto": GPLBM_SCHED_AUTO, "split": GPLBM_SCHED_SPLIT, "fused": GPLB
 SYMBOLS = ("gplbm_state_bytes", "gplbm_checkpoint_bytes", "gplbm_create", "gplbm_set_stream",
            "gplbm_init_fields", "gplbm_step", "gplbm_step_count", "gplbm_read_fields",
            "gplbm_diagnostics", "gplbm_save_state", "gplbm_load_state", "gplbm_schedule",
-           "gplbm_last_error", "gplbm_destroy")
+           "gplbm_last_error", "gplbm_destroy", "gplbm_adjoint_bytes", "gplbm_adjoint_begin",
+           "gplbm_adjoint_step", "gplbm_adjoint_finish", "gplbm_step_to")
 
 
 class gplbm_params(ctypes.Structure):
@@ -107,9 +108,17 @@ def load():
     lib.gplbm_last_error.restype = ctypes.c_char_p
     lib.gplbm_destroy.argtypes = [vp]
     lib.gplbm_destroy.restype = None
+    lib.gplbm_step_to.argtypes = [vp, vp, vp]
+    lib.gplbm_step_to.restype = ctypes.c_int
+    lib.gplbm_adjoint_bytes.argtypes = [P(gplbm_params), P(u64)]
+    lib.gplbm_adjoint_begin.argtypes = [vp, vp, u64, vp, vp]
+    lib.gplbm_adjoint_step.argtypes = [vp, vp, vp]
+    lib.gplbm_adjoint_finish.argtypes = [vp, vp, vp, vp, vp, P(ctypes.c_double)]
     for name in ("gplbm_state_bytes", "gplbm_checkpoint_bytes", "gplbm_create",
                  "gplbm_set_stream", "gplbm_init_fields", "gplbm_step", "gplbm_read_fields",
-                 "gplbm_diagnostics", "gplbm_save_state", "gplbm_load_state", "gplbm_schedule"):
+                 "gplbm_diagnostics", "gplbm_save_state", "gplbm_load_state", "gplbm_schedule",
+                 "gplbm_adjoint_bytes", "gplbm_adjoint_begin", "gplbm_adjoint_step",
+                 "gplbm_adjoint_finish"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -225,6 +234,37 @@ def gplbm_last_error(ctx) -> str:
 
 def gplbm_destroy(ctx):
     load().gplbm_destroy(ctx)
+
+
+def gplbm_step_to(ctx, src_ptr: int, dst_ptr: int):
+    _check(ctx, load().gplbm_step_to(ctx, ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr)))
+
+
+def gplbm_adjoint_bytes(p: gplbm_params) -> int:
+    out = ctypes.c_uint64()
+    rc = load().gplbm_adjoint_bytes(ctypes.byref(p), ctypes.byref(out))
+    if rc:
+        raise GplbmError(rc, "adjoint needs an FP64 context")
+    return out.value
+
+
+def gplbm_adjoint_begin(ctx, work_ptr: int, nbytes: int, phi_bar_ptr, c_bar_ptr):
+    _check(ctx, load().gplbm_adjoint_begin(ctx, ctypes.c_void_p(work_ptr), nbytes,
+                                           ctypes.c_void_p(phi_bar_ptr or None),
+                                           ctypes.c_void_p(c_bar_ptr or None)))
+
+
+def gplbm_adjoint_step(ctx, state_n_ptr: int, state_np1_ptr: int):
+    _check(ctx, load().gplbm_adjoint_step(ctx, ctypes.c_void_p(state_n_ptr),
+                                          ctypes.c_void_p(state_np1_ptr)))
+
+
+def gplbm_adjoint_finish(ctx, phi0_ptr, c0_ptr, phi0_bar_ptr, c0_bar_ptr):
+    out = (ctypes.c_double * 2)()
+    _check(ctx, load().gplbm_adjoint_finish(ctx, ctypes.c_void_p(phi0_ptr), ctypes.c_void_p(c0_ptr),
+                                            ctypes.c_void_p(phi0_bar_ptr),
+                                            ctypes.c_void_p(c0_bar_ptr), out))
+    return out[0], out[1]
 
 
 # ---- convenience owner ----------------------------------------------------

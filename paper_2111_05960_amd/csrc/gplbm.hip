@@ -12,6 +12,7 @@
 #include <string>
 
 #include "gplbm.h"
+#include "kernels_adjoint.h"
 #include "kernels_dev.h"
 #include "kernels_fused2d.h"
 #include "kernels_fused3d.h"
@@ -40,6 +41,10 @@ struct gplbm_ctx {
   hipStream_t stream;
   int device;
   std::string err;
+  // adjoint (FP64 contexts)
+  AdjWork adj;
+  int adj_cur;
+  bool adj_ready;
 };
 
 namespace {
@@ -442,6 +447,42 @@ int gplbm_step(gplbm_ctx* ctx, int64_t nsteps) {
   return dispatch<StepFn>(ctx, nsteps);
 }
 
+int gplbm_step_to(gplbm_ctx* ctx, const void* src_state, void* dst_state) {
+  if (!ctx || !src_state || !dst_state || src_state == dst_state) return GPLBM_E_INVALID;
+  if (int rc = use_device(ctx)) return rc;
+  // run one step with the context's buffers pointed at the two saved states
+  char* G0[2] = {ctx->G[0], ctx->G[1]};
+  char* H0[2] = {ctx->H[0], ctx->H[1]};
+  char* P0[2] = {ctx->PHI[0], ctx->PHI[1]};
+  char* L0[2] = {ctx->LAM[0], ctx->LAM[1]};
+  const int cur = ctx->cur;
+  const int64_t step = ctx->step;
+  const bool ready = ctx->ready;
+  char* s = (char*)src_state;
+  char* d = (char*)dst_state;
+  const size_t pp = ctx->pop_bytes, ph = ctx->phi_bytes;
+  ctx->G[cur] = s;
+  ctx->H[cur] = s + pp;
+  ctx->PHI[cur] = s + 2 * pp;
+  ctx->LAM[cur] = ctx->lam_bytes ? s + 2 * pp + ph : nullptr;
+  ctx->G[1 - cur] = d;
+  ctx->H[1 - cur] = d + pp;
+  ctx->PHI[1 - cur] = d + 2 * pp;
+  ctx->LAM[1 - cur] = ctx->lam_bytes ? d + 2 * pp + ph : nullptr;
+  ctx->ready = true;
+  const int rc = dispatch<StepFn>(ctx, 1);
+  for (int a = 0; a < 2; ++a) {
+    ctx->G[a] = G0[a];
+    ctx->H[a] = H0[a];
+    ctx->PHI[a] = P0[a];
+    ctx->LAM[a] = L0[a];
+  }
+  ctx->cur = cur;
+  ctx->step = step;
+  ctx->ready = ready;
+  return rc;
+}
+
 int64_t gplbm_step_count(const gplbm_ctx* ctx) { return ctx ? ctx->step : -1; }
 
 int gplbm_read_fields(gplbm_ctx* ctx, double* phi, double* c, double* mu) {
@@ -519,5 +560,162 @@ int gplbm_schedule(const gplbm_ctx* ctx) { return ctx ? ctx->sched : GPLBM_E_INV
 const char* gplbm_last_error(const gplbm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 void gplbm_destroy(gplbm_ctx* ctx) { delete ctx; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Adjoint (FP64 only).
+
+namespace {
+
+struct AdjLayout {
+  size_t pop, fld, vec, red, total;
+};
+
+AdjLayout adj_layout(const gplbm_params* p) {
+  AdjLayout l{};
+  const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+  const int Q = lattice_q(p->lattice);
+  l.pop = round_up((size_t)Q * N * 8);
+  l.fld = round_up((size_t)N * 8);
+  l.vec = round_up((size_t)3 * N * 8);
+  l.red = round_up(sizeof(double) * (2 * kDiagBlocks + 2));
+  // two adjoint states, A1..A4, B1..B4, two accumulators, reduction
+  l.total = 2 * (2 * l.pop + l.fld) + (l.pop + l.vec + 2 * l.fld) + (l.pop + l.fld + l.vec + l.fld) +
+            2 * l.fld + l.red;
+  return l;
+}
+
+template <class L>
+struct AdjOps {
+  static dim3 block() { return dim3(64, 4, 1); }
+  static dim3 grid(const gplbm_ctx* ctx) {
+    return dim3((ctx->p.nx + 63) / 64, (ctx->p.ny + 3) / 4, ctx->p.nz);
+  }
+  static double lam_M_W2(const gplbm_ctx* ctx) { return ctx->p.M_phi / (ctx->p.W * ctx->p.W); }
+  static FwdState fwd(const gplbm_ctx* ctx, const void* ck) {
+    const char* b = (const char*)ck;
+    return FwdState{(const double*)b, (const double*)(b + ctx->pop_bytes),
+                    (const double*)(b + 2 * ctx->pop_bytes)};
+  }
+  static int seed(gplbm_ctx* ctx, const double* phib, const double* cb) {
+    const Geo g = make_geo(ctx->p);
+    hipLaunchKernelGGL((k_adj_seed<L>), grid(ctx), block(), 0, ctx->stream, g, phib, cb, ctx->adj,
+                       ctx->adj_cur);
+    return check_launch(ctx, "adjoint seed");
+  }
+  static int step(gplbm_ctx* ctx, const void* s0, const void* s1) {
+    const Geo g = make_geo(ctx->p);
+    const Coef<double> K = make_coef<double>(ctx->p);
+    const int a = ctx->adj_cur, b = 1 - a;
+    const FwdState S0 = fwd(ctx, s0), S1 = fwd(ctx, s1);
+    hipLaunchKernelGGL((k_adj_ra<L>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx), S1,
+                       (const double*)ctx->adj.Gb[a], ctx->adj);
+    hipLaunchKernelGGL((k_adj_rb<L>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx), S0,
+                       S1, (const double*)ctx->adj.Hb[a], (const double*)ctx->adj.Pb[a], ctx->adj);
+    hipLaunchKernelGGL((k_adj_rc<L>), grid(ctx), block(), 0, ctx->stream, g, ctx->adj,
+                       ctx->adj.Gb[b], ctx->adj.Hb[b], ctx->adj.Pb[b]);
+    int rc = check_launch(ctx, "adjoint step");
+    if (rc) return rc;
+    ctx->adj_cur = b;
+    return GPLBM_OK;
+  }
+  static int finish(gplbm_ctx* ctx, const double* phi0, const double* c0, double* phi0b,
+                    double* c0b) {
+    const Geo g = make_geo(ctx->p);
+    const Coef<double> K = make_coef<double>(ctx->p);
+    hipLaunchKernelGGL((k_adj_init_a<L>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx),
+                       phi0, c0, ctx->adj, ctx->adj_cur, c0b);
+    hipLaunchKernelGGL((k_adj_init_b<L>), grid(ctx), block(), 0, ctx->stream, g, ctx->adj, phi0b);
+    hipLaunchKernelGGL(k_adj_reduce, dim3(kDiagBlocks), dim3(kDiagThreads), 0, ctx->stream,
+                       (const double*)ctx->adj.lamb, (const double*)ctx->adj.dlb, g.N, ctx->adj.red);
+    hipLaunchKernelGGL(k_adj_reduce_final, dim3(1), dim3(64), 0, ctx->stream,
+                       (const double*)ctx->adj.red, kDiagBlocks, ctx->adj.red + 2 * kDiagBlocks);
+    return check_launch(ctx, "adjoint finish");
+  }
+};
+
+template <template <class> class Fn, class... Args>
+int adj_dispatch(gplbm_ctx* ctx, Args... args) {
+  if (ctx->p.lattice == GPLBM_D2Q9) return Fn<D2Q9>::run(ctx, args...);
+  return Fn<D3Q19>::run(ctx, args...);
+}
+template <class L>
+struct AdjSeedFn {
+  static int run(gplbm_ctx* c, const double* a, const double* b) { return AdjOps<L>::seed(c, a, b); }
+};
+template <class L>
+struct AdjStepFn {
+  static int run(gplbm_ctx* c, const void* a, const void* b) { return AdjOps<L>::step(c, a, b); }
+};
+template <class L>
+struct AdjFinishFn {
+  static int run(gplbm_ctx* c, const double* a, const double* b, double* d, double* e) {
+    return AdjOps<L>::finish(c, a, b, d, e);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int gplbm_adjoint_bytes(const gplbm_params* p, uint64_t* bytes) {
+  if (check_params(p) || !bytes || p->precision != GPLBM_FP64) return GPLBM_E_INVALID;
+  *bytes = adj_layout(p).total;
+  return GPLBM_OK;
+}
+
+int gplbm_adjoint_begin(gplbm_ctx* ctx, void* work, uint64_t bytes, const double* phi_bar,
+                        const double* c_bar) {
+  if (!ctx || !work || ((uintptr_t)work) % kAlign) return GPLBM_E_INVALID;
+  if (ctx->p.precision != GPLBM_FP64) return fail(ctx, GPLBM_E_INVALID, "adjoint needs FP64");
+  const AdjLayout l = adj_layout(&ctx->p);
+  if (bytes < l.total) return fail(ctx, GPLBM_E_SIZE, "adjoint workspace too small");
+  if (int rc = use_device(ctx)) return rc;
+  char* b = (char*)work;
+  AdjWork& w = ctx->adj;
+  for (int a = 0; a < 2; ++a) {
+    w.Gb[a] = (double*)b; b += l.pop;
+    w.Hb[a] = (double*)b; b += l.pop;
+    w.Pb[a] = (double*)b; b += l.fld;
+  }
+  w.A1 = (double*)b; b += l.pop;
+  w.A2 = (double*)b; b += l.vec;
+  w.A3 = (double*)b; b += l.fld;
+  w.A4 = (double*)b; b += l.fld;
+  w.B1 = (double*)b; b += l.pop;
+  w.B2 = (double*)b; b += l.fld;
+  w.B3 = (double*)b; b += l.vec;
+  w.B4 = (double*)b; b += l.fld;
+  w.lamb = (double*)b; b += l.fld;
+  w.dlb = (double*)b; b += l.fld;
+  w.red = (double*)b;
+  ctx->adj_cur = 0;
+  int rc = adj_dispatch<AdjSeedFn>(ctx, phi_bar, c_bar);
+  ctx->adj_ready = rc == GPLBM_OK;
+  return rc;
+}
+
+int gplbm_adjoint_step(gplbm_ctx* ctx, const void* state_n, const void* state_np1) {
+  if (!ctx || !state_n || !state_np1) return GPLBM_E_INVALID;
+  if (!ctx->adj_ready) return fail(ctx, GPLBM_E_STATE, "adjoint step before adjoint begin");
+  if (int rc = use_device(ctx)) return rc;
+  return adj_dispatch<AdjStepFn>(ctx, state_n, state_np1);
+}
+
+int gplbm_adjoint_finish(gplbm_ctx* ctx, const double* phi0, const double* c0, double* phi0_bar,
+                         double* c0_bar, double* dJ_dparams) {
+  if (!ctx || !phi0 || !c0 || !phi0_bar || !c0_bar || !dJ_dparams) return GPLBM_E_INVALID;
+  if (!ctx->adj_ready) return fail(ctx, GPLBM_E_STATE, "adjoint finish before adjoint begin");
+  if (int rc = use_device(ctx)) return rc;
+  int rc = adj_dispatch<AdjFinishFn>(ctx, phi0, c0, phi0_bar, c0_bar);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(dJ_dparams, ctx->adj.red + 2 * kDiagBlocks, 2 * sizeof(double),
+                                hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail(ctx, GPLBM_E_DEVICE, std::string("adjoint finish: ") + hipGetErrorString(e));
+  ctx->adj_ready = false;
+  return GPLBM_OK;
+}
 
 }  // extern "C"

@@ -1,0 +1,490 @@
+// Hand-written adjoint (reverse mode) of the coupled step, FP64.
+//
+// The forward step maps the state S_n = (G = g~*^n, H = h~*^{n-1}, PHI = phi^n)
+// to S_{n+1} (geometry.h).  Given the adjoint of S_{n+1} (Gb', Hb', Pb') and
+// the forward states S_n and S_{n+1}, one reverse step produces the adjoint of
+// S_n and accumulates the parameter adjoints (lambda, D_l) per node.  Every
+// operation of the step is linear in the populations, so the reverse of a
+// collision is a weighted copy; the nonlinear parts (closure products, p'(phi),
+// the normal, mu D' grad phi, the anti-trapping product, D(phi) mu) are
+// differentiated by hand at the forward values, which the reverse kernels
+// recompute from S_n and S_{n+1}.
+//
+// Three kernels per reverse step (each node reads its neighbours only through
+// the previous kernel's output):
+//   ra: reverse of the g collision of step n+1 at every node: adjoint of the
+//       pulled g~^{n+1} (A1), of grad phi^{n+1} (A2), of c^{n+1} (A3) and the
+//       local part of the adjoint of phi^{n+1} (A4);
+//   rb: adjoint of h~*^n (own Hb' plus c^{n+1} from the neighbour it streams
+//       to), total adjoint of phi^{n+1} (own, A4, stencil transpose of A2),
+//       reverse of the h collision of step n and of
+//       phi^{n+1} = sum g~^{n+1} + S^n / 2: adjoint of the pulled h~^n (B1),
+//       of phi^{n+1} (B2), of grad phi^n (B3), local part of the adjoint of
+//       phi^n (B4);
+//   rc: transposes of the pulls and of the gradient stencil: the adjoint of
+//       S_n.
+// Parameters are held fixed except lambda and D_l (gamma, M_phi, W and a do
+// not follow D_l).
+#pragma once
+
+#include "kernels_split.h"
+
+namespace gplbm {
+
+struct AdjWork {
+  double* Gb[2];  // adjoint of G  (plane-major Q layout)
+  double* Hb[2];  // adjoint of H
+  double* Pb[2];  // adjoint of PHI
+  double *A1, *A2, *A3, *A4;  // A1: Q*N, A2: 3*N, A3: N, A4: N
+  double *B1, *B2, *B3, *B4;  // B1: Q*N, B2: N, B3: 3*N, B4: N
+  double *lamb, *dlb;         // per-node accumulators of dJ/dlambda, dJ/dD_l
+  double* red;                // reduction scratch
+};
+
+struct FwdState {
+  const double* G;
+  const double* H;
+  const double* PHI;
+};
+
+// Destination of the value stored in slot (k, x, y, z) under the pull
+// streaming: the node x + e_k reads it as population k, or, when x + e_k
+// lies beyond a zero-flux wall, x itself reads it as population opp(k).
+// Returns the destination population; (dx, dy, dz) the destination node.
+template <class L>
+__device__ __forceinline__ int push_dest(const Geo& g, int k, int x, int y, int z, int& dx, int& dy,
+                                         int& dz) {
+  dx = x;
+  dy = y;
+  dz = z;
+  // moving "backwards" by -e_k with pull_axis gives x + e_k
+  bool in = pull_axis(dx, -L::ex[k], g.nx, g.bcx) && pull_axis(dy, -L::ey[k], g.ny, g.bcy);
+  if (L::D == 3) in = in && pull_axis(dz, -L::ez[k], g.nz, g.bcz);
+  if (!in) {
+    dx = x;
+    dy = y;
+    dz = z;
+    return L::opp[k];
+  }
+  return k;
+}
+
+// Forward quantities at one node from a state: c, mu, phi, grad phi, normal.
+template <class L>
+struct NodeFwd {
+  double c, mu, phi, g[3], n[3], s;  // s = sqrt(|grad|^2 + eps^2)
+};
+
+template <class L>
+__device__ __forceinline__ NodeFwd<L> node_fwd(const Geo& g, const Coef<double>& K, const FwdState& S,
+                                               int x, int y, int z) {
+  NodeFwd<L> f;
+  double c = 0.0;
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    const double v = pull<L>(g, S.H, k, x, y, z);
+    c = k == 0 ? v : c + v;
+  }
+  f.c = c;
+  f.phi = S.PHI[node_index(g, x, y, z)];
+  f.mu = closure(K.cl, K.cs, K.mueq, c, f.phi);
+  gradient_normal<L, double>(GlobalPhi<double, double>{g, S.PHI, x, y, z}, K.eps2, f.g, f.n);
+  double nn = f.g[0] * f.g[0] + f.g[1] * f.g[1];
+  if (L::D == 3) nn = nn + f.g[2] * f.g[2];
+  f.s = sqrt(nn + K.eps2);
+  return f;
+}
+
+// Adjoint of the phi sources G_k (given their adjoints Gb_k) and of the
+// extra adjoint sbar_b of their zeroth moment, at (phi, mu, n).  Adds to
+// phi_b, mu_b, n_b and returns the lambda adjoint.
+template <class L>
+__device__ __forceinline__ double sources_adj(const Coef<double>& K, double lam_M_W2, double phi,
+                                              double mu, const double n[3], const double* Gb,
+                                              double sbar_b, double& phi_b, double& mu_b,
+                                              double nb[3]) {
+  const double pp = phi * (1.0 - phi);
+  double Gst_b = sbar_b, kphi_b = 0.0, Gdw_b = 0.0;
+  if (K.counter_term) {
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+      if (Gb == nullptr) break;
+      const double wg = L::w[k] * Gb[k];
+      Gst_b += wg;
+      if (k != L::REST) {
+        const double en = edot<L, double>(k, n[0], n[1], n[2]);
+        kphi_b += en * wg;
+        const double kphi = K.k4w * pp;
+        if (L::ex[k]) nb[0] += (L::ex[k] > 0 ? 1.0 : -1.0) * kphi * wg;
+        if (L::ey[k]) nb[1] += (L::ey[k] > 0 ? 1.0 : -1.0) * kphi * wg;
+        if (L::D == 3 && L::ez[k]) nb[2] += (L::ez[k] > 0 ? 1.0 : -1.0) * kphi * wg;
+      }
+    }
+  } else {
+    double s = 0.0;
+    if (Gb != nullptr) {
+#pragma unroll
+      for (int k = 0; k < L::Q; ++k) s += L::w[k] * Gb[k];
+    }
+    Gst_b += s;
+    Gdw_b = s + sbar_b;
+  }
+  const double Sphi = (6.0 * pp * K.dc) * (mu - K.mueq_c);
+  double pp_b = (K.kst * 6.0 * K.dc * (mu - K.mueq_c)) * Gst_b + K.k4w * kphi_b;
+  mu_b += (K.kst * 6.0 * pp * K.dc) * Gst_b;
+  if (!K.counter_term) {
+    pp_b += K.kdw * 2.0 * (1.0 - 2.0 * phi) * Gdw_b;
+    phi_b += K.kdw * 2.0 * pp * (-2.0) * Gdw_b;
+  }
+  phi_b += (1.0 - 2.0 * phi) * pp_b;
+  return -lam_M_W2 * Sphi * Gst_b;
+}
+
+// Adjoint of the normal n = g / s: adds the gradient adjoint to gb.
+template <class L>
+__device__ __forceinline__ void normal_adj(const NodeFwd<L>& f, const double nb[3], double gb[3]) {
+  const double nd = f.n[0] * nb[0] + f.n[1] * nb[1] + (L::D == 3 ? f.n[2] * nb[2] : 0.0);
+  for (int a = 0; a < L::D; ++a) gb[a] += (nb[a] - f.n[a] * nd) / f.s;
+}
+
+// Gather of the transposed gradient stencil at node (x, y, z):
+// sum over k != rest and over the nodes q with stencil(q + e_k) = (x, y, z)
+// of 3 w_k e_k . gb(q).
+__device__ __forceinline__ int preimage(int z, int e, int n, int bc, int out[2]) {
+  if (!bc) {
+    int v = z - e;
+    v = v < 0 ? v + n : (v >= n ? v - n : v);
+    out[0] = v;
+    return 1;
+  }
+  int m = 0;
+  if (e == 0) {
+    out[m++] = z;
+  } else if (e > 0) {
+    if (z - 1 >= 0) out[m++] = z - 1;
+    if (z == n - 1) out[m++] = z;
+  } else {
+    if (z + 1 <= n - 1) out[m++] = z + 1;
+    if (z == 0) out[m++] = z;
+  }
+  return m;
+}
+
+template <class L>
+__device__ __forceinline__ double stencil_adj_gather(const Geo& g, const double* gb3, int x, int y,
+                                                     int z) {
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    if (k == L::REST) continue;
+    int px[2], py[2], pz[2];
+    const int mx = preimage(x, L::ex[k], g.nx, g.bcx, px);
+    const int my = preimage(y, L::ey[k], g.ny, g.bcy, py);
+    const int mz = L::D == 3 ? preimage(z, L::ez[k], g.nz, g.bcz, pz) : (pz[0] = z, 1);
+    for (int a = 0; a < mx; ++a)
+      for (int b = 0; b < my; ++b)
+        for (int c = 0; c < mz; ++c) {
+          const int64_t q = node_index(g, px[a], py[b], pz[c]);
+          const double e_g = edot<L, double>(k, gb3[q], gb3[g.N + q], L::D == 3 ? gb3[2 * g.N + q] : 0.0);
+          acc += 3.0 * L::w[k] * e_g;
+        }
+  }
+  return acc;
+}
+
+// --------------------------------------------------------------------------
+
+template <class L>
+__global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> K, double lam_M_W2,
+                                                FwdState S1, const double* __restrict__ Gb1,
+                                                AdjWork w) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int64_t i = node_index(g, x, y, z);
+  const NodeFwd<L> f = node_fwd<L>(g, K, S1, x, y, z);  // c^{n+1}, mu^{n+1}, ...
+  const double om = K.omega_g;
+  double Gb[L::Q];
+  double phi_b = 0.0, mu_b = 0.0, nb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    const double a = Gb1[pop_index<L>(g, k, x, y, z)];
+    w.A1[pop_index<L>(g, k, x, y, z)] = (1.0 - om) * a;
+    Gb[k] = (1.0 - 0.5 * om) * a;
+    phi_b += om * L::w[k] * a;
+  }
+  const double lb = sources_adj<L>(K, lam_M_W2, f.phi, f.mu, f.n, Gb, 0.0, phi_b, mu_b, nb);
+  double gb[3] = {0.0, 0.0, 0.0};
+  normal_adj<L>(f, nb, gb);
+  for (int a = 0; a < 3; ++a) w.A2[a * g.N + i] = gb[a];
+  w.A3[i] = mu_b;                      // adjoint of c^{n+1}
+  phi_b += (K.cs - K.cl) * mu_b;       // closure
+  w.A4[i] = phi_b;
+  w.lamb[i] += lb;
+}
+
+template <class L>
+__global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> K, double lam_M_W2,
+                                                FwdState S0, FwdState S1,
+                                                const double* __restrict__ Hb1,
+                                                const double* __restrict__ Pb1, AdjWork w) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int64_t i = node_index(g, x, y, z);
+  // total adjoint of h~*^n in this node's slots
+  double Hb[L::Q];
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    int dx, dy, dz;
+    push_dest<L>(g, k, x, y, z, dx, dy, dz);
+    Hb[k] = Hb1[pop_index<L>(g, k, x, y, z)] + w.A3[node_index(g, dx, dy, dz)];
+  }
+  // adjoint of phi^{n+1} at this node
+  double p1b = Pb1[i] + w.A4[i] + stencil_adj_gather<L>(g, w.A2, x, y, z);
+  // forward quantities of step n
+  const NodeFwd<L> f = node_fwd<L>(g, K, S0, x, y, z);
+  const double phi1 = S1.PHI[i];
+  const double dtphi = phi1 - f.phi;
+  const double oh = K.omega_h;
+  const double Dp = K.Dp;
+  const double D = (K.Dl * f.phi) + (K.Ds * (1.0 - f.phi));
+  // reverse of h* = (1 - oh) h + oh heq + (1 - oh/2) H
+  double hb[L::Q];
+  double c_b = 0.0, lam_b = 0.0, Fb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    hb[k] = (1.0 - oh) * Hb[k];
+    const double heq_b = oh * Hb[k];
+    if (k == L::REST) {
+      c_b += heq_b;
+      lam_b += -(1.0 - L::w[k]) * heq_b;
+    } else {
+      lam_b += L::w[k] * heq_b;
+      const double HHb = (1.0 - 0.5 * oh) * Hb[k] * (K.gamma * L::w[k]);
+      if (L::ex[k]) Fb[0] += (L::ex[k] > 0 ? HHb : -HHb);
+      if (L::ey[k]) Fb[1] += (L::ey[k] > 0 ? HHb : -HHb);
+      if (L::D == 3 && L::ez[k]) Fb[2] += (L::ez[k] > 0 ? HHb : -HHb);
+    }
+  }
+  double mu_b = 0.0, phi_b = 0.0, dl_b = 0.0, gb[3] = {0.0, 0.0, 0.0}, nb[3] = {0.0, 0.0, 0.0};
+  // Lambda = gamma D mu
+  mu_b += K.gamma * D * lam_b;
+  const double D_b = K.gamma * f.mu * lam_b;
+  phi_b += (K.Dl - K.Ds) * D_b;
+  dl_b += f.phi * D_b;
+  // F = mu D' grad + jfac dtphi n
+  const double gF = f.g[0] * Fb[0] + f.g[1] * Fb[1] + (L::D == 3 ? f.g[2] * Fb[2] : 0.0);
+  mu_b += Dp * gF;
+  dl_b += f.mu * gF;
+  for (int a = 0; a < L::D; ++a) gb[a] += f.mu * Dp * Fb[a];
+  if (K.anti_trapping) {
+    const double nF = f.n[0] * Fb[0] + f.n[1] * Fb[1] + (L::D == 3 ? f.n[2] * Fb[2] : 0.0);
+    const double dt_b = K.jfac * nF;
+    for (int a = 0; a < L::D; ++a) nb[a] += K.jfac * dtphi * Fb[a];
+    p1b += dt_b;
+    phi_b -= dt_b;
+  }
+  // phi^{n+1} = sum g~^{n+1} + sbar^n / 2
+  const double lb = sources_adj<L>(K, lam_M_W2, f.phi, f.mu, f.n, nullptr, 0.5 * p1b, phi_b, mu_b, nb);
+  normal_adj<L>(f, nb, gb);
+  // closure and c^n = sum h~^n
+  c_b += mu_b;
+  phi_b += (K.cs - K.cl) * mu_b;
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) w.B1[pop_index<L>(g, k, x, y, z)] = hb[k] + c_b;
+  w.B2[i] = p1b;
+  for (int a = 0; a < 3; ++a) w.B3[a * g.N + i] = gb[a];
+  w.B4[i] = phi_b;
+  w.lamb[i] += lb;
+  w.dlb[i] += dl_b;
+}
+
+template <class L>
+__global__ void __launch_bounds__(256) k_adj_rc(Geo g, AdjWork w, double* __restrict__ Gb0,
+                                                double* __restrict__ Hb0, double* __restrict__ Pb0) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int64_t i = node_index(g, x, y, z);
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    int dx, dy, dz;
+    const int kk = push_dest<L>(g, k, x, y, z, dx, dy, dz);
+    const int64_t d = node_index(g, dx, dy, dz);
+    Hb0[pop_index<L>(g, k, x, y, z)] = w.B1[pop_index<L>(g, kk, dx, dy, dz)];
+    Gb0[pop_index<L>(g, k, x, y, z)] = w.A1[pop_index<L>(g, kk, dx, dy, dz)] + w.B2[d];
+  }
+  Pb0[i] = w.B4[i] + stencil_adj_gather<L>(g, w.B3, x, y, z);
+}
+
+// Seed: adjoint of S_K from dJ/dphi^K and dJ/dc^K (c^K = sum of pulled H).
+template <class L>
+__global__ void __launch_bounds__(256) k_adj_seed(Geo g, const double* __restrict__ phib,
+                                                  const double* __restrict__ cb, AdjWork w, int a) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int64_t i = node_index(g, x, y, z);
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    int dx, dy, dz;
+    push_dest<L>(g, k, x, y, z, dx, dy, dz);
+    w.Hb[a][pop_index<L>(g, k, x, y, z)] = cb ? cb[node_index(g, dx, dy, dz)] : 0.0;
+    w.Gb[a][pop_index<L>(g, k, x, y, z)] = 0.0;
+  }
+  w.Pb[a][i] = phib ? phib[i] : 0.0;
+  w.lamb[i] = 0.0;
+  w.dlb[i] = 0.0;
+}
+
+// Adjoint of the initialisation (phi0, c0) -> S_0, local part: writes the
+// adjoint of c0 and, in B4 / B3, the local part of the adjoint of phi0 and the
+// adjoint of grad phi0.
+template <class L>
+__global__ void __launch_bounds__(256) k_adj_init_a(Geo g, Coef<double> K, double lam_M_W2,
+                                                    const double* __restrict__ phi0,
+                                                    const double* __restrict__ c0, AdjWork w, int a,
+                                                    double* __restrict__ c0b) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int64_t i = node_index(g, x, y, z);
+  const double phi = phi0[i], cin = c0[i];
+  NodeFwd<L> f;
+  f.phi = phi;
+  gradient_normal<L, double>(GlobalPhi<double, double>{g, phi0, x, y, z}, K.eps2, f.g, f.n);
+  {
+    double nn = f.g[0] * f.g[0] + f.g[1] * f.g[1];
+    if (L::D == 3) nn = nn + f.g[2] * f.g[2];
+    f.s = sqrt(nn + K.eps2);
+  }
+  const double mu0 = closure(K.cl, K.cs, K.mueq, cin, phi);
+  // forward h~^0 and c^0
+  double F[3];
+  h_flux<L, double>(K, mu0, f.g, f.n, 0.0, false, F);
+  const double lam = h_lambda<double>(K, phi, mu0);
+  double c = 0.0;
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    const double hv = h_eq<L, double>(k, cin, lam) - 0.5 * h_source<L, double>(K, k, F);
+    c = k == 0 ? hv : c + hv;
+  }
+  const double mu = closure(K.cl, K.cs, K.mueq, c, phi);
+  // adjoints of the pulled h~^0 (from H of S_0) and of G of S_0
+  double hb[L::Q], Gb[L::Q], g0b[L::Q];
+  double phi_b = w.Pb[a][i], mu_b = 0.0, mu0_b = 0.0, nb[3] = {0.0, 0.0, 0.0};
+  double lb = 0.0;
+  const double om = K.omega_g;
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    hb[k] = pull<L>(g, (const double*)w.Hb[a], k, x, y, z);
+    const double gsb = w.Gb[a][pop_index<L>(g, k, x, y, z)];
+    g0b[k] = (1.0 - om) * gsb;
+    Gb[k] = (1.0 - 0.5 * om) * gsb;
+    phi_b += om * L::w[k] * gsb;
+  }
+  // g collision at time 0 (sources at phi, mu(c^0), n)
+  lb += sources_adj<L>(K, lam_M_W2, phi, mu, f.n, Gb, 0.0, phi_b, mu_b, nb);
+  const double c_b = mu_b;  // c^0 = sum h~^0
+  phi_b += (K.cs - K.cl) * mu_b;
+  // g~^0 = w phi - G^0 / 2
+  double G0b[L::Q];
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    phi_b += L::w[k] * g0b[k];
+    G0b[k] = -0.5 * g0b[k];
+  }
+  lb += sources_adj<L>(K, lam_M_W2, phi, mu0, f.n, G0b, 0.0, phi_b, mu0_b, nb);
+  // h~^0 = heq(c0, Lambda0) - H^0 / 2
+  double cin_b = 0.0, lam_b = 0.0, Fb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    const double hk = hb[k] + c_b;
+    if (k == L::REST) {
+      cin_b += hk;
+      lam_b += -(1.0 - L::w[k]) * hk;
+    } else {
+      lam_b += L::w[k] * hk;
+      const double HHb = -0.5 * hk * (K.gamma * L::w[k]);
+      if (L::ex[k]) Fb[0] += (L::ex[k] > 0 ? HHb : -HHb);
+      if (L::ey[k]) Fb[1] += (L::ey[k] > 0 ? HHb : -HHb);
+      if (L::D == 3 && L::ez[k]) Fb[2] += (L::ez[k] > 0 ? HHb : -HHb);
+    }
+  }
+  const double D = (K.Dl * phi) + (K.Ds * (1.0 - phi));
+  double dl_b = 0.0, gb[3] = {0.0, 0.0, 0.0};
+  mu0_b += K.gamma * D * lam_b;
+  const double D_b = K.gamma * mu0 * lam_b;
+  phi_b += (K.Dl - K.Ds) * D_b;
+  dl_b += phi * D_b;
+  const double gF = f.g[0] * Fb[0] + f.g[1] * Fb[1] + (L::D == 3 ? f.g[2] * Fb[2] : 0.0);
+  mu0_b += K.Dp * gF;
+  dl_b += mu0 * gF;
+  for (int d = 0; d < L::D; ++d) gb[d] += mu0 * K.Dp * Fb[d];
+  normal_adj<L>(f, nb, gb);
+  // mu0 = closure(c0, phi0)
+  cin_b += mu0_b;
+  phi_b += (K.cs - K.cl) * mu0_b;
+  c0b[i] = cin_b;
+  w.B4[i] = phi_b;
+  for (int d = 0; d < 3; ++d) w.B3[d * g.N + i] = gb[d];
+  w.lamb[i] += lb;
+  w.dlb[i] += dl_b;
+}
+
+template <class L>
+__global__ void __launch_bounds__(256) k_adj_init_b(Geo g, AdjWork w, double* __restrict__ phi0b) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int64_t i = node_index(g, x, y, z);
+  phi0b[i] = w.B4[i] + stencil_adj_gather<L>(g, w.B3, x, y, z);
+}
+
+// Deterministic sum of the two per-node accumulators (fixed launch shape).
+__global__ void __launch_bounds__(kDiagThreads) k_adj_reduce(const double* __restrict__ a,
+                                                             const double* __restrict__ b, int64_t n,
+                                                             double* __restrict__ part) {
+  __shared__ double ra[kDiagThreads], rb[kDiagThreads];
+  double sa = 0.0, sb = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    sa = sa + a[i];
+    sb = sb + b[i];
+  }
+  ra[threadIdx.x] = sa;
+  rb[threadIdx.x] = sb;
+  __syncthreads();
+  for (int s = kDiagThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      ra[threadIdx.x] = ra[threadIdx.x] + ra[threadIdx.x + s];
+      rb[threadIdx.x] = rb[threadIdx.x] + rb[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = ra[0];
+    part[2 * blockIdx.x + 1] = rb[0];
+  }
+}
+
+__global__ void k_adj_reduce_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double sa = 0.0, sb = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      sa = sa + part[2 * b];
+      sb = sb + part[2 * b + 1];
+    }
+    out[0] = sa;
+    out[1] = sb;
+  }
+}
+
+}  // namespace gplbm
