@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -101,6 +102,53 @@ def time_gpu(p, phi0, c0, precision, schedule, steps, warmup, log):
         f"{res['achieved_gbs']:.0f} GB/s algorithmic, mass drift {res['mass_drift_rel']:.2e}")
     del sim
     torch.cuda.empty_cache()
+    return res
+
+
+def time_adjoint(K, log, n=512):
+    """Differentiation workload: 2-D porous medium n^2 (D2Q9, periodic), K
+    steps in FP64; gradients of the final solid fraction with respect to
+    lambda, D_l and phi0 through the hand-written adjoint with sqrt(K)
+    checkpointing.  Returns forward and backward wall times (the backward
+    phase rebuilds each checkpoint segment and runs the reverse steps)."""
+    import torch
+    import workloads as wl
+    from paper_2111_05960_amd import adjoint
+
+    p, phi0, c0, _ = wl.config_porous2d(n=n)
+    dev = torch.device("cuda")
+    g_phi0 = torch.tensor(phi0, device=dev, requires_grad=True)
+    c0_t = torch.tensor(c0, device=dev)
+    g_lam = torch.tensor(p["lam"], dtype=torch.float64, requires_grad=True)
+    g_dl = torch.tensor(p["D_l"], dtype=torch.float64, requires_grad=True)
+    # untimed warm-up of both directions on a short run
+    phiK, _ = adjoint.gplbm_run(g_phi0, c0_t, g_lam, g_dl, p, 16)
+    adjoint.objectives(g_phi0, phiK, p["W"])[0].backward()
+    g_phi0.grad = None
+    g_lam.grad = None
+    g_dl.grad = None
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    base_mem = torch.cuda.memory_allocated()
+    t0 = time.perf_counter()
+    phiK, _ = adjoint.gplbm_run(g_phi0, c0_t, g_lam, g_dl, p, K)
+    J1, J2 = adjoint.objectives(g_phi0, phiK, p["W"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J1.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    peak = torch.cuda.max_memory_allocated() - base_mem
+    fwd, bwd = t1 - t0, t2 - t1
+    res = {"workload": f"porous2d_{n}_d2q9", "K": K, "precision": "fp64",
+           "checkpoint_every": int(math.ceil(math.sqrt(K))),
+           "forward_s": round(fwd, 4), "backward_s": round(bwd, 4),
+           "adjoint_forward_ratio": round(bwd / fwd, 3),
+           "peak_memory_gb": round(peak / 1e9, 3),
+           "J1": J1.item(), "dJ1_dlambda": g_lam.grad.item(), "dJ1_dDl": g_dl.grad.item(),
+           "dJ1_dphi0_norm": float(g_phi0.grad.norm().item())}
+    log(f"adjoint {res['workload']} K={K}: forward {fwd:.3f} s, backward {bwd:.3f} s "
+        f"(ratio {bwd / fwd:.2f}), peak {peak / 1e9:.2f} GB")
     return res
 
 
@@ -242,6 +290,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", action="store_true",
                     help="also time the other precision and schedule")
+    ap.add_argument("--adjoint-steps", type=int, default=4000,
+                    help="K of the differentiation workload (0 skips it)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run a 4 GiB device copy after the timed region (counter calibration)")
     ap.add_argument("--summarize-profile", nargs="+", metavar="DB",
@@ -286,6 +336,8 @@ def main():
                 r = time_gpu(p, phi0, c0, prec, sch, args.steps, args.warmup, log)
                 r["hbm_frac"] = round(r["achieved_gbs"] / HBM_PEAK_GBS, 4)
                 variants.append(dict(precision=prec, **r))
+
+    adj = time_adjoint(args.adjoint_steps, log) if args.adjoint_steps > 0 else None
 
     if args.calibration_copy:
         calibration_copy(log)
@@ -339,6 +391,8 @@ def main():
         "checks": {"mass_drift_rel": main_res["mass_drift_rel"], "nonfinite": main_res["nonfinite"]},
         "context": {"paper_v100_mlups_2d_1024sq_d2q9": 149.8},
     }
+    if adj is not None:
+        line["adjoint"] = adj
     if variants:
         line["variants"] = variants
     print(json.dumps(line), flush=True)

@@ -580,9 +580,8 @@ AdjLayout adj_layout(const gplbm_params* p) {
   l.fld = round_up((size_t)N * 8);
   l.vec = round_up((size_t)3 * N * 8);
   l.red = round_up(sizeof(double) * (2 * kDiagBlocks + 2));
-  // two adjoint states, A1..A4, B1..B4, two accumulators, reduction
-  l.total = 2 * (2 * l.pop + l.fld) + (l.pop + l.vec + 2 * l.fld) + (l.pop + l.fld + l.vec + l.fld) +
-            2 * l.fld + l.red;
+  // two sets (A1, B1, B2, B3, B4), A2..A4, two accumulators, reduction
+  l.total = 2 * (2 * l.pop + 2 * l.fld + l.vec) + (l.vec + 2 * l.fld) + 2 * l.fld + l.red;
   return l;
 }
 
@@ -600,8 +599,8 @@ struct AdjOps {
   }
   static int seed(gplbm_ctx* ctx, const double* phib, const double* cb) {
     const Geo g = make_geo(ctx->p);
-    hipLaunchKernelGGL((k_adj_seed<L>), grid(ctx), block(), 0, ctx->stream, g, phib, cb, ctx->adj,
-                       ctx->adj_cur);
+    hipLaunchKernelGGL((k_adj_seed<L>), grid(ctx), block(), 0, ctx->stream, g, phib, cb,
+                       ctx->adj.set[ctx->adj_cur], ctx->adj);
     return check_launch(ctx, "adjoint seed");
   }
   static int step(gplbm_ctx* ctx, const void* s0, const void* s1) {
@@ -610,11 +609,9 @@ struct AdjOps {
     const int a = ctx->adj_cur, b = 1 - a;
     const FwdState S0 = fwd(ctx, s0), S1 = fwd(ctx, s1);
     hipLaunchKernelGGL((k_adj_ra<L>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx), S1,
-                       (const double*)ctx->adj.Gb[a], ctx->adj);
+                       ctx->adj.set[a], ctx->adj.set[b], ctx->adj);
     hipLaunchKernelGGL((k_adj_rb<L>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx), S0,
-                       S1, (const double*)ctx->adj.Hb[a], (const double*)ctx->adj.Pb[a], ctx->adj);
-    hipLaunchKernelGGL((k_adj_rc<L>), grid(ctx), block(), 0, ctx->stream, g, ctx->adj,
-                       ctx->adj.Gb[b], ctx->adj.Hb[b], ctx->adj.Pb[b]);
+                       S1, ctx->adj.set[a], ctx->adj.set[b], ctx->adj);
     int rc = check_launch(ctx, "adjoint step");
     if (rc) return rc;
     ctx->adj_cur = b;
@@ -624,9 +621,11 @@ struct AdjOps {
                     double* c0b) {
     const Geo g = make_geo(ctx->p);
     const Coef<double> K = make_coef<double>(ctx->p);
+    const int a = ctx->adj_cur, b = 1 - a;
     hipLaunchKernelGGL((k_adj_init_a<L>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx),
-                       phi0, c0, ctx->adj, ctx->adj_cur, c0b);
-    hipLaunchKernelGGL((k_adj_init_b<L>), grid(ctx), block(), 0, ctx->stream, g, ctx->adj, phi0b);
+                       phi0, c0, ctx->adj.set[a], ctx->adj.set[b], ctx->adj, c0b);
+    hipLaunchKernelGGL((k_adj_init_b<L>), grid(ctx), block(), 0, ctx->stream, g, ctx->adj.set[b],
+                       phi0b);
     hipLaunchKernelGGL(k_adj_reduce, dim3(kDiagBlocks), dim3(kDiagThreads), 0, ctx->stream,
                        (const double*)ctx->adj.lamb, (const double*)ctx->adj.dlb, g.N, ctx->adj.red);
     hipLaunchKernelGGL(k_adj_reduce_final, dim3(1), dim3(64), 0, ctx->stream,
@@ -675,18 +674,15 @@ int gplbm_adjoint_begin(gplbm_ctx* ctx, void* work, uint64_t bytes, const double
   char* b = (char*)work;
   AdjWork& w = ctx->adj;
   for (int a = 0; a < 2; ++a) {
-    w.Gb[a] = (double*)b; b += l.pop;
-    w.Hb[a] = (double*)b; b += l.pop;
-    w.Pb[a] = (double*)b; b += l.fld;
+    w.set[a].A1 = (double*)b; b += l.pop;
+    w.set[a].B1 = (double*)b; b += l.pop;
+    w.set[a].B2 = (double*)b; b += l.fld;
+    w.set[a].B3 = (double*)b; b += l.vec;
+    w.set[a].B4 = (double*)b; b += l.fld;
   }
-  w.A1 = (double*)b; b += l.pop;
   w.A2 = (double*)b; b += l.vec;
   w.A3 = (double*)b; b += l.fld;
   w.A4 = (double*)b; b += l.fld;
-  w.B1 = (double*)b; b += l.pop;
-  w.B2 = (double*)b; b += l.fld;
-  w.B3 = (double*)b; b += l.vec;
-  w.B4 = (double*)b; b += l.fld;
   w.lamb = (double*)b; b += l.fld;
   w.dlb = (double*)b; b += l.fld;
   w.red = (double*)b;

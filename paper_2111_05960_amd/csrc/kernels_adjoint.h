@@ -10,19 +10,18 @@
 // differentiated by hand at the forward values, which the reverse kernels
 // recompute from S_n and S_{n+1}.
 //
-// Three kernels per reverse step (each node reads its neighbours only through
+// Two kernels per reverse step (each node reads its neighbours only through
 // the previous kernel's output):
-//   ra: reverse of the g collision of step n+1 at every node: adjoint of the
-//       pulled g~^{n+1} (A1), of grad phi^{n+1} (A2), of c^{n+1} (A3) and the
-//       local part of the adjoint of phi^{n+1} (A4);
-//   rb: adjoint of h~*^n (own Hb' plus c^{n+1} from the neighbour it streams
-//       to), total adjoint of phi^{n+1} (own, A4, stencil transpose of A2),
-//       reverse of the h collision of step n and of
-//       phi^{n+1} = sum g~^{n+1} + S^n / 2: adjoint of the pulled h~^n (B1),
-//       of phi^{n+1} (B2), of grad phi^n (B3), local part of the adjoint of
-//       phi^n (B4);
-//   rc: transposes of the pulls and of the gradient stencil: the adjoint of
-//       S_n.
+//   ra: gathers the adjoint of G' from the previous reverse step, then the
+//       reverse of the g collision of step n+1: adjoint of the pulled
+//       g~^{n+1} (A1), of grad phi^{n+1} (A2), of c^{n+1} (A3) and the local
+//       part of the adjoint of phi^{n+1} (A4);
+//   rb: adjoint of h~*^n (gathered from the previous step, plus c^{n+1} from
+//       the node it streams to), total adjoint of phi^{n+1} (gathered, A4,
+//       stencil transpose of A2), reverse of the h collision of step n and of
+//       phi^{n+1} = sum g~^{n+1} + S^n / 2: B1, B2, B3, B4.
+// The transposes of the pulls and of the gradient stencil are done as gathers
+// by the consumer, so the adjoint of a state is never written out.
 // Parameters are held fixed except lambda and D_l (gamma, M_phi, W and a do
 // not follow D_l).
 #pragma once
@@ -31,14 +30,25 @@
 
 namespace gplbm {
 
+// Intermediates of one reverse step that the next one (or the reverse of the
+// initialisation) gathers from; double-buffered by step parity.  The adjoint
+// of the state S_n is never materialised: its G, H and PHI parts are the
+// gathers  Gb(slot) = A1(dest) + B2(dest),  Hb(slot) = B1(dest),
+// Pb = B4 + stencil transpose of B3  (dest = the node and population that
+// pull the slot).
+struct AdjSet {
+  double* A1;  // Q*N: adjoint of the pulled g~^{n+1}
+  double* B1;  // Q*N: adjoint of the pulled h~^n
+  double* B2;  // N:   adjoint of phi^{n+1} (every pulled g adds to it)
+  double* B3;  // 3*N: adjoint of grad phi^n
+  double* B4;  // N:   local adjoint of phi^n
+};
+
 struct AdjWork {
-  double* Gb[2];  // adjoint of G  (plane-major Q layout)
-  double* Hb[2];  // adjoint of H
-  double* Pb[2];  // adjoint of PHI
-  double *A1, *A2, *A3, *A4;  // A1: Q*N, A2: 3*N, A3: N, A4: N
-  double *B1, *B2, *B3, *B4;  // B1: Q*N, B2: N, B3: 3*N, B4: N
-  double *lamb, *dlb;         // per-node accumulators of dJ/dlambda, dJ/dD_l
-  double* red;                // reduction scratch
+  AdjSet set[2];
+  double *A2, *A3, *A4;  // 3*N, N, N: adjoint of grad phi^{n+1}, c^{n+1}, local phi^{n+1}
+  double *lamb, *dlb;    // per-node accumulators of dJ/dlambda, dJ/dD_l
+  double* red;           // reduction scratch
 };
 
 struct FwdState {
@@ -194,10 +204,17 @@ __device__ __forceinline__ double stencil_adj_gather(const Geo& g, const double*
 
 // --------------------------------------------------------------------------
 
+// Adjoint of G' in slot (k, x, y, z), gathered from the previous set.
+template <class L>
+__device__ __forceinline__ double gather_Gb(const Geo& g, const AdjSet& P, int k, int x, int y, int z) {
+  int dx, dy, dz;
+  const int kk = push_dest<L>(g, k, x, y, z, dx, dy, dz);
+  return P.A1[pop_index<L>(g, kk, dx, dy, dz)] + P.B2[node_index(g, dx, dy, dz)];
+}
+
 template <class L>
 __global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> K, double lam_M_W2,
-                                                FwdState S1, const double* __restrict__ Gb1,
-                                                AdjWork w) {
+                                                FwdState S1, AdjSet P, AdjSet C, AdjWork w) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
@@ -209,8 +226,8 @@ __global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> K, double la
   double phi_b = 0.0, mu_b = 0.0, nb[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
-    const double a = Gb1[pop_index<L>(g, k, x, y, z)];
-    w.A1[pop_index<L>(g, k, x, y, z)] = (1.0 - om) * a;
+    const double a = gather_Gb<L>(g, P, k, x, y, z);
+    C.A1[pop_index<L>(g, k, x, y, z)] = (1.0 - om) * a;
     Gb[k] = (1.0 - 0.5 * om) * a;
     phi_b += om * L::w[k] * a;
   }
@@ -226,9 +243,8 @@ __global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> K, double la
 
 template <class L>
 __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> K, double lam_M_W2,
-                                                FwdState S0, FwdState S1,
-                                                const double* __restrict__ Hb1,
-                                                const double* __restrict__ Pb1, AdjWork w) {
+                                                FwdState S0, FwdState S1, AdjSet P, AdjSet C,
+                                                AdjWork w) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
@@ -239,11 +255,12 @@ __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> K, double la
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
     int dx, dy, dz;
-    push_dest<L>(g, k, x, y, z, dx, dy, dz);
-    Hb[k] = Hb1[pop_index<L>(g, k, x, y, z)] + w.A3[node_index(g, dx, dy, dz)];
+    const int kk = push_dest<L>(g, k, x, y, z, dx, dy, dz);
+    Hb[k] = P.B1[pop_index<L>(g, kk, dx, dy, dz)] + w.A3[node_index(g, dx, dy, dz)];
   }
   // adjoint of phi^{n+1} at this node
-  double p1b = Pb1[i] + w.A4[i] + stencil_adj_gather<L>(g, w.A2, x, y, z);
+  double p1b = P.B4[i] + stencil_adj_gather<L>(g, P.B3, x, y, z) + w.A4[i] +
+               stencil_adj_gather<L>(g, w.A2, x, y, z);
   // forward quantities of step n
   const NodeFwd<L> f = node_fwd<L>(g, K, S0, x, y, z);
   const double phi1 = S1.PHI[i];
@@ -294,50 +311,34 @@ __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> K, double la
   c_b += mu_b;
   phi_b += (K.cs - K.cl) * mu_b;
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k) w.B1[pop_index<L>(g, k, x, y, z)] = hb[k] + c_b;
-  w.B2[i] = p1b;
-  for (int a = 0; a < 3; ++a) w.B3[a * g.N + i] = gb[a];
-  w.B4[i] = phi_b;
+  for (int k = 0; k < L::Q; ++k) C.B1[pop_index<L>(g, k, x, y, z)] = hb[k] + c_b;
+  C.B2[i] = p1b;
+  for (int a = 0; a < 3; ++a) C.B3[a * g.N + i] = gb[a];
+  C.B4[i] = phi_b;
   w.lamb[i] += lb;
   w.dlb[i] += dl_b;
 }
 
-template <class L>
-__global__ void __launch_bounds__(256) k_adj_rc(Geo g, AdjWork w, double* __restrict__ Gb0,
-                                                double* __restrict__ Hb0, double* __restrict__ Pb0) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= g.nx || y >= g.ny) return;
-  const int64_t i = node_index(g, x, y, z);
-#pragma unroll
-  for (int k = 0; k < L::Q; ++k) {
-    int dx, dy, dz;
-    const int kk = push_dest<L>(g, k, x, y, z, dx, dy, dz);
-    const int64_t d = node_index(g, dx, dy, dz);
-    Hb0[pop_index<L>(g, k, x, y, z)] = w.B1[pop_index<L>(g, kk, dx, dy, dz)];
-    Gb0[pop_index<L>(g, k, x, y, z)] = w.A1[pop_index<L>(g, kk, dx, dy, dz)] + w.B2[d];
-  }
-  Pb0[i] = w.B4[i] + stencil_adj_gather<L>(g, w.B3, x, y, z);
-}
-
-// Seed: adjoint of S_K from dJ/dphi^K and dJ/dc^K (c^K = sum of pulled H).
+// Seed: the adjoint of S_K from dJ/dphi^K and dJ/dc^K (c^K = sum of the
+// pulled H), written as a set the first reverse step gathers from:
+// Gb = 0, Hb(slot) = dJ/dc^K(dest), Pb = dJ/dphi^K.
 template <class L>
 __global__ void __launch_bounds__(256) k_adj_seed(Geo g, const double* __restrict__ phib,
-                                                  const double* __restrict__ cb, AdjWork w, int a) {
+                                                  const double* __restrict__ cb, AdjSet P, AdjWork w) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= g.nx || y >= g.ny) return;
   const int64_t i = node_index(g, x, y, z);
+  const double cv = cb ? cb[i] : 0.0;
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
-    int dx, dy, dz;
-    push_dest<L>(g, k, x, y, z, dx, dy, dz);
-    w.Hb[a][pop_index<L>(g, k, x, y, z)] = cb ? cb[node_index(g, dx, dy, dz)] : 0.0;
-    w.Gb[a][pop_index<L>(g, k, x, y, z)] = 0.0;
+    P.A1[pop_index<L>(g, k, x, y, z)] = 0.0;
+    P.B1[pop_index<L>(g, k, x, y, z)] = cv;
   }
-  w.Pb[a][i] = phib ? phib[i] : 0.0;
+  P.B2[i] = 0.0;
+  for (int a = 0; a < 3; ++a) P.B3[a * g.N + i] = 0.0;
+  P.B4[i] = phib ? phib[i] : 0.0;
   w.lamb[i] = 0.0;
   w.dlb[i] = 0.0;
 }
@@ -348,8 +349,8 @@ __global__ void __launch_bounds__(256) k_adj_seed(Geo g, const double* __restric
 template <class L>
 __global__ void __launch_bounds__(256) k_adj_init_a(Geo g, Coef<double> K, double lam_M_W2,
                                                     const double* __restrict__ phi0,
-                                                    const double* __restrict__ c0, AdjWork w, int a,
-                                                    double* __restrict__ c0b) {
+                                                    const double* __restrict__ c0, AdjSet P,
+                                                    AdjSet C, AdjWork w, double* __restrict__ c0b) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
@@ -378,13 +379,14 @@ __global__ void __launch_bounds__(256) k_adj_init_a(Geo g, Coef<double> K, doubl
   const double mu = closure(K.cl, K.cs, K.mueq, c, phi);
   // adjoints of the pulled h~^0 (from H of S_0) and of G of S_0
   double hb[L::Q], Gb[L::Q], g0b[L::Q];
-  double phi_b = w.Pb[a][i], mu_b = 0.0, mu0_b = 0.0, nb[3] = {0.0, 0.0, 0.0};
+  double phi_b = P.B4[i] + stencil_adj_gather<L>(g, P.B3, x, y, z);
+  double mu_b = 0.0, mu0_b = 0.0, nb[3] = {0.0, 0.0, 0.0};
   double lb = 0.0;
   const double om = K.omega_g;
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
-    hb[k] = pull<L>(g, (const double*)w.Hb[a], k, x, y, z);
-    const double gsb = w.Gb[a][pop_index<L>(g, k, x, y, z)];
+    hb[k] = P.B1[pop_index<L>(g, k, x, y, z)];  // pull of the gathered Hb
+    const double gsb = gather_Gb<L>(g, P, k, x, y, z);
     g0b[k] = (1.0 - om) * gsb;
     Gb[k] = (1.0 - 0.5 * om) * gsb;
     phi_b += om * L::w[k] * gsb;
@@ -432,20 +434,20 @@ __global__ void __launch_bounds__(256) k_adj_init_a(Geo g, Coef<double> K, doubl
   cin_b += mu0_b;
   phi_b += (K.cs - K.cl) * mu0_b;
   c0b[i] = cin_b;
-  w.B4[i] = phi_b;
-  for (int d = 0; d < 3; ++d) w.B3[d * g.N + i] = gb[d];
+  C.B4[i] = phi_b;
+  for (int d = 0; d < 3; ++d) C.B3[d * g.N + i] = gb[d];
   w.lamb[i] += lb;
   w.dlb[i] += dl_b;
 }
 
 template <class L>
-__global__ void __launch_bounds__(256) k_adj_init_b(Geo g, AdjWork w, double* __restrict__ phi0b) {
+__global__ void __launch_bounds__(256) k_adj_init_b(Geo g, AdjSet C, double* __restrict__ phi0b) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= g.nx || y >= g.ny) return;
   const int64_t i = node_index(g, x, y, z);
-  phi0b[i] = w.B4[i] + stencil_adj_gather<L>(g, w.B3, x, y, z);
+  phi0b[i] = C.B4[i] + stencil_adj_gather<L>(g, C.B3, x, y, z);
 }
 
 // Deterministic sum of the two per-node accumulators (fixed launch shape).
