@@ -259,7 +259,8 @@ struct DevOps {
       const int a = ctx->cur, b = 1 - a;
       const DevStep st{state(ctx, a), state(ctx, b)};
       if (ctx->sched == GPLBM_SCHED_FUSED) {
-        DevFused3D<Codec>::launch(g, K, st, ctx->stream);
+        if (DevFused3D<Codec>::launch(g, K, st, ctx->stream))
+          return fail(ctx, GPLBM_E_DEVICE, "fused step launch failed");
       } else {
         hipLaunchKernelGGL((k_dev_split_h<Codec>), grid(ctx), block(), 0, ctx->stream, g, K, st);
         hipLaunchKernelGGL((k_dev_split_g<Codec>), grid(ctx), block(), 0, ctx->stream, g, K, st);

@@ -362,8 +362,12 @@ __global__ void __launch_bounds__(kDiagThreads) k_dev_diag_partial(Geo g, DevSta
 }
 
 // ---------------------------------------------------------------------------
+#ifndef GPLBM_DEV_TY
+#define GPLBM_DEV_TY 9
+#endif
+
 // Fused z-marching schedule in the deviation format (periodic domains).  Same
-// structure as k_fused3d; in addition a 3-plane LDS ring holds Lambda^{n-1}
+// structure as k_fused3d (x-aligned tiles, persistent grid, carry in registers); in addition a 3-plane LDS ring holds Lambda^{n-1}
 // on T+2 for the h references, and the phi^n ring serves the g references.
 
 __device__ __forceinline__ uint16_t bload16(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
@@ -375,29 +379,33 @@ __device__ __forceinline__ void bstore16_nt(uint16_t v, __amdgpu_buffer_rsrc_t r
   __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(V, v), r, voff, soff, 2);
 }
 
-template <int BX, int BY, int ZC, class Codec>
-__global__ void __launch_bounds__(BX* BY) k_dev_fused3d(Geo g, Coef<float> K, DevStep b,
-                                                        int tiles_x, int tiles_xy, int ntiles) {
+template <int TX, int TY, int ZC, class Codec>
+__global__ void __launch_bounds__((TileShape<TX, TY>::NT))
+    k_dev_fused3d(Geo g, Coef<float> K, DevStep b, int tiles_x, int tiles_xy, int ntiles) {
+  using Shape = TileShape<TX, TY>;
   constexpr int Q = 19;
-  constexpr int TX = BX - 2, TY = BY - 2;
+  constexpr int BX = Shape::BX, BY = Shape::BY;
   constexpr int AX = BX + 2, AY = BY + 2;
+  constexpr int NT = Shape::NT;
   __shared__ float phiA[3][AY][AX];  // phi^n, planes p-1, p, p+1
   __shared__ float lamA[3][AY][AX];  // Lambda^{n-1}, planes p-1, p, p+1
   __shared__ float phiB[3][BY][BX];  // phi^{n+1}, planes p-2, p-1, p
   __shared__ double acc[3][BY][BX];  // c^{n+1}
 
-  const int tile = xcd_tile(blockIdx.x, ntiles);
-  const int chunk = tile / tiles_xy, txy = tile % tiles_xy;
-  const int X0 = (txy % tiles_x) * TX, Y0 = (txy / tiles_x) * TY;
-  const int z0 = chunk * ZC, z1 = min(z0 + ZC, g.nz);
-  const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
+  int tx, ty;
+  bool valid;
+  Shape::node(threadIdx.x, tx, ty, valid);
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int plane = nx * ny;
   const uint32_t planeB = uint32_t(plane) * 2u;            // one 16-bit population plane
   const int64_t groupB = int64_t(plane) * kMov * 2;        // one z group of moving populations
 
+  for (int tile = first_tile(); tile < ntiles; tile += gridDim.x) {
+  const int chunk = tile / tiles_xy, txy = tile % tiles_xy;
+  const int X0 = (txy % tiles_x) * TX, Y0 = (txy / tiles_x) * TY;
+  const int z0 = chunk * ZC, z1 = min(z0 + ZC, nz);
   const int ux = X0 - 1 + tx, uy = Y0 - 1 + ty;
-  const bool out = ux < nx && uy < ny && tx >= 1 && tx <= TX && ty >= 1 && ty <= TY;
+  const bool out = valid && ux < nx && uy < ny && tx >= 1 && tx <= TX && ty >= 1 && ty <= TY;
   const int x = wrap_coord(ux, nx), y = wrap_coord(uy, ny);
   const int xo[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
   const int yo[3] = {(y == 0 ? ny - 1 : y - 1) * nx, y * nx, (y == ny - 1 ? 0 : y + 1) * nx};
@@ -411,7 +419,7 @@ __global__ void __launch_bounds__(BX* BY) k_dev_fused3d(Geo g, Coef<float> K, De
 
   auto load_tiles = [&](int p) {
     const int64_t zoff = (int64_t)wrap_coord(p, nz) * plane;
-    for (int l = threadIdx.x; l < AX * AY; l += BX * BY) {
+    for (int l = threadIdx.x; l < AX * AY; l += NT) {
       const int lx = l % AX, ly = l / AX;
       const int gx = wrap_coord(X0 - 2 + lx, nx), gy = wrap_coord(Y0 - 2 + ly, ny);
       phiA[ring3(p)][ly][lx] = b.cur.PHI[zoff + gy * nx + gx];
@@ -480,7 +488,7 @@ __global__ void __launch_bounds__(BX* BY) k_dev_fused3d(Geo g, Coef<float> K, De
     gradient_normal<LD, float>(atA, K.eps2, gr, n);
     const float sbar = source_moment<float>(K, phi, mu);
     const float phin = float(sg + 0.5 * double(sbar));
-    phiB[sA][ty][tx] = phin;
+    if (valid) phiB[sA][ty][tx] = phin;
     float F[3];
     h_flux<LD, float>(K, mu, gr, n, phin - phi, K.anti_trapping != 0, F);
     const float lam = h_lambda<float>(K, phi, mu);
@@ -511,7 +519,7 @@ __global__ void __launch_bounds__(BX* BY) k_dev_fused3d(Geo g, Coef<float> K, De
       if (j < 5 && up_ok) {
         const int k = j;
         const int tx2 = tx + LD::ex[k], ty2 = ty + LD::ey[k];
-        if (tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
+        if (valid && tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
           double& a = acc[ring3(p + 1)][ty2][tx2];
           a = k == 0 ? double(hdec[k]) : a + double(hdec[k]);
         }
@@ -519,7 +527,7 @@ __global__ void __launch_bounds__(BX* BY) k_dev_fused3d(Geo g, Coef<float> K, De
       if (own_p) {
         const int k = 5 + j;
         const int tx2 = tx + LD::ex[k], ty2 = ty + LD::ey[k];
-        if (tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
+        if (valid && tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
           double& a = acc[sA][ty2][tx2];
           a = a + double(hdec[k]);
         }
@@ -527,7 +535,7 @@ __global__ void __launch_bounds__(BX* BY) k_dev_fused3d(Geo g, Coef<float> K, De
       if (j < 5 && dn_ok) {
         const int k = 14 + j;
         const int tx2 = tx + LD::ex[k], ty2 = ty + LD::ey[k];
-        if (tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
+        if (valid && tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
           double& a = acc[ring3(p - 1)][ty2][tx2];
           a = a + double(hdec[k]);
         }
@@ -562,19 +570,26 @@ __global__ void __launch_bounds__(BX* BY) k_dev_fused3d(Geo g, Coef<float> K, De
 #pragma unroll
     for (int k = 0; k < Q; ++k) g_old[k] = g_new[k];
   }
+  __syncthreads();  // the LDS rings are refilled by the next tile
+  }
 }
 
 template <class Codec>
 struct DevFused3D {
-  static void launch(const Geo& g, const Coef<float>& K, const DevStep& b, hipStream_t st) {
-    constexpr int BX = 64, BY = 8, ZC = 32;
-    const int tiles_x = (g.nx + BX - 3) / (BX - 2);
-    const int tiles_y = (g.ny + BY - 3) / (BY - 2);
+  static int launch(const Geo& g, const Coef<float>& K, const DevStep& b, hipStream_t st) {
+    constexpr int TX = 64, TY = GPLBM_DEV_TY, ZC = 32;
+    constexpr int NT = TileShape<TX, TY>::NT;
+    auto kernel = k_dev_fused3d<TX, TY, ZC, Codec>;
+    const int tiles_x = (g.nx + TX - 1) / TX;
+    const int tiles_y = (g.ny + TY - 1) / TY;
     const int chunks = (g.nz + ZC - 1) / ZC;
     const int tiles_xy = tiles_x * tiles_y;
     const int ntiles = tiles_xy * chunks;
-    hipLaunchKernelGGL((k_dev_fused3d<BX, BY, ZC, Codec>), dim3(ntiles), dim3(BX * BY), 0, st, g,
-                       K, b, tiles_x, tiles_xy, ntiles);
+    static int resident[64] = {0};
+    const int grid = resident_grid(kernel, NT, ntiles, resident);
+    if (grid <= 0) return -1;
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(NT), 0, st, g, K, b, tiles_x, tiles_xy, ntiles);
+    return 0;
   }
 };
 

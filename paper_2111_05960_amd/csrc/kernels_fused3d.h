@@ -1,9 +1,9 @@
 // Fused schedule for D3Q19: one kernel per time step n -> n+1, marching in z.
 //
-// A block owns an x-y output tile T of (BX-2) x (BY-2) nodes and a chunk of
-// ZC planes, and runs one thread per node of the tile grown by one node in x
-// and y (T+1).  It walks the planes p = z0-1 .. z1 (one halo plane below and
-// above the chunk).  At plane p every thread
+// A block owns an x-y output tile T of TX x TY nodes and a chunk of ZC planes,
+// and computes the tile grown by one node in x and y (the region, BX x BY).
+// It walks the planes p = z0-1 .. z1 (one halo plane below and above the
+// chunk).  At plane p every thread
 //   - pulls h~^n (-> c^n, mu^n) and g~^{n+1} (-> phi^{n+1}),
 //   - takes phi^n of planes p-1, p, p+1 from a 3-plane LDS ring (T+2 in x-y)
 //     for the gradient, writes phi^{n+1}(p) into a second ring,
@@ -15,7 +15,18 @@
 // populations in index order across the three planes, the order of a pull.
 // After plane p, c^{n+1}(p-1) is complete and the threads of T run the g
 // collision of step n+1 at plane p-1, on the g~^{n+1} pulled one plane
-// earlier (kept in registers, or pulled again from the cache).
+// earlier (kept in registers, or in LDS where registers are short).
+//
+// Tiles are x-aligned: TX is a multiple of 64, tile origins are multiples of
+// TX, so every output row is a run of whole 128-byte lines and its stores are
+// full-line writes (partial-line writes cost about a third of the write
+// bandwidth).  Thread l < TX*BY takes region node (1 + l % TX, l / TX), one
+// wavefront per region row; the next 2*BY threads take the two halo columns.
+//
+// The grid is persistent: one block per resident slot, and in each round the
+// slots of an XCD (block b runs on XCD b mod 8) take consecutive tiles, so
+// that neighbouring tiles march in step and the lines of their shared halo are
+// still in the L2 when the second tile reads them.
 //
 // Addressing: with the plane-major layout f[z][k][y][x] every population a
 // thread pulls lies in one of three plane groups (z-1, z, z+1).  Each group is
@@ -26,10 +37,6 @@
 // Only periodic domains take this path (a wall would bounce some +z
 // populations into a plane one step later than the index order allows); the
 // split schedule serves the others.
-//
-// HBM traffic per node and step is the algorithmic minimum (2Q reads, 2Q
-// writes, phi read and write).  The x-y halo ring and the two halo planes are
-// recomputed; their pulls hit the L2.
 #pragma once
 
 #include "kernels_fused2d.h"
@@ -37,16 +44,6 @@
 namespace gplbm {
 
 __device__ __forceinline__ int ring3(int q) { return (q + 6) % 3; }
-
-#ifndef GPLBM_F3_REPULL
-#define GPLBM_F3_REPULL 0
-#endif
-#ifndef GPLBM_F3_MINBLOCKS
-#define GPLBM_F3_MINBLOCKS 1
-#endif
-#ifndef GPLBM_F3_PREFETCH
-#define GPLBM_F3_PREFETCH 0
-#endif
 
 // Raw buffer access: a resource (base, byte range) held in scalar registers,
 // a 32-bit per-lane offset and a 32-bit uniform offset.  Offsets outside the
@@ -80,240 +77,277 @@ __device__ __forceinline__ void bstore_nt(S v, __amdgpu_buffer_rsrc_t r, uint32_
   }
 }
 
-template <int BX, int BY, int ZC, class S, class C>
-__global__ void __launch_bounds__(BX* BY, GPLBM_F3_MINBLOCKS)
+// Region of an x-aligned tile and the thread -> node map described above.
+template <int TX_, int TY_>
+struct TileShape {
+  static constexpr int TX = TX_, TY = TY_;
+  static constexpr int BX = TX + 2, BY = TY + 2;
+  static constexpr int kMain = TX * BY;
+  static constexpr int kNodes = kMain + 2 * BY;
+  static constexpr int NT = (kNodes + 63) / 64 * 64;
+  static_assert(TX % 64 == 0, "output rows are whole wavefronts");
+  static_assert(NT <= 1024, "block size");
+  // region node (tx, ty) of thread l; threads past the region are not valid
+  // and shadow node (0, 0)
+  __device__ static void node(int l, int& tx, int& ty, bool& valid) {
+    if (l < kMain) {
+      tx = 1 + l % TX;
+      ty = l / TX;
+      valid = true;
+    } else {
+      const int j = l - kMain;
+      valid = j < 2 * BY;
+      const int jj = valid ? j : 0;
+      tx = jj < BY ? 0 : BX - 1;
+      ty = jj % BY;
+    }
+  }
+};
+
+// Resident grid of a persistent kernel: blocks per CU x CUs, a multiple of
+// the XCD count, no more than the tiles need.  Cached per device in *cache.
+template <class Kern>
+inline int resident_grid(Kern kernel, int threads, int ntiles, int* cache) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return -1;
+  if (cache[dev] == 0) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        per_cu < 1 || cus < 1)
+      return -1;
+    cache[dev] = max(kNumXcd, (per_cu * cus) / kNumXcd * kNumXcd);
+  }
+  return min(cache[dev], (ntiles + kNumXcd - 1) / kNumXcd * kNumXcd);
+}
+
+// First tile of block b in round 0 (the slots of an XCD take consecutive tiles).
+__device__ __forceinline__ int first_tile() {
+  const int slots = gridDim.x / kNumXcd;
+  return (blockIdx.x % kNumXcd) * slots + blockIdx.x / kNumXcd;
+}
+
+// Carry of the pulled g~^{n+1} from its plane to the collision one plane
+// later: in registers, or in two LDS buffers (by plane parity) written right
+// after the pull, which frees 2Q registers in FP64.
+enum class Carry { kRegisters, kLds };
+
+template <class S>
+struct Fused3DConfig;
+template <>
+struct Fused3DConfig<double> {
+  static constexpr int TX = 64, TY = 6, ZC = 32;
+  static constexpr Carry carry = Carry::kLds;
+};
+template <>
+struct Fused3DConfig<float> {
+  static constexpr int TX = 64, TY = 12, ZC = 32;
+  static constexpr Carry carry = Carry::kRegisters;
+};
+
+template <int TX, int TY, int ZC, Carry kCarryMode, class S, class C>
+__global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     k_fused3d(Geo g, Coef<C> K, StepBufs<S> b, int tiles_x, int tiles_xy, int ntiles) {
   using L = D3Q19;
+  using Shape = TileShape<TX, TY>;
   constexpr int Q = L::Q;
-  constexpr int TX = BX - 2, TY = BY - 2;
+  constexpr int BX = Shape::BX, BY = Shape::BY;
   constexpr int AX = BX + 2, AY = BY + 2;
-  constexpr int NT = BX * BY;
+  constexpr int NT = Shape::NT;
   constexpr int PHI_PER_THREAD = (AX * AY + NT - 1) / NT;
-  constexpr bool kCarry = GPLBM_F3_REPULL == 0;
-  constexpr int kPre = GPLBM_F3_PREFETCH;  // 0 none, 1 phi and h, 2 phi, h and g
+  constexpr bool kRegs = kCarryMode == Carry::kRegisters;
   __shared__ C phiA[3][AY][AX];      // phi^n, planes p-1, p, p+1
   __shared__ C phiB[3][BY][BX];      // phi^{n+1}, planes p-2, p-1, p
   __shared__ double acc[3][BY][BX];  // c^{n+1} being accumulated
+  // pulled g~^{n+1} of the output nodes by plane parity (LDS carry)
+  __shared__ C gkeep[kRegs ? 1 : 2][kRegs ? 1 : Q][kRegs ? 1 : TY][kRegs ? 1 : TX];
 
-  const int tile = xcd_tile(blockIdx.x, ntiles);
-  const int chunk = tile / tiles_xy, txy = tile % tiles_xy;
-  const int X0 = (txy % tiles_x) * TX, Y0 = (txy / tiles_x) * TY;
-  const int z0 = chunk * ZC, z1 = min(z0 + ZC, g.nz);
-  const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
+  int tx, ty;
+  bool valid;
+  Shape::node(threadIdx.x, tx, ty, valid);
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int plane = nx * ny;
-  const uint32_t planeB = uint32_t(plane) * sizeof(S);      // one population plane
-  const int64_t groupB = int64_t(plane) * Q * sizeof(S);    // one z plane group
+  const uint32_t planeB = uint32_t(plane) * sizeof(S);    // one population plane
+  const int64_t groupB = int64_t(plane) * Q * sizeof(S);  // one z plane group
 
-  const int ux = X0 - 1 + tx, uy = Y0 - 1 + ty;
-  const bool out = ux < nx && uy < ny && tx >= 1 && tx <= TX && ty >= 1 && ty <= TY;
-  const int x = wrap_coord(ux, nx), y = wrap_coord(uy, ny);
-  const int xo[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
-  const int yo[3] = {(y == 0 ? ny - 1 : y - 1) * nx, y * nx, (y == ny - 1 ? 0 : y + 1) * nx};
-  // byte offset, inside a population plane, of the source x - e_k (by e_x, e_y)
-  uint32_t xyb[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) xyb[a][c] = uint32_t(yo[a] + xo[c]) * sizeof(S);
-  const uint32_t selfB = xyb[1][1];
-  // phi^n tile positions this thread loads (T+2 in x-y)
-  uint32_t phi_off[PHI_PER_THREAD];
-#pragma unroll
-  for (int j = 0; j < PHI_PER_THREAD; ++j) {
-    const int l = min((int)threadIdx.x + j * NT, AX * AY - 1);
-    const int gx = wrap_coord(X0 - 2 + l % AX, nx), gy = wrap_coord(Y0 - 2 + l / AX, ny);
-    phi_off[j] = uint32_t(gy * nx + gx);
-  }
+  for (int tile = first_tile(); tile < ntiles; tile += gridDim.x) {
+    const int chunk = tile / tiles_xy, txy = tile % tiles_xy;
+    const int X0 = (txy % tiles_x) * TX, Y0 = (txy / tiles_x) * TY;
+    const int z0 = chunk * ZC, z1 = min(z0 + ZC, nz);
 
-  auto fetch_phi = [&](int p, S v[PHI_PER_THREAD]) {
-    const S* src = b.PHI + (int64_t)wrap_coord(p, nz) * plane;
+    const int ux = X0 - 1 + tx, uy = Y0 - 1 + ty;
+    const bool out = valid && ux < nx && uy < ny && tx >= 1 && tx <= TX && ty >= 1 && ty <= TY;
+    const int x = wrap_coord(ux, nx), y = wrap_coord(uy, ny);
+    const int xo[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
+    const int yo[3] = {(y == 0 ? ny - 1 : y - 1) * nx, y * nx, (y == ny - 1 ? 0 : y + 1) * nx};
+    // byte offset, inside a population plane, of the source x - e_k (by e_x, e_y)
+    uint32_t xyb[3][3];
 #pragma unroll
-    for (int j = 0; j < PHI_PER_THREAD; ++j) v[j] = src[phi_off[j]];
-  };
-  auto store_phi = [&](int p, const S v[PHI_PER_THREAD]) {
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xyb[a][c] = uint32_t(yo[a] + xo[c]) * sizeof(S);
+    const uint32_t selfB = xyb[1][1];
+    // phi^n tile positions this thread loads (T+2 in x-y)
+    uint32_t phi_off[PHI_PER_THREAD];
 #pragma unroll
     for (int j = 0; j < PHI_PER_THREAD; ++j) {
-      const int l = threadIdx.x + j * NT;
-      if (l < AX * AY) phiA[ring3(p)][l / AX][l % AX] = C(v[j]);
+      const int l = min((int)threadIdx.x + j * NT, AX * AY - 1);
+      const int gx = wrap_coord(X0 - 2 + l % AX, nx), gy = wrap_coord(Y0 - 2 + l / AX, ny);
+      phi_off[j] = uint32_t(gy * nx + gx);
     }
-  };
-  // pulls of plane p: population k at (x, y, z_p) comes from plane group z_p - e_z
-  auto fetch_pop = [&](const S* base, int p, S v[Q]) {
-    const int zp = wrap_coord(p, nz);
-    const int zs[3] = {(zp == 0 ? nz - 1 : zp - 1), zp, (zp == nz - 1 ? 0 : zp + 1)};
-    __amdgpu_buffer_rsrc_t R[3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-      R[j] = make_rsrc(reinterpret_cast<const char*>(base) + zs[j] * groupB, uint32_t(groupB));
-#pragma unroll
-    for (int k = 0; k < Q; ++k)
-      v[k] = bload<S>(R[1 - L::ez[k]], xyb[1 - L::ey[k]][1 - L::ex[k]], k * planeB);
-  };
-
-  {
-    S v[PHI_PER_THREAD];
-    fetch_phi(z0 - 2, v);
-    store_phi(z0 - 2, v);
-    fetch_phi(z0 - 1, v);
-    store_phi(z0 - 1, v);
-  }
-  S phi_nx[PHI_PER_THREAD];   // phi^n of plane p+1 (prefetched)
-  S h_nx[Q], g_nx[Q];         // pulls of plane p (prefetched)
-  if constexpr (kPre >= 1) {
-    fetch_phi(z0, phi_nx);
-    fetch_pop(b.H, z0 - 1, h_nx);
-    if constexpr (kPre >= 2) fetch_pop(b.G, z0 - 1, g_nx);
-  }
-
-  C g_old[kCarry ? Q : 1];
-#pragma unroll
-  for (int k = 0; k < (kCarry ? Q : 1); ++k) g_old[k] = C(0);
-
-  for (int p = z0 - 1; p <= z1; ++p) {
-    S hv[Q], gv[Q];
-    if constexpr (kPre >= 1) {
-      store_phi(p + 1, phi_nx);
-#pragma unroll
-      for (int k = 0; k < Q; ++k) hv[k] = h_nx[k];
-      if constexpr (kPre >= 2) {
-#pragma unroll
-        for (int k = 0; k < Q; ++k) gv[k] = g_nx[k];
-      }
-      __syncthreads();
-      // next plane's loads are in flight while this plane is computed
-      if (p + 1 <= z1) {
-        fetch_phi(p + 2, phi_nx);
-        fetch_pop(b.H, p + 1, h_nx);
-        if constexpr (kPre >= 2) fetch_pop(b.G, p + 1, g_nx);
-      }
-      if constexpr (kPre < 2) fetch_pop(b.G, p, gv);
-    } else {
+    auto load_phi = [&](int p) {
+      const S* src = b.PHI + (int64_t)wrap_coord(p, nz) * plane;
       S v[PHI_PER_THREAD];
-      fetch_phi(p + 1, v);
-      store_phi(p + 1, v);
+#pragma unroll
+      for (int j = 0; j < PHI_PER_THREAD; ++j) v[j] = src[phi_off[j]];
+#pragma unroll
+      for (int j = 0; j < PHI_PER_THREAD; ++j) {
+        const int l = threadIdx.x + j * NT;
+        if (l < AX * AY) phiA[ring3(p)][l / AX][l % AX] = C(v[j]);
+      }
+    };
+    // pulls of plane p: population k at (x, y, z_p) comes from plane group z_p - e_z
+    auto fetch_pop = [&](const S* base, int p, S v[Q]) {
+      const int zp = wrap_coord(p, nz);
+      const int zs[3] = {(zp == 0 ? nz - 1 : zp - 1), zp, (zp == nz - 1 ? 0 : zp + 1)};
+      __amdgpu_buffer_rsrc_t R[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        R[j] = make_rsrc(reinterpret_cast<const char*>(base) + zs[j] * groupB, uint32_t(groupB));
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+        v[k] = bload<S>(R[1 - L::ez[k]], xyb[1 - L::ey[k]][1 - L::ex[k]], k * planeB);
+    };
+
+    load_phi(z0 - 2);
+    load_phi(z0 - 1);
+    C g_old[kRegs ? Q : 1];
+#pragma unroll
+    for (int k = 0; k < (kRegs ? Q : 1); ++k) g_old[k] = C(0);
+
+    for (int p = z0 - 1; p <= z1; ++p) {
+      load_phi(p + 1);
       __syncthreads();
+      S hv[Q], gv[Q];
       fetch_pop(b.H, p, hv);
       fetch_pop(b.G, p, gv);
-    }
 
-    const int zp = wrap_coord(p, nz);
-    C h[Q];
-    C g_new[kCarry ? Q : 1];
-    double c = 0.0, sg = 0.0;
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      h[k] = C(hv[k]);
-      c = k == 0 ? double(hv[k]) : c + double(hv[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      if constexpr (kCarry) g_new[k] = C(gv[k]);
-      sg = k == 0 ? double(gv[k]) : sg + double(gv[k]);
-    }
-    const int sA = ring3(p);
-    const C phi = phiA[sA][ty + 1][tx + 1];
-    const C mu = C(closure(K.cl, K.cs, K.mueq, c, double(phi)));
-    auto atA = [&](int dx, int dy, int dz) -> C {
-      return phiA[ring3(p + dz)][ty + 1 + dy][tx + 1 + dx];
-    };
-    C gr[3], n[3];
-    gradient_normal<L, C>(atA, K.eps2, gr, n);
-    const C sbar = source_moment<C>(K, phi, mu);
-    const double phin = sg + 0.5 * double(sbar);
-    const C phin_c = C(phin);
-    phiB[sA][ty][tx] = phin_c;
-    const C dtphi = phin_c - phi;
-    C F[3];
-    h_flux<L, C>(K, mu, gr, n, dtphi, K.anti_trapping != 0, F);
-    const C lam = h_lambda<C>(K, phi, mu);
-    const C cc = C(c);
-    C hs[Q];
-#pragma unroll
-    for (int k = 0; k < Q; ++k)
-      hs[k] = C(S(h_collide<L, C>(K, k, h[k], h_eq<L, C>(k, cc, lam), h_source<L, C>(K, k, F))));
-
-    const bool own_p = p >= z0 && p < z1;
-    if (out && own_p) {
-      const auto Hw = make_rsrc(reinterpret_cast<char*>(b.Hn) + zp * groupB, uint32_t(groupB));
-#pragma unroll
-      for (int k = 0; k < Q; ++k) bstore_nt<S>(S(hs[k]), Hw, selfB, k * planeB);
-      __builtin_nontemporal_store(S(phin_c), &b.PHIn[(int64_t)zp * plane + y * nx + x]);
-    }
-
-    // in-block streaming of h* into the accumulator ring, 9 passes:
-    // pass j carries population j (e_z=+1, to plane p+1), population 5+j
-    // (e_z=0, to plane p) and population 14+j (e_z=-1, to plane p-1)
-    const bool up_ok = p + 1 >= z0 && p + 1 < z1, dn_ok = p - 1 >= z0 && p - 1 < z1;
-#pragma unroll
-    for (int j = 0; j < 9; ++j) {
-      if (j < 5 && up_ok) {
-        const int k = j;
-        const int tx2 = tx + L::ex[k], ty2 = ty + L::ey[k];
-        if (tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
-          double& a = acc[ring3(p + 1)][ty2][tx2];
-          a = k == 0 ? double(hs[k]) : a + double(hs[k]);
-        }
-      }
-      if (own_p) {
-        const int k = 5 + j;
-        const int tx2 = tx + L::ex[k], ty2 = ty + L::ey[k];
-        if (tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
-          double& a = acc[sA][ty2][tx2];
-          a = a + double(hs[k]);
-        }
-      }
-      if (j < 5 && dn_ok) {
-        const int k = 14 + j;
-        const int tx2 = tx + L::ex[k], ty2 = ty + L::ey[k];
-        if (tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
-          double& a = acc[ring3(p - 1)][ty2][tx2];
-          a = a + double(hs[k]);
-        }
-      }
-      __syncthreads();
-    }
-
-    // g collision of step n+1 at plane p-1
-    if (out && dn_ok) {
-      const int zq = wrap_coord(p - 1, nz);
-      const int sB = ring3(p - 1);
-      const double c1 = acc[sB][ty][tx];
-      const C phi1 = phiB[sB][ty][tx];
-      const C mu1 = C(closure(K.cl, K.cs, K.mueq, c1, double(phi1)));
-      auto atB = [&](int dx, int dy, int dz) -> C {
-        return phiB[ring3(p - 1 + dz)][ty + dy][tx + dx];
-      };
-      C gr1[3], n1[3];
-      gradient_normal<L, C>(atB, K.eps2, gr1, n1);
-      C G[Q];
-      phi_sources<L, C>(K, phi1, mu1, n1, G);
-      S gq[kCarry ? 1 : Q];
-      if constexpr (!kCarry) fetch_pop(b.G, p - 1, gq);
-      const auto Gw = make_rsrc(reinterpret_cast<char*>(b.Gn) + zq * groupB, uint32_t(groupB));
+      const int zp = wrap_coord(p, nz);
+      const bool own_p = p >= z0 && p < z1;
+      C h[Q];
+      C g_new[kRegs ? Q : 1];
+      double c = 0.0, sg = 0.0;
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
-        C gk;
-        if constexpr (kCarry)
-          gk = g_old[k];
-        else
-          gk = C(gq[k]);
-        bstore_nt<S>(S(g_collide<L, C>(K, k, gk, phi1, G[k])), Gw, selfB, k * planeB);
+        h[k] = C(hv[k]);
+        c = k == 0 ? double(hv[k]) : c + double(hv[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        if constexpr (kRegs) g_new[k] = C(gv[k]);
+        sg = k == 0 ? double(gv[k]) : sg + double(gv[k]);
+      }
+      if constexpr (!kRegs) {
+        if (out && own_p) {
+#pragma unroll
+          for (int k = 0; k < Q; ++k) gkeep[p & 1][k][ty - 1][tx - 1] = C(gv[k]);
+        }
+      }
+      const int sA = ring3(p);
+      const C phi = phiA[sA][ty + 1][tx + 1];
+      const C mu = C(closure(K.cl, K.cs, K.mueq, c, double(phi)));
+      auto atA = [&](int dx, int dy, int dz) -> C {
+        return phiA[ring3(p + dz)][ty + 1 + dy][tx + 1 + dx];
+      };
+      C gr[3], n[3];
+      gradient_normal<L, C>(atA, K.eps2, gr, n);
+      const C sbar = source_moment<C>(K, phi, mu);
+      const double phin = sg + 0.5 * double(sbar);
+      const C phin_c = C(phin);
+      if (valid) phiB[sA][ty][tx] = phin_c;
+      const C dtphi = phin_c - phi;
+      C F[3];
+      h_flux<L, C>(K, mu, gr, n, dtphi, K.anti_trapping != 0, F);
+      const C lam = h_lambda<C>(K, phi, mu);
+      const C cc = C(c);
+      C hs[Q];
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+        hs[k] = C(S(h_collide<L, C>(K, k, h[k], h_eq<L, C>(k, cc, lam), h_source<L, C>(K, k, F))));
+
+      if (out && own_p) {
+        const auto Hw = make_rsrc(reinterpret_cast<char*>(b.Hn) + zp * groupB, uint32_t(groupB));
+#pragma unroll
+        for (int k = 0; k < Q; ++k) bstore_nt<S>(S(hs[k]), Hw, selfB, k * planeB);
+        __builtin_nontemporal_store(S(phin_c), &b.PHIn[(int64_t)zp * plane + y * nx + x]);
+      }
+
+      // in-block streaming of h* into the accumulator ring, 9 passes:
+      // pass j carries population j (e_z=+1, to plane p+1), population 5+j
+      // (e_z=0, to plane p) and population 14+j (e_z=-1, to plane p-1)
+      const bool up_ok = p + 1 >= z0 && p + 1 < z1, dn_ok = p - 1 >= z0 && p - 1 < z1;
+#pragma unroll
+      for (int j = 0; j < 9; ++j) {
+        if (j < 5 && up_ok) {
+          const int k = j;
+          const int tx2 = tx + L::ex[k], ty2 = ty + L::ey[k];
+          if (valid && tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
+            double& a = acc[ring3(p + 1)][ty2][tx2];
+            a = k == 0 ? double(hs[k]) : a + double(hs[k]);
+          }
+        }
+        if (own_p) {
+          const int k = 5 + j;
+          const int tx2 = tx + L::ex[k], ty2 = ty + L::ey[k];
+          if (valid && tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
+            double& a = acc[sA][ty2][tx2];
+            a = a + double(hs[k]);
+          }
+        }
+        if (j < 5 && dn_ok) {
+          const int k = 14 + j;
+          const int tx2 = tx + L::ex[k], ty2 = ty + L::ey[k];
+          if (valid && tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
+            double& a = acc[ring3(p - 1)][ty2][tx2];
+            a = a + double(hs[k]);
+          }
+        }
+        __syncthreads();
+      }
+
+      // g collision of step n+1 at plane p-1
+      if (out && dn_ok) {
+        const int zq = wrap_coord(p - 1, nz);
+        const int sB = ring3(p - 1);
+        const double c1 = acc[sB][ty][tx];
+        const C phi1 = phiB[sB][ty][tx];
+        const C mu1 = C(closure(K.cl, K.cs, K.mueq, c1, double(phi1)));
+        auto atB = [&](int dx, int dy, int dz) -> C {
+          return phiB[ring3(p - 1 + dz)][ty + dy][tx + dx];
+        };
+        C gr1[3], n1[3];
+        gradient_normal<L, C>(atB, K.eps2, gr1, n1);
+        C G[Q];
+        phi_sources<L, C>(K, phi1, mu1, n1, G);
+        const auto Gw = make_rsrc(reinterpret_cast<char*>(b.Gn) + zq * groupB, uint32_t(groupB));
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          C gk;
+          if constexpr (kRegs)
+            gk = g_old[k];
+          else
+            gk = gkeep[(p - 1) & 1][k][ty - 1][tx - 1];
+          bstore_nt<S>(S(g_collide<L, C>(K, k, gk, phi1, G[k])), Gw, selfB, k * planeB);
+        }
+      }
+      if constexpr (kRegs) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) g_old[k] = g_new[k];
       }
     }
-    if constexpr (kCarry) {
-#pragma unroll
-      for (int k = 0; k < Q; ++k) g_old[k] = g_new[k];
-    }
+    __syncthreads();  // the LDS rings are refilled by the next tile
   }
 }
-
-#ifndef GPLBM_F3BX
-#define GPLBM_F3BX 64
-#define GPLBM_F3BY 8
-#define GPLBM_F3ZC 32
-#endif
-constexpr int kF3BX = GPLBM_F3BX, kF3BY = GPLBM_F3BY, kF3ZC = GPLBM_F3ZC;
 
 // 32-bit offsets inside a z plane group: Q * nx * ny * 8 bytes must fit.
 inline bool fused3d_supported(int nx, int ny, int nz, const int* bc) {
@@ -324,14 +358,19 @@ inline bool fused3d_supported(int nx, int ny, int nz, const int* bc) {
 template <class S, class C>
 struct Fused3D {
   static int launch(const Geo& g, const Coef<C>& K, const StepBufs<S>& b, hipStream_t st) {
-    constexpr int BX = kF3BX, BY = kF3BY, ZC = kF3ZC;
-    const int tiles_x = (g.nx + BX - 3) / (BX - 2);
-    const int tiles_y = (g.ny + BY - 3) / (BY - 2);
+    using Cfg = Fused3DConfig<S>;
+    constexpr int TX = Cfg::TX, TY = Cfg::TY, ZC = Cfg::ZC;
+    constexpr int NT = TileShape<TX, TY>::NT;
+    auto kernel = k_fused3d<TX, TY, ZC, Cfg::carry, S, C>;
+    const int tiles_x = (g.nx + TX - 1) / TX;
+    const int tiles_y = (g.ny + TY - 1) / TY;
     const int chunks = (g.nz + ZC - 1) / ZC;
     const int tiles_xy = tiles_x * tiles_y;
     const int ntiles = tiles_xy * chunks;
-    hipLaunchKernelGGL((k_fused3d<BX, BY, ZC, S, C>), dim3(ntiles), dim3(BX * BY), 0, st, g, K,
-                       b, tiles_x, tiles_xy, ntiles);
+    static int resident[64] = {0};
+    const int grid = resident_grid(kernel, NT, ntiles, resident);
+    if (grid <= 0) return -1;
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(NT), 0, st, g, K, b, tiles_x, tiles_xy, ntiles);
     return 0;
   }
 };
