@@ -362,8 +362,10 @@ __global__ void __launch_bounds__(kDiagThreads) k_dev_diag_partial(Geo g, DevSta
 }
 
 // ---------------------------------------------------------------------------
+// output rows per tile of the fused deviation kernel (64 x 13 outputs, 1024
+// threads at 4 waves per SIMD)
 #ifndef GPLBM_DEV_TY
-#define GPLBM_DEV_TY 9
+#define GPLBM_DEV_TY 13
 #endif
 
 // Fused z-marching schedule in the deviation format (periodic domains).  Same
