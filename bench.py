@@ -227,7 +227,8 @@ def summarize_profile(kind, dbs, out, workload, precision, schedule):
         for kname, counter, n, avg, tot in rows(db, "select kernel_name, counter_name, count(*), avg(value), sum(value) from counters_collection group by kernel_name, counter_name"):
             vals[(kname, counter)] = (n, avg)
             sums[(kname, counter)] = tot
-    step = [k for k in vals if "k_fused" in k[0] or "k_split" in k[0]]
+    step = [k for k in vals if any(t in k[0] for t in ("k_fused", "k_split", "k_dev_fused",
+                                                        "k_dev_split"))]
     copy = [k for k in sums if "neg" in k[0].lower()]
     fetch_copy = sum(v for k, v in sums.items() if k in copy and k[1] == "FETCH_SIZE")
     write_copy = sum(v for k, v in sums.items() if k in copy and k[1] == "WRITE_SIZE")
