@@ -19,6 +19,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# A prebuilt oracle library to load instead (the mutation check of the pins
+# runs them against deliberately broken copies of oracle.c).
+_LIB_OVERRIDE = os.environ.get("GPLBM_ORACLE_LIB")
 
 D2Q9, D3Q19 = 0, 1
 PERIODIC, ZERO_FLUX = 0, 1
@@ -44,12 +47,19 @@ class _Params(ctypes.Structure):
     ]
 
 
+def compile_library(src: str, out: str, quiet: bool = False) -> None:
+    """gcc, FP contraction off, OpenMP on."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-fPIC", "-shared", "-Wall", "-I", _HERE, "-o", out, src, "-lm"]
+    subprocess.run(cmd, check=True, capture_output=quiet)
+
+
 def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (FP contraction off, OpenMP on)."""
+    """Compile liboracle.so (unless a library override is set)."""
+    if _LIB_OVERRIDE:
+        return _LIB_OVERRIDE
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off",
-               "-fno-fast-math", "-fPIC", "-shared", "-Wall", "-o", _LIB, _SRC, "-lm"]
-        subprocess.run(cmd, check=True)
+        compile_library(_SRC, _LIB)
     return _LIB
 
 
@@ -59,9 +69,11 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        lib = ctypes.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            path = _LIB_OVERRIDE
+        else:
+            path = build(force=False)
+        lib = ctypes.CDLL(path)
         P = ctypes.POINTER
         dp = P(ctypes.c_double)
         lib.orc_create.restype = ctypes.c_void_p

@@ -35,3 +35,22 @@ def front_position(phi):
     zero-flux wall at x = -1/2: -1/2 + mean over y of sum_x (1 - phi)."""
     phi = np.asarray(phi)
     return -0.5 + (1.0 - phi).sum(axis=-1).mean()
+
+
+# Velocity sets in the population order of the oracle's state arrays: D2Q9 in
+# the paper's numbering (Sec. 3.1); D3Q19 grouped by e_z (+1, 0, -1), the
+# convention of this project (the paper does not number D3Q19).
+D2Q9_E = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [-1, 0, 0], [0, -1, 0],
+                   [1, 1, 0], [-1, 1, 0], [-1, -1, 0], [1, -1, 0]], dtype=np.float64)
+D3Q19_E = np.array([[0, 0, 1], [1, 0, 1], [-1, 0, 1], [0, 1, 1], [0, -1, 1],
+                    [0, 0, 0],
+                    [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0],
+                    [1, 1, 0], [-1, 1, 0], [-1, -1, 0], [1, -1, 0],
+                    [0, 0, -1], [-1, 0, -1], [1, 0, -1], [0, -1, -1], [0, 1, -1]],
+                   dtype=np.float64)
+
+
+def first_moment(f, lattice):
+    """sum_k e_k f_k for populations f of shape (Q, nz, ny, nx) -> (nz, ny, nx, 3)."""
+    e = D2Q9_E if lattice == 0 else D3Q19_E
+    return np.einsum("ka,k...->...a", e, f)

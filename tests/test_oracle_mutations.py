@@ -1,0 +1,168 @@
+"""Mutation check of the oracle's pins.
+
+Each entry below plants one plausible slip in a copy of oracle.c (a dropped
+term or factor, a flipped sign, a wrong index, a transposed operand, a wrong
+table entry), builds the copy, and runs the pins of test_oracle_pins.py
+against it.  Every mutant must make at least one pin fail: a pin set that
+lets one through does not pin that part of the oracle.  The shipped oracle
+is never modified; the mutants live in a temporary directory.
+"""
+import concurrent.futures
+import os
+import subprocess
+import sys
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+
+# (name, original text in oracle.c, replacement)
+MUTANTS = [
+    ("closure: phases swapped in c_co(phi)",
+     "double cco = (p->c_l_co * phi) + (p->c_s_co * (1.0 - phi));",
+     "double cco = (p->c_s_co * phi) + (p->c_l_co * (1.0 - phi));"),
+    ("closure: sign of c - c_co",
+     "return p->mu_eq + (c - cco);",
+     "return p->mu_eq + (cco - c);"),
+    ("gradient: factor 1/xi_s^2 = 3 dropped",
+     "g3[a] = 3.0 * acc[a];",
+     "g3[a] = acc[a];"),
+    ("gradient: central difference without 1/2",
+     "double dk = 0.5 * (phi_at(",
+     "double dk = 1.0 * (phi_at("),
+    ("gradient: difference reversed",
+     "(phi_at(s, f, x, y, z, s->e[k]) - phi_at(s, f, x, y, z, m))",
+     "(phi_at(s, f, x, y, z, m) - phi_at(s, f, x, y, z, s->e[k]))"),
+    ("gradient: weight w_k dropped",
+     "acc[a] = acc[a] + (s->w[k] * (double)s->e[k][a]) * dk;",
+     "acc[a] = acc[a] + ((double)s->e[k][a]) * dk;"),
+    ("normal: not normalised",
+     "n3[a] = g3[a] / den;",
+     "n3[a] = g3[a];"),
+    ("e_k . v: operand axes transposed",
+     "r = r + (double)s->e[k][a] * v[a];",
+     "r = r + (double)s->e[k][a] * v[s->D - 1 - a];"),
+    ("p'(phi): factor 6 dropped",
+     "double pprime = 6.0 * (phi * (1.0 - phi));",
+     "double pprime = (phi * (1.0 - phi));"),
+    ("G^st: sign flipped",
+     "double Gst = -((p->lambda * p->M_phi) / (p->W * p->W)) * Sphi;",
+     "double Gst = ((p->lambda * p->M_phi) / (p->W * p->W)) * Sphi;"),
+    ("G^st: W instead of W^2",
+     "double Gst = -((p->lambda * p->M_phi) / (p->W * p->W)) * Sphi;",
+     "double Gst = -((p->lambda * p->M_phi) / (p->W)) * Sphi;"),
+    ("counter term: sign flipped",
+     "G[k] = s->w[k] * (Gst + kphi * edot(s, k, n3));",
+     "G[k] = s->w[k] * (Gst - kphi * edot(s, k, n3));"),
+    ("counter term: 1/W instead of 4/W",
+     "double kphi = (4.0 / p->W) * (phi * (1.0 - phi));",
+     "double kphi = (1.0 / p->W) * (phi * (1.0 - phi));"),
+    ("double well: sign flipped",
+     "double Gdw = -((8.0 * p->M_phi) / (p->W * p->W)) * wdw;",
+     "double Gdw = ((8.0 * p->M_phi) / (p->W * p->W)) * wdw;"),
+    ("phi moment: source moment dropped (counter term)",
+     "*sbar = Gst;",
+     "*sbar = 0.0;"),
+    ("g collision: trapezoidal half source dropped",
+     "double t = (gk - s->w[k] * phi) + 0.5 * G[k];",
+     "double t = (gk - s->w[k] * phi);"),
+    ("g collision: half instead of full source",
+     "s->gs[k * N + i] = (gk - omega_g * t) + G[k];",
+     "s->gs[k * N + i] = (gk - omega_g * t) + 0.5 * G[k];"),
+    ("g relaxation: M = 3 tau instead of tau / 3",
+     "const double omega_g = 1.0 / (3.0 * p->M_phi + 0.5);",
+     "const double omega_g = 1.0 / (p->M_phi / 3.0 + 0.5);"),
+    ("h relaxation: tau_h = 1/gamma instead of 3/gamma",
+     "const double omega_h = 1.0 / (3.0 / p->gamma + 0.5);",
+     "const double omega_h = 1.0 / (1.0 / p->gamma + 0.5);"),
+    ("phi^{n+1}: half source moment dropped",
+     "s->phin[i] = sum + 0.5 * s->sbar[i];",
+     "s->phin[i] = sum;"),
+    ("anti-trapping: sign flipped",
+     "j = (((p->a_at * p->W) * dc) * dtphi) * s->nrm[3 * i + a];",
+     "j = -(((p->a_at * p->W) * dc) * dtphi) * s->nrm[3 * i + a];"),
+    ("anti-trapping: d phi / dt taken as zero",
+     "double dtphi = s->phin[i] - phi;",
+     "double dtphi = 0.0;"),
+    ("flux: mu D' grad phi term dropped",
+     "F[a] = (mu * (p->D_l - p->D_s)) * s->grad[3 * i + a] + j;",
+     "F[a] = j;"),
+    ("D(phi): phases swapped",
+     "double D = (p->D_l * phi) + (p->D_s * (1.0 - phi));",
+     "double D = (p->D_s * phi) + (p->D_l * (1.0 - phi));"),
+    ("h source: gamma dropped",
+     "return (s->p.gamma * s->w[k]) * edot(s, k, F);",
+     "return (s->w[k]) * edot(s, k, F);"),
+    ("h equilibrium: rest population c - Lambda",
+     "if (k == s->rest) return c - (1.0 - s->w[k]) * lam;",
+     "if (k == s->rest) return c - lam;"),
+    ("h collision: trapezoidal half source dropped",
+     "double t = (hk - h_equilibrium(s, k, c, lam)) + 0.5 * Hk;",
+     "double t = (hk - h_equilibrium(s, k, c, lam));"),
+    ("moment c: first population skipped",
+     "for (int k = 0; k < Q; ++k) c = c + s->h[k * N + i];",
+     "for (int k = 1; k < Q; ++k) c = c + s->h[k * N + i];"),
+    ("g bounce-back: population not reversed",
+     "s->g[k * N + i] = s->gs[s->opp[k] * N + i];",
+     "s->g[k * N + i] = s->gs[k * N + i];"),
+    ("h bounce-back: population not reversed",
+     "s->h[k * N + i] = s->hs[s->opp[k] * N + i];",
+     "s->h[k * N + i] = s->hs[k * N + i];"),
+    ("streaming: pull from x + e_k",
+     "int c3[3] = {x - s->e[k][0], y - s->e[k][1], z - s->e[k][2]};",
+     "int c3[3] = {x + s->e[k][0], y + s->e[k][1], z + s->e[k][2]};"),
+    ("wall ghost: periodic copy instead of mirror",
+     "return v < 0 ? 0 : n - 1;",
+     "return (v + n) % n;"),
+    ("init: g without the variable-change shift",
+     "s->g[k * N + i] = s->w[k] * phi - 0.5 * G[k];",
+     "s->g[k * N + i] = s->w[k] * phi;"),
+    ("init: h without the variable-change shift",
+     "s->h[k * N + i] = h_equilibrium(s, k, c, lam) - 0.5 * h_source(s, k, F);",
+     "s->h[k * N + i] = h_equilibrium(s, k, c, lam);"),
+    ("D2Q9 table: vector 5 mistyped",
+     "{1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};\nstatic const double d2q9_w",
+     "{1, -1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};\nstatic const double d2q9_w"),
+    ("D3Q19 table: axis and diagonal weights swapped",
+     "    1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,\n    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,\n    1.0 / 18.0,",
+     "    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,\n    1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,\n    1.0 / 18.0,"),
+]
+
+
+def _run_mutant(tmp, idx, name, old, new):
+    import oracle
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutant '{name}': original text not found exactly once"
+    mdir = os.path.join(tmp, f"m{idx:02d}")
+    os.makedirs(mdir, exist_ok=True)
+    msrc = os.path.join(mdir, "oracle.c")
+    with open(msrc, "w") as f:
+        f.write(src.replace(old, new))
+    lib = os.path.join(mdir, "liboracle.so")
+    oracle.compile_library(msrc, lib, quiet=True)
+    env = dict(os.environ, GPLBM_ORACLE_LIB=lib, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(HERE, "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    # exit 1: a pin failed; anything else but 0 (a crash) also exposes the slip
+    caught = r.returncode not in (0, 4, 5)
+    first_fail = ""
+    for line in r.stdout.splitlines():
+        if line.startswith("FAILED"):
+            first_fail = line
+            break
+    return name, caught, first_fail, r.returncode
+
+
+@pytest.mark.slow
+def test_every_mutant_is_caught_by_a_pin(tmp_path):
+    workers = min(8, os.cpu_count() or 1)
+    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+        futs = [ex.submit(_run_mutant, str(tmp_path), i, *m) for i, m in enumerate(MUTANTS)]
+        results = [f.result() for f in futs]
+    for name, caught, first_fail, rc in results:
+        print(f"{'caught' if caught else 'SURVIVED'} (rc {rc}) {name}: {first_fail}")
+    survivors = [name for name, caught, _, _ in results if not caught]
+    assert not survivors, f"mutants not caught by any pin: {survivors}"

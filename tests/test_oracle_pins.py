@@ -2,8 +2,8 @@
 
 None of these compares the oracle with itself: each checks a printed value, a
 closed-form solution, a conservation law or a special case that reduces to a
-textbook problem.  The mutation tests (test_oracle_mutations.py) show that a
-plausible slip in the oracle breaks at least one of them.
+textbook problem.  The mutation test (test_oracle_mutations.py) shows that
+each of a list of plausible slips in the oracle breaks at least one of them.
 """
 import json
 import math
@@ -284,3 +284,110 @@ def test_closed_box_reaches_equal_chemical_potentials(oracle_mod):
     dc = p["c_s_co"] - p["c_l_co"]
     lever = (mtot / (n * n) - p["c_l_co"]) / dc
     assert abs(o.diagnostics()["solid_fraction"] - lever) < 1e-3
+
+
+@pytest.mark.parametrize("counter_term", [0, 1])
+def test_uniform_fields_follow_the_source_recurrence(oracle_mod, counter_term):
+    """Uniform phi and c: no gradient, no normal, no flux, so c stays c0, and
+    the phi-LBE collapses to a scalar recurrence.  Summing the BGK collision
+    with the trapezoidal source over k, with sum g~ = phi - S_prev / 2 carried
+    from the previous step (the variable change, and Eq. Moment_Phi closed
+    with the source of the step's own collision), gives
+        phi^{n+1} = phi^n + S^n + (1 - omega_g) / 2 (S^n - S^{n-1}),
+    S^{-1} = S^0 (initial shift), omega_g = 1 / (3 M_phi + 1/2): explicit
+    Euler of d phi / dt = S plus a second-order difference.  S is the zeroth
+    moment of the sources (Eqs. SourceG_ST with SourceTerm_Coexistence, plus
+    SourceG_dw without the counter term, whose own moment vanishes)."""
+    shape = (1, 3, 4)
+    p = wl.base_params(shape=shape, bc=(0, 0, 0), counter_term=counter_term)
+    phi, c0 = 0.3, 0.5
+    o = oracle_mod.Oracle(p).init(np.full(shape, phi), np.full(shape, c0))
+    dc = p["c_s_co"] - p["c_l_co"]
+    M, W = p["M_phi"], p["W"]
+    omega = 1.0 / (3.0 * M + 0.5)
+
+    def source(phi):
+        mu = p["mu_eq"] + c0 - (p["c_l_co"] * phi + p["c_s_co"] * (1.0 - phi))
+        S = -(p["lam"] * M / W ** 2) * 6.0 * phi * (1.0 - phi) * dc * (mu - p["mu_eq"])
+        if not counter_term:
+            S += -(8.0 * M / W ** 2) * 2.0 * phi * (1.0 - phi) * (1.0 - 2.0 * phi)
+        return S
+
+    steps = 30
+    s_prev = source(phi)
+    for _ in range(steps):
+        S = source(phi)
+        phi = phi + S + 0.5 * (1.0 - omega) * (S - s_prev)
+        s_prev = S
+    assert abs(phi - 0.3) > 0.1  # the source moves phi well away from its start
+    o.step(steps)
+    f, c, _ = o.fields()
+    assert np.max(np.abs(f - phi)) < 1e-13
+    assert np.max(np.abs(c - c0)) < 1e-14
+
+
+@pytest.mark.parametrize("lattice", [0, 1])
+def test_wall_is_a_mirror_plane_for_wall_normal_fields(oracle_mod, lattice):
+    """For fields that vary only across a zero-flux wall, halfway bounce-back
+    (the oblique populations that bounce and those that would mirror are
+    equal by symmetry) and the mirror ghost of the gradient stencil make the
+    wall a symmetry plane: the run on [0, n) between two walls equals the
+    first half of the periodic run on [0, 2n) from the mirrored fields."""
+    n = 24
+    shape = (1, 4, n) if lattice == 0 else (2, 2, n)
+    p = wl.base_params(lattice=lattice, shape=shape, bc=(1, 0, 0))
+    p2 = dict(p, shape=shape[:2] + (2 * n,), bc=(0, 0, 0))
+    x = np.arange(n, dtype=np.float64)
+    phi1 = wl.tanh_profile(x - 5.0, p["W"])          # front two cells off the wall
+    c1 = 0.3 + 0.2 * np.cos(np.pi * x / n) - 0.25 * (1.0 - phi1)
+    phi0 = np.broadcast_to(phi1, shape).copy()
+    c0 = np.broadcast_to(c1, shape).copy()
+
+    def mirrored(f):
+        return np.concatenate([f, f[..., ::-1]], axis=-1)
+
+    a = oracle_mod.Oracle(p).init(phi0, c0).step(80).fields()
+    b = oracle_mod.Oracle(p2).init(mirrored(phi0), mirrored(c0)).step(80).fields()
+    assert np.max(np.abs(a[0] - phi0)) > 1e-3        # the fields did move
+    for fa, fb in zip(a, b):
+        assert np.max(np.abs(fa - fb[..., :n])) < 1e-12
+
+
+@pytest.mark.parametrize("lattice", [0, 1])
+def test_initial_populations_are_shifted_equilibria(oracle_mod, lattice):
+    """Reading (the paper does not give the initial populations): at t = 0
+    the populations before the variable change, g~ + G/2 and h~ + H/2, are
+    the equilibria, with no anti-trapping current.  Checked by moments at
+    the interior nodes of linear phi0 and c0, where the gradient is exact:
+    sum g~ = phi0 - S/2, sum h~ = c0, and the first moments
+    sum e_k g~_k = -(1/2) sum_k e_k G_k = -(1/6)(4/W) phi (1 - phi) n and
+    sum e_k h~_k = -(1/2) sum_k e_k H_k = -(gamma/6) F with
+    F = mu (D_l - D_s) grad phi (Eqs. SourceG_CT, SourceTerm_LBE_h; the
+    second moment of the weights is 1/3)."""
+    shape = (1, 9, 11) if lattice == 0 else (7, 9, 11)
+    p = wl.base_params(lattice=lattice, shape=shape, bc=(1, 1, 1 if lattice else 0),
+                       D_s=0.02)
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    b = np.array([0.031, -0.023, 0.019 if lattice else 0.0])
+    phi0 = 0.45 + b[0] * (x - 5) + b[1] * (y - 4) + b[2] * (z - 3 if lattice else 0)
+    c0 = 0.35 - 0.02 * x + 0.015 * y
+    o = oracle_mod.Oracle(p).init(phi0, c0)
+    g, h, _ = o.state()
+    inner = (slice(1, -1) if lattice else slice(None), slice(1, -1), slice(1, -1))
+    dc = p["c_s_co"] - p["c_l_co"]
+    M, W = p["M_phi"], p["W"]
+    mu = p["mu_eq"] + c0 - (p["c_l_co"] * phi0 + p["c_s_co"] * (1.0 - phi0))
+    Sst = -(p["lam"] * M / W ** 2) * 6.0 * phi0 * (1.0 - phi0) * dc * (mu - p["mu_eq"])
+    nrm = b / math.sqrt(float(b @ b) + p["eps_n"] ** 2)
+    kphi = (4.0 / W) * phi0 * (1.0 - phi0)
+    F = (mu * (p["D_l"] - p["D_s"]))[..., None] * b
+    assert np.max(np.abs(g.sum(0) - (phi0 - 0.5 * Sst))[inner]) < 1e-14
+    assert np.max(np.abs(h.sum(0) - c0)[inner]) < 1e-14
+    m1g = analytic.first_moment(g, lattice)
+    m1h = analytic.first_moment(h, lattice)
+    want_g = -(kphi / 6.0)[..., None] * nrm
+    want_h = -(p["gamma"] / 6.0) * F
+    assert np.max(np.abs(m1g - want_g)[inner]) < 1e-14
+    assert np.max(np.abs(m1h - want_h)[inner]) < 1e-14
+    assert np.max(np.abs(want_h[inner])) > 1e-3 and np.max(np.abs(want_g[inner])) > 1e-2
