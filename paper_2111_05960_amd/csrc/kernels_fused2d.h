@@ -1,7 +1,7 @@
 // Fused schedule for D2Q9: one kernel per time step n -> n+1.
 //
-// A block owns an output tile T of (BX-2) x (BY-2) nodes and runs one thread
-// per node of T grown by one node on each side (T+1).  Every thread of T+1:
+// A block owns an output tile T of TX x TY nodes (x-aligned, tiles.h) and
+// computes T grown by one node on each side (T+1).  Every thread of T+1:
 //   - pulls h~^n (sum -> c^n, mu^n) and g~^{n+1} (kept in registers),
 //   - reads phi^n around itself from an LDS tile covering T+2 (gradient,
 //     normal, source moment), forms phi^{n+1} and writes it to an LDS tile,
@@ -15,46 +15,34 @@
 // g~*^{n+1}, h~*^n and phi^{n+1}.
 //
 // HBM traffic per node and step is the minimum: Q + Q reads, Q + Q writes,
-// one phi read and one phi write.  The halo ring is recomputed (its pulls hit
-// the L2), and tiles are assigned to blocks so that the tiles of one XCD form
-// a contiguous band of the grid (blocks go to the 8 XCDs round robin).
+// one phi read and one phi write, plus the recomputed halo ring where the L2
+// misses it.  The grid is persistent with XCD-ordered rounds (tiles.h).
 #pragma once
 
 #include "kernels_split.h"
+#include "tiles.h"
 
 namespace gplbm {
 
-constexpr int kNumXcd = 8;
-
-// Map the hardware block id to a tile id so that each XCD receives a
-// contiguous range of tiles (block b runs on XCD b % 8).
-__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
-  const int r = b % kNumXcd, j = b / kNumXcd;
-  const int q = ntiles / kNumXcd, rem = ntiles % kNumXcd;
-  const int start = r * q + (r < rem ? r : rem);
-  return start + j;
-}
-
-__device__ __forceinline__ int wrap_coord(int u, int n) {
-  int v = u % n;
-  return v < 0 ? v + n : v;
-}
-
-template <int BX, int BY, class L, class S, class C>
-__global__ void __launch_bounds__(BX* BY) k_fused2d(Geo g, Coef<C> K, StepBufs<S> b, int tiles_x,
-                                                    int ntiles) {
-  constexpr int TX = BX - 2, TY = BY - 2;
+template <int TX, int TY, class L, class S, class C>
+__global__ void __launch_bounds__((TileShape<TX, TY>::NT))
+    k_fused2d(Geo g, Coef<C> K, StepBufs<S> b, int tiles_x, int ntiles) {
+  using Shape = TileShape<TX, TY>;
+  constexpr int BX = Shape::BX, BY = Shape::BY, NT = Shape::NT;
   constexpr int AX = BX + 2, AY = BY + 2;  // phi^n tile with a 2-node halo
   __shared__ C phiA[AY][AX];
   __shared__ C phiB[BY][BX];
   __shared__ double acc[BY][BX];
 
-  const int tile = xcd_tile(blockIdx.x, ntiles);
+  int tx, ty;
+  bool valid;
+  Shape::node(threadIdx.x, tx, ty, valid);
+
+  for (int tile = first_tile(); tile < ntiles; tile += gridDim.x) {
   const int X0 = (tile % tiles_x) * TX, Y0 = (tile / tiles_x) * TY;
-  const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
 
   // phi^n on T+2 (periodic wrap, or clamp = mirror ghost at a wall)
-  for (int l = threadIdx.x; l < AX * AY; l += BX * BY) {
+  for (int l = threadIdx.x; l < AX * AY; l += NT) {
     const int lx = l % AX, ly = l / AX;
     int ux = X0 - 2 + lx, uy = Y0 - 2 + ly;
     ux = g.bcx ? min(max(ux, 0), g.nx - 1) : wrap_coord(ux, g.nx);
@@ -64,8 +52,8 @@ __global__ void __launch_bounds__(BX* BY) k_fused2d(Geo g, Coef<C> K, StepBufs<S
 
   const int ux = X0 - 1 + tx, uy = Y0 - 1 + ty;  // unwrapped node of this thread
   const bool in_x = ux >= 0 && ux < g.nx, in_y = uy >= 0 && uy < g.ny;
-  const bool active = (in_x || !g.bcx) && (in_y || !g.bcy);
-  const bool out = in_x && in_y && tx >= 1 && tx <= TX && ty >= 1 && ty <= TY;
+  const bool active = valid && (in_x || !g.bcx) && (in_y || !g.bcy);
+  const bool out = valid && in_x && in_y && tx >= 1 && tx <= TX && ty >= 1 && ty <= TY;
   const int x = g.bcx ? ux : wrap_coord(ux, g.nx);
   const int y = g.bcy ? uy : wrap_coord(uy, g.ny);
   const int64_t i = active ? node_index(g, x, y, 0) : 0;
@@ -114,7 +102,7 @@ __global__ void __launch_bounds__(BX* BY) k_fused2d(Geo g, Coef<C> K, StepBufs<S
     for (int k = 0; k < L::Q; ++k)
       hs[k] = C(S(h_collide<L, C>(K, k, h[k], h_eq<L, C>(k, cc, lam), h_source<L, C>(K, k, F))));
   }
-  phiB[ty][tx] = phin_c;
+  if (valid) phiB[ty][tx] = phin_c;
   __syncthreads();
 
   // streaming of h* inside the tile: pass k adds the population k arriving
@@ -141,7 +129,7 @@ __global__ void __launch_bounds__(BX* BY) k_fused2d(Geo g, Coef<C> K, StepBufs<S
     __syncthreads();
   }
 
-  if (!out) return;
+  if (out) {
   const double c1 = acc[ty][tx];
   const C phi1 = phiB[ty][tx];
   const C mu1 = C(closure(K.cl, K.cs, K.mueq, c1, double(phi1)));
@@ -160,21 +148,37 @@ __global__ void __launch_bounds__(BX* BY) k_fused2d(Geo g, Coef<C> K, StepBufs<S
     b.Hn[pop_index<L>(g, k, x, y, 0)] = S(hs[k]);
   }
   b.PHIn[i] = S(phi1);
+  }
+  __syncthreads();  // the LDS tiles are refilled by the next tile
+  }
 }
 
-constexpr int kF2BX = 64, kF2BY = 8;
+#ifndef GPLBM_F2_TY
+#define GPLBM_F2_TY 8
+#endif
+#ifndef GPLBM_F2_PERSIST
+#define GPLBM_F2_PERSIST 1
+#endif
 
 inline bool fused2d_supported(int, int) { return true; }
 
 template <class L, class S, class C>
 struct Fused2D {
   static int launch(const Geo& g, const Coef<C>& K, const StepBufs<S>& b, hipStream_t st) {
-    constexpr int BX = kF2BX, BY = kF2BY;
-    const int tiles_x = (g.nx + BX - 3) / (BX - 2);
-    const int tiles_y = (g.ny + BY - 3) / (BY - 2);
+    constexpr int TX = 64, TY = GPLBM_F2_TY;
+    constexpr int NT = TileShape<TX, TY>::NT;
+    auto kernel = k_fused2d<TX, TY, L, S, C>;
+    const int tiles_x = (g.nx + TX - 1) / TX;
+    const int tiles_y = (g.ny + TY - 1) / TY;
     const int ntiles = tiles_x * tiles_y;
-    hipLaunchKernelGGL((k_fused2d<BX, BY, L, S, C>), dim3(ntiles), dim3(BX * BY), 0, st, g, K, b,
-                       tiles_x, ntiles);
+    static int resident[64] = {0};
+#if GPLBM_F2_PERSIST
+    const int grid = resident_grid(kernel, NT, ntiles, resident);
+#else
+    const int grid = (ntiles + kNumXcd - 1) / kNumXcd * kNumXcd;
+#endif
+    if (grid <= 0) return -1;
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(NT), 0, st, g, K, b, tiles_x, ntiles);
     return 0;
   }
 };

@@ -17,16 +17,11 @@
 // collision of step n+1 at plane p-1, on the g~^{n+1} pulled one plane
 // earlier (kept in registers, or in LDS where registers are short).
 //
-// Tiles are x-aligned: TX is a multiple of 64, tile origins are multiples of
-// TX, so every output row is a run of whole 128-byte lines and its stores are
-// full-line writes (partial-line writes cost about a third of the write
-// bandwidth).  Thread l < TX*BY takes region node (1 + l % TX, l / TX), one
-// wavefront per region row; the next 2*BY threads take the two halo columns.
-//
-// The grid is persistent: one block per resident slot, and in each round the
-// slots of an XCD (block b runs on XCD b mod 8) take consecutive tiles, so
-// that neighbouring tiles march in step and the lines of their shared halo are
-// still in the L2 when the second tile reads them.
+// Tiles are x-aligned with the halo columns in extra lanes, and the grid is
+// persistent with XCD-ordered rounds (tiles.h): every output row is whole
+// 128-byte lines (partial-line writes cost about a third of the write
+// bandwidth), and neighbouring tiles march in step so that the lines of their
+// shared halo are still in the L2 when the second tile reads them.
 //
 // Addressing: with the plane-major layout f[z][k][y][x] every population a
 // thread pulls lies in one of three plane groups (z-1, z, z+1).  Each group is
@@ -40,6 +35,7 @@
 #pragma once
 
 #include "kernels_fused2d.h"
+#include "tiles.h"
 
 namespace gplbm {
 
@@ -75,56 +71,6 @@ __device__ __forceinline__ void bstore_nt(S v, __amdgpu_buffer_rsrc_t r, uint32_
     using V = decltype(__builtin_amdgcn_raw_buffer_load_b32(r, 0, 0, 0));
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(V, v), r, voff, soff, kNT);
   }
-}
-
-// Region of an x-aligned tile and the thread -> node map described above.
-template <int TX_, int TY_>
-struct TileShape {
-  static constexpr int TX = TX_, TY = TY_;
-  static constexpr int BX = TX + 2, BY = TY + 2;
-  static constexpr int kMain = TX * BY;
-  static constexpr int kNodes = kMain + 2 * BY;
-  static constexpr int NT = (kNodes + 63) / 64 * 64;
-  static_assert(TX % 64 == 0, "output rows are whole wavefronts");
-  static_assert(NT <= 1024, "block size");
-  // region node (tx, ty) of thread l; threads past the region are not valid
-  // and shadow node (0, 0)
-  __device__ static void node(int l, int& tx, int& ty, bool& valid) {
-    if (l < kMain) {
-      tx = 1 + l % TX;
-      ty = l / TX;
-      valid = true;
-    } else {
-      const int j = l - kMain;
-      valid = j < 2 * BY;
-      const int jj = valid ? j : 0;
-      tx = jj < BY ? 0 : BX - 1;
-      ty = jj % BY;
-    }
-  }
-};
-
-// Resident grid of a persistent kernel: blocks per CU x CUs, a multiple of
-// the XCD count, no more than the tiles need.  Cached per device in *cache.
-template <class Kern>
-inline int resident_grid(Kern kernel, int threads, int ntiles, int* cache) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return -1;
-  if (cache[dev] == 0) {
-    int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        per_cu < 1 || cus < 1)
-      return -1;
-    cache[dev] = max(kNumXcd, (per_cu * cus) / kNumXcd * kNumXcd);
-  }
-  return min(cache[dev], (ntiles + kNumXcd - 1) / kNumXcd * kNumXcd);
-}
-
-// First tile of block b in round 0 (the slots of an XCD take consecutive tiles).
-__device__ __forceinline__ int first_tile() {
-  const int slots = gridDim.x / kNumXcd;
-  return (blockIdx.x % kNumXcd) * slots + blockIdx.x / kNumXcd;
 }
 
 // Carry of the pulled g~^{n+1} from its plane to the collision one plane

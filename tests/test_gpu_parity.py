@@ -60,6 +60,10 @@ CASES_3D = [
     ((70, 9, 13), (0, 0, 0), 1, 1),
     ((3, 4, 5), (0, 0, 0), 0, 1),
     ((33, 20, 130), (0, 0, 0), 1, 0),
+    # whole and ragged x-tiles of 64, y-tiles of 6 / 12 / 13, one z chunk
+    ((32, 12, 64), (0, 0, 0), 1, 1),
+    ((6, 27, 128), (0, 0, 0), 0, 1),
+    ((5, 7, 1), (0, 0, 0), 1, 1),
 ]
 
 
