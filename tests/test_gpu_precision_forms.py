@@ -1,0 +1,86 @@
+"""The four precision forms on the 3-D porous dissolution workload, against
+the FP64 oracle, through the C ABI.
+
+The instance is the generator of the 512^3 benchmark (Gaussian random field,
+correlation length 8, porosity 0.40, tanh profile of width W, liquid c = 0)
+at 64^3, periodic, so the fused kernels run as in the benchmark.  The solid
+dissolves; the solid fraction is compared every 500 steps and the fields at
+the end (2000 steps).
+
+Bars:
+  - FP64: bit-identical fields (the GPU repeats the oracle's arithmetic in
+    the same order); the norm bar is 1e-11;
+  - FP32: O(10) float operations per value and step at unit roundoff 6e-8,
+    accumulating like a random walk: ~6e-8 * 10 * sqrt(2000) = 3e-5 on phi;
+    bar 2e-4 on Linf(phi), interface position error 1e-3;
+  - FP16 deviations: interface position error 1e-3 lattice units
+    (3.8e-4 measured);
+  - BF16 deviations: 8 significand bits against the 11 of FP16, so 8x its
+    rounding per value; over this run the maximum interface error is about
+    30x the FP16 one (1.1e-2 measured): the bar 3e-2 guards the format (a
+    wrong reference or codec gives errors of order one), it is not a
+    precision claim;
+  - all: the solid fraction within 1e-5 (absolute, of 1) of the oracle's at
+    every sample (2.6e-6 measured in BF16).
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+BARS = {  # (Linf phi, interface position)
+    "fp64": (1e-11, 1e-11),
+    "fp32": (2e-4, 1e-3),
+    "fp16dev": (None, 1e-3),
+    "bf16dev": (None, 3e-2),
+}
+
+
+@pytest.fixture(scope="module")
+def gp():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2111_05960_amd import binding
+    binding.load()
+    return binding
+
+
+def interface_error(phi_a, phi_b, grad_b):
+    g = np.sqrt((grad_b ** 2).sum(axis=-1))
+    m = (phi_b > 0.1) & (phi_b < 0.9)
+    return float(np.max(np.abs(phi_a - phi_b)[m] / g[m]))
+
+
+def test_precision_forms_on_porous_64(gp, oracle_mod):
+    p, phi0, c0 = wl.config_porous3d(64)
+    chunk, nchunks = 500, 4
+    ref = oracle_mod.Oracle(p).init(phi0, c0)
+    sf_ref = [ref.diagnostics()["solid_fraction"]]
+    for _ in range(nchunks):
+        ref.step(chunk)
+        sf_ref.append(ref.diagnostics()["solid_fraction"])
+    phi_r, c_r, _ = ref.fields()
+    grad_r, _ = ref.gradient()
+    print(f"oracle solid fraction {sf_ref}", flush=True)
+    assert sf_ref[-1] < sf_ref[0] - 1e-3  # the solid dissolves
+    for prec, (bar_phi, bar_int) in BARS.items():
+        print(f"case porous 64^3 {prec}", flush=True)
+        sim = gp.Simulation(p, prec).init(phi0, c0)
+        sf = [sim.diagnostics()["solid_fraction"]]
+        for _ in range(nchunks):
+            sim.step(chunk)
+            sf.append(sim.diagnostics()["solid_fraction"])
+        phi_d, c_d, _ = sim.fields()
+        linf = float(np.max(np.abs(phi_d - phi_r)))
+        dint = interface_error(phi_d, phi_r, grad_r)
+        dsf = float(np.max(np.abs(np.array(sf) - np.array(sf_ref))))
+        print(f"  {prec} schedule={sim.schedule}: Linf(phi)={linf:.3e} d_int={dint:.3e} "
+              f"Linf(c)={np.max(np.abs(c_d - c_r)):.3e} max|d solid fraction|={dsf:.3e}",
+              flush=True)
+        if bar_phi is not None:
+            assert linf <= bar_phi
+        assert dint <= bar_int
+        assert dsf <= 1e-5
+        del sim
