@@ -11,11 +11,13 @@ initialised before the timed region.
 Printed: one JSON line with MLUPS (million node updates per second), the
 HBM roofline of the step kernel (algorithmic bytes per launch over the mean
 launch time, measured with HIP events on the stream the library launches on),
+the other precision forms of the same step beside it (FP32, FP16 and BF16
+deviation storage), the differentiation workload (adjoint / forward time),
 and the CPU oracle timed on a bounded crop of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--precision fp64|fp32]
+    python bench.py [--steps K] [--warmup W] [--precision fp64|fp32|fp16dev|bf16dev]
                     [--schedule auto|split|fused] [--workload NAME]
-                    [--no-cpu-baseline] [--variants]
+                    [--no-cpu-baseline] [--no-forms] [--adjoint-steps K] [--variants]
 """
 from __future__ import annotations
 
@@ -289,6 +291,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp16dev", "bf16dev"])
     ap.add_argument("--schedule", default="auto", choices=["auto", "split", "fused"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip timing the other precision forms of the step")
     ap.add_argument("--variants", action="store_true",
                     help="also time the other precision and schedule")
     ap.add_argument("--adjoint-steps", type=int, default=4000,
@@ -327,6 +331,22 @@ def main():
     log(f"workload {args.workload} generated in {time.perf_counter() - t0:.1f} s")
 
     main_res = time_gpu(p, phi0, c0, args.precision, args.schedule, args.steps, args.warmup, log)
+    # the other precision forms of the same step, side by side (auto schedule)
+    forms = {}
+    if not args.no_forms:
+        precs = ("fp64", "fp32") + (("fp16dev", "bf16dev") if p["lattice"] == 1 else ())
+        for prec in precs:
+            if prec == args.precision:
+                continue
+            r = time_gpu(p, phi0, c0, prec, "auto", args.steps, args.warmup, log)
+            t = stored_traffic(args.workload, prec, r["schedule"])
+            forms[prec] = {
+                "mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                "schedule": r["schedule"], "bytes_per_node_step": r["bytes_per_node_step"],
+                "achieved_gbs": round(r["achieved_gbs"], 1),
+                "hbm_frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                "traffic_gb_per_step": None if t is None else round(t["bytes_per_step"] / 1e9, 3),
+                "mass_drift_rel": r["mass_drift_rel"]}
     variants = []
     if args.variants:
         precs = ("fp64", "fp32") + (("fp16dev", "bf16dev") if p["lattice"] == 1 else ())
@@ -392,6 +412,8 @@ def main():
         "checks": {"mass_drift_rel": main_res["mass_drift_rel"], "nonfinite": main_res["nonfinite"]},
         "context": {"paper_v100_mlups_2d_1024sq_d2q9": 149.8},
     }
+    if forms:
+        line["precision_forms"] = forms
     if adj is not None:
         line["adjoint"] = adj
     if variants:
