@@ -14,10 +14,11 @@
 // the previous kernel's output):
 //   ra: gathers the adjoint of G' from the previous reverse step, then the
 //       reverse of the g collision of step n+1: adjoint of the pulled
-//       g~^{n+1} (A1), of grad phi^{n+1} (A2), of c^{n+1} (A3) and the local
-//       part of the adjoint of phi^{n+1} (A4);
+//       g~^{n+1} (A1), of grad phi^{n+1} (A2, plus the previous step's B3),
+//       of c^{n+1} (A3) and the local adjoint of phi^{n+1} (A4, plus the
+//       previous step's B4);
 //   rb: adjoint of h~*^n (gathered from the previous step, plus c^{n+1} from
-//       the node it streams to), total adjoint of phi^{n+1} (gathered, A4,
+//       the node it streams to), total adjoint of phi^{n+1} (A4 and the
 //       stencil transpose of A2), reverse of the h collision of step n and of
 //       phi^{n+1} = sum g~^{n+1} + S^n / 2: B1, B2, B3, B4.
 // The transposes of the pulls and of the gradient stencil are done as gathers
@@ -234,10 +235,13 @@ __global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> K, double la
   const double lb = sources_adj<L>(K, lam_M_W2, f.phi, f.mu, f.n, Gb, 0.0, phi_b, mu_b, nb);
   double gb[3] = {0.0, 0.0, 0.0};
   normal_adj<L>(f, nb, gb);
-  for (int a = 0; a < 3; ++a) w.A2[a * g.N + i] = gb[a];
+  // the h collision of step n+1 (previous reverse step) also used grad phi^{n+1}
+  // and phi^{n+1}: their adjoints are added here, so that rb applies the
+  // transposed stencil once
+  for (int a = 0; a < L::D; ++a) w.A2[a * g.N + i] = gb[a] + P.B3[a * g.N + i];
   w.A3[i] = mu_b;                      // adjoint of c^{n+1}
   phi_b += (K.cs - K.cl) * mu_b;       // closure
-  w.A4[i] = phi_b;
+  w.A4[i] = phi_b + P.B4[i];
   w.lamb[i] += lb;
 }
 
@@ -258,9 +262,8 @@ __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> K, double la
     const int kk = push_dest<L>(g, k, x, y, z, dx, dy, dz);
     Hb[k] = P.B1[pop_index<L>(g, kk, dx, dy, dz)] + w.A3[node_index(g, dx, dy, dz)];
   }
-  // adjoint of phi^{n+1} at this node
-  double p1b = P.B4[i] + stencil_adj_gather<L>(g, P.B3, x, y, z) + w.A4[i] +
-               stencil_adj_gather<L>(g, w.A2, x, y, z);
+  // adjoint of phi^{n+1} at this node (A2, A4 hold both collisions' parts)
+  double p1b = w.A4[i] + stencil_adj_gather<L>(g, w.A2, x, y, z);
   // forward quantities of step n
   const NodeFwd<L> f = node_fwd<L>(g, K, S0, x, y, z);
   const double phi1 = S1.PHI[i];
