@@ -316,8 +316,8 @@ def main():
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the step runs on a single MI355X and this build "
-              "has no multi-GPU path (see DESIGN.md for how it would shard).", file=sys.stderr)
+        print("bench.py measures one GPU: the step runs on a single MI355X; there is no "
+              "multi-GPU path (--gpus 1 only).", file=sys.stderr)
         sys.exit(2)
 
     import torch
