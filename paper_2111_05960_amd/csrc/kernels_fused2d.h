@@ -16,7 +16,7 @@
 //
 // HBM traffic per node and step is the minimum: Q + Q reads, Q + Q writes,
 // one phi read and one phi write, plus the recomputed halo ring where the L2
-// misses it.  The grid is persistent with XCD-ordered rounds (tiles.h).
+// misses it.  The grid is persistent with XCD-ordered passes (tiles.h).
 #pragma once
 
 #include "kernels_split.h"

@@ -18,7 +18,7 @@
 // earlier (kept in registers, or in LDS where registers are short).
 //
 // Tiles are x-aligned with the halo columns in extra lanes, and the grid is
-// persistent with XCD-ordered rounds (tiles.h): every output row is whole
+// persistent with XCD-ordered passes (tiles.h): every output row is whole
 // 128-byte lines (partial-line writes cost about a third of the write
 // bandwidth), and neighbouring tiles march in step so that the lines of their
 // shared halo are still in the L2 when the second tile reads them.

@@ -8,9 +8,10 @@
 // row when TX = 64, and the next 2*BY threads take the two halo columns.
 //
 // Persistent grid: one block per resident slot (occupancy x CUs); in each
-// round the slots of an XCD (block b runs on XCD b mod 8) take consecutive
-// tiles, so that neighbouring tiles run at the same time and the lines of
-// their shared halo are still in that XCD's L2 when the second tile reads
+// pass over the grid the slots of an XCD (block b runs on XCD b mod 8) take
+// consecutive
+// tiles, so that neighbouring tiles run at the same time and the lines
+// of their shared halo are still in that XCD's L2 when the second tile reads
 // them.
 #pragma once
 
@@ -68,8 +69,8 @@ inline int resident_grid(Kern kernel, int threads, int ntiles, int* cache) {
   return min(cache[dev], (ntiles + kNumXcd - 1) / kNumXcd * kNumXcd);
 }
 
-// First tile of this block in round 0 (the slots of an XCD take consecutive
-// tiles); the block then strides by gridDim.x.
+// First tile of this block in the first pass (the slots of an XCD take
+// consecutive tiles); the block then strides by gridDim.x.
 __device__ __forceinline__ int first_tile() {
   const int slots = gridDim.x / kNumXcd;
   return (blockIdx.x % kNumXcd) * slots + blockIdx.x / kNumXcd;
