@@ -9,10 +9,9 @@
 //
 // Persistent grid: one block per resident slot (occupancy x CUs); in each
 // pass over the grid the slots of an XCD (block b runs on XCD b mod 8) take
-// consecutive
-// tiles, so that neighbouring tiles run at the same time and the lines
-// of their shared halo are still in that XCD's L2 when the second tile reads
-// them.
+// consecutive tiles, so that neighbouring tiles run at the same time and the
+// lines of their shared halo are still in that XCD's L2 when the second tile
+// reads them.
 #pragma once
 
 #include <hip/hip_runtime.h>
