@@ -107,12 +107,13 @@ def time_gpu(p, phi0, c0, precision, schedule, steps, warmup, log):
     return res
 
 
-def time_adjoint(K, log, n=512):
+def time_adjoint(K, log, n=512, precision="fp64"):
     """Differentiation workload: 2-D porous medium n^2 (D2Q9, periodic), K
-    steps in FP64; gradients of the final solid fraction with respect to
-    lambda, D_l and phi0 through the hand-written adjoint with sqrt(K)
-    checkpointing.  Returns forward and backward wall times (the backward
-    phase rebuilds each checkpoint segment and runs the reverse steps)."""
+    steps (FP64, or FP32 forward states with the FP64 reverse sweep);
+    gradients of the final solid fraction with respect to lambda, D_l and
+    phi0 through the hand-written adjoint with sqrt(K) checkpointing.
+    Returns forward and backward wall times (the backward phase rebuilds each
+    checkpoint segment and runs the reverse steps)."""
     import torch
     import workloads as wl
     from paper_2111_05960_amd import adjoint
@@ -124,7 +125,7 @@ def time_adjoint(K, log, n=512):
     g_lam = torch.tensor(p["lam"], dtype=torch.float64, requires_grad=True)
     g_dl = torch.tensor(p["D_l"], dtype=torch.float64, requires_grad=True)
     # untimed warm-up of both directions on a short run
-    phiK, _ = adjoint.gplbm_run(g_phi0, c0_t, g_lam, g_dl, p, 16)
+    phiK, _ = adjoint.gplbm_run(g_phi0, c0_t, g_lam, g_dl, p, 16, precision=precision)
     adjoint.objectives(g_phi0, phiK, p["W"])[0].backward()
     g_phi0.grad = None
     g_lam.grad = None
@@ -133,7 +134,7 @@ def time_adjoint(K, log, n=512):
     torch.cuda.reset_peak_memory_stats()
     base_mem = torch.cuda.memory_allocated()
     t0 = time.perf_counter()
-    phiK, _ = adjoint.gplbm_run(g_phi0, c0_t, g_lam, g_dl, p, K)
+    phiK, _ = adjoint.gplbm_run(g_phi0, c0_t, g_lam, g_dl, p, K, precision=precision)
     J1, J2 = adjoint.objectives(g_phi0, phiK, p["W"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -142,28 +143,33 @@ def time_adjoint(K, log, n=512):
     t2 = time.perf_counter()
     peak = torch.cuda.max_memory_allocated() - base_mem
     fwd, bwd = t1 - t0, t2 - t1
-    res = {"workload": f"porous2d_{n}_d2q9", "K": K, "precision": "fp64",
+    res = {"workload": f"porous2d_{n}_d2q9", "K": K, "precision": precision,
            "checkpoint_every": int(math.ceil(math.sqrt(K))),
            "forward_s": round(fwd, 4), "backward_s": round(bwd, 4),
            "adjoint_forward_ratio": round(bwd / fwd, 3),
            "peak_memory_gb": round(peak / 1e9, 3),
            "J1": J1.item(), "dJ1_dlambda": g_lam.grad.item(), "dJ1_dDl": g_dl.grad.item(),
            "dJ1_dphi0_norm": float(g_phi0.grad.norm().item())}
-    log(f"adjoint {res['workload']} K={K}: forward {fwd:.3f} s, backward {bwd:.3f} s "
+    log(f"adjoint {res['workload']} {precision} K={K}: forward {fwd:.3f} s, backward {bwd:.3f} s "
         f"(ratio {bwd / fwd:.2f}), peak {peak / 1e9:.2f} GB")
     return res
 
 
 def kernel_source_hash() -> str:
-    """Hash of the HIP sources: a stored traffic measurement is only used
-    while the kernels it was taken on are unchanged."""
+    """Hash of the HIP sources with comments and layout removed: a stored
+    traffic measurement is only used while the code it was taken on is
+    unchanged."""
     import hashlib
+    import re
     d = os.path.join(ROOT, "paper_2111_05960_amd", "csrc")
     h = hashlib.sha256()
     for f in sorted(os.listdir(d)):
         if f.endswith((".h", ".hip")):
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
+            with open(os.path.join(d, f)) as fh:
+                src = fh.read()
+            src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+            src = re.sub(r"//[^\n]*", " ", src)
+            h.update(f.encode() + b"\0" + " ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 
@@ -358,7 +364,10 @@ def main():
                 r["hbm_frac"] = round(r["achieved_gbs"] / HBM_PEAK_GBS, 4)
                 variants.append(dict(precision=prec, **r))
 
-    adj = time_adjoint(args.adjoint_steps, log) if args.adjoint_steps > 0 else None
+    adj = None
+    if args.adjoint_steps > 0:
+        adj = time_adjoint(args.adjoint_steps, log)
+        adj["fp32_forward"] = time_adjoint(args.adjoint_steps, log, precision="fp32")
 
     if args.calibration_copy:
         calibration_copy(log)

@@ -1,13 +1,15 @@
 """Differentiable coupled run: torch.autograd.Function over the library's
 forward step and its hand-written adjoint, with sqrt(K) checkpointing.
 
-    phiK, cK = gplbm_run(phi0, c0, lam, D_l, cfg, K)
+    phiK, cK = gplbm_run(phi0, c0, lam, D_l, cfg, K, precision="fp64")
 
 phi0, c0: float64 CUDA tensors of the grid's shape; lam, D_l: float64 scalar
 tensors; cfg: the parameter mapping (its lam and D_l are replaced).  Any
 torch objective J(phiK, cK) can then be differentiated: backward returns
 dJ/dphi0, dJ/dc0, dJ/dlambda and dJ/dD_l, all computed by the GPU kernels of
-libgplbm.so (this module only schedules them).
+libgplbm.so (this module only schedules them).  precision "fp32" runs the
+forward (and its re-computation) in FP32 storage and arithmetic; the reverse
+sweep stays FP64, taken at the FP32 states.
 
 Checkpointing: forward keeps the state every s = ceil(sqrt(K)) steps;
 backward rebuilds each segment from its checkpoint (gplbm_step_to, no copies)
@@ -28,9 +30,9 @@ def _aligned(t: torch.Tensor) -> int:
 
 class _Run(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, phi0, c0, lam, D_l, cfg, K, seg):
+    def forward(ctx, phi0, c0, lam, D_l, cfg, K, seg, precision):
         cfg = dict(cfg, lam=float(lam), D_l=float(D_l))
-        sim = B.Simulation(cfg, "fp64")
+        sim = B.Simulation(cfg, precision)
         dev = sim.device
         phi0d = phi0.detach().to(dev, torch.float64).contiguous()
         c0d = c0.detach().to(dev, torch.float64).contiguous()
@@ -77,12 +79,15 @@ class _Run(torch.autograd.Function):
         del states, work
         return (g_phi0.reshape(ctx.shape), g_c0.reshape(ctx.shape),
                 torch.tensor(dlam, dtype=torch.float64), torch.tensor(ddl, dtype=torch.float64),
-                None, None, None)
+                None, None, None, None)
 
 
-def gplbm_run(phi0, c0, lam, D_l, cfg, K, seg=None):
-    """(phi^K, c^K) after K steps; differentiable in phi0, c0, lam and D_l."""
-    return _Run.apply(phi0, c0, lam, D_l, cfg, K, seg)
+def gplbm_run(phi0, c0, lam, D_l, cfg, K, seg=None, precision="fp64"):
+    """(phi^K, c^K) after K steps; differentiable in phi0, c0, lam and D_l.
+    precision: "fp64" or "fp32" (forward storage and arithmetic)."""
+    if precision not in ("fp64", "fp32"):
+        raise ValueError("the adjoint runs over FP64 or FP32 forward states")
+    return _Run.apply(phi0, c0, lam, D_l, cfg, K, seg, precision)
 
 
 def objectives(phi0, phiK, W):

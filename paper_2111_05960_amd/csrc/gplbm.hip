@@ -565,7 +565,7 @@ void gplbm_destroy(gplbm_ctx* ctx) { delete ctx; }
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// Adjoint (FP64 only).
+// Adjoint: FP64 reverse sweep over FP64 or FP32 forward states.
 
 namespace {
 
@@ -586,17 +586,17 @@ AdjLayout adj_layout(const gplbm_params* p) {
   return l;
 }
 
-template <class L>
+template <class L, class S>
 struct AdjOps {
   static dim3 block() { return dim3(64, 4, 1); }
   static dim3 grid(const gplbm_ctx* ctx) {
     return dim3((ctx->p.nx + 63) / 64, (ctx->p.ny + 3) / 4, ctx->p.nz);
   }
   static double lam_M_W2(const gplbm_ctx* ctx) { return ctx->p.M_phi / (ctx->p.W * ctx->p.W); }
-  static FwdState fwd(const gplbm_ctx* ctx, const void* ck) {
+  static FwdState<S> fwd(const gplbm_ctx* ctx, const void* ck) {
     const char* b = (const char*)ck;
-    return FwdState{(const double*)b, (const double*)(b + ctx->pop_bytes),
-                    (const double*)(b + 2 * ctx->pop_bytes)};
+    return FwdState<S>{(const S*)b, (const S*)(b + ctx->pop_bytes),
+                       (const S*)(b + 2 * ctx->pop_bytes)};
   }
   static int seed(gplbm_ctx* ctx, const double* phib, const double* cb) {
     const Geo g = make_geo(ctx->p);
@@ -608,11 +608,11 @@ struct AdjOps {
     const Geo g = make_geo(ctx->p);
     const Coef<double> K = make_coef<double>(ctx->p);
     const int a = ctx->adj_cur, b = 1 - a;
-    const FwdState S0 = fwd(ctx, s0), S1 = fwd(ctx, s1);
-    hipLaunchKernelGGL((k_adj_ra<L>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx), S1,
-                       ctx->adj.set[a], ctx->adj.set[b], ctx->adj);
-    hipLaunchKernelGGL((k_adj_rb<L>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx), S0,
+    const FwdState<S> S0 = fwd(ctx, s0), S1 = fwd(ctx, s1);
+    hipLaunchKernelGGL((k_adj_ra<L, S>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx),
                        S1, ctx->adj.set[a], ctx->adj.set[b], ctx->adj);
+    hipLaunchKernelGGL((k_adj_rb<L, S>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx),
+                       S0, S1, ctx->adj.set[a], ctx->adj.set[b], ctx->adj);
     int rc = check_launch(ctx, "adjoint step");
     if (rc) return rc;
     ctx->adj_cur = b;
@@ -635,32 +635,40 @@ struct AdjOps {
   }
 };
 
-template <template <class> class Fn, class... Args>
+template <template <class, class> class Fn, class... Args>
 int adj_dispatch(gplbm_ctx* ctx, Args... args) {
-  if (ctx->p.lattice == GPLBM_D2Q9) return Fn<D2Q9>::run(ctx, args...);
-  return Fn<D3Q19>::run(ctx, args...);
+  const bool f64 = ctx->p.precision == GPLBM_FP64;
+  if (ctx->p.lattice == GPLBM_D2Q9)
+    return f64 ? Fn<D2Q9, double>::run(ctx, args...) : Fn<D2Q9, float>::run(ctx, args...);
+  return f64 ? Fn<D3Q19, double>::run(ctx, args...) : Fn<D3Q19, float>::run(ctx, args...);
 }
-template <class L>
+template <class L, class S>
 struct AdjSeedFn {
-  static int run(gplbm_ctx* c, const double* a, const double* b) { return AdjOps<L>::seed(c, a, b); }
-};
-template <class L>
-struct AdjStepFn {
-  static int run(gplbm_ctx* c, const void* a, const void* b) { return AdjOps<L>::step(c, a, b); }
-};
-template <class L>
-struct AdjFinishFn {
-  static int run(gplbm_ctx* c, const double* a, const double* b, double* d, double* e) {
-    return AdjOps<L>::finish(c, a, b, d, e);
+  static int run(gplbm_ctx* c, const double* a, const double* b) {
+    return AdjOps<L, S>::seed(c, a, b);
   }
 };
+template <class L, class S>
+struct AdjStepFn {
+  static int run(gplbm_ctx* c, const void* a, const void* b) { return AdjOps<L, S>::step(c, a, b); }
+};
+template <class L, class S>
+struct AdjFinishFn {
+  static int run(gplbm_ctx* c, const double* a, const double* b, double* d, double* e) {
+    return AdjOps<L, S>::finish(c, a, b, d, e);
+  }
+};
+
+bool adjoint_precision(int precision) {
+  return precision == GPLBM_FP64 || precision == GPLBM_FP32;
+}
 
 }  // namespace
 
 extern "C" {
 
 int gplbm_adjoint_bytes(const gplbm_params* p, uint64_t* bytes) {
-  if (check_params(p) || !bytes || p->precision != GPLBM_FP64) return GPLBM_E_INVALID;
+  if (check_params(p) || !bytes || !adjoint_precision(p->precision)) return GPLBM_E_INVALID;
   *bytes = adj_layout(p).total;
   return GPLBM_OK;
 }
@@ -668,7 +676,8 @@ int gplbm_adjoint_bytes(const gplbm_params* p, uint64_t* bytes) {
 int gplbm_adjoint_begin(gplbm_ctx* ctx, void* work, uint64_t bytes, const double* phi_bar,
                         const double* c_bar) {
   if (!ctx || !work || ((uintptr_t)work) % kAlign) return GPLBM_E_INVALID;
-  if (ctx->p.precision != GPLBM_FP64) return fail(ctx, GPLBM_E_INVALID, "adjoint needs FP64");
+  if (!adjoint_precision(ctx->p.precision))
+    return fail(ctx, GPLBM_E_INVALID, "adjoint needs an FP64 or FP32 context");
   const AdjLayout l = adj_layout(&ctx->p);
   if (bytes < l.total) return fail(ctx, GPLBM_E_SIZE, "adjoint workspace too small");
   if (int rc = use_device(ctx)) return rc;

@@ -52,10 +52,13 @@ struct AdjWork {
   double* red;           // reduction scratch
 };
 
+// A forward state in the storage type S of the context (FP64 or FP32); the
+// reverse kernels recompute the forward quantities from it in FP64.
+template <class S>
 struct FwdState {
-  const double* G;
-  const double* H;
-  const double* PHI;
+  const S* G;
+  const S* H;
+  const S* PHI;
 };
 
 // Destination of the value stored in slot (k, x, y, z) under the pull
@@ -86,20 +89,20 @@ struct NodeFwd {
   double c, mu, phi, g[3], n[3], s;  // s = sqrt(|grad|^2 + eps^2)
 };
 
-template <class L>
-__device__ __forceinline__ NodeFwd<L> node_fwd(const Geo& g, const Coef<double>& K, const FwdState& S,
+template <class L, class S>
+__device__ __forceinline__ NodeFwd<L> node_fwd(const Geo& g, const Coef<double>& K, const FwdState<S>& F,
                                                int x, int y, int z) {
   NodeFwd<L> f;
   double c = 0.0;
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
-    const double v = pull<L>(g, S.H, k, x, y, z);
+    const double v = double(pull<L>(g, F.H, k, x, y, z));
     c = k == 0 ? v : c + v;
   }
   f.c = c;
-  f.phi = S.PHI[node_index(g, x, y, z)];
+  f.phi = double(F.PHI[node_index(g, x, y, z)]);
   f.mu = closure(K.cl, K.cs, K.mueq, c, f.phi);
-  gradient_normal<L, double>(GlobalPhi<double, double>{g, S.PHI, x, y, z}, K.eps2, f.g, f.n);
+  gradient_normal<L, double>(GlobalPhi<S, double>{g, F.PHI, x, y, z}, K.eps2, f.g, f.n);
   double nn = f.g[0] * f.g[0] + f.g[1] * f.g[1];
   if (L::D == 3) nn = nn + f.g[2] * f.g[2];
   f.s = sqrt(nn + K.eps2);
@@ -213,15 +216,15 @@ __device__ __forceinline__ double gather_Gb(const Geo& g, const AdjSet& P, int k
   return P.A1[pop_index<L>(g, kk, dx, dy, dz)] + P.B2[node_index(g, dx, dy, dz)];
 }
 
-template <class L>
+template <class L, class S>
 __global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> K, double lam_M_W2,
-                                                FwdState S1, AdjSet P, AdjSet C, AdjWork w) {
+                                                FwdState<S> S1, AdjSet P, AdjSet C, AdjWork w) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= g.nx || y >= g.ny) return;
   const int64_t i = node_index(g, x, y, z);
-  const NodeFwd<L> f = node_fwd<L>(g, K, S1, x, y, z);  // c^{n+1}, mu^{n+1}, ...
+  const NodeFwd<L> f = node_fwd<L, S>(g, K, S1, x, y, z);  // c^{n+1}, mu^{n+1}, ...
   const double om = K.omega_g;
   double Gb[L::Q];
   double phi_b = 0.0, mu_b = 0.0, nb[3] = {0.0, 0.0, 0.0};
@@ -245,9 +248,9 @@ __global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> K, double la
   w.lamb[i] += lb;
 }
 
-template <class L>
+template <class L, class S>
 __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> K, double lam_M_W2,
-                                                FwdState S0, FwdState S1, AdjSet P, AdjSet C,
+                                                FwdState<S> S0, FwdState<S> S1, AdjSet P, AdjSet C,
                                                 AdjWork w) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -265,8 +268,8 @@ __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> K, double la
   // adjoint of phi^{n+1} at this node (A2, A4 hold both collisions' parts)
   double p1b = w.A4[i] + stencil_adj_gather<L>(g, w.A2, x, y, z);
   // forward quantities of step n
-  const NodeFwd<L> f = node_fwd<L>(g, K, S0, x, y, z);
-  const double phi1 = S1.PHI[i];
+  const NodeFwd<L> f = node_fwd<L, S>(g, K, S0, x, y, z);
+  const double phi1 = double(S1.PHI[i]);
   const double dtphi = phi1 - f.phi;
   const double oh = K.omega_h;
   const double Dp = K.Dp;

@@ -123,3 +123,35 @@ def test_adjoint_against_finite_differences(adj):
             rel = abs(ad[k] - fd[k]) / max(abs(fd[k]), 1e-30)
             print(f"J{which + 1} d/d{k}: adjoint {ad[k]:.10e} fd {fd[k]:.10e} rel {rel:.2e}", flush=True)
             assert rel <= 1e-5, (which, k, ad[k], fd[k])
+
+
+def test_fp32_forward_gradients_close_to_fp64(adj):
+    """FP32 forward (storage and arithmetic), FP64 reverse sweep at the FP32
+    states: the gradients of J1 and J2 agree with the FP64 run's.  Bar: the
+    FP32 trajectory departs from the FP64 one by ~1e-5 relative over these
+    200 steps (rounding 6e-8 per operation, O(10) operations per value and
+    step, random-walk growth) and the gradient is a smooth function of the
+    states, so 1e-3 relative leaves an order of magnitude of margin."""
+    p, phi0, c0, _ = wl.config_porous2d(n=96)
+    K = 200
+    dev = "cuda"
+    c0_t = torch.tensor(c0, device=dev)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        out = []
+        for which in (0, 1):
+            g_phi0 = torch.tensor(phi0, device=dev, requires_grad=True)
+            g_lam = torch.tensor(p["lam"], dtype=torch.float64, requires_grad=True)
+            g_dl = torch.tensor(p["D_l"], dtype=torch.float64, requires_grad=True)
+            phiK, _ = adj.gplbm_run(g_phi0, c0_t, g_lam, g_dl, p, K, precision=prec)
+            J = adj.objectives(g_phi0, phiK, p["W"])[which]
+            J.backward()
+            out.append((g_lam.grad.item(), g_dl.grad.item(), g_phi0.grad.cpu().numpy()))
+        res[prec] = out
+    for which in (0, 1):
+        a, b = res["fp32"][which], res["fp64"][which]
+        errs = {"lambda": _rel(a[0], b[0]), "D_l": _rel(a[1], b[1]),
+                "phi0": float(np.linalg.norm(a[2] - b[2]) / np.linalg.norm(b[2]))}
+        print(f"J{which + 1}: FP32-forward vs FP64 relative differences {errs}", flush=True)
+        for k, e in errs.items():
+            assert e <= 1e-3, (which, k, e)
