@@ -30,6 +30,34 @@ def stefan_mu_liquid(x, t, alpha, D_l, mu_eq, mu_inf):
     return mu_inf + (mu_eq - mu_inf) * erfc(x / (2.0 * math.sqrt(D_l * t))) / erfc(alpha)
 
 
+def maugis_u(a: float, D: float) -> float:
+    """u_Phi(alpha) of the two-sided solution (Sec. 4.2, Eq. solution_u)."""
+    return math.sqrt(D / math.pi) * math.exp(-a * a / (4.0 * D)) / math.erfc(a / (2.0 * math.sqrt(D)))
+
+
+def maugis_alpha(cs_inf, cl_inf, m_s, m_l, df_min, D_s, D_l) -> float:
+    """Root of the binary transcendental equation of the two-sided diffusion
+    problem (Sec. 4.2, Eq. Transcendental_Eq), with dm = m_s - m_l:
+    -alpha dm^2 / 2 = df_min [u_s(-alpha) + u_l(alpha)]
+                      + dm [(m_s - cs_inf) u_s(-alpha) + (m_l - cl_inf) u_l(alpha)]."""
+    dm = m_s - m_l
+
+    def f(a):
+        us, ul = maugis_u(-a, D_s), maugis_u(a, D_l)
+        return 0.5 * a * dm * dm + df_min * (us + ul) + dm * ((m_s - cs_inf) * us + (m_l - cl_inf) * ul)
+    return brentq(f, -2.0, 2.0, xtol=1e-15, rtol=1e-15)
+
+
+def maugis_composition(x, t, alpha, cs_inf, cl_inf, cs_co, cl_co, D_s, D_l):
+    """Compositions of the two-sided solution (Eqs. x_i_Ds-Dl, Compos_Solid,
+    Compos_Liq): solid for x < alpha sqrt(t), liquid beyond."""
+    x = np.asarray(x, dtype=np.float64)
+    xi = alpha * math.sqrt(t)
+    cs = cs_inf + (cs_co - cs_inf) * erfc(-x / (2.0 * math.sqrt(D_s * t))) / erfc(-alpha / (2.0 * math.sqrt(D_s)))
+    cl = cl_inf + (cl_co - cl_inf) * erfc(x / (2.0 * math.sqrt(D_l * t))) / erfc(alpha / (2.0 * math.sqrt(D_l)))
+    return np.where(x < xi, cs, cl)
+
+
 def front_position(phi):
     """Interface position of a planar front with solid on the left and the
     zero-flux wall at x = -1/2: -1/2 + mean over y of sum_x (1 - phi)."""

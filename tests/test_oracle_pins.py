@@ -391,3 +391,20 @@ def test_initial_populations_are_shifted_equilibria(oracle_mod, lattice):
     assert np.max(np.abs(m1g - want_g)[inner]) < 1e-14
     assert np.max(np.abs(m1h - want_h)[inner]) < 1e-14
     assert np.max(np.abs(want_h[inner])) > 1e-3 and np.max(np.abs(want_g[inner])) > 1e-2
+
+
+def test_maugis_root_matches_printed():
+    """The two-sided (precipitation) transcendental equation of Sec. 4.2
+    gives the printed root; the composition profiles then take the
+    coexistence values on both sides of the interface and the far-field
+    values away from it (the analytic helper used by the GPU validation)."""
+    g = golden()["maugis_precipitation"]
+    a = analytic.maugis_alpha(g["cs_inf"], g["cl_inf"], g["m_s"], g["m_l"], g["df_min"],
+                              g["D_s"], g["D_l"])
+    assert abs(a - g["alpha"]) < 0.6 * 10 ** (-g["printed_digits"])
+    t = 5e-4
+    xi = a * math.sqrt(t)
+    c = analytic.maugis_composition([xi - 1e-12, xi + 1e-12, -0.25, 0.25], t, a, g["cs_inf"],
+                                    g["cl_inf"], 0.6, 0.5, g["D_s"], g["D_l"])
+    assert abs(c[0] - 0.6) < 1e-9 and abs(c[1] - 0.5) < 1e-9
+    assert abs(c[2] - g["cs_inf"]) < 1e-9 and abs(c[3] - g["cl_inf"]) < 1e-9

@@ -225,3 +225,43 @@ def random_state_fields(shape, seed: int, smooth: bool = True):
     rng = np.random.default_rng(seed + 1000)
     c0 = c0 + 0.05 * rng.standard_normal(c0.shape)
     return phi0.reshape(shape), c0.reshape(shape)
+
+
+# --------------------------------------------------------------------------
+# The paper's one-dimensional validation runs (Sec. 4.2) at its own
+# parameters: domain [-0.25, 0.25] x [0, 0.0036], 5000 x 36 D2Q9 nodes,
+# dx = 1e-4, dt = 5e-9, bounce-back walls at x = +-0.25, periodic in y.
+# Diffusivities and mobilities scale by dt / dx^2 = 0.5, lengths by 1 / dx.
+
+PAPER_DX, PAPER_DT = 1e-4, 5e-9
+
+
+def paper_x(nx: int = 5000) -> np.ndarray:
+    """Physical x of the node centres (walls half a cell beyond the ends)."""
+    return -0.25 + (np.arange(nx) + 0.5) * PAPER_DX
+
+
+def paper_validation(kind: str):
+    """(params, phi0, c0) of the dissolution (D_s = 0, anti-trapping,
+    W = 5e-3, lambda* = 230) or precipitation (D_s = 0.9, D_l = 1, no
+    anti-trapping, W = 1.2e-3, lambda* = 277) validation; c^co = (0.6, 0.5),
+    mu_eq = 0.4, M_phi = 1.2, D_l = 1 in physical units."""
+    s = PAPER_DT / PAPER_DX ** 2
+    if kind == "dissolution":
+        W, lam, D_s, at, cs_inf, cl_inf = 5e-3, 230.0, 0.0, 1, 0.6, 0.4
+    elif kind == "precipitation":
+        W, lam, D_s, at, cs_inf, cl_inf = 1.2e-3, 277.0, 0.9, 0, 0.75, 0.4
+    else:
+        raise ValueError(kind)
+    D_l = 1.0 * s
+    p = base_params(lattice=D2Q9, shape=(1, 36, 5000), bc=(ZERO_FLUX, PERIODIC, PERIODIC),
+                    counter_term=1, anti_trapping=at, W=W / PAPER_DX, M_phi=1.2 * s,
+                    D_l=D_l, D_s=D_s * s, a_at=0.25 * (1.0 - D_s / 1.0), lam=lam,
+                    c_s_co=0.6, c_l_co=0.5, mu_eq=0.4)
+    x = paper_x()
+    t = np.tanh(2.0 * x / W)
+    phi1 = 0.5 * (1.0 + t)
+    c1 = 0.5 * (cl_inf + cs_inf + (cl_inf - cs_inf) * t)
+    phi0 = np.broadcast_to(phi1, (1, 36, 5000)).copy()
+    c0 = np.broadcast_to(c1, (1, 36, 5000)).copy()
+    return p, phi0, c0
