@@ -7,6 +7,15 @@ compared to the ones the paper prints for its own runs:
   liquid chemical potential against the one-sided Stefan solution (Eqs.
   x_i_Ds0, Analytical_muL_Ds0) over the liquid x_i(t) < x <= L_x at
   t = 5e-5, 2.5e-4, 5e-4 (printed: 1.6e-3, 7.2e-4, 5.4e-4);
+- the same dissolution with and without anti-trapping (lambda* = 230 and the
+  paper's best-fit 500) at t = 1e-4 over the plotted zoom [-0.015, 0.002]:
+  the chemical potential against the analytic solution (mu_eq in the solid,
+  Eq. Analytical_muL_Ds0 in the liquid), the composition against the
+  semi-analytical solution c^sas = c_l^as phi + c_s^co (1 - phi) (Eqs.
+  Analytical_Cl_Ds0, Semi-AnalyticalSol; the sharp analytic composition
+  jumps at the interface, which a profile of width W cannot follow) (printed:
+  c 3.6e-3 with, 4.8e-3 without; mu 3.5e-3 with, 6.8e-3 without): the
+  anti-trapping current must lower both errors;
 - precipitation, D_s = 0.9, D_l = 1, no anti-trapping, W = 12 cells,
   lambda* = 277: the compositions against the two-sided solution (Eqs.
   x_i_Ds-Dl, Compos_Solid, Compos_Liq) over [-0.04, 0.04] at t = 2.5e-5 and
@@ -97,3 +106,37 @@ def test_precipitation_two_sided_at_paper_parameters(gp):
         errs.append((e, printed))
     for e, printed in errs:
         assert e <= 2.0 * printed
+
+
+def test_anti_trapping_effect_at_paper_parameters(gp):
+    g = json.load(open(GOLDEN))
+    d, e = g["dissolution_validation"], g["anti_trapping_effect"]
+    t = e["t"]
+    steps = int(round(t / wl.PAPER_DT))
+    x = wl.paper_x()
+    m = (x >= e["range"][0]) & (x <= e["range"][1])
+    res = {}
+    for case in ("with", "without"):
+        p, phi0, c0 = wl.paper_validation("dissolution")
+        if case == "without":
+            p = dict(p, anti_trapping=0, lam=e["lambda_without"])
+        alpha = analytic.stefan_alpha(d["mu_eq"], d["mu_inf"], p["c_s_co"] - p["c_l_co"])
+        xi = analytic.stefan_front(alpha, d["D_l"], t)
+        print(f"case anti-trapping {case} t={t} steps={steps}", flush=True)
+        sim = gp.Simulation(p, "fp64").init(phi0, c0)
+        sim.step(steps)
+        phi, c, mu = sim.fields()
+        xs = x[m]
+        mu_l = analytic.stefan_mu_liquid(xs, t, alpha, d["D_l"], d["mu_eq"], d["mu_inf"])
+        mu_as = np.where(xs < xi, d["mu_eq"], mu_l)
+        phi1 = phi[0].mean(axis=0)[m]
+        c_sas = (mu_l + (p["c_l_co"] - d["mu_eq"])) * phi1 + p["c_s_co"] * (1.0 - phi1)
+        ec = _l2(c[0].mean(axis=0)[m], c_sas)
+        emu = _l2(mu[0].mean(axis=0)[m], mu_as)
+        res[case] = (ec, emu)
+        print(f"  L2(c) = {ec:.3e} (printed {e['L2_c'][case]:.1e}), "
+              f"L2(mu) = {emu:.3e} (printed {e['L2_mu'][case]:.1e})", flush=True)
+    for case in ("with", "without"):
+        assert res[case][0] <= 2.0 * e["L2_c"][case]
+        assert res[case][1] <= 2.0 * e["L2_mu"][case]
+    assert res["with"][0] < res["without"][0] and res["with"][1] < res["without"][1]
