@@ -282,10 +282,60 @@ def cpu_baseline(p, phi0, c0, log, budget_s=12.0):
             break
     mlups = n_nodes * steps / dt / 1e6
     log(f"cpu oracle: {mlups:.2f} MLUPS on {oracle.threads()} threads ({steps} steps of {q['shape']})")
+    single = cpu_single_thread(p, log)
     return {"value": round(mlups, 3), "unit": "MLUPS", "cores": oracle.threads(), "kind": "oracle",
             "sample": f"{steps} FP64 steps of the {'x'.join(map(str, q['shape'][::-1]))} crop "
                       f"[0,{q['shape'][-1]}) of the same workload, zero-flux faces, "
-                      f"{dt:.1f} s wall"}
+                      f"{dt:.1f} s wall",
+            "cpu_model": cpu_model(), "single_thread": single}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_SINGLE_THREAD = """
+import sys, time
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+import oracle, workloads as wl
+lat, n = int(sys.argv[2]), int(sys.argv[3])
+shape = (n, n, n) if lat == wl.D3Q19 else (1, n, n)
+p = wl.base_params(lattice=lat, shape=shape, bc=(1, 1, 1 if lat == wl.D3Q19 else 0))
+phi0, c0 = wl.random_state_fields(shape, seed=1)
+o = oracle.Oracle(p).init(phi0, c0)
+o.step(1)
+t0, k = time.perf_counter(), 0
+while time.perf_counter() - t0 < 3.0:
+    o.step(1)
+    k += 1
+print(np.prod(shape) * k / (time.perf_counter() - t0) / 1e6, oracle.threads())
+"""
+
+
+def cpu_single_thread(p, log):
+    """The oracle on one thread (OMP_NUM_THREADS=1, a child process), on a
+    small random instance of the same lattice, about 3 s of stepping."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    n = 48 if p["lattice"] == 1 else 256
+    try:
+        out = subprocess.run([sys.executable, "-c", _SINGLE_THREAD, ROOT, str(p["lattice"]), str(n)],
+                             env=env, capture_output=True, text=True, timeout=120, check=True)
+        v, th = out.stdout.split()
+    except (subprocess.SubprocessError, ValueError) as e:
+        log(f"single-thread oracle timing failed: {e}")
+        return None
+    log(f"cpu oracle, 1 thread: {float(v):.2f} MLUPS")
+    return {"value": round(float(v), 3), "unit": "MLUPS", "threads": int(th),
+            "sample": f"{'x'.join([str(n)] * (3 if p['lattice'] == 1 else 2))} random fields, zero flux, ~3 s"}
 
 
 def main():
