@@ -37,7 +37,7 @@ class _Params(ctypes.Structure):
         ("bc", ctypes.c_int32 * 3),
         ("counter_term", ctypes.c_int32),
         ("anti_trapping", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("h_lattice", ctypes.c_int32),
         ("W", ctypes.c_double), ("M_phi", ctypes.c_double),
         ("lam", ctypes.c_double), ("D_l", ctypes.c_double),
         ("D_s", ctypes.c_double), ("gamma", ctypes.c_double),
@@ -80,6 +80,7 @@ def _load():
         lib.orc_create.argtypes = [P(_Params)]
         lib.orc_destroy.argtypes = [ctypes.c_void_p]
         lib.orc_q.argtypes = [ctypes.c_void_p]
+        lib.orc_qh.argtypes = [ctypes.c_void_p]
         lib.orc_nodes.restype = ctypes.c_int64
         lib.orc_nodes.argtypes = [ctypes.c_void_p]
         lib.orc_step_count.restype = ctypes.c_int64
@@ -108,7 +109,8 @@ class Oracle:
 
     ``cfg`` is a mapping with ``lattice`` (0 D2Q9, 1 D3Q19), ``shape``
     (nz, ny, nx), ``bc`` (per axis x, y, z: 0 periodic, 1 zero flux),
-    ``counter_term``, ``anti_trapping`` and the scalar keys of PARAM_KEYS.
+    ``counter_term``, ``anti_trapping``, the scalar keys of PARAM_KEYS and
+    optionally ``h_lattice`` (0: h on the lattice of g, 1: h on D2Q5 / D3Q7).
     """
 
     def __init__(self, cfg):
@@ -121,6 +123,7 @@ class Oracle:
             p.bc[a] = int(cfg["bc"][a])
         p.counter_term = int(cfg["counter_term"])
         p.anti_trapping = int(cfg["anti_trapping"])
+        p.h_lattice = int(cfg.get("h_lattice", 0))
         for key in PARAM_KEYS:
             setattr(p, key, float(cfg[key]))
         self._p = p
@@ -129,6 +132,7 @@ class Oracle:
         if not self._h:
             raise ValueError("oracle rejected the parameters")
         self.Q = lib.orc_q(self._h)
+        self.Qh = lib.orc_qh(self._h)
         self.N = nx * ny * nz
         self._lib = lib
 
@@ -173,10 +177,10 @@ class Oracle:
     def state(self):
         """Natural state (g, h, phi): populations of shape (Q, nz, ny, nx)."""
         g = np.empty(self.Q * self.N)
-        h = np.empty(self.Q * self.N)
+        h = np.empty(self.Qh * self.N)
         phi = np.empty(self.N)
         self._lib.orc_get_state(self._h, _ptr(g), _ptr(h), _ptr(phi))
-        return (g.reshape((self.Q,) + self.shape), h.reshape((self.Q,) + self.shape),
+        return (g.reshape((self.Q,) + self.shape), h.reshape((self.Qh,) + self.shape),
                 phi.reshape(self.shape))
 
     def set_state(self, g, h, phi, step: int = 0):

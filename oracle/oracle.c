@@ -30,7 +30,9 @@
  *       anti-trapping current, Eq. (Anti-trapping_Equilibrium).
  *   S8  BGK collision of h, Eqs. (LBE_Composition), (Heq_Composition) and
  *       (SourceTerm_LBE_h), with D(phi) = D_l phi + D_s (1 - phi) and
- *       1/(tau_h + 1/2), tau_h = 3 / gamma.
+ *       1/(tau_h + 1/2), tau_h = 1 / (gamma xi_s^2): 3 / gamma on D2Q9,
+ *       D3Q19 and D2Q5 (xi_s^2 = 1/3), 4 / gamma on D3Q7 (xi_s^2 = 1/4), so
+ *       that the diffusivity is D in every case.
  *   S9  streaming of h.
  *
  * Evaluation order.  Every floating-point expression below is written out in
@@ -64,7 +66,11 @@
 /* Velocity sets.  D2Q9 follows the paper's numbering (Sec. 3.1).  D3Q19 is
  * not listed in the paper; its numbering is this oracle's convention and is
  * grouped by e_z: the five e_z=+1 vectors, the rest vector, the eight
- * in-plane moving vectors, the five e_z=-1 vectors.                         */
+ * in-plane moving vectors, the five e_z=-1 vectors.  The lighter sets for
+ * h (the paper names D2Q5 and D3Q7 among the standard lattices, Sec. 3.1):
+ * D2Q5 = the first five vectors of D2Q9, weights 1/3, 1/6 (xi_s^2 = 1/3);
+ * D3Q7 grouped by e_z like D3Q19: (0,0,1), rest, +-x, +-y, (0,0,-1),
+ * weights 1/4 (rest), 1/8 (xi_s^2 = 1/4).                                  */
 
 static const int d2q9_e[9][3] = {
     {0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0},
@@ -86,12 +92,24 @@ static const double d3q19_w[19] = {
     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
     1.0 / 18.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
+static const int d2q5_e[5][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0}};
+static const double d2q5_w[5] = {1.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0};
+static const int d3q7_e[7][3] = {{0, 0, 1}, {0, 0, 0}, {1, 0, 0}, {-1, 0, 0},
+                                 {0, 1, 0}, {0, -1, 0}, {0, 0, -1}};
+static const double d3q7_w[7] = {1.0 / 8.0, 1.0 / 4.0, 1.0 / 8.0, 1.0 / 8.0,
+                                 1.0 / 8.0, 1.0 / 8.0, 1.0 / 8.0};
+
 struct orc_state {
   orc_params p;
-  int Q, D, rest;
+  int Q, D, rest;           /* lattice of g (and of the gradient stencil) */
   int e[19][3];
   int opp[19];
   double w[19];
+  int Qh, resth;            /* lattice of h */
+  int eh[19][3];
+  int opph[19];
+  double wh[19];
+  double cs2h;              /* xi_s^2 of the h lattice */
   int64_t N;
   /* natural state */
   double *g, *h, *phi;
@@ -127,9 +145,9 @@ static double phi_at(const orc_state* s, const double* f, int x, int y, int z,
 /* Source node of the pull x - e_k.  Returns 0 and sets *src when the source
  * lies in the domain (after periodic wrap), 1 when the population crosses a
  * zero-flux wall (halfway bounce-back). */
-static int pull_source(const orc_state* s, int x, int y, int z, int k,
-                       int64_t* src) {
-  int c3[3] = {x - s->e[k][0], y - s->e[k][1], z - s->e[k][2]};
+static int pull_source(const orc_state* s, const int (*e)[3], int x, int y,
+                       int z, int k, int64_t* src) {
+  int c3[3] = {x - e[k][0], y - e[k][1], z - e[k][2]};
   int n3[3] = {s->p.nx, s->p.ny, s->p.nz};
   for (int a = 0; a < 3; ++a) {
     if (c3[a] < 0 || c3[a] >= n3[a]) {
@@ -205,10 +223,10 @@ static void phi_sources(const orc_state* s, double phi, double mu,
   }
 }
 
-/* Equilibrium of h, Eq. (Heq_Composition). */
+/* Equilibrium of h, Eq. (Heq_Composition), on the h lattice. */
 static double h_equilibrium(const orc_state* s, int k, double c, double lam) {
-  if (k == s->rest) return c - (1.0 - s->w[k]) * lam;
-  return s->w[k] * lam;
+  if (k == s->resth) return c - (1.0 - s->wh[k]) * lam;
+  return s->wh[k] * lam;
 }
 
 /* Lambda = gamma D(phi) mu, D(phi) = D_l phi + D_s (1 - phi). */
@@ -217,9 +235,11 @@ static double h_lambda(const orc_params* p, double phi, double mu) {
   return (p->gamma * D) * mu;
 }
 
-/* H_k = gamma w_k e_k . F */
+/* H_k = gamma w_k e_k . F, on the h lattice */
 static double h_source(const orc_state* s, int k, const double* F) {
-  return (s->p.gamma * s->w[k]) * edot(s, k, F);
+  double r = 0.0;
+  for (int a = 0; a < s->D; ++a) r = r + (double)s->eh[k][a] * F[a];
+  return (s->p.gamma * s->wh[k]) * r;
 }
 
 /* ---------------------------------------------------------------------- */
@@ -229,6 +249,7 @@ orc_state* orc_create(const orc_params* p) {
   if (p->lattice != ORC_D2Q9 && p->lattice != ORC_D3Q19) return NULL;
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return NULL;
   if (p->lattice == ORC_D2Q9 && p->nz != 1) return NULL;
+  if (p->h_lattice != 0 && p->h_lattice != 1) return NULL;
   orc_state* s = (orc_state*)calloc(1, sizeof(orc_state));
   s->p = *p;
   if (p->lattice == ORC_D2Q9) {
@@ -246,12 +267,33 @@ orc_state* orc_create(const orc_params* p) {
       if (s->e[j][0] == -s->e[k][0] && s->e[j][1] == -s->e[k][1] &&
           s->e[j][2] == -s->e[k][2])
         s->opp[k] = j;
+  if (p->h_lattice == 0) {
+    s->Qh = s->Q; s->resth = s->rest;
+    memcpy(s->eh, s->e, sizeof(s->e));
+    memcpy(s->wh, s->w, sizeof(s->w));
+    s->cs2h = 1.0 / 3.0;
+  } else if (p->lattice == ORC_D2Q9) {
+    s->Qh = 5; s->resth = 0;
+    memcpy(s->eh, d2q5_e, sizeof(d2q5_e));
+    memcpy(s->wh, d2q5_w, sizeof(d2q5_w));
+    s->cs2h = 1.0 / 3.0;
+  } else {
+    s->Qh = 7; s->resth = 1;
+    memcpy(s->eh, d3q7_e, sizeof(d3q7_e));
+    memcpy(s->wh, d3q7_w, sizeof(d3q7_w));
+    s->cs2h = 1.0 / 4.0;
+  }
+  for (int k = 0; k < s->Qh; ++k)
+    for (int j = 0; j < s->Qh; ++j)
+      if (s->eh[j][0] == -s->eh[k][0] && s->eh[j][1] == -s->eh[k][1] &&
+          s->eh[j][2] == -s->eh[k][2])
+        s->opph[k] = j;
   s->N = (int64_t)p->nx * p->ny * p->nz;
-  int64_t N = s->N, Q = s->Q;
+  int64_t N = s->N, Q = s->Q, Qh = s->Qh;
   s->g = (double*)calloc(Q * N, sizeof(double));
-  s->h = (double*)calloc(Q * N, sizeof(double));
+  s->h = (double*)calloc(Qh * N, sizeof(double));
   s->gs = (double*)calloc(Q * N, sizeof(double));
-  s->hs = (double*)calloc(Q * N, sizeof(double));
+  s->hs = (double*)calloc(Qh * N, sizeof(double));
   s->phi = (double*)calloc(N, sizeof(double));
   s->phin = (double*)calloc(N, sizeof(double));
   s->c = (double*)calloc(N, sizeof(double));
@@ -276,6 +318,7 @@ void orc_destroy(orc_state* s) {
 }
 
 int orc_q(const orc_state* s) { return s->Q; }
+int orc_qh(const orc_state* s) { return s->Qh; }
 int64_t orc_nodes(const orc_state* s) { return s->N; }
 int64_t orc_step_count(const orc_state* s) { return s->step; }
 
@@ -291,7 +334,7 @@ int orc_threads(void) {
  * initial populations is in the file header). */
 int orc_init(orc_state* s, const double* phi0, const double* c0) {
   const orc_params* p = &s->p;
-  const int nx = p->nx, ny = p->ny, nz = p->nz, Q = s->Q;
+  const int nx = p->nx, ny = p->ny, nz = p->nz, Q = s->Q, Qh = s->Qh;
   const int64_t N = s->N;
   memcpy(s->phi, phi0, N * sizeof(double));
 #pragma omp parallel for
@@ -305,7 +348,7 @@ int orc_init(orc_state* s, const double* phi0, const double* c0) {
     for (int k = 0; k < Q; ++k) s->g[k * N + i] = s->w[k] * phi - 0.5 * G[k];
     for (int a = 0; a < s->D; ++a) F[a] = (mu * (p->D_l - p->D_s)) * g3[a];
     double lam = h_lambda(p, phi, mu);
-    for (int k = 0; k < Q; ++k)
+    for (int k = 0; k < Qh; ++k)
       s->h[k * N + i] = h_equilibrium(s, k, c, lam) - 0.5 * h_source(s, k, F);
   }
   (void)ny; (void)nz;
@@ -317,10 +360,10 @@ int orc_init(orc_state* s, const double* phi0, const double* c0) {
 /* One time step n -> n+1 (S1..S9). */
 static void step_once(orc_state* s) {
   const orc_params* p = &s->p;
-  const int nx = p->nx, ny = p->ny, Q = s->Q, D = s->D;
+  const int nx = p->nx, ny = p->ny, Q = s->Q, Qh = s->Qh, D = s->D;
   const int64_t N = s->N;
   const double omega_g = 1.0 / (3.0 * p->M_phi + 0.5);
-  const double omega_h = 1.0 / (3.0 / p->gamma + 0.5);
+  const double omega_h = 1.0 / (1.0 / (p->gamma * s->cs2h) + 0.5);
   const double dc = p->c_s_co - p->c_l_co;
 
   /* S1-S4: moments, closure, gradient, sources, collision of g. */
@@ -328,7 +371,7 @@ static void step_once(orc_state* s) {
   for (int64_t i = 0; i < N; ++i) {
     int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
     double c = 0.0;
-    for (int k = 0; k < Q; ++k) c = c + s->h[k * N + i];
+    for (int k = 0; k < Qh; ++k) c = c + s->h[k * N + i];
     double phi = s->phi[i];
     double mu = closure(p, c, phi);
     double g3[3], n3[3], G[19], sbar;
@@ -353,7 +396,7 @@ static void step_once(orc_state* s) {
     int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
     for (int k = 0; k < Q; ++k) {
       int64_t src;
-      if (pull_source(s, x, y, z, k, &src))
+      if (pull_source(s, s->e, x, y, z, k, &src))
         s->g[k * N + i] = s->gs[s->opp[k] * N + i];
       else
         s->g[k * N + i] = s->gs[k * N + src];
@@ -379,7 +422,7 @@ static void step_once(orc_state* s) {
       F[a] = (mu * (p->D_l - p->D_s)) * s->grad[3 * i + a] + j;
     }
     double lam = h_lambda(p, phi, mu);
-    for (int k = 0; k < Q; ++k) {
+    for (int k = 0; k < Qh; ++k) {
       double hk = s->h[k * N + i];
       double Hk = h_source(s, k, F);
       double t = (hk - h_equilibrium(s, k, c, lam)) + 0.5 * Hk;
@@ -390,10 +433,10 @@ static void step_once(orc_state* s) {
 #pragma omp parallel for
   for (int64_t i = 0; i < N; ++i) {
     int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
-    for (int k = 0; k < Q; ++k) {
+    for (int k = 0; k < Qh; ++k) {
       int64_t src;
-      if (pull_source(s, x, y, z, k, &src))
-        s->h[k * N + i] = s->hs[s->opp[k] * N + i];
+      if (pull_source(s, s->eh, x, y, z, k, &src))
+        s->h[k * N + i] = s->hs[s->opph[k] * N + i];
       else
         s->h[k * N + i] = s->hs[k * N + src];
     }
@@ -411,7 +454,7 @@ int orc_step(orc_state* s, int64_t nsteps) {
 /* phi^n, c^n and mu^n at the current time. */
 void orc_fields(const orc_state* s, double* phi, double* c, double* mu) {
   const int64_t N = s->N;
-  const int Q = s->Q;
+  const int Q = s->Qh;
 #pragma omp parallel for
   for (int64_t i = 0; i < N; ++i) {
     double cc = 0.0;
@@ -439,17 +482,17 @@ void orc_gradient(const orc_state* s, double* grad3, double* nrm3) {
 }
 
 void orc_get_state(const orc_state* s, double* g, double* h, double* phi) {
-  const int64_t QN = (int64_t)s->Q * s->N;
+  const int64_t QN = (int64_t)s->Q * s->N, QhN = (int64_t)s->Qh * s->N;
   if (g) memcpy(g, s->g, QN * sizeof(double));
-  if (h) memcpy(h, s->h, QN * sizeof(double));
+  if (h) memcpy(h, s->h, QhN * sizeof(double));
   if (phi) memcpy(phi, s->phi, s->N * sizeof(double));
 }
 
 void orc_set_state(orc_state* s, const double* g, const double* h,
                    const double* phi, int64_t step) {
-  const int64_t QN = (int64_t)s->Q * s->N;
+  const int64_t QN = (int64_t)s->Q * s->N, QhN = (int64_t)s->Qh * s->N;
   memcpy(s->g, g, QN * sizeof(double));
-  memcpy(s->h, h, QN * sizeof(double));
+  memcpy(s->h, h, QhN * sizeof(double));
   memcpy(s->phi, phi, s->N * sizeof(double));
   s->step = step;
   s->ready = 1;
@@ -461,7 +504,7 @@ void orc_set_state(orc_state* s, const double* g, const double* h,
  * out[6] 1 if any phi or c is not finite, out[7] step. */
 void orc_diagnostics(const orc_state* s, double* out) {
   const int64_t N = s->N;
-  const int Q = s->Q;
+  const int Q = s->Qh;
   double mass = 0.0, solid = 0.0, count = 0.0, sphi = 0.0;
   double mn = INFINITY, mx = -INFINITY;
   int bad = 0;

@@ -21,7 +21,7 @@ typedef struct {
   int32_t bc[3];
   int32_t counter_term;  /* 1: counter term G^ct_k, 0: double-well term G^dw */
   int32_t anti_trapping; /* 1: anti-trapping current in the h source */
-  int32_t pad_;
+  int32_t h_lattice;     /* 0: h on the lattice of g; 1: h on D2Q5 / D3Q7 */
   double W, M_phi, lambda, D_l, D_s, gamma, a_at;
   double c_s_co, c_l_co, mu_eq, eps_n;
 } orc_params;
@@ -30,7 +30,8 @@ typedef struct orc_state orc_state;
 
 orc_state* orc_create(const orc_params* p);
 void orc_destroy(orc_state* s);
-int orc_q(const orc_state* s);
+int orc_q(const orc_state* s);  /* populations of g */
+int orc_qh(const orc_state* s); /* populations of h */
 int64_t orc_nodes(const orc_state* s);
 int64_t orc_step_count(const orc_state* s);
 int orc_threads(void);

@@ -78,7 +78,17 @@ D3Q19_E = np.array([[0, 0, 1], [1, 0, 1], [-1, 0, 1], [0, 1, 1], [0, -1, 1],
                    dtype=np.float64)
 
 
-def first_moment(f, lattice):
+# the light sets for h: D2Q5 = the first five vectors of D2Q9; D3Q7 grouped
+# by e_z like D3Q19
+D2Q5_E = D2Q9_E[:5]
+D3Q7_E = np.array([[0, 0, 1], [0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0],
+                   [0, 0, -1]], dtype=np.float64)
+
+
+def first_moment(f, lattice, light=False):
     """sum_k e_k f_k for populations f of shape (Q, nz, ny, nx) -> (nz, ny, nx, 3)."""
-    e = D2Q9_E if lattice == 0 else D3Q19_E
+    if light:
+        e = D2Q5_E if lattice == 0 else D3Q7_E
+    else:
+        e = D2Q9_E if lattice == 0 else D3Q19_E
     return np.einsum("ka,k...->...a", e, f)

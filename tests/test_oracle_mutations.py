@@ -2,8 +2,8 @@
 
 Each entry below plants one plausible slip in a copy of oracle.c (a dropped
 term or factor, a flipped sign, a wrong index, a transposed operand, a wrong
-table entry), builds the copy, and runs the pins of test_oracle_pins.py
-against it.  Every mutant must make at least one pin fail: a pin set that
+table entry, for the full lattices and for the light h lattices), builds the
+copy, and runs the pins of test_oracle_pins.py against it.  Every mutant must make at least one pin fail: a pin set that
 lets one through does not pin that part of the oracle.  The shipped oracle
 is never modified; the mutants live in a temporary directory.
 """
@@ -74,9 +74,12 @@ MUTANTS = [
     ("g relaxation: M = 3 tau instead of tau / 3",
      "const double omega_g = 1.0 / (3.0 * p->M_phi + 0.5);",
      "const double omega_g = 1.0 / (p->M_phi / 3.0 + 0.5);"),
-    ("h relaxation: tau_h = 1/gamma instead of 3/gamma",
-     "const double omega_h = 1.0 / (3.0 / p->gamma + 0.5);",
+    ("h relaxation: tau_h = 1/gamma instead of 1/(gamma xi_s^2)",
+     "const double omega_h = 1.0 / (1.0 / (p->gamma * s->cs2h) + 0.5);",
      "const double omega_h = 1.0 / (1.0 / p->gamma + 0.5);"),
+    ("h relaxation: D3Q7 with the xi_s^2 of D3Q19",
+     "    s->cs2h = 1.0 / 4.0;",
+     "    s->cs2h = 1.0 / 3.0;"),
     ("phi^{n+1}: half source moment dropped",
      "s->phin[i] = sum + 0.5 * s->sbar[i];",
      "s->phin[i] = sum;"),
@@ -93,26 +96,32 @@ MUTANTS = [
      "double D = (p->D_l * phi) + (p->D_s * (1.0 - phi));",
      "double D = (p->D_s * phi) + (p->D_l * (1.0 - phi));"),
     ("h source: gamma dropped",
-     "return (s->p.gamma * s->w[k]) * edot(s, k, F);",
-     "return (s->w[k]) * edot(s, k, F);"),
+     "return (s->p.gamma * s->wh[k]) * r;",
+     "return (s->wh[k]) * r;"),
     ("h equilibrium: rest population c - Lambda",
-     "if (k == s->rest) return c - (1.0 - s->w[k]) * lam;",
-     "if (k == s->rest) return c - lam;"),
+     "if (k == s->resth) return c - (1.0 - s->wh[k]) * lam;",
+     "if (k == s->resth) return c - lam;"),
     ("h collision: trapezoidal half source dropped",
      "double t = (hk - h_equilibrium(s, k, c, lam)) + 0.5 * Hk;",
      "double t = (hk - h_equilibrium(s, k, c, lam));"),
     ("moment c: first population skipped",
-     "for (int k = 0; k < Q; ++k) c = c + s->h[k * N + i];",
-     "for (int k = 1; k < Q; ++k) c = c + s->h[k * N + i];"),
+     "for (int k = 0; k < Qh; ++k) c = c + s->h[k * N + i];",
+     "for (int k = 1; k < Qh; ++k) c = c + s->h[k * N + i];"),
     ("g bounce-back: population not reversed",
      "s->g[k * N + i] = s->gs[s->opp[k] * N + i];",
      "s->g[k * N + i] = s->gs[k * N + i];"),
     ("h bounce-back: population not reversed",
-     "s->h[k * N + i] = s->hs[s->opp[k] * N + i];",
+     "s->h[k * N + i] = s->hs[s->opph[k] * N + i];",
      "s->h[k * N + i] = s->hs[k * N + i];"),
+    ("D3Q7 table: rest and axis weights swapped",
+     "static const double d3q7_w[7] = {1.0 / 8.0, 1.0 / 4.0, 1.0 / 8.0, 1.0 / 8.0,",
+     "static const double d3q7_w[7] = {1.0 / 8.0, 1.0 / 8.0, 1.0 / 4.0, 1.0 / 8.0,"),
+    ("D2Q5 table: weights of D2Q9",
+     "static const double d2q5_w[5] = {1.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0};",
+     "static const double d2q5_w[5] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0};"),
     ("streaming: pull from x + e_k",
-     "int c3[3] = {x - s->e[k][0], y - s->e[k][1], z - s->e[k][2]};",
-     "int c3[3] = {x + s->e[k][0], y + s->e[k][1], z + s->e[k][2]};"),
+     "int c3[3] = {x - e[k][0], y - e[k][1], z - e[k][2]};",
+     "int c3[3] = {x + e[k][0], y + e[k][1], z + e[k][2]};"),
     ("wall ghost: periodic copy instead of mirror",
      "return v < 0 ? 0 : n - 1;",
      "return (v + n) % n;"),

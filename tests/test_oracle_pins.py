@@ -85,10 +85,13 @@ def test_table3_K_printed_vs_integrand():
 # Closed-form solutions
 
 
-def test_stefan_dissolution_front_and_profile(oracle_mod):
+@pytest.mark.parametrize("h_lattice", [0, 1])
+def test_stefan_dissolution_front_and_profile(oracle_mod, h_lattice):
     """Workload 0 (planar dissolution, D_s = 0, anti-trapping, lambda*)
-    against the one-sided Stefan solution of Sec. 4.2."""
+    against the one-sided Stefan solution of Sec. 4.2, with h on D2Q9 and
+    on D2Q5."""
     p, phi0, c0, nsteps = wl.config0()
+    p = dict(p, h_lattice=h_lattice)
     mu_inf = p["mu_eq"] + 0.0 - p["c_l_co"]
     alpha = analytic.stefan_alpha(p["mu_eq"], mu_inf, p["c_s_co"] - p["c_l_co"])
     assert abs(alpha - (-0.0586022)) < 1e-6
@@ -132,18 +135,30 @@ def test_circle_curvature_flow(oracle_mod, counter_term):
         assert abs(rate / (2 * M) - 1.0) < 0.03, rate
 
 
-def test_ade_fourier_mode_decay(oracle_mod):
+@pytest.mark.parametrize("lattice,h_lattice,axis", [
+    (0, 0, 2), (0, 1, 2), (0, 1, 1), (1, 0, 0), (1, 1, 0), (1, 1, 2)])
+def test_ade_fourier_mode_decay(oracle_mod, lattice, h_lattice, axis):
     """phi = 1 everywhere: the c-LBE reduces to the textbook advection-free
-    diffusion LBM, so a Fourier mode of c decays as exp(-D_l k^2 t)."""
+    diffusion LBM, so a Fourier mode of c decays as exp(-D_l k^2 t) -- on
+    the full lattices and on the light ones (D2Q5, D3Q7, whose xi_s^2 = 1/4
+    sets tau_h = 4 / gamma), along x, y and z (axis 2, 1, 0 of the array)."""
     L = 128
-    p = wl.base_params(shape=(1, 4, L), bc=(0, 0, 0))
-    x = np.arange(L)
+    shape = [1 if lattice == 0 else 2, 2, 2]
+    shape[axis] = L
+    shape = tuple(shape)
+    p = wl.base_params(lattice=lattice, shape=shape, bc=(0, 0, 0), h_lattice=h_lattice)
     k = 2 * np.pi / L
-    phi0 = np.ones((1, 4, L))
-    c0 = p["c_l_co"] + 0.01 * np.broadcast_to(np.cos(k * x), (1, 4, L))
+    idx = [None, None, None]
+    idx[axis] = slice(None)
+    mode = np.cos(k * np.arange(L))[tuple(idx)]
+    phi0 = np.ones(shape)
+    c0 = p["c_l_co"] + 0.01 * np.broadcast_to(mode, shape)
     o = oracle_mod.Oracle(p).init(phi0, c0)
     o.step(100)
-    amp = lambda: 2 * np.abs(np.fft.rfft(o.fields()[1][0, 0])[1]) / L
+
+    def amp():
+        line = np.moveaxis(o.fields()[1], axis, -1).reshape(-1, L)[0]
+        return 2 * np.abs(np.fft.rfft(line)[1]) / L
     a0 = amp()
     o.step(2000)
     a1 = amp()
@@ -156,17 +171,19 @@ def test_ade_fourier_mode_decay(oracle_mod):
 # Conservation laws and special cases
 
 
-@pytest.mark.parametrize("lattice,shape,bc", [
-    (0, (1, 24, 40), (1, 0, 0)),
-    (0, (1, 24, 40), (1, 1, 0)),
-    (0, (1, 24, 40), (0, 0, 0)),
-    (1, (10, 12, 14), (1, 0, 1)),
-    (1, (10, 12, 14), (0, 0, 0)),
+@pytest.mark.parametrize("lattice,shape,bc,h_lattice", [
+    (0, (1, 24, 40), (1, 0, 0), 0),
+    (0, (1, 24, 40), (1, 1, 0), 0),
+    (0, (1, 24, 40), (0, 0, 0), 0),
+    (1, (10, 12, 14), (1, 0, 1), 0),
+    (1, (10, 12, 14), (0, 0, 0), 0),
+    (0, (1, 24, 40), (1, 1, 0), 1),
+    (1, (10, 12, 14), (1, 0, 1), 1),
 ])
-def test_solute_mass_conserved(oracle_mod, lattice, shape, bc):
+def test_solute_mass_conserved(oracle_mod, lattice, shape, bc, h_lattice):
     """sum_k h^eq_k = c, sum_k H_k = 0 and streaming permutes populations, so
     the total solute is conserved to round-off (Eq. Moment0_LBM_Concent)."""
-    p = wl.base_params(lattice=lattice, shape=shape, bc=bc)
+    p = wl.base_params(lattice=lattice, shape=shape, bc=bc, h_lattice=h_lattice)
     phi0, c0 = wl.random_state_fields(shape, seed=3)
     o = oracle_mod.Oracle(p).init(phi0, c0)
     m0 = o.diagnostics()["total_mass"]
@@ -326,8 +343,8 @@ def test_uniform_fields_follow_the_source_recurrence(oracle_mod, counter_term):
     assert np.max(np.abs(c - c0)) < 1e-14
 
 
-@pytest.mark.parametrize("lattice", [0, 1])
-def test_wall_is_a_mirror_plane_for_wall_normal_fields(oracle_mod, lattice):
+@pytest.mark.parametrize("lattice,h_lattice", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_wall_is_a_mirror_plane_for_wall_normal_fields(oracle_mod, lattice, h_lattice):
     """For fields that vary only across a zero-flux wall, halfway bounce-back
     (the oblique populations that bounce and those that would mirror are
     equal by symmetry) and the mirror ghost of the gradient stencil make the
@@ -335,7 +352,7 @@ def test_wall_is_a_mirror_plane_for_wall_normal_fields(oracle_mod, lattice):
     first half of the periodic run on [0, 2n) from the mirrored fields."""
     n = 24
     shape = (1, 4, n) if lattice == 0 else (2, 2, n)
-    p = wl.base_params(lattice=lattice, shape=shape, bc=(1, 0, 0))
+    p = wl.base_params(lattice=lattice, shape=shape, bc=(1, 0, 0), h_lattice=h_lattice)
     p2 = dict(p, shape=shape[:2] + (2 * n,), bc=(0, 0, 0))
     x = np.arange(n, dtype=np.float64)
     phi1 = wl.tanh_profile(x - 5.0, p["W"])          # front two cells off the wall
@@ -353,8 +370,8 @@ def test_wall_is_a_mirror_plane_for_wall_normal_fields(oracle_mod, lattice):
         assert np.max(np.abs(fa - fb[..., :n])) < 1e-12
 
 
-@pytest.mark.parametrize("lattice", [0, 1])
-def test_initial_populations_are_shifted_equilibria(oracle_mod, lattice):
+@pytest.mark.parametrize("lattice,h_lattice", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_initial_populations_are_shifted_equilibria(oracle_mod, lattice, h_lattice):
     """Reading (the paper does not give the initial populations): at t = 0
     the populations before the variable change, g~ + G/2 and h~ + H/2, are
     the equilibria, with no anti-trapping current.  Checked by moments at
@@ -366,7 +383,7 @@ def test_initial_populations_are_shifted_equilibria(oracle_mod, lattice):
     second moment of the weights is 1/3)."""
     shape = (1, 9, 11) if lattice == 0 else (7, 9, 11)
     p = wl.base_params(lattice=lattice, shape=shape, bc=(1, 1, 1 if lattice else 0),
-                       D_s=0.02)
+                       D_s=0.02, h_lattice=h_lattice)
     nz, ny, nx = shape
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     b = np.array([0.031, -0.023, 0.019 if lattice else 0.0])
@@ -385,9 +402,10 @@ def test_initial_populations_are_shifted_equilibria(oracle_mod, lattice):
     assert np.max(np.abs(g.sum(0) - (phi0 - 0.5 * Sst))[inner]) < 1e-14
     assert np.max(np.abs(h.sum(0) - c0)[inner]) < 1e-14
     m1g = analytic.first_moment(g, lattice)
-    m1h = analytic.first_moment(h, lattice)
+    m1h = analytic.first_moment(h, lattice, light=bool(h_lattice))
+    cs2h = 0.25 if (lattice == 1 and h_lattice) else 1.0 / 3.0
     want_g = -(kphi / 6.0)[..., None] * nrm
-    want_h = -(p["gamma"] / 6.0) * F
+    want_h = -(p["gamma"] * cs2h / 2.0) * F
     assert np.max(np.abs(m1g - want_g)[inner]) < 1e-14
     assert np.max(np.abs(m1h - want_h)[inner]) < 1e-14
     assert np.max(np.abs(want_h[inner])) > 1e-3 and np.max(np.abs(want_g[inner])) > 1e-2
