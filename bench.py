@@ -11,13 +11,15 @@ initialised before the timed region.
 Printed: one JSON line with MLUPS (million node updates per second), the
 HBM roofline of the step kernel (algorithmic bytes per launch over the mean
 launch time, measured with HIP events on the stream the library launches on),
-the other precision forms of the same step beside it (FP32, FP16 and BF16
-deviation storage), the differentiation workload (adjoint / forward time),
-and the CPU oracle timed on a bounded crop of the same workload.
+the other forms of the same step beside it (FP32, FP16 and BF16 deviation
+storage; h on the light lattice D3Q7 / D2Q5 in FP64 and FP32), the
+differentiation workload (adjoint / forward time), and the CPU oracle timed on
+a bounded crop of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--precision fp64|fp32|fp16dev|bf16dev]
-                    [--schedule auto|split|fused] [--workload NAME]
-                    [--no-cpu-baseline] [--no-forms] [--adjoint-steps K] [--variants]
+                    [--h-lattice full|light] [--schedule auto|split|fused]
+                    [--workload NAME] [--no-cpu-baseline] [--no-forms]
+                    [--adjoint-steps K] [--variants]
 """
 from __future__ import annotations
 
@@ -35,15 +37,23 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 PROFILE_CMD = ""
 
 
-def bytes_per_node_step(lattice_q: int, precision: str) -> int:
+def bytes_per_node_step(lattice_q: int, precision: str, lattice_qh: int | None = None) -> int:
     """Algorithmic bytes each node-step must move: read and write both
-    distributions once, and read and write the carried phi field (and, for the
-    16-bit deviation formats, the Lambda field their h references need)."""
+    distributions once (Q populations of g, Qh of h), and read and write the
+    carried phi field (and, for the 16-bit deviation formats, the Lambda field
+    their h references need)."""
+    qh = lattice_q if lattice_qh is None else lattice_qh
     if precision in ("fp16dev", "bf16dev"):
         dist = (lattice_q - 1) * 2 + 4          # 16-bit moving + FP32 rest
         return 2 * (2 * dist + 4 + 4)
     elem = 8 if precision == "fp64" else 4
-    return (4 * lattice_q + 2) * elem
+    return (2 * lattice_q + 2 * qh + 2) * elem
+
+
+def form_name(precision: str, h_lattice: str) -> str:
+    """Label of a form of the step: the precision, with '_light_h' when h
+    runs on D3Q7 / D2Q5."""
+    return precision + ("_light_h" if h_lattice == "light" else "")
 
 
 WORKLOADS = {
@@ -66,10 +76,11 @@ def make_workload(name):
     return p, phi0, c0
 
 
-def time_gpu(p, phi0, c0, precision, schedule, steps, warmup, log):
+def time_gpu(p, phi0, c0, precision, schedule, steps, warmup, log, h_lattice="full"):
     import torch
     from paper_2111_05960_amd import Simulation
 
+    p = dict(p, h_lattice=1 if h_lattice == "light" else 0)
     sim = Simulation(p, precision, schedule)
     sim.init(phi0, c0)
     torch.cuda.synchronize()
@@ -90,17 +101,17 @@ def time_gpu(p, phi0, c0, precision, schedule, steps, warmup, log):
     d1 = sim.diagnostics(allow_nonfinite=True)
     N = sim.N
     launches = 1 if sim.schedule == "fused" else 2
-    balg = bytes_per_node_step(sim.Q, precision)
+    balg = bytes_per_node_step(sim.Q, precision, sim.Qh)
     ms_step = ms / steps
     res = dict(
         mlups=N * steps / (ms * 1e-3) / 1e6, ms_per_step=ms_step, wall_s=wall,
-        schedule=sim.schedule, launches_per_step=launches, nodes=N, Q=sim.Q,
+        schedule=sim.schedule, launches_per_step=launches, nodes=N, Q=sim.Q, Qh=sim.Qh,
         bytes_per_node_step=balg,
         achieved_gbs=balg * N / (ms_step * 1e-3) / 1e9,
         mass_drift_rel=abs(d1["total_mass"] - d0["total_mass"]) / abs(d0["total_mass"]),
         nonfinite=d1["nonfinite"], solid_fraction=[d0["solid_fraction"], d1["solid_fraction"]],
     )
-    log(f"gpu {precision} {sim.schedule}: {res['mlups']:.1f} MLUPS, {ms_step:.3f} ms/step, "
+    log(f"gpu {form_name(precision, h_lattice)} {sim.schedule}: {res['mlups']:.1f} MLUPS, {ms_step:.3f} ms/step, "
         f"{res['achieved_gbs']:.0f} GB/s algorithmic, mass drift {res['mass_drift_rel']:.2e}")
     del sim
     torch.cuda.empty_cache()
@@ -345,6 +356,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="porous3d_512_d3q19", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp16dev", "bf16dev"])
+    ap.add_argument("--h-lattice", default="full", choices=["full", "light"],
+                    help="h on the lattice of g, or on D3Q7 / D2Q5 (FP64 and FP32)")
     ap.add_argument("--schedule", default="auto", choices=["auto", "split", "fused"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
@@ -366,7 +379,7 @@ def main():
         global PROFILE_CMD
         PROFILE_CMD = args.profile_cmd
         summarize_profile(args.profile_kind, args.summarize_profile, args.out, args.workload,
-                          args.precision, args.schedule)
+                          form_name(args.precision, args.h_lattice), args.schedule)
         return
 
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
@@ -386,17 +399,21 @@ def main():
     p, phi0, c0 = make_workload(args.workload)
     log(f"workload {args.workload} generated in {time.perf_counter() - t0:.1f} s")
 
-    main_res = time_gpu(p, phi0, c0, args.precision, args.schedule, args.steps, args.warmup, log)
-    # the other precision forms of the same step, side by side (auto schedule)
+    main_form = form_name(args.precision, args.h_lattice)
+    main_res = time_gpu(p, phi0, c0, args.precision, args.schedule, args.steps, args.warmup, log,
+                        args.h_lattice)
+    # the other forms of the same step, side by side (auto schedule)
     forms = {}
     if not args.no_forms:
         precs = ("fp64", "fp32") + (("fp16dev", "bf16dev") if p["lattice"] == 1 else ())
-        for prec in precs:
-            if prec == args.precision:
+        todo = [(prec, "full") for prec in precs] + [("fp64", "light"), ("fp32", "light")]
+        for prec, hl in todo:
+            name = form_name(prec, hl)
+            if name == main_form:
                 continue
-            r = time_gpu(p, phi0, c0, prec, "auto", args.steps, args.warmup, log)
-            t = stored_traffic(args.workload, prec, r["schedule"])
-            forms[prec] = {
+            r = time_gpu(p, phi0, c0, prec, "auto", args.steps, args.warmup, log, hl)
+            t = stored_traffic(args.workload, name, r["schedule"])
+            forms[name] = {
                 "mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
                 "schedule": r["schedule"], "bytes_per_node_step": r["bytes_per_node_step"],
                 "achieved_gbs": round(r["achieved_gbs"], 1),
@@ -425,7 +442,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p, phi0, c0, log)
-    traffic = stored_traffic(args.workload, args.precision, main_res["schedule"])
+    traffic = stored_traffic(args.workload, main_form, main_res["schedule"])
 
     nz, ny, nx = p["shape"]
     achieved = main_res["achieved_gbs"]
@@ -446,6 +463,8 @@ def main():
         "config": {
             "workload": args.workload,
             "lattice": "D3Q19" if p["lattice"] == 1 else "D2Q9",
+            "h_lattice": {(1, "full"): "D3Q19", (1, "light"): "D3Q7", (0, "full"): "D2Q9",
+                          (0, "light"): "D2Q5"}[(p["lattice"], args.h_lattice)],
             "grid": [nx, ny, nz],
             "bc": "periodic",
             "precision": args.precision,

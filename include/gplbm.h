@@ -7,7 +7,8 @@
  * device address on the device that was current when gplbm_create ran; the
  * stream argument is a hipStream_t passed as void*.
  *
- * What one step computes (lattice units dx = dt = 1, xi_s^2 = 1/3):
+ * What one step computes (lattice units dx = dt = 1; xi_s^2 = 1/3 on D2Q9,
+ * D3Q19 and D2Q5, 1/4 on D3Q7):
  *   - phi-LBE, Sec. 3.2: BGK collision with trapezoidal source,
  *     Eq. (LBE_PhaseField_Eq), g^eq = w_k phi (Eq. Geq_Allen-Cahn_Eq-1),
  *     sources Eqs. (TermG), (SourceG_ST), (SourceG_dw) / (SourceG_CT) with
@@ -52,9 +53,18 @@ extern "C" {
 #define GPLBM_E_NONFINITE (-4) /* diagnostics found a non-finite phi or c */
 #define GPLBM_E_STATE (-5)     /* step / read before gplbm_init_fields */
 
-/* lattices (the same lattice serves both distributions) */
+/* lattices of g (phi); h (c) runs on the same one or on the light one */
 #define GPLBM_D2Q9 0
 #define GPLBM_D3Q19 1
+
+/* lattice of h.  LIGHT: D2Q5 under D2Q9, D3Q7 under D3Q19 (Sec. 3.3 leaves
+ * the lattice of the c-LBE open; its equilibrium needs only the zeroth and
+ * an isotropic second moment).  The relaxation time becomes
+ * tau_h = 1 / (gamma xi_s^2) (3 / gamma, or 4 / gamma on D3Q7) so that the
+ * diffusivity stays D(phi); H_k = gamma w_k e_k . F on the h lattice.  FP64
+ * and FP32 only; no adjoint. */
+#define GPLBM_H_FULL 0
+#define GPLBM_H_LIGHT 1
 
 /* boundary conditions per axis */
 #define GPLBM_PERIODIC 0
@@ -84,12 +94,12 @@ typedef struct gplbm_params {
   int32_t counter_term;  /* 1: counter term G^ct_k (Eq. ModelA_EqPhi_CounterTerm); 0: G^dw */
   int32_t anti_trapping; /* 1: anti-trapping current in the h source */
   int32_t schedule;      /* GPLBM_SCHED_* */
-  int32_t reserved;      /* must be 0 */
+  int32_t h_lattice;     /* GPLBM_H_FULL or GPLBM_H_LIGHT */
   double W;              /* interface width */
   double M_phi;          /* phase-field mobility; tau_g = 3 M_phi */
   double lambda;         /* coupling constant */
   double D_l, D_s;       /* diffusivities of liquid and solid */
-  double gamma;          /* relaxation control of the c-LBE; tau_h = 3 / gamma */
+  double gamma;          /* relaxation control of the c-LBE; tau_h = 1 / (gamma xi_s^2) */
   double a_at;           /* anti-trapping coefficient a (1/4 for D_s = 0) */
   double c_s_co, c_l_co; /* coexistence compositions */
   double mu_eq;          /* equilibrium chemical potential */
@@ -182,8 +192,9 @@ int gplbm_load_state(gplbm_ctx* ctx, const void* dev_src, int64_t step);
  *   writes dJ/dphi0 and dJ/dc0 (device, N doubles) and dJ/dlambda, dJ/dD_l into
  *   dJ_dparams (host, 2 doubles).  Parameter sums are reduced in a fixed
  *   order.  Synchronises the stream.
- * Return GPLBM_E_INVALID for FP16/BF16-deviation contexts or null pointers,
- * GPLBM_E_SIZE for a short workspace, GPLBM_E_STATE out of order. */
+ * Return GPLBM_E_INVALID for FP16/BF16-deviation or GPLBM_H_LIGHT contexts
+ * or null pointers, GPLBM_E_SIZE for a short workspace, GPLBM_E_STATE out of
+ * order. */
 int gplbm_adjoint_bytes(const gplbm_params* p, uint64_t* bytes);
 int gplbm_adjoint_begin(gplbm_ctx* ctx, void* work, uint64_t bytes, const double* phi_bar,
                         const double* c_bar);

@@ -26,6 +26,7 @@ GPLBM_E_NONFINITE = -4
 GPLBM_E_STATE = -5
 
 GPLBM_D2Q9, GPLBM_D3Q19 = 0, 1
+GPLBM_H_FULL, GPLBM_H_LIGHT = 0, 1
 GPLBM_PERIODIC, GPLBM_ZERO_FLUX = 0, 1
 GPLBM_FP64, GPLBM_FP32, GPLBM_FP16_DEV, GPLBM_BF16_DEV = 0, 1, 2, 3
 GPLBM_SCHED_AUTO, GPLBM_SCHED_SPLIT, GPLBM_SCHED_FUSED = 0, 1, 2
@@ -51,7 +52,7 @@ class gplbm_params(ctypes.Structure):
         ("counter_term", ctypes.c_int32),
         ("anti_trapping", ctypes.c_int32),
         ("schedule", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("h_lattice", ctypes.c_int32),
         ("W", ctypes.c_double), ("M_phi", ctypes.c_double), ("lam", ctypes.c_double),
         ("D_l", ctypes.c_double), ("D_s", ctypes.c_double), ("gamma", ctypes.c_double),
         ("a_at", ctypes.c_double), ("c_s_co", ctypes.c_double), ("c_l_co", ctypes.c_double),
@@ -127,7 +128,8 @@ def load():
 def make_params(cfg, precision="fp64", schedule="auto") -> gplbm_params:
     """C parameter struct from a mapping with the keys lattice, shape
     (nz, ny, nx), bc, counter_term, anti_trapping, W, M_phi, lam, D_l, D_s,
-    gamma, a_at, c_s_co, c_l_co, mu_eq, eps_n."""
+    gamma, a_at, c_s_co, c_l_co, mu_eq, eps_n, and optionally h_lattice
+    (0: h on the lattice of g, the default; 1: h on D2Q5 / D3Q7)."""
     p = gplbm_params()
     nz, ny, nx = cfg["shape"]
     p.lattice = int(cfg["lattice"])
@@ -138,7 +140,7 @@ def make_params(cfg, precision="fp64", schedule="auto") -> gplbm_params:
     p.counter_term = int(cfg["counter_term"])
     p.anti_trapping = int(cfg["anti_trapping"])
     p.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
-    p.reserved = 0
+    p.h_lattice = int(cfg.get("h_lattice", 0))
     for key in ("W", "M_phi", "lam", "D_l", "D_s", "gamma", "a_at", "c_s_co", "c_l_co",
                 "mu_eq", "eps_n"):
         setattr(p, key, float(cfg[key]))
@@ -285,6 +287,10 @@ class Simulation:
         self.shape = tuple(int(s) for s in cfg["shape"])
         self.N = self.shape[0] * self.shape[1] * self.shape[2]
         self.Q = 9 if self.params.lattice == GPLBM_D2Q9 else 19
+        if self.params.h_lattice == GPLBM_H_LIGHT:
+            self.Qh = 5 if self.params.lattice == GPLBM_D2Q9 else 7
+        else:
+            self.Qh = self.Q
         nbytes = gplbm_state_bytes(self.params)
         with torch.cuda.device(self.device):
             self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)

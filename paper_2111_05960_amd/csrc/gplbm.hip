@@ -2,8 +2,8 @@
 // contract in include/gplbm.h).
 //
 // Host side: validation, the carving of the borrowed device buffer, the
-// per-run constants, and the dispatch of the kernels over lattice and
-// precision.  No device allocation happens here.
+// per-run constants, and the dispatch of the kernels over the lattices of g
+// and h and the precision.  No device allocation happens here.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -22,10 +22,12 @@ using namespace gplbm;
 
 struct gplbm_ctx {
   gplbm_params p;
-  int Q;
+  int Q;             // populations of g
+  int Qh;            // populations of h
   int64_t N;
   size_t elem;        // bytes per stored phi value
-  size_t pop_bytes;   // one distribution (rounded up)
+  size_t pop_bytes;   // the g distribution (rounded up)
+  size_t hpop_bytes;  // the h distribution (rounded up)
   size_t mov_bytes;   // deviation formats: the 16-bit moving part of a distribution
   size_t phi_bytes;   // N*elem rounded up
   size_t lam_bytes;   // deviation formats: the Lambda field
@@ -55,6 +57,17 @@ size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 int lattice_q(int lattice) { return lattice == GPLBM_D2Q9 ? 9 : 19; }
 
+int lattice_qh(const gplbm_params* p) {
+  if (p->h_lattice == GPLBM_H_LIGHT) return p->lattice == GPLBM_D2Q9 ? D2Q5::Q : D3Q7::Q;
+  return lattice_q(p->lattice);
+}
+
+// xi_s^2 of the h lattice
+double lattice_cs2h(const gplbm_params& p) {
+  if (p.h_lattice == GPLBM_H_LIGHT) return p.lattice == GPLBM_D2Q9 ? D2Q5::cs2 : D3Q7::cs2;
+  return p.lattice == GPLBM_D2Q9 ? D2Q9::cs2 : D3Q19::cs2;
+}
+
 // Returns an error text, or nullptr when the parameters are acceptable.
 const char* check_params(const gplbm_params* p) {
   if (!p) return "null parameters";
@@ -67,7 +80,9 @@ const char* check_params(const gplbm_params* p) {
   if (p->precision >= GPLBM_FP16_DEV && p->lattice != GPLBM_D3Q19)
     return "deviation storage is implemented for D3Q19";
   if (p->schedule < GPLBM_SCHED_AUTO || p->schedule > GPLBM_SCHED_FUSED) return "unknown schedule";
-  if (p->reserved != 0) return "reserved field must be 0";
+  if (p->h_lattice != GPLBM_H_FULL && p->h_lattice != GPLBM_H_LIGHT) return "unknown h lattice";
+  if (p->h_lattice == GPLBM_H_LIGHT && p->precision >= GPLBM_FP16_DEV)
+    return "deviation storage needs h on the lattice of g";
   if (!(p->W > 0.0) || !std::isfinite(p->W)) return "W must be > 0";
   if (!(p->M_phi > 0.0) || !std::isfinite(p->M_phi)) return "M_phi must be > 0 (omega_g in (0,2))";
   if (!(p->gamma > 0.0) || !std::isfinite(p->gamma)) return "gamma must be > 0 (omega_h in (0,2))";
@@ -79,8 +94,10 @@ const char* check_params(const gplbm_params* p) {
   return nullptr;
 }
 
+// Borrowed buffer: G[0], G[1], H[0], H[1], PHI[0], PHI[1], LAM[0], LAM[1],
+// reduction scratch.  A saved state: G, H, PHI, LAM.
 struct Layout {
-  size_t elem, pop, mov, phi, lam, red, total, ckpt;
+  size_t elem, pop, hpop, mov, phi, lam, red, total, ckpt;
 };
 
 Layout layout(const gplbm_params* p) {
@@ -91,17 +108,19 @@ Layout layout(const gplbm_params* p) {
     l.elem = 4;
     l.mov = round_up((size_t)(Q - 1) * N * 2);
     l.pop = l.mov + round_up((size_t)N * 4);
+    l.hpop = l.pop;
     l.lam = round_up((size_t)N * 4);
   } else {
     l.elem = p->precision == GPLBM_FP64 ? 8 : 4;
     l.mov = 0;
     l.pop = round_up((size_t)Q * N * l.elem);
+    l.hpop = round_up((size_t)lattice_qh(p) * N * l.elem);
     l.lam = 0;
   }
   l.phi = round_up((size_t)N * l.elem);
   l.red = round_up(sizeof(double) * (kDiagBlocks * kDiagVals + kDiagVals));
-  l.total = 4 * l.pop + 2 * l.phi + 2 * l.lam + l.red;
-  l.ckpt = 2 * l.pop + l.phi + l.lam;
+  l.total = 2 * l.pop + 2 * l.hpop + 2 * l.phi + 2 * l.lam + l.red;
+  l.ckpt = l.pop + l.hpop + l.phi + l.lam;
   return l;
 }
 
@@ -122,7 +141,9 @@ Coef<C> make_coef(const gplbm_params& p) {
   Coef<C> K{};
   const double dc = p.c_s_co - p.c_l_co;
   K.omega_g = C(1.0 / (3.0 * p.M_phi + 0.5));
-  K.omega_h = C(1.0 / (3.0 / p.gamma + 0.5));
+  // tau_h = 1 / (gamma xi_s^2): the diffusivity of the c-LBE is D(phi) on
+  // every h lattice
+  K.omega_h = C(1.0 / (1.0 / (p.gamma * lattice_cs2h(p)) + 0.5));
   K.dc = C(dc);
   K.kst = C(-((p.lambda * p.M_phi) / (p.W * p.W)));
   K.k4w = C(4.0 / p.W);
@@ -154,8 +175,9 @@ Geo make_geo(const gplbm_params& p) {
   return g;
 }
 
-// Typed operations for one lattice L and storage / arithmetic types S, C.
-template <class L, class S, class C>
+// Typed operations for the lattices L (g) and LH (h) and the storage /
+// arithmetic types S, C.
+template <class L, class LH, class S, class C>
 struct Ops {
   static dim3 block() { return dim3(64, 4, 1); }
   static dim3 grid(const gplbm_ctx* ctx) {
@@ -166,7 +188,7 @@ struct Ops {
   static int init(gplbm_ctx* ctx, const double* phi0, const double* c0) {
     const Geo g = make_geo(ctx->p);
     const int a = ctx->cur;
-    hipLaunchKernelGGL((k_init<L, S, C>), grid(ctx), block(), 0, ctx->stream, g, coef(ctx), phi0,
+    hipLaunchKernelGGL((k_init<L, LH, S, C>), grid(ctx), block(), 0, ctx->stream, g, coef(ctx), phi0,
                        c0, (S*)ctx->G[a], (S*)ctx->H[a], (S*)ctx->PHI[a]);
     return check_launch(ctx, "init");
   }
@@ -178,8 +200,8 @@ struct Ops {
       const int a = ctx->cur, b = 1 - a;
       StepBufs<S> bufs{(const S*)ctx->G[a], (const S*)ctx->H[a], (const S*)ctx->PHI[a],
                        (S*)ctx->H[b],       (S*)ctx->PHI[b],       (S*)ctx->G[b]};
-      hipLaunchKernelGGL((k_split_h<L, S, C>), grid(ctx), block(), 0, ctx->stream, g, K, bufs);
-      hipLaunchKernelGGL((k_split_g<L, S, C>), grid(ctx), block(), 0, ctx->stream, g, K, bufs);
+      hipLaunchKernelGGL((k_split_h<L, LH, S, C>), grid(ctx), block(), 0, ctx->stream, g, K, bufs);
+      hipLaunchKernelGGL((k_split_g<L, LH, S, C>), grid(ctx), block(), 0, ctx->stream, g, K, bufs);
       int rc = check_launch(ctx, "split step");
       if (rc) return rc;
       ctx->cur = b;
@@ -195,7 +217,7 @@ struct Ops {
       const int a = ctx->cur, b = 1 - a;
       StepBufs<S> bufs{(const S*)ctx->G[a], (const S*)ctx->H[a], (const S*)ctx->PHI[a],
                        (S*)ctx->H[b],       (S*)ctx->PHI[b],       (S*)ctx->G[b]};
-      int rc = FusedLaunch<L, S, C>::launch(g, K, bufs, ctx->stream);
+      int rc = FusedLaunch<L, LH, S, C>::launch(g, K, bufs, ctx->stream);
       if (rc) return fail(ctx, GPLBM_E_DEVICE, "fused step launch failed");
       rc = check_launch(ctx, "fused step");
       if (rc) return rc;
@@ -208,7 +230,7 @@ struct Ops {
   static int fields(gplbm_ctx* ctx, double* phi, double* c, double* mu) {
     const Geo g = make_geo(ctx->p);
     const int a = ctx->cur;
-    hipLaunchKernelGGL((k_fields<L, S>), grid(ctx), block(), 0, ctx->stream, g, ctx->p.c_l_co,
+    hipLaunchKernelGGL((k_fields<LH, S>), grid(ctx), block(), 0, ctx->stream, g, ctx->p.c_l_co,
                        ctx->p.c_s_co, ctx->p.mu_eq, (const S*)ctx->H[a], (const S*)ctx->PHI[a],
                        phi, c, mu);
     return check_launch(ctx, "read fields");
@@ -219,7 +241,7 @@ struct Ops {
     const int a = ctx->cur;
     double* part = ctx->red;
     double* out = ctx->red + kDiagBlocks * kDiagVals;
-    hipLaunchKernelGGL((k_diag_partial<L, S>), dim3(kDiagBlocks), dim3(kDiagThreads), 0,
+    hipLaunchKernelGGL((k_diag_partial<LH, S>), dim3(kDiagBlocks), dim3(kDiagThreads), 0,
                        ctx->stream, g, (const S*)ctx->H[a], (const S*)ctx->PHI[a], part);
     hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagThreads), 0, ctx->stream,
                        (const double*)part, kDiagBlocks, out);
@@ -298,51 +320,63 @@ struct DevAdapter {
   static int diag(gplbm_ctx* c) { return DevOps<Codec>::diag(c); }
 };
 
-template <template <class, class, class> class Fn, class... Args>
-int dispatch(gplbm_ctx* ctx, Args... args) {
-  if (ctx->p.precision == GPLBM_FP16_DEV) return Fn<DevAdapter<F16Codec>, void, void>::run(ctx, args...);
-  if (ctx->p.precision == GPLBM_BF16_DEV) return Fn<DevAdapter<BF16Codec>, void, void>::run(ctx, args...);
-  if (ctx->p.lattice == GPLBM_D2Q9) {
-    if (ctx->p.precision == GPLBM_FP64) return Fn<D2Q9, double, double>::run(ctx, args...);
-    return Fn<D2Q9, float, float>::run(ctx, args...);
-  }
-  if (ctx->p.precision == GPLBM_FP64) return Fn<D3Q19, double, double>::run(ctx, args...);
-  return Fn<D3Q19, float, float>::run(ctx, args...);
+template <template <class, class, class, class> class Fn, class L, class LH, class... Args>
+int dispatch_prec(gplbm_ctx* ctx, Args... args) {
+  if (ctx->p.precision == GPLBM_FP64) return Fn<L, LH, double, double>::run(ctx, args...);
+  return Fn<L, LH, float, float>::run(ctx, args...);
 }
 
-template <class L, class S, class C>
+template <template <class, class, class, class> class Fn, class... Args>
+int dispatch(gplbm_ctx* ctx, Args... args) {
+  if (ctx->p.precision == GPLBM_FP16_DEV)
+    return Fn<DevAdapter<F16Codec>, void, void, void>::run(ctx, args...);
+  if (ctx->p.precision == GPLBM_BF16_DEV)
+    return Fn<DevAdapter<BF16Codec>, void, void, void>::run(ctx, args...);
+  const bool light = ctx->p.h_lattice == GPLBM_H_LIGHT;
+  if (ctx->p.lattice == GPLBM_D2Q9)
+    return light ? dispatch_prec<Fn, D2Q9, D2Q5>(ctx, args...)
+                 : dispatch_prec<Fn, D2Q9, D2Q9>(ctx, args...);
+  return light ? dispatch_prec<Fn, D3Q19, D3Q7>(ctx, args...)
+               : dispatch_prec<Fn, D3Q19, D3Q19>(ctx, args...);
+}
+
+template <class L, class LH, class S, class C>
 struct InitFn {
-  static int run(gplbm_ctx* c, const double* a, const double* b) { return Ops<L, S, C>::init(c, a, b); }
-};
-template <class A>
-struct InitFn<A, void, void> {
-  static int run(gplbm_ctx* c, const double* a, const double* b) { return A::init(c, a, b); }
-};
-template <class L, class S, class C>
-struct StepFn {
-  static int run(gplbm_ctx* c, int64_t n) {
-    return c->sched == GPLBM_SCHED_FUSED ? Ops<L, S, C>::step_fused(c, n)
-                                         : Ops<L, S, C>::step_split(c, n);
+  static int run(gplbm_ctx* c, const double* a, const double* b) {
+    return Ops<L, LH, S, C>::init(c, a, b);
   }
 };
 template <class A>
-struct StepFn<A, void, void> {
+struct InitFn<A, void, void, void> {
+  static int run(gplbm_ctx* c, const double* a, const double* b) { return A::init(c, a, b); }
+};
+template <class L, class LH, class S, class C>
+struct StepFn {
+  static int run(gplbm_ctx* c, int64_t n) {
+    return c->sched == GPLBM_SCHED_FUSED ? Ops<L, LH, S, C>::step_fused(c, n)
+                                         : Ops<L, LH, S, C>::step_split(c, n);
+  }
+};
+template <class A>
+struct StepFn<A, void, void, void> {
   static int run(gplbm_ctx* c, int64_t n) { return A::step(c, n); }
 };
-template <class L, class S, class C>
+template <class L, class LH, class S, class C>
 struct FieldsFn {
-  static int run(gplbm_ctx* c, double* a, double* b, double* d) { return Ops<L, S, C>::fields(c, a, b, d); }
+  static int run(gplbm_ctx* c, double* a, double* b, double* d) {
+    return Ops<L, LH, S, C>::fields(c, a, b, d);
+  }
 };
 template <class A>
-struct FieldsFn<A, void, void> {
+struct FieldsFn<A, void, void, void> {
   static int run(gplbm_ctx* c, double* a, double* b, double* d) { return A::fields(c, a, b, d); }
 };
-template <class L, class S, class C>
+template <class L, class LH, class S, class C>
 struct DiagFn {
-  static int run(gplbm_ctx* c) { return Ops<L, S, C>::diag(c); }
+  static int run(gplbm_ctx* c) { return Ops<L, LH, S, C>::diag(c); }
 };
 template <class A>
-struct DiagFn<A, void, void> {
+struct DiagFn<A, void, void, void> {
   static int run(gplbm_ctx* c) { return A::diag(c); }
 };
 
@@ -393,23 +427,26 @@ int gplbm_create(const gplbm_params* p, void* dev_buf, uint64_t bytes, void* str
   ctx->p = *p;
   if (ctx->p.lattice == GPLBM_D2Q9) ctx->p.bc[2] = GPLBM_PERIODIC;
   ctx->Q = lattice_q(p->lattice);
+  ctx->Qh = lattice_qh(p);
   ctx->N = (int64_t)p->nx * p->ny * p->nz;
   ctx->elem = lay.elem;
   ctx->pop_bytes = lay.pop;
+  ctx->hpop_bytes = lay.hpop;
   ctx->mov_bytes = lay.mov;
   ctx->phi_bytes = lay.phi;
   ctx->lam_bytes = lay.lam;
   char* b = (char*)dev_buf;
-  const size_t pop = lay.pop, phi = lay.phi, lam = lay.lam;
+  const size_t pop = lay.pop, hpop = lay.hpop, phi = lay.phi, lam = lay.lam;
+  const size_t pops = 2 * pop + 2 * hpop;
   ctx->G[0] = b;
   ctx->G[1] = b + pop;
   ctx->H[0] = b + 2 * pop;
-  ctx->H[1] = b + 3 * pop;
-  ctx->PHI[0] = b + 4 * pop;
-  ctx->PHI[1] = b + 4 * pop + phi;
-  ctx->LAM[0] = lam ? b + 4 * pop + 2 * phi : nullptr;
-  ctx->LAM[1] = lam ? b + 4 * pop + 2 * phi + lam : nullptr;
-  ctx->red = (double*)(b + 4 * pop + 2 * phi + 2 * lam);
+  ctx->H[1] = b + 2 * pop + hpop;
+  ctx->PHI[0] = b + pops;
+  ctx->PHI[1] = b + pops + phi;
+  ctx->LAM[0] = lam ? b + pops + 2 * phi : nullptr;
+  ctx->LAM[1] = lam ? b + pops + 2 * phi + lam : nullptr;
+  ctx->red = (double*)(b + pops + 2 * phi + 2 * lam);
   ctx->cur = 0;
   ctx->step = 0;
   ctx->ready = false;
@@ -461,15 +498,15 @@ int gplbm_step_to(gplbm_ctx* ctx, const void* src_state, void* dst_state) {
   const bool ready = ctx->ready;
   char* s = (char*)src_state;
   char* d = (char*)dst_state;
-  const size_t pp = ctx->pop_bytes, ph = ctx->phi_bytes;
+  const size_t pp = ctx->pop_bytes, hp = ctx->hpop_bytes, ph = ctx->phi_bytes;
   ctx->G[cur] = s;
   ctx->H[cur] = s + pp;
-  ctx->PHI[cur] = s + 2 * pp;
-  ctx->LAM[cur] = ctx->lam_bytes ? s + 2 * pp + ph : nullptr;
+  ctx->PHI[cur] = s + pp + hp;
+  ctx->LAM[cur] = ctx->lam_bytes ? s + pp + hp + ph : nullptr;
   ctx->G[1 - cur] = d;
   ctx->H[1 - cur] = d + pp;
-  ctx->PHI[1 - cur] = d + 2 * pp;
-  ctx->LAM[1 - cur] = ctx->lam_bytes ? d + 2 * pp + ph : nullptr;
+  ctx->PHI[1 - cur] = d + pp + hp;
+  ctx->LAM[1 - cur] = ctx->lam_bytes ? d + pp + hp + ph : nullptr;
   ctx->ready = true;
   const int rc = dispatch<StepFn>(ctx, 1);
   for (int a = 0; a < 2; ++a) {
@@ -523,15 +560,15 @@ int gplbm_save_state(gplbm_ctx* ctx, void* dev_dst) {
   if (int rc = use_device(ctx)) return rc;
   const int a = ctx->cur;
   char* d = (char*)dev_dst;
-  hipError_t e = hipMemcpyAsync(d, ctx->G[a], ctx->pop_bytes, hipMemcpyDeviceToDevice, ctx->stream);
+  const size_t pp = ctx->pop_bytes, hp = ctx->hpop_bytes, ph = ctx->phi_bytes;
+  hipError_t e = hipMemcpyAsync(d, ctx->G[a], pp, hipMemcpyDeviceToDevice, ctx->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(d + ctx->pop_bytes, ctx->H[a], ctx->pop_bytes, hipMemcpyDeviceToDevice, ctx->stream);
+    e = hipMemcpyAsync(d + pp, ctx->H[a], hp, hipMemcpyDeviceToDevice, ctx->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(d + 2 * ctx->pop_bytes, ctx->PHI[a], ctx->phi_bytes, hipMemcpyDeviceToDevice,
-                       ctx->stream);
+    e = hipMemcpyAsync(d + pp + hp, ctx->PHI[a], ph, hipMemcpyDeviceToDevice, ctx->stream);
   if (e == hipSuccess && ctx->lam_bytes)
-    e = hipMemcpyAsync(d + 2 * ctx->pop_bytes + ctx->phi_bytes, ctx->LAM[a], ctx->lam_bytes,
-                       hipMemcpyDeviceToDevice, ctx->stream);
+    e = hipMemcpyAsync(d + pp + hp + ph, ctx->LAM[a], ctx->lam_bytes, hipMemcpyDeviceToDevice,
+                       ctx->stream);
   if (e != hipSuccess) return fail(ctx, GPLBM_E_DEVICE, std::string("save: ") + hipGetErrorString(e));
   return GPLBM_OK;
 }
@@ -541,15 +578,15 @@ int gplbm_load_state(gplbm_ctx* ctx, const void* dev_src, int64_t step) {
   if (int rc = use_device(ctx)) return rc;
   const int a = ctx->cur;
   const char* s = (const char*)dev_src;
-  hipError_t e = hipMemcpyAsync(ctx->G[a], s, ctx->pop_bytes, hipMemcpyDeviceToDevice, ctx->stream);
+  const size_t pp = ctx->pop_bytes, hp = ctx->hpop_bytes, ph = ctx->phi_bytes;
+  hipError_t e = hipMemcpyAsync(ctx->G[a], s, pp, hipMemcpyDeviceToDevice, ctx->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(ctx->H[a], s + ctx->pop_bytes, ctx->pop_bytes, hipMemcpyDeviceToDevice, ctx->stream);
+    e = hipMemcpyAsync(ctx->H[a], s + pp, hp, hipMemcpyDeviceToDevice, ctx->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(ctx->PHI[a], s + 2 * ctx->pop_bytes, ctx->phi_bytes, hipMemcpyDeviceToDevice,
-                       ctx->stream);
+    e = hipMemcpyAsync(ctx->PHI[a], s + pp + hp, ph, hipMemcpyDeviceToDevice, ctx->stream);
   if (e == hipSuccess && ctx->lam_bytes)
-    e = hipMemcpyAsync(ctx->LAM[a], s + 2 * ctx->pop_bytes + ctx->phi_bytes, ctx->lam_bytes,
-                       hipMemcpyDeviceToDevice, ctx->stream);
+    e = hipMemcpyAsync(ctx->LAM[a], s + pp + hp + ph, ctx->lam_bytes, hipMemcpyDeviceToDevice,
+                       ctx->stream);
   if (e != hipSuccess) return fail(ctx, GPLBM_E_DEVICE, std::string("load: ") + hipGetErrorString(e));
   ctx->step = step;
   ctx->ready = true;
@@ -596,7 +633,7 @@ struct AdjOps {
   static FwdState<S> fwd(const gplbm_ctx* ctx, const void* ck) {
     const char* b = (const char*)ck;
     return FwdState<S>{(const S*)b, (const S*)(b + ctx->pop_bytes),
-                       (const S*)(b + 2 * ctx->pop_bytes)};
+                       (const S*)(b + ctx->pop_bytes + ctx->hpop_bytes)};
   }
   static int seed(gplbm_ctx* ctx, const double* phib, const double* cb) {
     const Geo g = make_geo(ctx->p);
@@ -659,8 +696,9 @@ struct AdjFinishFn {
   }
 };
 
-bool adjoint_precision(int precision) {
-  return precision == GPLBM_FP64 || precision == GPLBM_FP32;
+// The adjoint is written for h on the lattice of g, in FP64 or FP32.
+bool adjoint_supported(const gplbm_params& p) {
+  return (p.precision == GPLBM_FP64 || p.precision == GPLBM_FP32) && p.h_lattice == GPLBM_H_FULL;
 }
 
 }  // namespace
@@ -668,7 +706,7 @@ bool adjoint_precision(int precision) {
 extern "C" {
 
 int gplbm_adjoint_bytes(const gplbm_params* p, uint64_t* bytes) {
-  if (check_params(p) || !bytes || !adjoint_precision(p->precision)) return GPLBM_E_INVALID;
+  if (check_params(p) || !bytes || !adjoint_supported(*p)) return GPLBM_E_INVALID;
   *bytes = adj_layout(p).total;
   return GPLBM_OK;
 }
@@ -676,8 +714,8 @@ int gplbm_adjoint_bytes(const gplbm_params* p, uint64_t* bytes) {
 int gplbm_adjoint_begin(gplbm_ctx* ctx, void* work, uint64_t bytes, const double* phi_bar,
                         const double* c_bar) {
   if (!ctx || !work || ((uintptr_t)work) % kAlign) return GPLBM_E_INVALID;
-  if (!adjoint_precision(ctx->p.precision))
-    return fail(ctx, GPLBM_E_INVALID, "adjoint needs an FP64 or FP32 context");
+  if (!adjoint_supported(ctx->p))
+    return fail(ctx, GPLBM_E_INVALID, "adjoint needs an FP64 or FP32 context with h on the g lattice");
   const AdjLayout l = adj_layout(&ctx->p);
   if (bytes < l.total) return fail(ctx, GPLBM_E_SIZE, "adjoint workspace too small");
   if (int rc = use_device(ctx)) return rc;

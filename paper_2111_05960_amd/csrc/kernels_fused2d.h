@@ -1,4 +1,5 @@
-// Fused schedule for D2Q9: one kernel per time step n -> n+1.
+// Fused schedule in 2-D: one kernel per time step n -> n+1.  g runs on
+// D2Q9 (L), h on D2Q9 or D2Q5 (LH).
 //
 // A block owns an output tile T of TX x TY nodes (x-aligned, tiles.h) and
 // computes T grown by one node on each side (T+1).  Every thread of T+1:
@@ -7,14 +8,14 @@
 //     normal, source moment), forms phi^{n+1} and writes it to an LDS tile,
 //   - runs the h collision of step n (anti-trapping current from
 //     phi^{n+1} - phi^n).
-// The post-collision h* of T+1 are then streamed inside the block: Q passes,
+// The post-collision h* of T+1 are then streamed inside the block: Qh passes,
 // one per population in index order, each adding the population that arrives
 // at every node of T into an LDS accumulator, so that c^{n+1} is summed in the
 // same order as a pull would sum it.  Finally the threads of T run the g
 // collision of step n+1 (gradient of phi^{n+1} from the LDS tile) and write
 // g~*^{n+1}, h~*^n and phi^{n+1}.
 //
-// HBM traffic per node and step is the minimum: Q + Q reads, Q + Q writes,
+// HBM traffic per node and step is the minimum: Q + Qh reads, Q + Qh writes,
 // one phi read and one phi write, plus the recomputed halo ring where the L2
 // misses it.  The grid is persistent with XCD-ordered passes (tiles.h).
 #pragma once
@@ -24,7 +25,7 @@
 
 namespace gplbm {
 
-template <int TX, int TY, class L, class S, class C>
+template <int TX, int TY, class L, class LH, class S, class C>
 __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     k_fused2d(Geo g, Coef<C> K, StepBufs<S> b, int tiles_x, int ntiles) {
   using Shape = TileShape<TX, TY>;
@@ -62,15 +63,15 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   const int ym = (g.bcy && uy == 0) ? 0 : -1, yp = (g.bcy && uy == g.ny - 1) ? 0 : 1;
   __syncthreads();
 
-  C gn[L::Q];  // g~^{n+1}
-  C hs[L::Q];  // h~*^n
+  C gn[L::Q];   // g~^{n+1}
+  C hs[LH::Q];  // h~*^n
   C phin_c = C(0);
   if (active) {
-    C h[L::Q];
+    C h[LH::Q];
     double c = 0.0;
 #pragma unroll
-    for (int k = 0; k < L::Q; ++k) {
-      S v = pull<L>(g, b.H, k, x, y, 0);
+    for (int k = 0; k < LH::Q; ++k) {
+      S v = pull<LH>(g, b.H, k, x, y, 0);
       h[k] = C(v);
       c = k == 0 ? double(v) : c + double(v);
     }
@@ -99,8 +100,9 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     const C lam = h_lambda<C>(K, phi, mu);
     const C cc = C(c);
 #pragma unroll
-    for (int k = 0; k < L::Q; ++k)
-      hs[k] = C(S(h_collide<L, C>(K, k, h[k], h_eq<L, C>(k, cc, lam), h_source<L, C>(K, k, F))));
+    for (int k = 0; k < LH::Q; ++k)
+      hs[k] = C(S(h_collide<LH, C>(K, k, h[k], h_eq<LH, C>(k, cc, lam),
+                                   h_source<LH, C>(K, k, F))));
   }
   if (valid) phiB[ty][tx] = phin_c;
   __syncthreads();
@@ -108,10 +110,10 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   // streaming of h* inside the tile: pass k adds the population k arriving
   // at every output node (from x - e_k, or bounced back at a wall)
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k) {
+  for (int k = 0; k < LH::Q; ++k) {
     if (active) {
-      const int tx2 = tx + L::ex[k], ty2 = ty + L::ey[k];
-      const int vx = ux + L::ex[k], vy = uy + L::ey[k];
+      const int tx2 = tx + LH::ex[k], ty2 = ty + LH::ey[k];
+      const int vx = ux + LH::ex[k], vy = uy + LH::ey[k];
       const bool tgt_in = tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY && vx >= 0 &&
                           vx < g.nx && vy >= 0 && vy < g.ny;
       if (tgt_in) {
@@ -120,10 +122,10 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
         else acc[ty2][tx2] = acc[ty2][tx2] + v;
       }
       // population k of this node bounced back: its source x - e_k is beyond a wall
-      if (out && k != 0) {
-        const bool wall = (g.bcx && (ux - L::ex[k] < 0 || ux - L::ex[k] >= g.nx)) ||
-                          (g.bcy && (uy - L::ey[k] < 0 || uy - L::ey[k] >= g.ny));
-        if (wall) acc[ty][tx] = acc[ty][tx] + double(hs[L::opp[k]]);
+      if (out && k != LH::REST) {
+        const bool wall = (g.bcx && (ux - LH::ex[k] < 0 || ux - LH::ex[k] >= g.nx)) ||
+                          (g.bcy && (uy - LH::ey[k] < 0 || uy - LH::ey[k] >= g.ny));
+        if (wall) acc[ty][tx] = acc[ty][tx] + double(hs[LH::opp[k]]);
       }
     }
     __syncthreads();
@@ -143,10 +145,10 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   C G[L::Q];
   phi_sources<L, C>(K, phi1, mu1, n, G);
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k) {
+  for (int k = 0; k < L::Q; ++k)
     b.Gn[pop_index<L>(g, k, x, y, 0)] = S(g_collide<L, C>(K, k, gn[k], phi1, G[k]));
-    b.Hn[pop_index<L>(g, k, x, y, 0)] = S(hs[k]);
-  }
+#pragma unroll
+  for (int k = 0; k < LH::Q; ++k) b.Hn[pop_index<LH>(g, k, x, y, 0)] = S(hs[k]);
   b.PHIn[i] = S(phi1);
   }
   __syncthreads();  // the LDS tiles are refilled by the next tile
@@ -162,12 +164,12 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
 
 inline bool fused2d_supported(int, int) { return true; }
 
-template <class L, class S, class C>
+template <class L, class LH, class S, class C>
 struct Fused2D {
   static int launch(const Geo& g, const Coef<C>& K, const StepBufs<S>& b, hipStream_t st) {
     constexpr int TX = 64, TY = GPLBM_F2_TY;
     constexpr int NT = TileShape<TX, TY>::NT;
-    auto kernel = k_fused2d<TX, TY, L, S, C>;
+    auto kernel = k_fused2d<TX, TY, L, LH, S, C>;
     const int tiles_x = (g.nx + TX - 1) / TX;
     const int tiles_y = (g.ny + TY - 1) / TY;
     const int ntiles = tiles_x * tiles_y;

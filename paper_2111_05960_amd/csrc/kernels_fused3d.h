@@ -1,4 +1,5 @@
-// Fused schedule for D3Q19: one kernel per time step n -> n+1, marching in z.
+// Fused schedule in 3-D: one kernel per time step n -> n+1, marching in z.
+// g runs on D3Q19, h on D3Q19 or D3Q7 (LH).
 //
 // A block owns an x-y output tile T of TX x TY nodes and a chunk of ZC planes,
 // and computes the tile grown by one node in x and y (the region, BX x BY).
@@ -10,9 +11,10 @@
 //   - runs the h collision of step n.
 // The post-collision h* are then streamed inside the block into a ring of
 // three LDS accumulator planes: the e_z = +1 populations go to plane p+1, the
-// in-plane ones to plane p, the e_z = -1 ones to plane p-1.  Because D3Q19 is
-// numbered by layers of e_z (+1, 0, -1), every node's c^{n+1} receives its
-// populations in index order across the three planes, the order of a pull.
+// in-plane ones to plane p, the e_z = -1 ones to plane p-1.  Because D3Q19 and
+// D3Q7 are numbered by layers of e_z (+1, 0, -1), every node's c^{n+1}
+// receives its populations in index order across the three planes, the order
+// of a pull.
 // After plane p, c^{n+1}(p-1) is complete and the threads of T run the g
 // collision of step n+1 at plane p-1, on the g~^{n+1} pulled one plane
 // earlier (kept in registers, or in LDS where registers are short).
@@ -24,10 +26,10 @@
 // shared halo are still in the L2 when the second tile reads them.
 //
 // Addressing: with the plane-major layout f[z][k][y][x] every population a
-// thread pulls lies in one of three plane groups (z-1, z, z+1).  Each group is
-// a buffer resource in scalar registers; the population plane k*nx*ny is the
-// uniform offset and the (x, y) source the per-lane offset, so a load costs no
-// vector address arithmetic.
+// thread pulls lies in one of three plane groups (z-1, z, z+1) of Q planes
+// each (Qh for h).  Each group is a buffer resource in scalar registers; the
+// population plane k*nx*ny is the uniform offset and the (x, y) source the
+// per-lane offset, so a load costs no vector address arithmetic.
 //
 // Only periodic domains take this path (a wall would bounce some +z
 // populations into a plane one step later than the index order allows); the
@@ -73,6 +75,24 @@ __device__ __forceinline__ void bstore_nt(S v, __amdgpu_buffer_rsrc_t r, uint32_
   }
 }
 
+// Pulls of the populations of lattice P at z plane zp: population k comes
+// from plane group zp - e_z and (x, y) - (e_x, e_y), whose byte offset inside
+// a population plane is xyb[1 - e_y][1 - e_x].
+template <class P, class S>
+__device__ __forceinline__ void fetch_pops(const S* base, int zp, int nz, int plane,
+                                           const uint32_t (&xyb)[3][3], S (&v)[P::Q]) {
+  const int64_t groupB = int64_t(plane) * P::Q * sizeof(S);
+  const uint32_t planeB = uint32_t(plane) * sizeof(S);
+  const int zs[3] = {(zp == 0 ? nz - 1 : zp - 1), zp, (zp == nz - 1 ? 0 : zp + 1)};
+  __amdgpu_buffer_rsrc_t R[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    R[j] = make_rsrc(reinterpret_cast<const char*>(base) + zs[j] * groupB, uint32_t(groupB));
+#pragma unroll
+  for (int k = 0; k < P::Q; ++k)
+    v[k] = bload<S>(R[1 - P::ez[k]], xyb[1 - P::ey[k]][1 - P::ex[k]], k * planeB);
+}
+
 // Carry of the pulled g~^{n+1} from its plane to the collision one plane
 // later: in registers, or in two LDS buffers (by plane parity) written right
 // after the pull, which frees 2Q registers in FP64.
@@ -91,12 +111,16 @@ struct Fused3DConfig<float> {
   static constexpr Carry carry = Carry::kRegisters;
 };
 
-template <int TX, int TY, int ZC, Carry kCarryMode, class S, class C>
+template <int TX, int TY, int ZC, Carry kCarryMode, class LH, class S, class C>
 __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     k_fused3d(Geo g, Coef<C> K, StepBufs<S> b, int tiles_x, int tiles_xy, int ntiles) {
   using L = D3Q19;
   using Shape = TileShape<TX, TY>;
-  constexpr int Q = L::Q;
+  constexpr int Q = L::Q, QH = LH::Q;
+  // e_z layers of the h lattice: +1 at [0, NU), 0 at [NU, NU+NM), -1 after
+  constexpr int NU = count_ez<LH>(1), NM = count_ez<LH>(0), ND = count_ez<LH>(-1);
+  constexpr int NPASS = NM > NU ? (NM > ND ? NM : ND) : (NU > ND ? NU : ND);
+  static_assert(NU + NM + ND == QH, "h lattice must be numbered by layers of e_z");
   constexpr int BX = Shape::BX, BY = Shape::BY;
   constexpr int AX = BX + 2, AY = BY + 2;
   constexpr int NT = Shape::NT;
@@ -113,8 +137,9 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   Shape::node(threadIdx.x, tx, ty, valid);
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int plane = nx * ny;
-  const uint32_t planeB = uint32_t(plane) * sizeof(S);    // one population plane
-  const int64_t groupB = int64_t(plane) * Q * sizeof(S);  // one z plane group
+  const uint32_t planeB = uint32_t(plane) * sizeof(S);     // one population plane
+  const int64_t groupB = int64_t(plane) * Q * sizeof(S);   // one z plane group of g
+  const int64_t groupH = int64_t(plane) * QH * sizeof(S);  // one z plane group of h
 
   for (int tile = first_tile(); tile < ntiles; tile += gridDim.x) {
     const int chunk = tile / tiles_xy, txy = tile % tiles_xy;
@@ -152,18 +177,6 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
         if (l < AX * AY) phiA[ring3(p)][l / AX][l % AX] = C(v[j]);
       }
     };
-    // pulls of plane p: population k at (x, y, z_p) comes from plane group z_p - e_z
-    auto fetch_pop = [&](const S* base, int p, S v[Q]) {
-      const int zp = wrap_coord(p, nz);
-      const int zs[3] = {(zp == 0 ? nz - 1 : zp - 1), zp, (zp == nz - 1 ? 0 : zp + 1)};
-      __amdgpu_buffer_rsrc_t R[3];
-#pragma unroll
-      for (int j = 0; j < 3; ++j)
-        R[j] = make_rsrc(reinterpret_cast<const char*>(base) + zs[j] * groupB, uint32_t(groupB));
-#pragma unroll
-      for (int k = 0; k < Q; ++k)
-        v[k] = bload<S>(R[1 - L::ez[k]], xyb[1 - L::ey[k]][1 - L::ex[k]], k * planeB);
-    };
 
     load_phi(z0 - 2);
     load_phi(z0 - 1);
@@ -174,17 +187,17 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     for (int p = z0 - 1; p <= z1; ++p) {
       load_phi(p + 1);
       __syncthreads();
-      S hv[Q], gv[Q];
-      fetch_pop(b.H, p, hv);
-      fetch_pop(b.G, p, gv);
-
       const int zp = wrap_coord(p, nz);
+      S hv[QH], gv[Q];
+      fetch_pops<LH, S>(b.H, zp, nz, plane, xyb, hv);
+      fetch_pops<L, S>(b.G, zp, nz, plane, xyb, gv);
+
       const bool own_p = p >= z0 && p < z1;
-      C h[Q];
+      C h[QH];
       C g_new[kRegs ? Q : 1];
       double c = 0.0, sg = 0.0;
 #pragma unroll
-      for (int k = 0; k < Q; ++k) {
+      for (int k = 0; k < QH; ++k) {
         h[k] = C(hv[k]);
         c = k == 0 ? double(hv[k]) : c + double(hv[k]);
       }
@@ -216,43 +229,44 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
       h_flux<L, C>(K, mu, gr, n, dtphi, K.anti_trapping != 0, F);
       const C lam = h_lambda<C>(K, phi, mu);
       const C cc = C(c);
-      C hs[Q];
+      C hs[QH];
 #pragma unroll
-      for (int k = 0; k < Q; ++k)
-        hs[k] = C(S(h_collide<L, C>(K, k, h[k], h_eq<L, C>(k, cc, lam), h_source<L, C>(K, k, F))));
+      for (int k = 0; k < QH; ++k)
+        hs[k] = C(S(h_collide<LH, C>(K, k, h[k], h_eq<LH, C>(k, cc, lam),
+                                     h_source<LH, C>(K, k, F))));
 
       if (out && own_p) {
-        const auto Hw = make_rsrc(reinterpret_cast<char*>(b.Hn) + zp * groupB, uint32_t(groupB));
+        const auto Hw = make_rsrc(reinterpret_cast<char*>(b.Hn) + zp * groupH, uint32_t(groupH));
 #pragma unroll
-        for (int k = 0; k < Q; ++k) bstore_nt<S>(S(hs[k]), Hw, selfB, k * planeB);
+        for (int k = 0; k < QH; ++k) bstore_nt<S>(S(hs[k]), Hw, selfB, k * planeB);
         __builtin_nontemporal_store(S(phin_c), &b.PHIn[(int64_t)zp * plane + y * nx + x]);
       }
 
-      // in-block streaming of h* into the accumulator ring, 9 passes:
-      // pass j carries population j (e_z=+1, to plane p+1), population 5+j
-      // (e_z=0, to plane p) and population 14+j (e_z=-1, to plane p-1)
+      // in-block streaming of h* into the accumulator ring, NPASS passes:
+      // pass j carries population j (e_z=+1, to plane p+1), population NU+j
+      // (e_z=0, to plane p) and population NU+NM+j (e_z=-1, to plane p-1)
       const bool up_ok = p + 1 >= z0 && p + 1 < z1, dn_ok = p - 1 >= z0 && p - 1 < z1;
 #pragma unroll
-      for (int j = 0; j < 9; ++j) {
-        if (j < 5 && up_ok) {
+      for (int j = 0; j < NPASS; ++j) {
+        if (j < NU && up_ok) {
           const int k = j;
-          const int tx2 = tx + L::ex[k], ty2 = ty + L::ey[k];
+          const int tx2 = tx + LH::ex[k], ty2 = ty + LH::ey[k];
           if (valid && tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
             double& a = acc[ring3(p + 1)][ty2][tx2];
             a = k == 0 ? double(hs[k]) : a + double(hs[k]);
           }
         }
-        if (own_p) {
-          const int k = 5 + j;
-          const int tx2 = tx + L::ex[k], ty2 = ty + L::ey[k];
+        if (j < NM && own_p) {
+          const int k = NU + j;
+          const int tx2 = tx + LH::ex[k], ty2 = ty + LH::ey[k];
           if (valid && tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
             double& a = acc[sA][ty2][tx2];
             a = a + double(hs[k]);
           }
         }
-        if (j < 5 && dn_ok) {
-          const int k = 14 + j;
-          const int tx2 = tx + L::ex[k], ty2 = ty + L::ey[k];
+        if (j < ND && dn_ok) {
+          const int k = NU + NM + j;
+          const int tx2 = tx + LH::ex[k], ty2 = ty + LH::ey[k];
           if (valid && tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
             double& a = acc[ring3(p - 1)][ty2][tx2];
             a = a + double(hs[k]);
@@ -301,13 +315,13 @@ inline bool fused3d_supported(int nx, int ny, int nz, const int* bc) {
          (int64_t)nx * ny * nz < ((int64_t)1 << 31);
 }
 
-template <class S, class C>
+template <class LH, class S, class C>
 struct Fused3D {
   static int launch(const Geo& g, const Coef<C>& K, const StepBufs<S>& b, hipStream_t st) {
     using Cfg = Fused3DConfig<S>;
     constexpr int TX = Cfg::TX, TY = Cfg::TY, ZC = Cfg::ZC;
     constexpr int NT = TileShape<TX, TY>::NT;
-    auto kernel = k_fused3d<TX, TY, ZC, Cfg::carry, S, C>;
+    auto kernel = k_fused3d<TX, TY, ZC, Cfg::carry, LH, S, C>;
     const int tiles_x = (g.nx + TX - 1) / TX;
     const int tiles_y = (g.ny + TY - 1) / TY;
     const int chunks = (g.nz + ZC - 1) / ZC;
@@ -321,13 +335,13 @@ struct Fused3D {
   }
 };
 
-template <class L, class S, class C>
+template <class L, class LH, class S, class C>
 struct FusedLaunch {
   static int launch(const Geo& g, const Coef<C>& K, const StepBufs<S>& b, hipStream_t st) {
     if constexpr (L::D == 2)
-      return Fused2D<L, S, C>::launch(g, K, b, st);
+      return Fused2D<L, LH, S, C>::launch(g, K, b, st);
     else
-      return Fused3D<S, C>::launch(g, K, b, st);
+      return Fused3D<LH, S, C>::launch(g, K, b, st);
   }
 };
 

@@ -45,7 +45,7 @@ struct GlobalPhi {
   }
 };
 
-template <class L, class S, class C>
+template <class L, class LH, class S, class C>
 __global__ void __launch_bounds__(256) k_split_h(Geo g, Coef<C> K, StepBufs<S> b) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -53,11 +53,11 @@ __global__ void __launch_bounds__(256) k_split_h(Geo g, Coef<C> K, StepBufs<S> b
   if (x >= g.nx || y >= g.ny) return;
   const int64_t i = node_index(g, x, y, z);
 
-  C h[L::Q];
+  C h[LH::Q];
   double c = 0.0;
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k) {
-    S v = pull<L>(g, b.H, k, x, y, z);
+  for (int k = 0; k < LH::Q; ++k) {
+    S v = pull<LH>(g, b.H, k, x, y, z);
     h[k] = C(v);
     c = k == 0 ? double(v) : c + double(v);
   }
@@ -82,14 +82,15 @@ __global__ void __launch_bounds__(256) k_split_h(Geo g, Coef<C> K, StepBufs<S> b
   const C lam = h_lambda<C>(K, phi, mu);
   const C cc = C(c);
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k) {
-    C Hk = h_source<L, C>(K, k, F);
-    b.Hn[pop_index<L>(g, k, x, y, z)] = S(h_collide<L, C>(K, k, h[k], h_eq<L, C>(k, cc, lam), Hk));
+  for (int k = 0; k < LH::Q; ++k) {
+    C Hk = h_source<LH, C>(K, k, F);
+    b.Hn[pop_index<LH>(g, k, x, y, z)] =
+        S(h_collide<LH, C>(K, k, h[k], h_eq<LH, C>(k, cc, lam), Hk));
   }
   b.PHIn[i] = S(phin);
 }
 
-template <class L, class S, class C>
+template <class L, class LH, class S, class C>
 __global__ void __launch_bounds__(256) k_split_g(Geo g, Coef<C> K, StepBufs<S> b) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -99,8 +100,8 @@ __global__ void __launch_bounds__(256) k_split_g(Geo g, Coef<C> K, StepBufs<S> b
 
   double c = 0.0;
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k) {
-    double v = double(pull<L>(g, (const S*)b.Hn, k, x, y, z));
+  for (int k = 0; k < LH::Q; ++k) {
+    double v = double(pull<LH>(g, (const S*)b.Hn, k, x, y, z));
     c = k == 0 ? v : c + v;
   }
   const C phi = C(b.PHIn[i]);
@@ -123,7 +124,7 @@ __global__ void __launch_bounds__(256) k_split_g(Geo g, Coef<C> K, StepBufs<S> b
 // "unstreamed": each value goes to the slot the pull of the first step reads
 // it from (the inverse of the pull permutation).
 
-template <class L, class S, class C>
+template <class L, class LH, class S, class C>
 __global__ void __launch_bounds__(256) k_init(Geo g, Coef<C> K, const double* __restrict__ phi0,
                                               const double* __restrict__ c0, S* __restrict__ G,
                                               S* __restrict__ H, S* __restrict__ PHI) {
@@ -157,12 +158,12 @@ __global__ void __launch_bounds__(256) k_init(Geo g, Coef<C> K, const double* __
   C F[3];
   h_flux<L, C>(K, mu0, gr, n, C(0), false, F);
   const C lam = h_lambda<C>(K, phi, mu0);
-  S hs[L::Q];
+  S hs[LH::Q];
   double c = 0.0;
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k) {
-    C Hk = h_source<L, C>(K, k, F);
-    hs[k] = S(h_eq<L, C>(k, C(cin), lam) - C(0.5) * Hk);
+  for (int k = 0; k < LH::Q; ++k) {
+    C Hk = h_source<LH, C>(K, k, F);
+    hs[k] = S(h_eq<LH, C>(k, C(cin), lam) - C(0.5) * Hk);
     c = k == 0 ? double(hs[k]) : c + double(hs[k]);
   }
   // collision of g at time 0 with c^0 = sum_k h~^0_k
@@ -176,15 +177,15 @@ __global__ void __launch_bounds__(256) k_init(Geo g, Coef<C> K, const double* __
   }
   // h~^0 into the slots the first pull reads
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k) {
+  for (int k = 0; k < LH::Q; ++k) {
     int dx = x, dy = y, dz = z;
     // destination x - e_k of the value arriving at x along k
-    bool in = pull_axis(dx, L::ex[k], g.nx, g.bcx) && pull_axis(dy, L::ey[k], g.ny, g.bcy);
-    if (L::D == 3) in = in && pull_axis(dz, L::ez[k], g.nz, g.bcz);
+    bool in = pull_axis(dx, LH::ex[k], g.nx, g.bcx) && pull_axis(dy, LH::ey[k], g.ny, g.bcy);
+    if (LH::D == 3) in = in && pull_axis(dz, LH::ez[k], g.nz, g.bcz);
     if (in)
-      H[pop_index<L>(g, k, dx, dy, dz)] = hs[k];
+      H[pop_index<LH>(g, k, dx, dy, dz)] = hs[k];
     else
-      H[pop_index<L>(g, L::opp[k], x, y, z)] = hs[k];
+      H[pop_index<LH>(g, LH::opp[k], x, y, z)] = hs[k];
   }
   PHI[i] = S(phi);
 }

@@ -51,9 +51,45 @@ def test_state_bytes_layout(lib):
         assert B.gplbm_state_bytes(cp) >= 4 * pop + 2 * phi
 
 
+@pytest.mark.parametrize("lattice,shape,qg,qh", [
+    (wl.D3Q19, (16, 12, 10), 19, 7), (wl.D2Q9, (1, 12, 10), 9, 5)])
+def test_state_bytes_layout_light_h(lib, lattice, shape, qg, qh):
+    """h on D2Q5 / D3Q7: the h distribution holds Qh populations per node."""
+    p = wl.base_params(lattice=lattice, shape=shape, bc=(0, 0, 0), h_lattice=1)
+    n = shape[0] * shape[1] * shape[2]
+    rnd = lambda v: (v + 255) // 256 * 256
+    for prec, elem in (("fp64", 8), ("fp32", 4)):
+        cp = B.make_params(p, prec)
+        assert cp.h_lattice == 1
+        pg, ph, phi = rnd(qg * n * elem), rnd(qh * n * elem), rnd(n * elem)
+        assert B.gplbm_checkpoint_bytes(cp) == pg + ph + phi
+        assert B.gplbm_state_bytes(cp) >= 2 * pg + 2 * ph + 2 * phi
+        full = B.make_params(dict(p, h_lattice=0), prec)
+        assert B.gplbm_state_bytes(full) - B.gplbm_state_bytes(cp) == 2 * (pg - ph)
+
+
+@pytest.mark.parametrize("prec", ["fp16dev", "bf16dev"])
+def test_light_h_rejected_with_deviation_storage(lib, prec):
+    cp = B.make_params(wl.base_params(lattice=wl.D3Q19, shape=(8, 8, 8), bc=(0, 0, 0),
+                                      h_lattice=1), prec)
+    with pytest.raises(B.GplbmError) as e:
+        B.gplbm_state_bytes(cp)
+    assert e.value.code == B.GPLBM_E_INVALID
+
+
+def test_adjoint_rejects_light_h(lib):
+    cp = B.make_params(wl.base_params(lattice=wl.D3Q19, shape=(8, 8, 8), bc=(0, 0, 0),
+                                      h_lattice=1), "fp64")
+    out = ctypes.c_uint64()
+    assert lib.gplbm_adjoint_bytes(ctypes.byref(cp), ctypes.byref(out)) == B.GPLBM_E_INVALID
+    cp.h_lattice = 0
+    assert lib.gplbm_adjoint_bytes(ctypes.byref(cp), ctypes.byref(out)) == B.GPLBM_OK
+
+
 @pytest.mark.parametrize("field,value", [
     ("M_phi", 0.0), ("M_phi", -1.0), ("gamma", 0.0), ("W", 0.0), ("nz", 2), ("nx", 0),
     ("lattice", 7), ("precision", 9), ("schedule", 5), ("lam", float("nan")),
+    ("h_lattice", 2), ("h_lattice", -1),
 ])
 def test_invalid_parameters_rejected(lib, field, value):
     p = wl.base_params()
