@@ -28,6 +28,8 @@ PERIODIC, ZERO_FLUX = 0, 1
 
 PARAM_KEYS = ("W", "M_phi", "lam", "D_l", "D_s", "gamma", "a_at",
               "c_s_co", "c_l_co", "mu_eq", "eps_n")
+# general quadratic free energies (free_energy = 1), with their defaults
+QUADRATIC_KEYS = (("eps_s", 1.0), ("eps_l", 1.0), ("m_s", 0.0), ("m_l", 0.0), ("df_min", 0.0))
 
 
 class _Params(ctypes.Structure):
@@ -38,12 +40,17 @@ class _Params(ctypes.Structure):
         ("counter_term", ctypes.c_int32),
         ("anti_trapping", ctypes.c_int32),
         ("h_lattice", ctypes.c_int32),
+        ("h_scheme", ctypes.c_int32),
+        ("free_energy", ctypes.c_int32),
         ("W", ctypes.c_double), ("M_phi", ctypes.c_double),
         ("lam", ctypes.c_double), ("D_l", ctypes.c_double),
         ("D_s", ctypes.c_double), ("gamma", ctypes.c_double),
         ("a_at", ctypes.c_double), ("c_s_co", ctypes.c_double),
         ("c_l_co", ctypes.c_double), ("mu_eq", ctypes.c_double),
         ("eps_n", ctypes.c_double),
+        ("eps_s", ctypes.c_double), ("eps_l", ctypes.c_double),
+        ("m_s", ctypes.c_double), ("m_l", ctypes.c_double),
+        ("df_min", ctypes.c_double),
     ]
 
 
@@ -92,6 +99,7 @@ def _load():
         lib.orc_get_state.argtypes = [ctypes.c_void_p, dp, dp, dp]
         lib.orc_set_state.argtypes = [ctypes.c_void_p, dp, dp, dp, ctypes.c_int64]
         lib.orc_diagnostics.argtypes = [ctypes.c_void_p, dp]
+        lib.orc_local.argtypes = [P(_Params), ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
         _lib = lib
     return _lib
 
@@ -104,28 +112,48 @@ def threads() -> int:
     return int(_load().orc_threads())
 
 
+def _params(cfg) -> _Params:
+    nz, ny, nx = cfg["shape"]
+    p = _Params()
+    p.lattice = int(cfg["lattice"])
+    p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+    for a in range(3):
+        p.bc[a] = int(cfg["bc"][a])
+    p.counter_term = int(cfg["counter_term"])
+    p.anti_trapping = int(cfg["anti_trapping"])
+    p.h_lattice = int(cfg.get("h_lattice", 0))
+    p.h_scheme = int(cfg.get("h_scheme", 0))
+    p.free_energy = int(cfg.get("free_energy", 0))
+    for key in PARAM_KEYS:
+        setattr(p, key, float(cfg[key]))
+    for key, default in QUADRATIC_KEYS:
+        setattr(p, key, float(cfg.get(key, default)))
+    return p
+
+
+def local(cfg, phi: float, c: float, mu: float):
+    """The oracle's local forms at one point: (closure mu(c, phi), bracket
+    of S_phi at mu, composition jump of the anti-trapping current at mu)."""
+    out = np.empty(3)
+    _load().orc_local(ctypes.byref(_params(cfg)), float(phi), float(c), float(mu), _ptr(out))
+    return float(out[0]), float(out[1]), float(out[2])
+
+
 class Oracle:
     """One simulation on the CPU oracle.
 
     ``cfg`` is a mapping with ``lattice`` (0 D2Q9, 1 D3Q19), ``shape``
     (nz, ny, nx), ``bc`` (per axis x, y, z: 0 periodic, 1 zero flux),
     ``counter_term``, ``anti_trapping``, the scalar keys of PARAM_KEYS and
-    optionally ``h_lattice`` (0: h on the lattice of g, 1: h on D2Q5 / D3Q7).
+    optionally ``h_lattice`` (0: h on the lattice of g, 1: h on D2Q5 / D3Q7),
+    ``h_scheme`` (0: source H_k, 1: h^eq,alt) and ``free_energy`` (0: equal
+    curvatures, 1: general quadratic with the keys of QUADRATIC_KEYS).
     """
 
     def __init__(self, cfg):
         lib = _load()
         nz, ny, nx = cfg["shape"]
-        p = _Params()
-        p.lattice = int(cfg["lattice"])
-        p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
-        for a in range(3):
-            p.bc[a] = int(cfg["bc"][a])
-        p.counter_term = int(cfg["counter_term"])
-        p.anti_trapping = int(cfg["anti_trapping"])
-        p.h_lattice = int(cfg.get("h_lattice", 0))
-        for key in PARAM_KEYS:
-            setattr(p, key, float(cfg[key]))
+        p = _params(cfg)
         self._p = p
         self.shape = (nz, ny, nx)
         self._h = lib.orc_create(ctypes.byref(p))

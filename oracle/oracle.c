@@ -15,24 +15,30 @@
  *
  * One step n -> n+1 follows the paper's order (Sec. 3.2 then Sec. 3.3):
  *   S1  c^n = sum_k h~^n_k ; mu^n by the closure, Eq. (PotChim_Equilibirum)
- *       with Eq. (Coexistence_Interpol), h(phi) = phi.
+ *       with Eq. (Coexistence_Interpol), h(phi) = phi (equal curvatures
+ *       eps_s = eps_l), or Eq. (Closure) for general quadratic free
+ *       energies.
  *   S2  directional derivatives and the gradient, Eqs. (DerivDirec_Grad) and
  *       (Grad); normal n = grad / sqrt(|grad|^2 + eps_n^2).
  *   S3  sources of the phi-LBE, Eqs. (TermG), (SourceG_ST), (SourceG_dw) or
- *       (SourceG_CT), with S_phi from Eq. (SourceTerm_Coexistence) and
- *       p'(phi) = 6 phi (1 - phi) (Tab. 2).
+ *       (SourceG_CT), with S_phi from Eq. (SourceTerm_Equilibrium) (general:
+ *       Eq. (SourceTerm)) and p'(phi) = 6 phi (1 - phi) (Tab. 2).
  *   S4  BGK collision with the trapezoidal source, Eq. (LBE_PhaseField_Eq),
  *       g~eq = w_k phi - G_k / 2, 1/(tau_g + 1/2) with M_phi = tau_g / 3.
  *   S5  streaming (periodic wrap or halfway bounce-back).
  *   S6  phi^{n+1} = sum_k g~^{n+1}_k + (1/2) sum_k G_k, Eq. (Moment_Phi), with
  *       the source moment taken from this step's collision at the same node.
  *   S7  dphi/dt = phi^{n+1} - phi^n (explicit Euler, h solved after g) and the
- *       anti-trapping current, Eq. (Anti-trapping_Equilibrium).
+ *       anti-trapping current, Eq. (Anti-trapping_Equilibrium) (general:
+ *       Eq. (Anti-Trapping_Quadratic)).
  *   S8  BGK collision of h, Eqs. (LBE_Composition), (Heq_Composition) and
  *       (SourceTerm_LBE_h), with D(phi) = D_l phi + D_s (1 - phi) and
  *       1/(tau_h + 1/2), tau_h = 1 / (gamma xi_s^2): 3 / gamma on D2Q9,
  *       D3Q19 and D2Q5 (xi_s^2 = 1/3), 4 / gamma on D3Q7 (xi_s^2 = 1/4), so
- *       that the diffusivity is D in every case.
+ *       that the diffusivity is D in every case.  Alternative scheme
+ *       (h_scheme = ORC_H_EQ_ALT): Eqs. (LBE_Concent_Alt) and
+ *       (Seq_Concent_Alt), relaxation to h^eq,alt with F folded into the
+ *       moving populations, w_k (Lambda + e_k . F / xi_s^2), and no source.
  *   S9  streaming of h.
  *
  * Evaluation order.  Every floating-point expression below is written out in
@@ -50,7 +56,12 @@
  *     bounce-back (the wall wins over a periodic wrap on another axis);
  *   - the initial populations are the equilibria shifted by the variable
  *     change: g~^0 = w_k phi0 - G^0_k / 2, h~^0 = h^eq_k - H^0_k / 2 with no
- *     anti-trapping current (dphi/dt unknown at t = 0).
+ *     anti-trapping current (dphi/dt unknown at t = 0); with h^eq,alt there
+ *     is no source, and h~^0 = h^eq,alt_k with the same F (no j_at);
+ *   - the general free energies keep the paper's h(phi) = phi,
+ *     q(phi) = phi + (1 - phi) D_s / D_l and a = a_at: the paper fixes these
+ *     choices for eps_s = eps_l and defers eps_s != eps_l, so the same
+ *     interpolations are taken there.
  */
 #include <math.h>
 #include <stdint.h>
@@ -162,11 +173,42 @@ static int pull_source(const orc_state* s, const int (*e)[3], int x, int y,
 /* ---------------------------------------------------------------------- */
 /* Local pieces of the scheme (one node).                                  */
 
-/* Closure for equal curvatures: mu = mu_eq + (c - c_co(phi)),
- * c_co(phi) = c_l phi + c_s (1 - phi). */
+/* Closure, h(phi) = phi.  Equal curvatures, Eqs. (PotChim_Equilibirum) and
+ * (Coexistence_Interpol): mu = mu_eq + (c - c_co(phi)),
+ * c_co(phi) = c_l phi + c_s (1 - phi).  General quadratic free energies,
+ * Eq. (Closure): mu = sqrt(eps_s eps_l) / (eps_s phi + eps_l (1 - phi))
+ * (c - phi m_l - (1 - phi) m_s). */
 static double closure(const orc_params* p, double c, double phi) {
+  if (p->free_energy == ORC_FE_QUADRATIC) {
+    double fac = sqrt(p->eps_s * p->eps_l) / ((p->eps_s * phi) + (p->eps_l * (1.0 - phi)));
+    return fac * ((c - (phi * p->m_l)) - ((1.0 - phi) * p->m_s));
+  }
   double cco = (p->c_l_co * phi) + (p->c_s_co * (1.0 - phi));
   return p->mu_eq + (c - cco);
+}
+
+/* Bracket of the coupling source, S_phi = p'(phi) * bracket.  Equal
+ * curvatures, Eq. (SourceTerm_Equilibrium): dc (mu - mu_eq).  General,
+ * Eq. (SourceTerm): ((eps_l - eps_s) / sqrt(eps_l eps_s)) mu^2 / 2
+ * - (m_l - m_s) mu - df_min. */
+static double coupling_bracket(const orc_params* p, double mu) {
+  if (p->free_energy == ORC_FE_QUADRATIC) {
+    double k2 = (p->eps_l - p->eps_s) / sqrt(p->eps_l * p->eps_s);
+    return (((k2 * (mu * mu)) * 0.5) - ((p->m_l - p->m_s) * mu)) - p->df_min;
+  }
+  return (p->c_s_co - p->c_l_co) * (mu - p->mu_eq);
+}
+
+/* Composition jump of the anti-trapping current, j_at = a W jump dphi/dt n.
+ * Equal curvatures, Eq. (Anti-trapping_Equilibrium): c_s_co - c_l_co.
+ * General, Eq. (Anti-Trapping_Quadratic):
+ * -((eps_s - eps_l) / sqrt(eps_s eps_l)) mu + m_s - m_l. */
+static double at_jump(const orc_params* p, double mu) {
+  if (p->free_energy == ORC_FE_QUADRATIC) {
+    double ks = -((p->eps_s - p->eps_l) / sqrt(p->eps_s * p->eps_l));
+    return ((ks * mu) + p->m_s) - p->m_l;
+  }
+  return p->c_s_co - p->c_l_co;
 }
 
 /* S2: gradient of phi at (x,y,z) by directional derivatives, and the
@@ -204,10 +246,9 @@ static double edot(const orc_state* s, int k, const double* v) {
 static void phi_sources(const orc_state* s, double phi, double mu,
                         const double* n3, double* G, double* sbar) {
   const orc_params* p = &s->p;
-  double dc = p->c_s_co - p->c_l_co;
-  /* G^st = -(lambda M / W^2) S_phi, S_phi = p'(phi) dc (mu - mu_eq) */
+  /* G^st = -(lambda M / W^2) S_phi, S_phi = p'(phi) * bracket */
   double pprime = 6.0 * (phi * (1.0 - phi));
-  double Sphi = (pprime * dc) * (mu - p->mu_eq);
+  double Sphi = pprime * coupling_bracket(p, mu);
   double Gst = -((p->lambda * p->M_phi) / (p->W * p->W)) * Sphi;
   if (p->counter_term) {
     /* G^ct_k = (4/W) phi (1 - phi) e_k . n */
@@ -242,6 +283,17 @@ static double h_source(const orc_state* s, int k, const double* F) {
   return (s->p.gamma * s->wh[k]) * r;
 }
 
+/* Alternative equilibrium, Eq. (Seq_Concent_Alt), on the h lattice: the rest
+ * population as in Eq. (Heq_Composition), the moving ones
+ * w_k (Lambda + e_k . F / xi_s^2). */
+static double h_equilibrium_alt(const orc_state* s, int k, double c, double lam,
+                                const double* F) {
+  if (k == s->resth) return c - (1.0 - s->wh[k]) * lam;
+  double r = 0.0;
+  for (int a = 0; a < s->D; ++a) r = r + (double)s->eh[k][a] * F[a];
+  return s->wh[k] * (lam + r / s->cs2h);
+}
+
 /* ---------------------------------------------------------------------- */
 
 orc_state* orc_create(const orc_params* p) {
@@ -250,6 +302,9 @@ orc_state* orc_create(const orc_params* p) {
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return NULL;
   if (p->lattice == ORC_D2Q9 && p->nz != 1) return NULL;
   if (p->h_lattice != 0 && p->h_lattice != 1) return NULL;
+  if (p->h_scheme != ORC_H_SOURCE && p->h_scheme != ORC_H_EQ_ALT) return NULL;
+  if (p->free_energy != ORC_FE_EQUAL && p->free_energy != ORC_FE_QUADRATIC) return NULL;
+  if (p->free_energy == ORC_FE_QUADRATIC && !(p->eps_s > 0.0 && p->eps_l > 0.0)) return NULL;
   orc_state* s = (orc_state*)calloc(1, sizeof(orc_state));
   s->p = *p;
   if (p->lattice == ORC_D2Q9) {
@@ -348,8 +403,12 @@ int orc_init(orc_state* s, const double* phi0, const double* c0) {
     for (int k = 0; k < Q; ++k) s->g[k * N + i] = s->w[k] * phi - 0.5 * G[k];
     for (int a = 0; a < s->D; ++a) F[a] = (mu * (p->D_l - p->D_s)) * g3[a];
     double lam = h_lambda(p, phi, mu);
-    for (int k = 0; k < Qh; ++k)
-      s->h[k * N + i] = h_equilibrium(s, k, c, lam) - 0.5 * h_source(s, k, F);
+    for (int k = 0; k < Qh; ++k) {
+      if (p->h_scheme == ORC_H_EQ_ALT)
+        s->h[k * N + i] = h_equilibrium_alt(s, k, c, lam, F);
+      else
+        s->h[k * N + i] = h_equilibrium(s, k, c, lam) - 0.5 * h_source(s, k, F);
+    }
   }
   (void)ny; (void)nz;
   s->step = 0;
@@ -364,7 +423,6 @@ static void step_once(orc_state* s) {
   const int64_t N = s->N;
   const double omega_g = 1.0 / (3.0 * p->M_phi + 0.5);
   const double omega_h = 1.0 / (1.0 / (p->gamma * s->cs2h) + 0.5);
-  const double dc = p->c_s_co - p->c_l_co;
 
   /* S1-S4: moments, closure, gradient, sources, collision of g. */
 #pragma omp parallel for
@@ -415,18 +473,25 @@ static void step_once(orc_state* s) {
     double phi = s->phi[i], mu = s->mu[i], c = s->c[i];
     double F[3] = {0.0, 0.0, 0.0};
     double dtphi = s->phin[i] - phi;
+    double jump = at_jump(p, mu);
     for (int a = 0; a < D; ++a) {
       double j = 0.0;
       if (p->anti_trapping)
-        j = (((p->a_at * p->W) * dc) * dtphi) * s->nrm[3 * i + a];
+        j = (((p->a_at * p->W) * jump) * dtphi) * s->nrm[3 * i + a];
       F[a] = (mu * (p->D_l - p->D_s)) * s->grad[3 * i + a] + j;
     }
     double lam = h_lambda(p, phi, mu);
     for (int k = 0; k < Qh; ++k) {
       double hk = s->h[k * N + i];
-      double Hk = h_source(s, k, F);
-      double t = (hk - h_equilibrium(s, k, c, lam)) + 0.5 * Hk;
-      s->hs[k * N + i] = (hk - omega_h * t) + Hk;
+      if (p->h_scheme == ORC_H_EQ_ALT) {
+        /* Eq. (LBE_Concent_Alt): relaxation to h^eq,alt, no source */
+        double t = hk - h_equilibrium_alt(s, k, c, lam, F);
+        s->hs[k * N + i] = hk - omega_h * t;
+      } else {
+        double Hk = h_source(s, k, F);
+        double t = (hk - h_equilibrium(s, k, c, lam)) + 0.5 * Hk;
+        s->hs[k * N + i] = (hk - omega_h * t) + Hk;
+      }
     }
   }
   /* S9: streaming of h. */
@@ -528,4 +593,10 @@ void orc_diagnostics(const orc_state* s, double* out) {
   out[5] = mx;
   out[6] = bad ? 1.0 : 0.0;
   out[7] = (double)s->step;
+}
+
+void orc_local(const orc_params* p, double phi, double c, double mu, double* out) {
+  out[0] = closure(p, c, phi);
+  out[1] = coupling_bracket(p, mu);
+  out[2] = at_jump(p, mu);
 }

@@ -14,6 +14,8 @@ extern "C" {
 
 enum { ORC_D2Q9 = 0, ORC_D3Q19 = 1 };
 enum { ORC_PERIODIC = 0, ORC_ZERO_FLUX = 1 };
+enum { ORC_H_SOURCE = 0, ORC_H_EQ_ALT = 1 };        /* h_scheme */
+enum { ORC_FE_EQUAL = 0, ORC_FE_QUADRATIC = 1 };    /* free_energy */
 
 typedef struct {
   int32_t lattice;
@@ -22,8 +24,12 @@ typedef struct {
   int32_t counter_term;  /* 1: counter term G^ct_k, 0: double-well term G^dw */
   int32_t anti_trapping; /* 1: anti-trapping current in the h source */
   int32_t h_lattice;     /* 0: h on the lattice of g; 1: h on D2Q5 / D3Q7 */
+  int32_t h_scheme;      /* ORC_H_SOURCE: source H_k; ORC_H_EQ_ALT: h^eq,alt, H = 0 */
+  int32_t free_energy;   /* ORC_FE_EQUAL: eps_s = eps_l (c_s_co, c_l_co, mu_eq);
+                            ORC_FE_QUADRATIC: general (eps_s, eps_l, m_s, m_l, df_min) */
   double W, M_phi, lambda, D_l, D_s, gamma, a_at;
   double c_s_co, c_l_co, mu_eq, eps_n;
+  double eps_s, eps_l, m_s, m_l, df_min;
 } orc_params;
 
 typedef struct orc_state orc_state;
@@ -43,6 +49,9 @@ void orc_get_state(const orc_state* s, double* g, double* h, double* phi);
 void orc_set_state(orc_state* s, const double* g, const double* h,
                    const double* phi, int64_t step);
 void orc_diagnostics(const orc_state* s, double* out8);
+/* The local forms at one point, for pins: out[0] = closure mu(c, phi),
+ * out[1] = bracket of S_phi at mu, out[2] = composition jump of j_at at mu. */
+void orc_local(const orc_params* p, double phi, double c, double mu, double* out3);
 
 #ifdef __cplusplus
 }

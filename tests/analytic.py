@@ -92,3 +92,34 @@ def first_moment(f, lattice, light=False):
     else:
         e = D2Q9_E if lattice == 0 else D3Q19_E
     return np.einsum("ka,k...->...a", e, f)
+
+
+# General quadratic free energies (eps_s != eps_l), Sec. 2.3, in the reduced
+# variables of the paper (mu = mu_bar V_m E, omega = omega_bar E,
+# E = sqrt(eps_s eps_l)).  Stated from the grand potentials of the two phases,
+# Eq. (Quadratic_grand-potential_Liquid), and the composition of the mixture,
+# Eq. (Composition_Quadratic), not from the closure or the source the oracle
+# evaluates.
+
+
+def quad_omega(mu, eps_phi, eps_s, eps_l, m_phi, f_min_bar):
+    """Reduced grand potential of one phase: -(E / eps_phi) mu^2 / 2
+    - m_phi mu + f_min_bar."""
+    E = math.sqrt(eps_s * eps_l)
+    return -(E / eps_phi) * mu * mu / 2.0 - m_phi * mu + f_min_bar
+
+
+def quad_composition(phi, mu, eps_s, eps_l, m_s, m_l):
+    """c(phi, mu) of Eq. (Composition_Quadratic) with h(phi) = phi, in reduced
+    units: phi m_l + (1 - phi) m_s + (phi E / eps_l + (1 - phi) E / eps_s) mu."""
+    E = math.sqrt(eps_s * eps_l)
+    return phi * m_l + (1.0 - phi) * m_s + (phi * E / eps_l + (1.0 - phi) * E / eps_s) * mu
+
+
+def quad_mu_eq(eps_s, eps_l, m_s, m_l, df_min, near=0.0):
+    """Equilibrium chemical potential: equal grand potentials of the two
+    phases, Eq. (Egalite_grand-potentiel), omega_l(mu) = omega_s(mu) with
+    f_min_s - f_min_l = df_min; the root nearest to `near`."""
+    f = lambda m: (quad_omega(m, eps_l, eps_s, eps_l, m_l, 0.0)
+                   - quad_omega(m, eps_s, eps_s, eps_l, m_s, df_min))
+    return brentq(f, near - 0.5, near + 0.5, xtol=1e-15, rtol=1e-15)

@@ -84,8 +84,8 @@ MUTANTS = [
      "s->phin[i] = sum + 0.5 * s->sbar[i];",
      "s->phin[i] = sum;"),
     ("anti-trapping: sign flipped",
-     "j = (((p->a_at * p->W) * dc) * dtphi) * s->nrm[3 * i + a];",
-     "j = -(((p->a_at * p->W) * dc) * dtphi) * s->nrm[3 * i + a];"),
+     "j = (((p->a_at * p->W) * jump) * dtphi) * s->nrm[3 * i + a];",
+     "j = -(((p->a_at * p->W) * jump) * dtphi) * s->nrm[3 * i + a];"),
     ("anti-trapping: d phi / dt taken as zero",
      "double dtphi = s->phin[i] - phi;",
      "double dtphi = 0.0;"),
@@ -99,8 +99,8 @@ MUTANTS = [
      "return (s->p.gamma * s->wh[k]) * r;",
      "return (s->wh[k]) * r;"),
     ("h equilibrium: rest population c - Lambda",
-     "if (k == s->resth) return c - (1.0 - s->wh[k]) * lam;",
-     "if (k == s->resth) return c - lam;"),
+     "if (k == s->resth) return c - (1.0 - s->wh[k]) * lam;\n  return s->wh[k] * lam;",
+     "if (k == s->resth) return c - lam;\n  return s->wh[k] * lam;"),
     ("h collision: trapezoidal half source dropped",
      "double t = (hk - h_equilibrium(s, k, c, lam)) + 0.5 * Hk;",
      "double t = (hk - h_equilibrium(s, k, c, lam));"),
@@ -134,6 +134,53 @@ MUTANTS = [
     ("D2Q9 table: vector 5 mistyped",
      "{1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};\nstatic const double d2q9_w",
      "{1, -1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};\nstatic const double d2q9_w"),
+    # the alternative equilibrium h^eq,alt
+    ("h^eq,alt: flux term dropped",
+     "return s->wh[k] * (lam + r / s->cs2h);",
+     "return s->wh[k] * lam;"),
+    ("h^eq,alt: 1/xi_s^2 dropped",
+     "return s->wh[k] * (lam + r / s->cs2h);",
+     "return s->wh[k] * (lam + r);"),
+    ("h^eq,alt: flux with the wrong sign",
+     "return s->wh[k] * (lam + r / s->cs2h);",
+     "return s->wh[k] * (lam - r / s->cs2h);"),
+    ("h^eq,alt: rest population c - Lambda",
+     "if (k == s->resth) return c - (1.0 - s->wh[k]) * lam;\n  double r = 0.0;",
+     "if (k == s->resth) return c - lam;\n  double r = 0.0;"),
+    ("alt collision: source added as well",
+     "s->hs[k * N + i] = hk - omega_h * t;",
+     "s->hs[k * N + i] = (hk - omega_h * t) + h_source(s, k, F);"),
+    ("alt init: shifted by -H/2",
+     "s->h[k * N + i] = h_equilibrium_alt(s, k, c, lam, F);",
+     "s->h[k * N + i] = h_equilibrium_alt(s, k, c, lam, F) - 0.5 * h_source(s, k, F);"),
+    # general quadratic free energies
+    ("closure (general): eps_s and eps_l swapped in the denominator",
+     "/ ((p->eps_s * phi) + (p->eps_l * (1.0 - phi)));",
+     "/ ((p->eps_l * phi) + (p->eps_s * (1.0 - phi)));"),
+    ("closure (general): m_s and m_l swapped",
+     "return fac * ((c - (phi * p->m_l)) - ((1.0 - phi) * p->m_s));",
+     "return fac * ((c - (phi * p->m_s)) - ((1.0 - phi) * p->m_l));"),
+    ("closure (general): prefactor dropped",
+     "return fac * ((c - (phi * p->m_l)) - ((1.0 - phi) * p->m_s));",
+     "return ((c - (phi * p->m_l)) - ((1.0 - phi) * p->m_s));"),
+    ("source (general): sign of the mu^2 term",
+     "return (((k2 * (mu * mu)) * 0.5) - ((p->m_l - p->m_s) * mu)) - p->df_min;",
+     "return (((-k2 * (mu * mu)) * 0.5) - ((p->m_l - p->m_s) * mu)) - p->df_min;"),
+    ("source (general): 1/2 of the mu^2 term dropped",
+     "return (((k2 * (mu * mu)) * 0.5) - ((p->m_l - p->m_s) * mu)) - p->df_min;",
+     "return (((k2 * (mu * mu)) * 1.0) - ((p->m_l - p->m_s) * mu)) - p->df_min;"),
+    ("source (general): m_l - m_s reversed",
+     "return (((k2 * (mu * mu)) * 0.5) - ((p->m_l - p->m_s) * mu)) - p->df_min;",
+     "return (((k2 * (mu * mu)) * 0.5) - ((p->m_s - p->m_l) * mu)) - p->df_min;"),
+    ("source (general): sign of df_min",
+     "return (((k2 * (mu * mu)) * 0.5) - ((p->m_l - p->m_s) * mu)) - p->df_min;",
+     "return (((k2 * (mu * mu)) * 0.5) - ((p->m_l - p->m_s) * mu)) + p->df_min;"),
+    ("anti-trapping (general): sign of the mu term",
+     "double ks = -((p->eps_s - p->eps_l) / sqrt(p->eps_s * p->eps_l));",
+     "double ks = ((p->eps_s - p->eps_l) / sqrt(p->eps_s * p->eps_l));"),
+    ("anti-trapping (general): m_s - m_l reversed",
+     "return ((ks * mu) + p->m_s) - p->m_l;",
+     "return ((ks * mu) + p->m_l) - p->m_s;"),
     ("D3Q19 table: axis and diagonal weights swapped",
      "    1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,\n    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,\n    1.0 / 18.0,",
      "    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,\n    1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,\n    1.0 / 18.0,"),
