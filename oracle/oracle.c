@@ -187,10 +187,10 @@ static double closure(const orc_params* p, double c, double phi) {
   return p->mu_eq + (c - cco);
 }
 
-/* Bracket of the coupling source, S_phi = p'(phi) * bracket.  Equal
- * curvatures, Eq. (SourceTerm_Equilibrium): dc (mu - mu_eq).  General,
- * Eq. (SourceTerm): ((eps_l - eps_s) / sqrt(eps_l eps_s)) mu^2 / 2
- * - (m_l - m_s) mu - df_min. */
+/* Bracket of the coupling source for general quadratic free energies,
+ * S_phi = p'(phi) * bracket, Eq. (SourceTerm):
+ * ((eps_l - eps_s) / sqrt(eps_l eps_s)) mu^2 / 2 - (m_l - m_s) mu - df_min.
+ * (Equal curvatures: dc (mu - mu_eq), Eq. (SourceTerm_Equilibrium).) */
 static double coupling_bracket(const orc_params* p, double mu) {
   if (p->free_energy == ORC_FE_QUADRATIC) {
     double k2 = (p->eps_l - p->eps_s) / sqrt(p->eps_l * p->eps_s);
@@ -246,9 +246,13 @@ static double edot(const orc_state* s, int k, const double* v) {
 static void phi_sources(const orc_state* s, double phi, double mu,
                         const double* n3, double* G, double* sbar) {
   const orc_params* p = &s->p;
-  /* G^st = -(lambda M / W^2) S_phi, S_phi = p'(phi) * bracket */
+  /* G^st = -(lambda M / W^2) S_phi */
   double pprime = 6.0 * (phi * (1.0 - phi));
-  double Sphi = pprime * coupling_bracket(p, mu);
+  double Sphi;
+  if (p->free_energy == ORC_FE_QUADRATIC)
+    Sphi = pprime * coupling_bracket(p, mu);
+  else /* S_phi = p'(phi) dc (mu - mu_eq) */
+    Sphi = (pprime * (p->c_s_co - p->c_l_co)) * (mu - p->mu_eq);
   double Gst = -((p->lambda * p->M_phi) / (p->W * p->W)) * Sphi;
   if (p->counter_term) {
     /* G^ct_k = (4/W) phi (1 - phi) e_k . n */
