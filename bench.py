@@ -12,12 +12,14 @@ Printed: one JSON line with MLUPS (million node updates per second), the
 HBM roofline of the step kernel (algorithmic bytes per launch over the mean
 launch time, measured with HIP events on the stream the library launches on),
 the other forms of the same step beside it (FP32, FP16 and BF16 deviation
-storage; h on the light lattice D3Q7 / D2Q5 in FP64 and FP32), the
+storage; h on the light lattice D3Q7 / D2Q5 in FP64 and FP32; the alternative
+equilibrium h^eq,alt and general quadratic free energies in FP64), the
 differentiation workload (adjoint / forward time), and the CPU oracle timed on
 a bounded crop of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--precision fp64|fp32|fp16dev|bf16dev]
-                    [--h-lattice full|light] [--schedule auto|split|fused]
+                    [--h-lattice full|light] [--h-scheme source|alt]
+                    [--free-energy equal|quadratic] [--schedule auto|split|fused]
                     [--workload NAME] [--no-cpu-baseline] [--no-forms]
                     [--adjoint-steps K] [--variants]
 """
@@ -50,10 +52,28 @@ def bytes_per_node_step(lattice_q: int, precision: str, lattice_qh: int | None =
     return (2 * lattice_q + 2 * qh + 2) * elem
 
 
-def form_name(precision: str, h_lattice: str) -> str:
+def form_name(precision: str, h_lattice: str = "full", h_scheme: str = "source",
+              free_energy: str = "equal") -> str:
     """Label of a form of the step: the precision, with '_light_h' when h
-    runs on D3Q7 / D2Q5."""
-    return precision + ("_light_h" if h_lattice == "light" else "")
+    runs on D3Q7 / D2Q5, '_alt_h' with h^eq,alt, '_quadratic' with general
+    quadratic free energies."""
+    return (precision + ("_light_h" if h_lattice == "light" else "")
+            + ("_alt_h" if h_scheme == "alt" else "")
+            + ("_quadratic" if free_energy == "quadratic" else ""))
+
+
+# general quadratic free energies for the workloads: eps_l / eps_s = 1.5,
+# minima at the coexistence compositions of the equal-curvature parameters and
+# df_min = 0, so that mu_eq = 0 and the coexistence compositions are unchanged
+QUADRATIC = dict(free_energy=1, eps_s=1.0, eps_l=1.5)
+
+
+def form_params(p, h_lattice="full", h_scheme="source", free_energy="equal"):
+    q = dict(p, h_lattice=1 if h_lattice == "light" else 0,
+             h_scheme=1 if h_scheme == "alt" else 0)
+    if free_energy == "quadratic":
+        q.update(QUADRATIC, m_s=p["c_s_co"], m_l=p["c_l_co"], df_min=0.0)
+    return q
 
 
 WORKLOADS = {
@@ -76,11 +96,12 @@ def make_workload(name):
     return p, phi0, c0
 
 
-def time_gpu(p, phi0, c0, precision, schedule, steps, warmup, log, h_lattice="full"):
+def time_gpu(p, phi0, c0, precision, schedule, steps, warmup, log, h_lattice="full",
+             h_scheme="source", free_energy="equal"):
     import torch
     from paper_2111_05960_amd import Simulation
 
-    p = dict(p, h_lattice=1 if h_lattice == "light" else 0)
+    p = form_params(p, h_lattice, h_scheme, free_energy)
     sim = Simulation(p, precision, schedule)
     sim.init(phi0, c0)
     torch.cuda.synchronize()
@@ -111,7 +132,8 @@ def time_gpu(p, phi0, c0, precision, schedule, steps, warmup, log, h_lattice="fu
         mass_drift_rel=abs(d1["total_mass"] - d0["total_mass"]) / abs(d0["total_mass"]),
         nonfinite=d1["nonfinite"], solid_fraction=[d0["solid_fraction"], d1["solid_fraction"]],
     )
-    log(f"gpu {form_name(precision, h_lattice)} {sim.schedule}: {res['mlups']:.1f} MLUPS, {ms_step:.3f} ms/step, "
+    log(f"gpu {form_name(precision, h_lattice, h_scheme, free_energy)} {sim.schedule}: "
+        f"{res['mlups']:.1f} MLUPS, {ms_step:.3f} ms/step, "
         f"{res['achieved_gbs']:.0f} GB/s algorithmic, mass drift {res['mass_drift_rel']:.2e}")
     del sim
     torch.cuda.empty_cache()
@@ -358,6 +380,10 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp16dev", "bf16dev"])
     ap.add_argument("--h-lattice", default="full", choices=["full", "light"],
                     help="h on the lattice of g, or on D3Q7 / D2Q5 (FP64 and FP32)")
+    ap.add_argument("--h-scheme", default="source", choices=["source", "alt"],
+                    help="source H_k, or h^eq,alt (FP64 and FP32)")
+    ap.add_argument("--free-energy", default="equal", choices=["equal", "quadratic"],
+                    help="equal curvatures, or general quadratic (FP64 and FP32)")
     ap.add_argument("--schedule", default="auto", choices=["auto", "split", "fused"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
@@ -379,7 +405,8 @@ def main():
         global PROFILE_CMD
         PROFILE_CMD = args.profile_cmd
         summarize_profile(args.profile_kind, args.summarize_profile, args.out, args.workload,
-                          form_name(args.precision, args.h_lattice), args.schedule)
+                          form_name(args.precision, args.h_lattice, args.h_scheme,
+                                    args.free_energy), args.schedule)
         return
 
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
@@ -399,19 +426,22 @@ def main():
     p, phi0, c0 = make_workload(args.workload)
     log(f"workload {args.workload} generated in {time.perf_counter() - t0:.1f} s")
 
-    main_form = form_name(args.precision, args.h_lattice)
+    variant = (args.h_lattice, args.h_scheme, args.free_energy)
+    main_form = form_name(args.precision, *variant)
     main_res = time_gpu(p, phi0, c0, args.precision, args.schedule, args.steps, args.warmup, log,
-                        args.h_lattice)
+                        *variant)
     # the other forms of the same step, side by side (auto schedule)
     forms = {}
     if not args.no_forms:
         precs = ("fp64", "fp32") + (("fp16dev", "bf16dev") if p["lattice"] == 1 else ())
-        todo = [(prec, "full") for prec in precs] + [("fp64", "light"), ("fp32", "light")]
-        for prec, hl in todo:
-            name = form_name(prec, hl)
+        todo = ([(prec, "full", "source", "equal") for prec in precs]
+                + [("fp64", "light", "source", "equal"), ("fp32", "light", "source", "equal"),
+                   ("fp64", "full", "alt", "equal"), ("fp64", "full", "source", "quadratic")])
+        for prec, *var in todo:
+            name = form_name(prec, *var)
             if name == main_form:
                 continue
-            r = time_gpu(p, phi0, c0, prec, "auto", args.steps, args.warmup, log, hl)
+            r = time_gpu(p, phi0, c0, prec, "auto", args.steps, args.warmup, log, *var)
             t = stored_traffic(args.workload, name, r["schedule"])
             forms[name] = {
                 "mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
@@ -441,7 +471,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(p, phi0, c0, log)
+        cpu = cpu_baseline(form_params(p, *variant), phi0, c0, log)
     traffic = stored_traffic(args.workload, main_form, main_res["schedule"])
 
     nz, ny, nx = p["shape"]
@@ -465,6 +495,7 @@ def main():
             "lattice": "D3Q19" if p["lattice"] == 1 else "D2Q9",
             "h_lattice": {(1, "full"): "D3Q19", (1, "light"): "D3Q7", (0, "full"): "D2Q9",
                           (0, "light"): "D2Q5"}[(p["lattice"], args.h_lattice)],
+            "h_scheme": args.h_scheme, "free_energy": args.free_energy,
             "grid": [nx, ny, nz],
             "bc": "periodic",
             "precision": args.precision,

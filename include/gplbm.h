@@ -66,6 +66,26 @@ extern "C" {
 #define GPLBM_H_FULL 0
 #define GPLBM_H_LIGHT 1
 
+/* scheme of the c-LBE.  SOURCE: Eqs. (LBE_Composition), (Heq_Composition),
+ * (SourceTerm_LBE_h).  EQ_ALT: Eqs. (LBE_Concent_Alt), (Seq_Concent_Alt), the
+ * flux F = mu D' grad phi + j_at folded into the moving populations of the
+ * equilibrium, w_k (gamma D mu + e_k . F / xi_s^2), no source; the initial
+ * populations are that equilibrium (no variable-change shift).  FP64 and
+ * FP32 only; no adjoint. */
+#define GPLBM_H_SOURCE 0
+#define GPLBM_H_EQ_ALT 1
+
+/* free energies of the two phases (parabolas, Sec. 2.3).  EQUAL: equal
+ * curvatures, parameterised by c_s_co, c_l_co, mu_eq (closure
+ * Eq. (PotChim_Equilibirum), source Eq. (SourceTerm_Equilibrium),
+ * anti-trapping Eq. (Anti-trapping_Equilibrium)).  QUADRATIC: general
+ * eps_s != eps_l, parameterised by eps_s, eps_l, m_s, m_l, df_min (closure
+ * Eq. (Closure), source Eq. (SourceTerm), anti-trapping
+ * Eq. (Anti-Trapping_Quadratic)), with the interpolations h(phi) = phi,
+ * q(phi) and a of the equal case.  FP64 and FP32 only; no adjoint. */
+#define GPLBM_FE_EQUAL 0
+#define GPLBM_FE_QUADRATIC 1
+
 /* boundary conditions per axis */
 #define GPLBM_PERIODIC 0
 #define GPLBM_ZERO_FLUX 1 /* halfway bounce-back, walls at -1/2 and n-1/2 */
@@ -95,6 +115,8 @@ typedef struct gplbm_params {
   int32_t anti_trapping; /* 1: anti-trapping current in the h source */
   int32_t schedule;      /* GPLBM_SCHED_* */
   int32_t h_lattice;     /* GPLBM_H_FULL or GPLBM_H_LIGHT */
+  int32_t h_scheme;      /* GPLBM_H_SOURCE or GPLBM_H_EQ_ALT */
+  int32_t free_energy;   /* GPLBM_FE_EQUAL or GPLBM_FE_QUADRATIC */
   double W;              /* interface width */
   double M_phi;          /* phase-field mobility; tau_g = 3 M_phi */
   double lambda;         /* coupling constant */
@@ -104,6 +126,10 @@ typedef struct gplbm_params {
   double c_s_co, c_l_co; /* coexistence compositions */
   double mu_eq;          /* equilibrium chemical potential */
   double eps_n;          /* regularisation of the normal */
+  /* GPLBM_FE_QUADRATIC only: curvatures eps_s, eps_l > 0 (only their ratio
+   * enters), compositions m_s, m_l at the minima, reduced df_min = f_s^min -
+   * f_l^min; c_s_co, c_l_co, mu_eq are then unused */
+  double eps_s, eps_l, m_s, m_l, df_min;
 } gplbm_params;
 
 typedef struct gplbm_diag {

@@ -27,6 +27,8 @@ GPLBM_E_STATE = -5
 
 GPLBM_D2Q9, GPLBM_D3Q19 = 0, 1
 GPLBM_H_FULL, GPLBM_H_LIGHT = 0, 1
+GPLBM_H_SOURCE, GPLBM_H_EQ_ALT = 0, 1
+GPLBM_FE_EQUAL, GPLBM_FE_QUADRATIC = 0, 1
 GPLBM_PERIODIC, GPLBM_ZERO_FLUX = 0, 1
 GPLBM_FP64, GPLBM_FP32, GPLBM_FP16_DEV, GPLBM_BF16_DEV = 0, 1, 2, 3
 GPLBM_SCHED_AUTO, GPLBM_SCHED_SPLIT, GPLBM_SCHED_FUSED = 0, 1, 2
@@ -53,10 +55,14 @@ class gplbm_params(ctypes.Structure):
         ("anti_trapping", ctypes.c_int32),
         ("schedule", ctypes.c_int32),
         ("h_lattice", ctypes.c_int32),
+        ("h_scheme", ctypes.c_int32),
+        ("free_energy", ctypes.c_int32),
         ("W", ctypes.c_double), ("M_phi", ctypes.c_double), ("lam", ctypes.c_double),
         ("D_l", ctypes.c_double), ("D_s", ctypes.c_double), ("gamma", ctypes.c_double),
         ("a_at", ctypes.c_double), ("c_s_co", ctypes.c_double), ("c_l_co", ctypes.c_double),
         ("mu_eq", ctypes.c_double), ("eps_n", ctypes.c_double),
+        ("eps_s", ctypes.c_double), ("eps_l", ctypes.c_double),
+        ("m_s", ctypes.c_double), ("m_l", ctypes.c_double), ("df_min", ctypes.c_double),
     ]
 
 
@@ -129,7 +135,10 @@ def make_params(cfg, precision="fp64", schedule="auto") -> gplbm_params:
     """C parameter struct from a mapping with the keys lattice, shape
     (nz, ny, nx), bc, counter_term, anti_trapping, W, M_phi, lam, D_l, D_s,
     gamma, a_at, c_s_co, c_l_co, mu_eq, eps_n, and optionally h_lattice
-    (0: h on the lattice of g, the default; 1: h on D2Q5 / D3Q7)."""
+    (0: h on the lattice of g, the default; 1: h on D2Q5 / D3Q7), h_scheme
+    (0: source H_k, the default; 1: h^eq,alt) and free_energy (0: equal
+    curvatures, the default; 1: general quadratic, with eps_s, eps_l, m_s,
+    m_l, df_min)."""
     p = gplbm_params()
     nz, ny, nx = cfg["shape"]
     p.lattice = int(cfg["lattice"])
@@ -141,6 +150,11 @@ def make_params(cfg, precision="fp64", schedule="auto") -> gplbm_params:
     p.anti_trapping = int(cfg["anti_trapping"])
     p.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
     p.h_lattice = int(cfg.get("h_lattice", 0))
+    p.h_scheme = int(cfg.get("h_scheme", 0))
+    p.free_energy = int(cfg.get("free_energy", 0))
+    for key, default in (("eps_s", 1.0), ("eps_l", 1.0), ("m_s", 0.0), ("m_l", 0.0),
+                         ("df_min", 0.0)):
+        setattr(p, key, float(cfg.get(key, default)))
     for key in ("W", "M_phi", "lam", "D_l", "D_s", "gamma", "a_at", "c_s_co", "c_l_co",
                 "mu_eq", "eps_n"):
         setattr(p, key, float(cfg[key]))

@@ -83,6 +83,17 @@ const char* check_params(const gplbm_params* p) {
   if (p->h_lattice != GPLBM_H_FULL && p->h_lattice != GPLBM_H_LIGHT) return "unknown h lattice";
   if (p->h_lattice == GPLBM_H_LIGHT && p->precision >= GPLBM_FP16_DEV)
     return "deviation storage needs h on the lattice of g";
+  if (p->h_scheme != GPLBM_H_SOURCE && p->h_scheme != GPLBM_H_EQ_ALT) return "unknown h scheme";
+  if (p->free_energy != GPLBM_FE_EQUAL && p->free_energy != GPLBM_FE_QUADRATIC)
+    return "unknown free energy";
+  if (p->precision >= GPLBM_FP16_DEV && (p->h_scheme != GPLBM_H_SOURCE || p->free_energy != GPLBM_FE_EQUAL))
+    return "deviation storage needs the source scheme and equal curvatures";
+  if (p->free_energy == GPLBM_FE_QUADRATIC) {
+    if (!(p->eps_s > 0.0) || !(p->eps_l > 0.0) || !std::isfinite(p->eps_s) || !std::isfinite(p->eps_l))
+      return "eps_s and eps_l must be > 0";
+    if (!std::isfinite(p->m_s) || !std::isfinite(p->m_l) || !std::isfinite(p->df_min))
+      return "non-finite parameter";
+  }
   if (!(p->W > 0.0) || !std::isfinite(p->W)) return "W must be > 0";
   if (!(p->M_phi > 0.0) || !std::isfinite(p->M_phi)) return "M_phi must be > 0 (omega_g in (0,2))";
   if (!(p->gamma > 0.0) || !std::isfinite(p->gamma)) return "gamma must be > 0 (omega_h in (0,2))";
@@ -136,6 +147,22 @@ int check_launch(gplbm_ctx* ctx, const char* what) {
   return GPLBM_OK;
 }
 
+ClosureK closure_k(const gplbm_params& p) {
+  ClosureK q{};
+  q.quad = p.free_energy == GPLBM_FE_QUADRATIC ? 1 : 0;
+  q.cl = p.c_l_co;
+  q.cs = p.c_s_co;
+  q.mueq = p.mu_eq;
+  if (q.quad) {
+    q.efac = std::sqrt(p.eps_s * p.eps_l);
+    q.eps_s = p.eps_s;
+    q.eps_l = p.eps_l;
+    q.m_s = p.m_s;
+    q.m_l = p.m_l;
+  }
+  return q;
+}
+
 template <class C>
 Coef<C> make_coef(const gplbm_params& p) {
   Coef<C> K{};
@@ -160,6 +187,18 @@ Coef<C> make_coef(const gplbm_params& p) {
   K.mueq = p.mu_eq;
   K.counter_term = p.counter_term ? 1 : 0;
   K.anti_trapping = p.anti_trapping ? 1 : 0;
+  K.h_alt = p.h_scheme == GPLBM_H_EQ_ALT ? 1 : 0;
+  K.fe_quad = p.free_energy == GPLBM_FE_QUADRATIC ? 1 : 0;
+  K.q = closure_k(p);
+  if (K.fe_quad) {
+    K.k2 = C((p.eps_l - p.eps_s) / std::sqrt(p.eps_l * p.eps_s));
+    K.dml = C(p.m_l - p.m_s);
+    K.dfm = C(p.df_min);
+    K.ks = C(-((p.eps_s - p.eps_l) / std::sqrt(p.eps_s * p.eps_l)));
+    K.ms = C(p.m_s);
+    K.ml = C(p.m_l);
+    K.aW = C(p.a_at * p.W);
+  }
   return K;
 }
 
@@ -184,6 +223,10 @@ struct Ops {
     return dim3((ctx->p.nx + 63) / 64, (ctx->p.ny + 3) / 4, ctx->p.nz);
   }
   static Coef<C> coef(const gplbm_ctx* ctx) { return make_coef<C>(ctx->p); }
+  // the alternative h scheme or the general free energies
+  static bool general(const gplbm_ctx* ctx) {
+    return ctx->p.h_scheme != GPLBM_H_SOURCE || ctx->p.free_energy != GPLBM_FE_EQUAL;
+  }
 
   static int init(gplbm_ctx* ctx, const double* phi0, const double* c0) {
     const Geo g = make_geo(ctx->p);
@@ -200,8 +243,17 @@ struct Ops {
       const int a = ctx->cur, b = 1 - a;
       StepBufs<S> bufs{(const S*)ctx->G[a], (const S*)ctx->H[a], (const S*)ctx->PHI[a],
                        (S*)ctx->H[b],       (S*)ctx->PHI[b],       (S*)ctx->G[b]};
-      hipLaunchKernelGGL((k_split_h<L, LH, S, C>), grid(ctx), block(), 0, ctx->stream, g, K, bufs);
-      hipLaunchKernelGGL((k_split_g<L, LH, S, C>), grid(ctx), block(), 0, ctx->stream, g, K, bufs);
+      if (general(ctx)) {
+        hipLaunchKernelGGL((k_split_h<L, LH, S, C, true>), grid(ctx), block(), 0, ctx->stream, g, K,
+                           bufs);
+        hipLaunchKernelGGL((k_split_g<L, LH, S, C, true>), grid(ctx), block(), 0, ctx->stream, g, K,
+                           bufs);
+      } else {
+        hipLaunchKernelGGL((k_split_h<L, LH, S, C, false>), grid(ctx), block(), 0, ctx->stream, g,
+                           K, bufs);
+        hipLaunchKernelGGL((k_split_g<L, LH, S, C, false>), grid(ctx), block(), 0, ctx->stream, g,
+                           K, bufs);
+      }
       int rc = check_launch(ctx, "split step");
       if (rc) return rc;
       ctx->cur = b;
@@ -217,7 +269,8 @@ struct Ops {
       const int a = ctx->cur, b = 1 - a;
       StepBufs<S> bufs{(const S*)ctx->G[a], (const S*)ctx->H[a], (const S*)ctx->PHI[a],
                        (S*)ctx->H[b],       (S*)ctx->PHI[b],       (S*)ctx->G[b]};
-      int rc = FusedLaunch<L, LH, S, C>::launch(g, K, bufs, ctx->stream);
+      int rc = general(ctx) ? FusedLaunch<L, LH, S, C, true>::launch(g, K, bufs, ctx->stream)
+                            : FusedLaunch<L, LH, S, C, false>::launch(g, K, bufs, ctx->stream);
       if (rc) return fail(ctx, GPLBM_E_DEVICE, "fused step launch failed");
       rc = check_launch(ctx, "fused step");
       if (rc) return rc;
@@ -230,9 +283,8 @@ struct Ops {
   static int fields(gplbm_ctx* ctx, double* phi, double* c, double* mu) {
     const Geo g = make_geo(ctx->p);
     const int a = ctx->cur;
-    hipLaunchKernelGGL((k_fields<LH, S>), grid(ctx), block(), 0, ctx->stream, g, ctx->p.c_l_co,
-                       ctx->p.c_s_co, ctx->p.mu_eq, (const S*)ctx->H[a], (const S*)ctx->PHI[a],
-                       phi, c, mu);
+    hipLaunchKernelGGL((k_fields<LH, S>), grid(ctx), block(), 0, ctx->stream, g,
+                       closure_k(ctx->p), (const S*)ctx->H[a], (const S*)ctx->PHI[a], phi, c, mu);
     return check_launch(ctx, "read fields");
   }
 
@@ -696,9 +748,11 @@ struct AdjFinishFn {
   }
 };
 
-// The adjoint is written for h on the lattice of g, in FP64 or FP32.
+// The adjoint is written for h on the lattice of g with the source scheme and
+// equal curvatures, in FP64 or FP32.
 bool adjoint_supported(const gplbm_params& p) {
-  return (p.precision == GPLBM_FP64 || p.precision == GPLBM_FP32) && p.h_lattice == GPLBM_H_FULL;
+  return (p.precision == GPLBM_FP64 || p.precision == GPLBM_FP32) && p.h_lattice == GPLBM_H_FULL &&
+         p.h_scheme == GPLBM_H_SOURCE && p.free_energy == GPLBM_FE_EQUAL;
 }
 
 }  // namespace
@@ -715,7 +769,9 @@ int gplbm_adjoint_begin(gplbm_ctx* ctx, void* work, uint64_t bytes, const double
                         const double* c_bar) {
   if (!ctx || !work || ((uintptr_t)work) % kAlign) return GPLBM_E_INVALID;
   if (!adjoint_supported(ctx->p))
-    return fail(ctx, GPLBM_E_INVALID, "adjoint needs an FP64 or FP32 context with h on the g lattice");
+    return fail(ctx, GPLBM_E_INVALID,
+                "adjoint needs an FP64 or FP32 context with h on the g lattice, the source "
+                "scheme and equal curvatures");
   const AdjLayout l = adj_layout(&ctx->p);
   if (bytes < l.total) return fail(ctx, GPLBM_E_SIZE, "adjoint workspace too small");
   if (int rc = use_device(ctx)) return rc;

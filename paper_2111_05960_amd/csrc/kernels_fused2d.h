@@ -25,9 +25,11 @@
 
 namespace gplbm {
 
-template <int TX, int TY, class L, class LH, class S, class C>
-__global__ void __launch_bounds__((TileShape<TX, TY>::NT))
-    k_fused2d(Geo g, Coef<C> K, StepBufs<S> b, int tiles_x, int ntiles) {
+// FP32: at most 80 VGPRs, so that two blocks of 11 waves share a CU.
+template <int TX, int TY, class L, class LH, class S, class C, bool kGen>
+__global__ void __launch_bounds__((TileShape<TX, TY>::NT), (sizeof(S) == 4 ? 6 : 1))
+    k_fused2d(Geo g, Coef<C> Kin, StepBufs<S> b, int tiles_x, int ntiles) {
+  const Coef<C> K = variant<kGen>(Kin);
   using Shape = TileShape<TX, TY>;
   constexpr int BX = Shape::BX, BY = Shape::BY, NT = Shape::NT;
   constexpr int AX = BX + 2, AY = BY + 2;  // phi^n tile with a 2-node halo
@@ -83,7 +85,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
       sg = k == 0 ? double(v) : sg + double(v);
     }
     const C phi = phiA[ty + 1][tx + 1];
-    const C mu = C(closure(K.cl, K.cs, K.mueq, c, double(phi)));
+    const C mu = C(closure(K.q, c, double(phi)));
     auto at = [&](int dx, int dy, int) -> C {
       const int ox = dx < 0 ? xm : (dx > 0 ? xp : 0);
       const int oy = dy < 0 ? ym : (dy > 0 ? yp : 0);
@@ -100,9 +102,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     const C lam = h_lambda<C>(K, phi, mu);
     const C cc = C(c);
 #pragma unroll
-    for (int k = 0; k < LH::Q; ++k)
-      hs[k] = C(S(h_collide<LH, C>(K, k, h[k], h_eq<LH, C>(k, cc, lam),
-                                   h_source<LH, C>(K, k, F))));
+    for (int k = 0; k < LH::Q; ++k) hs[k] = C(S(h_update<LH, C>(K, k, h[k], cc, lam, F)));
   }
   if (valid) phiB[ty][tx] = phin_c;
   __syncthreads();
@@ -134,7 +134,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   if (out) {
   const double c1 = acc[ty][tx];
   const C phi1 = phiB[ty][tx];
-  const C mu1 = C(closure(K.cl, K.cs, K.mueq, c1, double(phi1)));
+  const C mu1 = C(closure(K.q, c1, double(phi1)));
   auto at1 = [&](int dx, int dy, int) -> C {
     const int ox = dx < 0 ? xm : (dx > 0 ? xp : 0);
     const int oy = dy < 0 ? ym : (dy > 0 ? yp : 0);
@@ -164,12 +164,12 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
 
 inline bool fused2d_supported(int, int) { return true; }
 
-template <class L, class LH, class S, class C>
+template <class L, class LH, class S, class C, bool kGen>
 struct Fused2D {
   static int launch(const Geo& g, const Coef<C>& K, const StepBufs<S>& b, hipStream_t st) {
     constexpr int TX = 64, TY = GPLBM_F2_TY;
     constexpr int NT = TileShape<TX, TY>::NT;
-    auto kernel = k_fused2d<TX, TY, L, LH, S, C>;
+    auto kernel = k_fused2d<TX, TY, L, LH, S, C, kGen>;
     const int tiles_x = (g.nx + TX - 1) / TX;
     const int tiles_y = (g.ny + TY - 1) / TY;
     const int ntiles = tiles_x * tiles_y;

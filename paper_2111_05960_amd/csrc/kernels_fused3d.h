@@ -111,9 +111,10 @@ struct Fused3DConfig<float> {
   static constexpr Carry carry = Carry::kRegisters;
 };
 
-template <int TX, int TY, int ZC, Carry kCarryMode, class LH, class S, class C>
+template <int TX, int TY, int ZC, Carry kCarryMode, class LH, class S, class C, bool kGen>
 __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
-    k_fused3d(Geo g, Coef<C> K, StepBufs<S> b, int tiles_x, int tiles_xy, int ntiles) {
+    k_fused3d(Geo g, Coef<C> Kin, StepBufs<S> b, int tiles_x, int tiles_xy, int ntiles) {
+  const Coef<C> K = variant<kGen>(Kin);
   using L = D3Q19;
   using Shape = TileShape<TX, TY>;
   constexpr int Q = L::Q, QH = LH::Q;
@@ -214,7 +215,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
       }
       const int sA = ring3(p);
       const C phi = phiA[sA][ty + 1][tx + 1];
-      const C mu = C(closure(K.cl, K.cs, K.mueq, c, double(phi)));
+      const C mu = C(closure(K.q, c, double(phi)));
       auto atA = [&](int dx, int dy, int dz) -> C {
         return phiA[ring3(p + dz)][ty + 1 + dy][tx + 1 + dx];
       };
@@ -231,9 +232,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
       const C cc = C(c);
       C hs[QH];
 #pragma unroll
-      for (int k = 0; k < QH; ++k)
-        hs[k] = C(S(h_collide<LH, C>(K, k, h[k], h_eq<LH, C>(k, cc, lam),
-                                     h_source<LH, C>(K, k, F))));
+      for (int k = 0; k < QH; ++k) hs[k] = C(S(h_update<LH, C>(K, k, h[k], cc, lam, F)));
 
       if (out && own_p) {
         const auto Hw = make_rsrc(reinterpret_cast<char*>(b.Hn) + zp * groupH, uint32_t(groupH));
@@ -281,7 +280,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
         const int sB = ring3(p - 1);
         const double c1 = acc[sB][ty][tx];
         const C phi1 = phiB[sB][ty][tx];
-        const C mu1 = C(closure(K.cl, K.cs, K.mueq, c1, double(phi1)));
+        const C mu1 = C(closure(K.q, c1, double(phi1)));
         auto atB = [&](int dx, int dy, int dz) -> C {
           return phiB[ring3(p - 1 + dz)][ty + dy][tx + dx];
         };
@@ -315,13 +314,13 @@ inline bool fused3d_supported(int nx, int ny, int nz, const int* bc) {
          (int64_t)nx * ny * nz < ((int64_t)1 << 31);
 }
 
-template <class LH, class S, class C>
+template <class LH, class S, class C, bool kGen>
 struct Fused3D {
   static int launch(const Geo& g, const Coef<C>& K, const StepBufs<S>& b, hipStream_t st) {
     using Cfg = Fused3DConfig<S>;
     constexpr int TX = Cfg::TX, TY = Cfg::TY, ZC = Cfg::ZC;
     constexpr int NT = TileShape<TX, TY>::NT;
-    auto kernel = k_fused3d<TX, TY, ZC, Cfg::carry, LH, S, C>;
+    auto kernel = k_fused3d<TX, TY, ZC, Cfg::carry, LH, S, C, kGen>;
     const int tiles_x = (g.nx + TX - 1) / TX;
     const int tiles_y = (g.ny + TY - 1) / TY;
     const int chunks = (g.nz + ZC - 1) / ZC;
@@ -335,13 +334,13 @@ struct Fused3D {
   }
 };
 
-template <class L, class LH, class S, class C>
+template <class L, class LH, class S, class C, bool kGen>
 struct FusedLaunch {
   static int launch(const Geo& g, const Coef<C>& K, const StepBufs<S>& b, hipStream_t st) {
     if constexpr (L::D == 2)
-      return Fused2D<L, LH, S, C>::launch(g, K, b, st);
+      return Fused2D<L, LH, S, C, kGen>::launch(g, K, b, st);
     else
-      return Fused3D<LH, S, C>::launch(g, K, b, st);
+      return Fused3D<LH, S, C, kGen>::launch(g, K, b, st);
   }
 };
 

@@ -45,8 +45,9 @@ struct GlobalPhi {
   }
 };
 
-template <class L, class LH, class S, class C>
-__global__ void __launch_bounds__(256) k_split_h(Geo g, Coef<C> K, StepBufs<S> b) {
+template <class L, class LH, class S, class C, bool kGen>
+__global__ void __launch_bounds__(256) k_split_h(Geo g, Coef<C> Kin, StepBufs<S> b) {
+  const Coef<C> K = variant<kGen>(Kin);
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
@@ -62,7 +63,7 @@ __global__ void __launch_bounds__(256) k_split_h(Geo g, Coef<C> K, StepBufs<S> b
     c = k == 0 ? double(v) : c + double(v);
   }
   const C phi = C(b.PHI[i]);
-  const double mu_d = closure(K.cl, K.cs, K.mueq, c, double(phi));
+  const double mu_d = closure(K.q, c, double(phi));
   const C mu = C(mu_d);
   C gr[3], n[3];
   gradient_normal<L, C>(GlobalPhi<S, C>{g, b.PHI, x, y, z}, K.eps2, gr, n);
@@ -82,16 +83,14 @@ __global__ void __launch_bounds__(256) k_split_h(Geo g, Coef<C> K, StepBufs<S> b
   const C lam = h_lambda<C>(K, phi, mu);
   const C cc = C(c);
 #pragma unroll
-  for (int k = 0; k < LH::Q; ++k) {
-    C Hk = h_source<LH, C>(K, k, F);
-    b.Hn[pop_index<LH>(g, k, x, y, z)] =
-        S(h_collide<LH, C>(K, k, h[k], h_eq<LH, C>(k, cc, lam), Hk));
-  }
+  for (int k = 0; k < LH::Q; ++k)
+    b.Hn[pop_index<LH>(g, k, x, y, z)] = S(h_update<LH, C>(K, k, h[k], cc, lam, F));
   b.PHIn[i] = S(phin);
 }
 
-template <class L, class LH, class S, class C>
-__global__ void __launch_bounds__(256) k_split_g(Geo g, Coef<C> K, StepBufs<S> b) {
+template <class L, class LH, class S, class C, bool kGen>
+__global__ void __launch_bounds__(256) k_split_g(Geo g, Coef<C> Kin, StepBufs<S> b) {
+  const Coef<C> K = variant<kGen>(Kin);
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
@@ -105,7 +104,7 @@ __global__ void __launch_bounds__(256) k_split_g(Geo g, Coef<C> K, StepBufs<S> b
     c = k == 0 ? v : c + v;
   }
   const C phi = C(b.PHIn[i]);
-  const C mu = C(closure(K.cl, K.cs, K.mueq, c, double(phi)));
+  const C mu = C(closure(K.q, c, double(phi)));
   C gr[3], n[3];
   gradient_normal<L, C>(GlobalPhi<S, C>{g, b.PHIn, x, y, z}, K.eps2, gr, n);
   C G[L::Q];
@@ -152,7 +151,7 @@ __global__ void __launch_bounds__(256) k_init(Geo g, Coef<C> K, const double* __
   gradient_normal<L, C>(InitPhi{g, phi0, x, y, z}, K.eps2, gr, n);
 
   // initial populations from (phi0, c0)
-  const C mu0 = C(closure(K.cl, K.cs, K.mueq, cin, double(phi)));
+  const C mu0 = C(closure(K.q, cin, double(phi)));
   C G0[L::Q];
   phi_sources<L, C>(K, phi, mu0, n, G0);
   C F[3];
@@ -162,12 +161,11 @@ __global__ void __launch_bounds__(256) k_init(Geo g, Coef<C> K, const double* __
   double c = 0.0;
 #pragma unroll
   for (int k = 0; k < LH::Q; ++k) {
-    C Hk = h_source<LH, C>(K, k, F);
-    hs[k] = S(h_eq<LH, C>(k, C(cin), lam) - C(0.5) * Hk);
+    hs[k] = S(h_initial<LH, C>(K, k, C(cin), lam, F));
     c = k == 0 ? double(hs[k]) : c + double(hs[k]);
   }
   // collision of g at time 0 with c^0 = sum_k h~^0_k
-  const C mu = C(closure(K.cl, K.cs, K.mueq, c, double(phi)));
+  const C mu = C(closure(K.q, c, double(phi)));
   C Gk[L::Q];
   phi_sources<L, C>(K, phi, mu, n, Gk);
 #pragma unroll
@@ -194,8 +192,7 @@ __global__ void __launch_bounds__(256) k_init(Geo g, Coef<C> K, const double* __
 // Read-out of phi^n, c^n, mu^n as doubles.
 
 template <class L, class S>
-__global__ void __launch_bounds__(256) k_fields(Geo g, double cl, double cs, double mueq,
-                                                const S* __restrict__ H,
+__global__ void __launch_bounds__(256) k_fields(Geo g, ClosureK q, const S* __restrict__ H,
                                                 const S* __restrict__ PHI, double* phi_out,
                                                 double* c_out, double* mu_out) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -212,7 +209,7 @@ __global__ void __launch_bounds__(256) k_fields(Geo g, double cl, double cs, dou
   const double phi = double(PHI[i]);
   if (phi_out) phi_out[i] = phi;
   if (c_out) c_out[i] = c;
-  if (mu_out) mu_out[i] = closure(cl, cs, mueq, c, phi);
+  if (mu_out) mu_out[i] = closure(q, c, phi);
 }
 
 // ---------------------------------------------------------------------------

@@ -8,12 +8,17 @@
 // from the formulas alone.
 //
 //   closure           mu = mu_eq + (c - (c_l phi + c_s (1 - phi)))
-//                     Eqs. (PotChim_Equilibirum), (Coexistence_Interpol)
+//                     Eqs. (PotChim_Equilibirum), (Coexistence_Interpol);
+//                     general quadratic free energies, Eq. (Closure):
+//                     mu = (sqrt(eps_s eps_l) / (eps_s phi + eps_l (1 - phi)))
+//                          ((c - phi m_l) - (1 - phi) m_s)
 //   gradient          grad = 3 sum_k w_k e_k d_k, d_k = (phi(x+e_k) - phi(x-e_k))/2
 //                     Eqs. (DerivDirec_Grad), (Grad)
 //   normal            n = grad / sqrt(|grad|^2 + eps_n^2)
 //   phi sources       G^st = kst S_phi, S_phi = 6 phi(1-phi) dc (mu - mu_eq),
 //                     kst = -lambda M / W^2               Eqs. (SourceG_ST), (SourceTerm_Coexistence)
+//                     general: S_phi = 6 phi(1-phi) ((k2 mu^2 / 2 - (m_l - m_s) mu) - df_min),
+//                     k2 = (eps_l - eps_s) / sqrt(eps_l eps_s)   Eq. (SourceTerm)
 //                     G^ct_k = (4/W) phi(1-phi) e_k.n     Eq. (SourceG_CT)
 //                     G^dw = kdw 2 phi(1-phi)(1-2phi), kdw = -8 M / W^2   Eq. (SourceG_dw)
 //                     G_k = w_k (G^st + G^curv)           Eq. (TermG)
@@ -21,11 +26,16 @@
 //                     Eq. (LBE_PhaseField_Eq), omega_g = 1/(3 M + 1/2)
 //   h source          F = (mu (D_l - D_s)) grad + (a W dc) dphi/dt n,
 //                     H_k = (gamma w_k) e_k.F             Eq. (SourceTerm_LBE_h)
+//                     general: dc -> (ks mu + m_s) - m_l,
+//                     ks = -(eps_s - eps_l) / sqrt(eps_s eps_l)   Eq. (Anti-Trapping_Quadratic)
 //   h equilibrium     Lambda = (gamma D(phi)) mu, D = D_l phi + D_s (1-phi)
 //                     h^eq_rest = c - (1 - w_rest) Lambda, h^eq_k = w_k Lambda
 //                     Eq. (Heq_Composition)
 //   h collision       h* = (h - omega_h ((h - h^eq_k) + H_k/2)) + H_k
-//                     Eq. (LBE_Composition), omega_h = 1/(3/gamma + 1/2)
+//                     Eq. (LBE_Composition), omega_h = 1/(1/(gamma xi_s^2) + 1/2)
+//   h alternative     h^eq,alt_k = w_k (Lambda + e_k.F / xi_s^2) (k moving),
+//                     h* = h - omega_h (h - h^eq,alt_k), no source
+//                     Eqs. (LBE_Concent_Alt), (Seq_Concent_Alt)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -33,6 +43,23 @@
 #include "lattice.h"
 
 namespace gplbm {
+
+// Closure constants (always double).  quad = 0: equal curvatures (c_l, c_s,
+// mu_eq); quad = 1: general quadratic free energies (efac = sqrt(eps_s eps_l)).
+struct ClosureK {
+  int quad;
+  double cl, cs, mueq;
+  double efac, eps_s, eps_l, m_s, m_l;
+};
+
+__device__ __forceinline__ double closure(const ClosureK& q, double c, double phi) {
+  if (q.quad) {
+    double fac = q.efac / ((q.eps_s * phi) + (q.eps_l * (1.0 - phi)));
+    return fac * ((c - (phi * q.m_l)) - ((1.0 - phi) * q.m_s));
+  }
+  double cco = (q.cl * phi) + (q.cs * (1.0 - phi));
+  return q.mueq + (c - cco);
+}
 
 // Per-run constants, computed once on the host in double and converted to
 // the arithmetic type C of the kernel.
@@ -50,7 +77,27 @@ struct Coef {
   C mueq_c;            // mu_eq in C
   double cl, cs, mueq; // closure constants (always double)
   int counter_term, anti_trapping;
+  int h_alt;           // 1: relaxation to h^eq,alt without source
+  int fe_quad;         // 1: general quadratic free energies
+  ClosureK q;          // closure
+  C k2, dml, dfm;      // general source: (eps_l-eps_s)/sqrt(eps_l eps_s), m_l - m_s, df_min
+  C ks, ms, ml, aW;    // general anti-trapping: -(eps_s-eps_l)/sqrt(eps_s eps_l), m_s, m_l, a W
 };
+
+// The coefficients a step kernel works with: the general instantiation
+// (kGen) keeps the run's scheme flags, the basic one fixes them to the source
+// scheme and equal curvatures at compile time, so that its code carries none
+// of the general branches.
+template <bool kGen, class C>
+__device__ __forceinline__ Coef<C> variant(const Coef<C>& K) {
+  Coef<C> R = K;
+  if constexpr (!kGen) {
+    R.h_alt = 0;
+    R.fe_quad = 0;
+    R.q.quad = 0;
+  }
+  return R;
+}
 
 __device__ __forceinline__ double closure(double cl, double cs, double mueq, double c,
                                           double phi) {
@@ -108,13 +155,20 @@ __device__ __forceinline__ void gradient_normal(const F& phi_at, C eps2, C g[3],
   n[2] = L::D == 3 ? g[2] / den : C(0);
 }
 
+// Coupling source S_phi = p'(phi) * bracket.
+template <class C>
+__device__ __forceinline__ C coupling(const Coef<C>& K, C pprime, C mu) {
+  if (K.fe_quad) return pprime * (((K.k2 * (mu * mu)) * C(0.5) - (K.dml * mu)) - K.dfm);
+  return (pprime * K.dc) * (mu - K.mueq_c);
+}
+
 // Zeroth moment of the phi source at a node (closed form): G^st, plus G^dw
 // without the counter term.
 template <class C>
 __device__ __forceinline__ C source_moment(const Coef<C>& K, C phi, C mu) {
   C pp = phi * (C(1) - phi);
   C pprime = C(6) * pp;
-  C Sphi = (pprime * K.dc) * (mu - K.mueq_c);
+  C Sphi = coupling<C>(K, pprime, mu);
   C Gst = K.kst * Sphi;
   if (K.counter_term) return Gst;
   C wdw = C(2) * (pp * (C(1) - C(2) * phi));
@@ -128,7 +182,7 @@ __device__ __forceinline__ void phi_sources(const Coef<C>& K, C phi, C mu, const
                                             C G[L::Q]) {
   C pp = phi * (C(1) - phi);
   C pprime = C(6) * pp;
-  C Sphi = (pprime * K.dc) * (mu - K.mueq_c);
+  C Sphi = coupling<C>(K, pprime, mu);
   C Gst = K.kst * Sphi;
   if (K.counter_term) {
     C kphi = K.k4w * pp;
@@ -159,10 +213,12 @@ template <class L, class C>
 __device__ __forceinline__ void h_flux(const Coef<C>& K, C mu, const C g[3], const C n[3],
                                        C dtphi, bool with_at, C F[3]) {
   C md = mu * K.Dp;
+  C jf = K.jfac;
+  if (K.fe_quad) jf = K.aW * (((K.ks * mu) + K.ms) - K.ml);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     F[a] = md * g[a];
-    if (with_at) F[a] = F[a] + (K.jfac * dtphi) * n[a];
+    if (with_at) F[a] = F[a] + (jf * dtphi) * n[a];
   }
 }
 
@@ -192,6 +248,31 @@ __device__ __forceinline__ C h_collide(const Coef<C>& K, int k, C h, C heq, C Hk
   }
   C t = (h - heq) + C(0.5) * Hk;
   return (h - K.omega_h * t) + Hk;
+}
+
+// Alternative equilibrium with the flux F folded into the moving populations.
+template <class L, class C>
+__device__ __forceinline__ C h_eq_alt(int k, C c, C lam, const C F[3]) {
+  if (k == L::REST) return c - C(1.0 - L::w[k]) * lam;
+  return C(L::w[k]) * (lam + edot<L, C>(k, F[0], F[1], F[2]) / C(L::cs2));
+}
+
+// Post-collision h_k of either scheme.
+template <class L, class C>
+__device__ __forceinline__ C h_update(const Coef<C>& K, int k, C h, C c, C lam, const C F[3]) {
+  if (K.h_alt) {
+    C t = h - h_eq_alt<L, C>(k, c, lam, F);
+    return h - K.omega_h * t;
+  }
+  return h_collide<L, C>(K, k, h, h_eq<L, C>(k, c, lam), h_source<L, C>(K, k, F));
+}
+
+// Initial h~^0_k of either scheme: the equilibrium shifted by -H_k/2, or
+// h^eq,alt itself (no source, no shift).
+template <class L, class C>
+__device__ __forceinline__ C h_initial(const Coef<C>& K, int k, C c, C lam, const C F[3]) {
+  if (K.h_alt) return h_eq_alt<L, C>(k, c, lam, F);
+  return h_eq<L, C>(k, c, lam) - C(0.5) * h_source<L, C>(K, k, F);
 }
 
 }  // namespace gplbm

@@ -36,7 +36,7 @@ def test_every_declared_function_is_exported(lib):
 
 
 def test_struct_sizes_match_header(lib):
-    assert ctypes.sizeof(B.gplbm_params) == 4 * 12 + 8 * 11
+    assert ctypes.sizeof(B.gplbm_params) == 4 * 14 + 8 * 16
     assert ctypes.sizeof(B.gplbm_diag) == 8 * 7 + 8
 
 
@@ -120,3 +120,33 @@ def test_null_context_is_rejected(lib):
     assert lib.gplbm_step(None, 1) == B.GPLBM_E_INVALID
     assert lib.gplbm_init_fields(None, None, None) == B.GPLBM_E_INVALID
     assert lib.gplbm_step_count(None) == -1
+
+
+@pytest.mark.parametrize("prec", ["fp16dev", "bf16dev"])
+@pytest.mark.parametrize("over", [dict(h_scheme=1), dict(free_energy=1, eps_s=1.0, eps_l=2.0)])
+def test_variants_rejected_with_deviation_storage(lib, prec, over):
+    cp = B.make_params(wl.base_params(lattice=wl.D3Q19, shape=(8, 8, 8), bc=(0, 0, 0), **over),
+                       prec)
+    with pytest.raises(B.GplbmError) as e:
+        B.gplbm_state_bytes(cp)
+    assert e.value.code == B.GPLBM_E_INVALID
+
+
+@pytest.mark.parametrize("over", [dict(h_scheme=1), dict(free_energy=1, eps_s=1.0, eps_l=2.0)])
+def test_adjoint_rejects_variants(lib, over):
+    cp = B.make_params(wl.base_params(lattice=wl.D2Q9, shape=(1, 8, 8), bc=(0, 0, 0), **over),
+                       "fp64")
+    out = ctypes.c_uint64()
+    assert B.gplbm_state_bytes(cp) > 0
+    assert lib.gplbm_adjoint_bytes(ctypes.byref(cp), ctypes.byref(out)) == B.GPLBM_E_INVALID
+
+
+@pytest.mark.parametrize("field,value", [("h_scheme", 2), ("free_energy", 3), ("eps_s", 0.0),
+                                         ("eps_l", -1.0), ("m_s", float("inf"))])
+def test_variant_parameters_validated(lib, field, value):
+    cp = B.make_params(wl.base_params(free_energy=1, eps_s=1.0, eps_l=2.0))
+    assert B.gplbm_state_bytes(cp) > 0
+    setattr(cp, field, value)
+    with pytest.raises(B.GplbmError) as e:
+        B.gplbm_state_bytes(cp)
+    assert e.value.code == B.GPLBM_E_INVALID
