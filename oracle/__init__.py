@@ -24,6 +24,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _LIB_OVERRIDE = os.environ.get("GPLBM_ORACLE_LIB")
 
 D2Q9, D3Q19 = 0, 1
+D2Q5, D3Q7 = 2, 3  # g (and h) on the light lattices
 PERIODIC, ZERO_FLUX = 0, 1
 
 PARAM_KEYS = ("W", "M_phi", "lam", "D_l", "D_s", "gamma", "a_at",

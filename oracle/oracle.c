@@ -8,8 +8,8 @@
  * the benchmark load it.  It shares no code, header or constant table with
  * the HIP library, and the product path never calls it.
  *
- * Everything is double precision, in lattice units (dx = dt = 1, s = 1,
- * xi_s^2 = 1/3).  Arrays are structure-of-arrays f[k][z][y][x], x fastest.
+ * Everything is double precision, in lattice units (dx = dt = 1, s = 1;
+ * xi_s^2 = 1/3, or 1/4 on D3Q7).  Arrays are structure-of-arrays f[k][z][y][x], x fastest.
  * The state at time n is the "natural" one: post-streaming populations
  * g~^n_k(x), h~^n_k(x) and the phase field phi^n(x).
  *
@@ -19,12 +19,16 @@
  *       eps_s = eps_l), or Eq. (Closure) for general quadratic free
  *       energies.
  *   S2  directional derivatives and the gradient, Eqs. (DerivDirec_Grad) and
- *       (Grad); normal n = grad / sqrt(|grad|^2 + eps_n^2).
+ *       (Grad), grad = (1 / xi_s^2) sum_k w_k e_k d_k on the lattice of g
+ *       (central differences on D2Q5 / D3Q7); normal
+ *       n = grad / sqrt(|grad|^2 + eps_n^2).
  *   S3  sources of the phi-LBE, Eqs. (TermG), (SourceG_ST), (SourceG_dw) or
  *       (SourceG_CT), with S_phi from Eq. (SourceTerm_Equilibrium) (general:
  *       Eq. (SourceTerm)) and p'(phi) = 6 phi (1 - phi) (Tab. 2).
  *   S4  BGK collision with the trapezoidal source, Eq. (LBE_PhaseField_Eq),
- *       g~eq = w_k phi - G_k / 2, 1/(tau_g + 1/2) with M_phi = tau_g / 3.
+ *       g~eq = w_k phi - G_k / 2, 1/(tau_g + 1/2) with M_phi = xi_s^2 tau_g
+ *       (tau_g = 3 M_phi; 4 M_phi on D3Q7, so that the mobility is M_phi
+ *       on every lattice, as for tau_h).
  *   S5  streaming (periodic wrap or halfway bounce-back).
  *   S6  phi^{n+1} = sum_k g~^{n+1}_k + (1/2) sum_k G_k, Eq. (Moment_Phi), with
  *       the source moment taken from this step's collision at the same node.
@@ -113,6 +117,7 @@ static const double d3q7_w[7] = {1.0 / 8.0, 1.0 / 4.0, 1.0 / 8.0, 1.0 / 8.0,
 struct orc_state {
   orc_params p;
   int Q, D, rest;           /* lattice of g (and of the gradient stencil) */
+  double inv_cs2g;          /* 1 / xi_s^2 of the g lattice: 3, or 4 on D3Q7 */
   int e[19][3];
   int opp[19];
   double w[19];
@@ -227,7 +232,7 @@ static void gradient_normal(const orc_state* s, const double* f, int x, int y,
   double nn = 0.0;
   for (int a = 0; a < 3; ++a) g3[a] = 0.0;
   for (int a = 0; a < s->D; ++a) {
-    g3[a] = 3.0 * acc[a];
+    g3[a] = s->inv_cs2g * acc[a];
     nn = nn + g3[a] * g3[a];
   }
   double den = sqrt(nn + s->p.eps_n * s->p.eps_n);
@@ -302,35 +307,47 @@ static double h_equilibrium_alt(const orc_state* s, int k, double c, double lam,
 
 orc_state* orc_create(const orc_params* p) {
   if (!p) return NULL;
-  if (p->lattice != ORC_D2Q9 && p->lattice != ORC_D3Q19) return NULL;
+  if (p->lattice < ORC_D2Q9 || p->lattice > ORC_D3Q7) return NULL;
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return NULL;
-  if (p->lattice == ORC_D2Q9 && p->nz != 1) return NULL;
+  if ((p->lattice == ORC_D2Q9 || p->lattice == ORC_D2Q5) && p->nz != 1) return NULL;
   if (p->h_lattice != 0 && p->h_lattice != 1) return NULL;
   if (p->h_scheme != ORC_H_SOURCE && p->h_scheme != ORC_H_EQ_ALT) return NULL;
   if (p->free_energy != ORC_FE_EQUAL && p->free_energy != ORC_FE_QUADRATIC) return NULL;
   if (p->free_energy == ORC_FE_QUADRATIC && !(p->eps_s > 0.0 && p->eps_l > 0.0)) return NULL;
   orc_state* s = (orc_state*)calloc(1, sizeof(orc_state));
   s->p = *p;
+  s->inv_cs2g = 3.0;
   if (p->lattice == ORC_D2Q9) {
     s->Q = 9; s->D = 2; s->rest = 0;
     memcpy(s->e, d2q9_e, sizeof(d2q9_e));
     memcpy(s->w, d2q9_w, sizeof(d2q9_w));
     s->p.bc[2] = ORC_PERIODIC;
-  } else {
+  } else if (p->lattice == ORC_D3Q19) {
     s->Q = 19; s->D = 3; s->rest = 5;
     memcpy(s->e, d3q19_e, sizeof(d3q19_e));
     memcpy(s->w, d3q19_w, sizeof(d3q19_w));
+  } else if (p->lattice == ORC_D2Q5) {
+    s->Q = 5; s->D = 2; s->rest = 0;
+    memcpy(s->e, d2q5_e, sizeof(d2q5_e));
+    memcpy(s->w, d2q5_w, sizeof(d2q5_w));
+    s->p.bc[2] = ORC_PERIODIC;
+  } else {
+    s->Q = 7; s->D = 3; s->rest = 1;
+    memcpy(s->e, d3q7_e, sizeof(d3q7_e));
+    memcpy(s->w, d3q7_w, sizeof(d3q7_w));
+    s->inv_cs2g = 4.0;
   }
+  const int light_g = p->lattice == ORC_D2Q5 || p->lattice == ORC_D3Q7;
   for (int k = 0; k < s->Q; ++k)
     for (int j = 0; j < s->Q; ++j)
       if (s->e[j][0] == -s->e[k][0] && s->e[j][1] == -s->e[k][1] &&
           s->e[j][2] == -s->e[k][2])
         s->opp[k] = j;
-  if (p->h_lattice == 0) {
+  if (p->h_lattice == 0 || light_g) {
     s->Qh = s->Q; s->resth = s->rest;
     memcpy(s->eh, s->e, sizeof(s->e));
     memcpy(s->wh, s->w, sizeof(s->w));
-    s->cs2h = 1.0 / 3.0;
+    s->cs2h = p->lattice == ORC_D3Q7 ? 1.0 / 4.0 : 1.0 / 3.0;
   } else if (p->lattice == ORC_D2Q9) {
     s->Qh = 5; s->resth = 0;
     memcpy(s->eh, d2q5_e, sizeof(d2q5_e));
@@ -425,7 +442,7 @@ static void step_once(orc_state* s) {
   const orc_params* p = &s->p;
   const int nx = p->nx, ny = p->ny, Q = s->Q, Qh = s->Qh, D = s->D;
   const int64_t N = s->N;
-  const double omega_g = 1.0 / (3.0 * p->M_phi + 0.5);
+  const double omega_g = 1.0 / (s->inv_cs2g * p->M_phi + 0.5);
   const double omega_h = 1.0 / (1.0 / (p->gamma * s->cs2h) + 0.5);
 
   /* S1-S4: moments, closure, gradient, sources, collision of g. */

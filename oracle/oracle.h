@@ -12,7 +12,7 @@
 extern "C" {
 #endif
 
-enum { ORC_D2Q9 = 0, ORC_D3Q19 = 1 };
+enum { ORC_D2Q9 = 0, ORC_D3Q19 = 1, ORC_D2Q5 = 2, ORC_D3Q7 = 3 }; /* lattice of g */
 enum { ORC_PERIODIC = 0, ORC_ZERO_FLUX = 1 };
 enum { ORC_H_SOURCE = 0, ORC_H_EQ_ALT = 1 };        /* h_scheme */
 enum { ORC_FE_EQUAL = 0, ORC_FE_QUADRATIC = 1 };    /* free_energy */
@@ -23,7 +23,8 @@ typedef struct {
   int32_t bc[3];
   int32_t counter_term;  /* 1: counter term G^ct_k, 0: double-well term G^dw */
   int32_t anti_trapping; /* 1: anti-trapping current in the h source */
-  int32_t h_lattice;     /* 0: h on the lattice of g; 1: h on D2Q5 / D3Q7 */
+  int32_t h_lattice;     /* 0: h on the lattice of g; 1: h on D2Q5 / D3Q7 (g on
+                            D2Q5 / D3Q7 always takes h on the same lattice) */
   int32_t h_scheme;      /* ORC_H_SOURCE: source H_k; ORC_H_EQ_ALT: h^eq,alt, H = 0 */
   int32_t free_energy;   /* ORC_FE_EQUAL: eps_s = eps_l (c_s_co, c_l_co, mu_eq);
                             ORC_FE_QUADRATIC: general (eps_s, eps_l, m_s, m_l, df_min) */

@@ -86,9 +86,10 @@ D3Q7_E = np.array([[0, 0, 1], [0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -
 
 
 def first_moment(f, lattice, light=False):
-    """sum_k e_k f_k for populations f of shape (Q, nz, ny, nx) -> (nz, ny, nx, 3)."""
-    if light:
-        e = D2Q5_E if lattice == 0 else D3Q7_E
+    """sum_k e_k f_k for populations f of shape (Q, nz, ny, nx) -> (nz, ny, nx, 3);
+    lattice 0 D2Q9, 1 D3Q19, 2 D2Q5, 3 D3Q7 (light: the light lattice of 0, 1)."""
+    if light or lattice in (2, 3):
+        e = D2Q5_E if lattice in (0, 2) else D3Q7_E
     else:
         e = D2Q9_E if lattice == 0 else D3Q19_E
     return np.einsum("ka,k...->...a", e, f)
@@ -123,3 +124,12 @@ def quad_mu_eq(eps_s, eps_l, m_s, m_l, df_min, near=0.0):
     f = lambda m: (quad_omega(m, eps_l, eps_s, eps_l, m_l, 0.0)
                    - quad_omega(m, eps_s, eps_s, eps_l, m_s, df_min))
     return brentq(f, near - 0.5, near + 0.5, xtol=1e-15, rtol=1e-15)
+
+
+def lattice_cs2(lattice: int) -> float:
+    """xi_s^2, the second moment of the weights: 1/4 on D3Q7, 1/3 otherwise."""
+    return 0.25 if lattice == 3 else 1.0 / 3.0
+
+
+def lattice_dim(lattice: int) -> int:
+    return 2 if lattice in (0, 2) else 3

@@ -26,9 +26,12 @@ MUTANTS = [
     ("closure: sign of c - c_co",
      "return p->mu_eq + (c - cco);",
      "return p->mu_eq + (cco - c);"),
-    ("gradient: factor 1/xi_s^2 = 3 dropped",
-     "g3[a] = 3.0 * acc[a];",
+    ("gradient: factor 1/xi_s^2 dropped",
+     "g3[a] = s->inv_cs2g * acc[a];",
      "g3[a] = acc[a];"),
+    ("gradient: 3 instead of 1/xi_s^2 (D3Q7)",
+     "g3[a] = s->inv_cs2g * acc[a];",
+     "g3[a] = 3.0 * acc[a];"),
     ("gradient: central difference without 1/2",
      "double dk = 0.5 * (phi_at(",
      "double dk = 1.0 * (phi_at("),
@@ -71,9 +74,18 @@ MUTANTS = [
     ("g collision: half instead of full source",
      "s->gs[k * N + i] = (gk - omega_g * t) + G[k];",
      "s->gs[k * N + i] = (gk - omega_g * t) + 0.5 * G[k];"),
-    ("g relaxation: M = 3 tau instead of tau / 3",
-     "const double omega_g = 1.0 / (3.0 * p->M_phi + 0.5);",
-     "const double omega_g = 1.0 / (p->M_phi / 3.0 + 0.5);"),
+    ("g relaxation: M = tau / xi_s^2 instead of xi_s^2 tau",
+     "const double omega_g = 1.0 / (s->inv_cs2g * p->M_phi + 0.5);",
+     "const double omega_g = 1.0 / (p->M_phi / s->inv_cs2g + 0.5);"),
+    ("g relaxation: tau_g = 3 M on D3Q7",
+     "const double omega_g = 1.0 / (s->inv_cs2g * p->M_phi + 0.5);",
+     "const double omega_g = 1.0 / (3.0 * p->M_phi + 0.5);"),
+    ("g lattice D3Q7: 1/xi_s^2 = 3",
+     "    s->inv_cs2g = 4.0;",
+     "    s->inv_cs2g = 3.0;"),
+    ("g lattice D3Q7: h relaxed with the xi_s^2 of D3Q19",
+     "s->cs2h = p->lattice == ORC_D3Q7 ? 1.0 / 4.0 : 1.0 / 3.0;",
+     "s->cs2h = 1.0 / 3.0;"),
     ("h relaxation: tau_h = 1/gamma instead of 1/(gamma xi_s^2)",
      "const double omega_h = 1.0 / (1.0 / (p->gamma * s->cs2h) + 0.5);",
      "const double omega_h = 1.0 / (1.0 / p->gamma + 0.5);"),

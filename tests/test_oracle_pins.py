@@ -136,14 +136,15 @@ def test_quadratic_local_forms(oracle_mod, eps_s, eps_l):
 # Closed-form solutions
 
 
-@pytest.mark.parametrize("h_lattice,h_scheme", [(0, 0), (1, 0), (0, 1), (1, 1)])
-def test_stefan_dissolution_front_and_profile(oracle_mod, h_lattice, h_scheme):
+@pytest.mark.parametrize("lattice,h_lattice,h_scheme",
+                         [(0, 0, 0), (0, 1, 0), (0, 0, 1), (0, 1, 1), (2, 0, 0)])
+def test_stefan_dissolution_front_and_profile(oracle_mod, lattice, h_lattice, h_scheme):
     """Workload 0 (planar dissolution, D_s = 0, anti-trapping, lambda*)
     against the one-sided Stefan solution of Sec. 4.2, with h on D2Q9 and
     on D2Q5, with the source H_k or with the flux folded into h^eq,alt
-    (Eqs. LBE_Concent_Alt, Seq_Concent_Alt)."""
+    (Eqs. LBE_Concent_Alt, Seq_Concent_Alt), and with g and h on D2Q5."""
     p, phi0, c0, nsteps = wl.config0()
-    p = dict(p, h_lattice=h_lattice, h_scheme=h_scheme)
+    p = dict(p, lattice=lattice, h_lattice=h_lattice, h_scheme=h_scheme)
     mu_inf = p["mu_eq"] + 0.0 - p["c_l_co"]
     alpha = analytic.stefan_alpha(p["mu_eq"], mu_inf, p["c_s_co"] - p["c_l_co"])
     assert abs(alpha - (-0.0586022)) < 1e-6
@@ -166,14 +167,14 @@ def test_stefan_dissolution_front_and_profile(oracle_mod, h_lattice, h_scheme):
     assert np.all(np.abs(c[0, :, :80] - p["c_s_co"]) < 1e-3)
 
 
-@pytest.mark.parametrize("counter_term", [0, 1])
-def test_circle_curvature_flow(oracle_mod, counter_term):
+@pytest.mark.parametrize("lattice,counter_term", [(0, 0), (0, 1), (2, 0), (2, 1)])
+def test_circle_curvature_flow(oracle_mod, lattice, counter_term):
     """lambda = 0: without the counter term the grain follows mean-curvature
     flow R^2 = R0^2 - 2 M t (Eq. ModelA_EqPhi); with it the radius stays put
     (Eq. ModelA_EqPhi_CounterTerm)."""
     W, M = 6.0, 0.05
-    p = wl.base_params(shape=(1, 128, 128), bc=(0, 0, 0), counter_term=counter_term,
-                       lam=0.0, W=W)
+    p = wl.base_params(lattice=lattice, shape=(1, 128, 128), bc=(0, 0, 0),
+                       counter_term=counter_term, lam=0.0, W=W)
     phi0, c0 = wl.disc(128, 128, 30.0, W, 1.0, 0.1)
     o = oracle_mod.Oracle(p).init(phi0, c0)
     o.step(400)
@@ -188,14 +189,14 @@ def test_circle_curvature_flow(oracle_mod, counter_term):
 
 
 @pytest.mark.parametrize("lattice,h_lattice,axis", [
-    (0, 0, 2), (0, 1, 2), (0, 1, 1), (1, 0, 0), (1, 1, 0), (1, 1, 2)])
+    (0, 0, 2), (0, 1, 2), (0, 1, 1), (1, 0, 0), (1, 1, 0), (1, 1, 2), (2, 0, 1), (3, 0, 0)])
 def test_ade_fourier_mode_decay(oracle_mod, lattice, h_lattice, axis):
     """phi = 1 everywhere: the c-LBE reduces to the textbook advection-free
     diffusion LBM, so a Fourier mode of c decays as exp(-D_l k^2 t) -- on
     the full lattices and on the light ones (D2Q5, D3Q7, whose xi_s^2 = 1/4
     sets tau_h = 4 / gamma), along x, y and z (axis 2, 1, 0 of the array)."""
     L = 128
-    shape = [1 if lattice == 0 else 2, 2, 2]
+    shape = [1 if analytic.lattice_dim(lattice) == 2 else 2, 2, 2]
     shape[axis] = L
     shape = tuple(shape)
     p = wl.base_params(lattice=lattice, shape=shape, bc=(0, 0, 0), h_lattice=h_lattice)
@@ -219,6 +220,36 @@ def test_ade_fourier_mode_decay(oracle_mod, lattice, h_lattice, axis):
     assert np.max(np.abs(o.fields()[0] - 1.0)) < 1e-15
 
 
+@pytest.mark.parametrize("lattice,axis", [(0, 2), (2, 2), (2, 1), (1, 0), (3, 0), (3, 2)])
+def test_phase_field_fourier_mode_decay(oracle_mod, lattice, axis):
+    """lambda = 0, counter term on, phi a perturbation of amplitude 1e-9 about
+    0: the counter term phi (1 - phi) n is of second order in the amplitude
+    (|grad phi| << eps_n), so the phi-LBE reduces to the textbook diffusion
+    LBM and a Fourier mode decays as exp(-M_phi k^2 t) -- on D2Q9, D3Q19 and
+    on D2Q5 / D3Q7 (xi_s^2 = 1/4 sets tau_g = 4 M_phi), along x, y and z."""
+    L = 128
+    three = analytic.lattice_dim(lattice) == 3
+    shape = [2 if three else 1, 2, 2]
+    shape[axis] = L
+    shape = tuple(shape)
+    p = wl.base_params(lattice=lattice, shape=shape, bc=(0, 0, 0), lam=0.0, counter_term=1)
+    k = 2 * np.pi / L
+    idx = [None, None, None]
+    idx[axis] = slice(None)
+    phi0 = 1e-9 * np.broadcast_to(np.cos(k * np.arange(L))[tuple(idx)], shape)
+    o = oracle_mod.Oracle(p).init(phi0, np.full(shape, p["c_l_co"]))
+    o.step(100)
+
+    def amp():
+        line = np.moveaxis(o.fields()[0], axis, -1).reshape(-1, L)[0]
+        return 2 * np.abs(np.fft.rfft(line)[1]) / L
+    a0 = amp()
+    o.step(2000)
+    a1 = amp()
+    rate = -math.log(a1 / a0) / 2000
+    assert abs(rate / (p["M_phi"] * k * k) - 1.0) < 2e-3, rate
+
+
 # --------------------------------------------------------------------------
 # Conservation laws and special cases
 
@@ -233,6 +264,9 @@ def test_ade_fourier_mode_decay(oracle_mod, lattice, h_lattice, axis):
     (1, (10, 12, 14), (1, 0, 1), 1, 0),
     (0, (1, 24, 40), (1, 1, 0), 0, 1),
     (1, (10, 12, 14), (1, 0, 1), 1, 1),
+    (2, (1, 24, 40), (1, 1, 0), 0, 0),
+    (3, (10, 12, 14), (1, 0, 1), 0, 0),
+    (3, (10, 12, 14), (0, 0, 0), 0, 1),
 ])
 def test_solute_mass_conserved(oracle_mod, lattice, shape, bc, h_lattice, h_scheme):
     """sum_k h^eq_k = c (also for h^eq,alt), sum_k H_k = 0 and streaming
@@ -248,7 +282,8 @@ def test_solute_mass_conserved(oracle_mod, lattice, shape, bc, h_lattice, h_sche
     assert abs(m1 - m0) / abs(m0) < 1e-12
 
 
-@pytest.mark.parametrize("lattice,shape", [(0, (1, 32, 32)), (1, (12, 12, 12))])
+@pytest.mark.parametrize("lattice,shape", [(0, (1, 32, 32)), (1, (12, 12, 12)),
+                                           (2, (1, 32, 32)), (3, (12, 12, 12))])
 def test_phase_conserved_without_coupling(oracle_mod, lattice, shape):
     """lambda = 0 with the counter term: the phi equation is conservative
     (Eq. ModelA_EqPhi_CounterTerm, divergence form), so sum phi is kept."""
@@ -274,19 +309,21 @@ def test_pure_solid_is_stationary(oracle_mod):
     assert np.array_equal(g0, g1) and np.array_equal(h0, h1) and np.array_equal(f0, f1)
 
 
-@pytest.mark.parametrize("lattice", [0, 1])
+@pytest.mark.parametrize("lattice", [0, 1, 2, 3])
 def test_gradient_exact_on_linear_field(oracle_mod, lattice):
     """Directional derivatives (Eq. DerivDirec_Grad) combined by Eq. (Grad)
-    are exact for a linear field at interior nodes."""
-    shape = (1, 9, 11) if lattice == 0 else (7, 9, 11)
-    p = wl.base_params(lattice=lattice, shape=shape, bc=(1, 1, 1 if lattice else 0))
+    are exact for a linear field at interior nodes (on D2Q5 / D3Q7 they are
+    central differences)."""
+    three = analytic.lattice_dim(lattice) == 3
+    shape = (7, 9, 11) if three else (1, 9, 11)
+    p = wl.base_params(lattice=lattice, shape=shape, bc=(1, 1, 1 if three else 0))
     nz, ny, nx = shape
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    b = (0.013, -0.021, 0.017 if lattice else 0.0)
+    b = (0.013, -0.021, 0.017 if three else 0.0)
     phi = 0.4 + b[0] * x + b[1] * y + b[2] * z
     o = oracle_mod.Oracle(p).init(phi, np.zeros(shape))
     g, n = o.gradient()
-    inner = (slice(1, -1) if lattice else slice(None), slice(1, -1), slice(1, -1))
+    inner = (slice(1, -1) if three else slice(None), slice(1, -1), slice(1, -1))
     for a in range(3):
         assert np.max(np.abs(g[inner][..., a] - b[a])) < 1e-14
     bn = np.array(b) / math.sqrt(sum(v * v for v in b) + p["eps_n"] ** 2)
@@ -359,8 +396,8 @@ def test_closed_box_reaches_equal_chemical_potentials(oracle_mod):
     assert abs(o.diagnostics()["solid_fraction"] - lever) < 1e-3
 
 
-@pytest.mark.parametrize("counter_term", [0, 1])
-def test_uniform_fields_follow_the_source_recurrence(oracle_mod, counter_term):
+@pytest.mark.parametrize("lattice,counter_term", [(0, 0), (0, 1), (3, 1)])
+def test_uniform_fields_follow_the_source_recurrence(oracle_mod, lattice, counter_term):
     """Uniform phi and c: no gradient, no normal, no flux, so c stays c0, and
     the phi-LBE collapses to a scalar recurrence.  Summing the BGK collision
     with the trapezoidal source over k, with sum g~ = phi - S_prev / 2 carried
@@ -371,13 +408,13 @@ def test_uniform_fields_follow_the_source_recurrence(oracle_mod, counter_term):
     Euler of d phi / dt = S plus a second-order difference.  S is the zeroth
     moment of the sources (Eqs. SourceG_ST with SourceTerm_Coexistence, plus
     SourceG_dw without the counter term, whose own moment vanishes)."""
-    shape = (1, 3, 4)
-    p = wl.base_params(shape=shape, bc=(0, 0, 0), counter_term=counter_term)
+    shape = (1, 3, 4) if analytic.lattice_dim(lattice) == 2 else (3, 3, 4)
+    p = wl.base_params(lattice=lattice, shape=shape, bc=(0, 0, 0), counter_term=counter_term)
     phi, c0 = 0.3, 0.5
     o = oracle_mod.Oracle(p).init(np.full(shape, phi), np.full(shape, c0))
     dc = p["c_s_co"] - p["c_l_co"]
     M, W = p["M_phi"], p["W"]
-    omega = 1.0 / (3.0 * M + 0.5)
+    omega = 1.0 / (M / analytic.lattice_cs2(lattice) + 0.5)
 
     def source(phi):
         mu = p["mu_eq"] + c0 - (p["c_l_co"] * phi + p["c_s_co"] * (1.0 - phi))
@@ -400,7 +437,8 @@ def test_uniform_fields_follow_the_source_recurrence(oracle_mod, counter_term):
 
 
 @pytest.mark.parametrize("lattice,h_lattice,h_scheme",
-                         [(0, 0, 0), (1, 0, 0), (0, 1, 0), (1, 1, 0), (0, 0, 1), (1, 1, 1)])
+                         [(0, 0, 0), (1, 0, 0), (0, 1, 0), (1, 1, 0), (0, 0, 1), (1, 1, 1),
+                          (2, 0, 0), (3, 0, 0)])
 def test_wall_is_a_mirror_plane_for_wall_normal_fields(oracle_mod, lattice, h_lattice,
                                                        h_scheme):
     """For fields that vary only across a zero-flux wall, halfway bounce-back
@@ -409,7 +447,7 @@ def test_wall_is_a_mirror_plane_for_wall_normal_fields(oracle_mod, lattice, h_la
     wall a symmetry plane: the run on [0, n) between two walls equals the
     first half of the periodic run on [0, 2n) from the mirrored fields."""
     n = 24
-    shape = (1, 4, n) if lattice == 0 else (2, 2, n)
+    shape = (1, 4, n) if analytic.lattice_dim(lattice) == 2 else (2, 2, n)
     p = wl.base_params(lattice=lattice, shape=shape, bc=(1, 0, 0), h_lattice=h_lattice,
                        h_scheme=h_scheme)
     p2 = dict(p, shape=shape[:2] + (2 * n,), bc=(0, 0, 0))
@@ -430,7 +468,8 @@ def test_wall_is_a_mirror_plane_for_wall_normal_fields(oracle_mod, lattice, h_la
 
 
 @pytest.mark.parametrize("lattice,h_lattice,h_scheme",
-                         [(0, 0, 0), (1, 0, 0), (0, 1, 0), (1, 1, 0), (0, 0, 1), (1, 1, 1)])
+                         [(0, 0, 0), (1, 0, 0), (0, 1, 0), (1, 1, 0), (0, 0, 1), (1, 1, 1),
+                          (2, 0, 0), (3, 0, 0)])
 def test_initial_populations_are_shifted_equilibria(oracle_mod, lattice, h_lattice, h_scheme):
     """Reading (the paper does not give the initial populations): at t = 0
     the populations before the variable change, g~ + G/2 and h~ + H/2, are
@@ -443,17 +482,18 @@ def test_initial_populations_are_shifted_equilibria(oracle_mod, lattice, h_latti
     second moment of the weights is 1/3).  With h^eq,alt there is no source
     and no shift: sum e_k h~_k is the first moment of h^eq,alt, which is F
     itself (Eq. Seq_Concent_Alt: w_k e_k . F / xi_s^2 summed with e_k)."""
-    shape = (1, 9, 11) if lattice == 0 else (7, 9, 11)
-    p = wl.base_params(lattice=lattice, shape=shape, bc=(1, 1, 1 if lattice else 0),
+    three = analytic.lattice_dim(lattice) == 3
+    shape = (7, 9, 11) if three else (1, 9, 11)
+    p = wl.base_params(lattice=lattice, shape=shape, bc=(1, 1, 1 if three else 0),
                        D_s=0.02, h_lattice=h_lattice, h_scheme=h_scheme)
     nz, ny, nx = shape
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    b = np.array([0.031, -0.023, 0.019 if lattice else 0.0])
-    phi0 = 0.45 + b[0] * (x - 5) + b[1] * (y - 4) + b[2] * (z - 3 if lattice else 0)
+    b = np.array([0.031, -0.023, 0.019 if three else 0.0])
+    phi0 = 0.45 + b[0] * (x - 5) + b[1] * (y - 4) + b[2] * (z - 3 if three else 0)
     c0 = 0.35 - 0.02 * x + 0.015 * y
     o = oracle_mod.Oracle(p).init(phi0, c0)
     g, h, _ = o.state()
-    inner = (slice(1, -1) if lattice else slice(None), slice(1, -1), slice(1, -1))
+    inner = (slice(1, -1) if three else slice(None), slice(1, -1), slice(1, -1))
     dc = p["c_s_co"] - p["c_l_co"]
     M, W = p["M_phi"], p["W"]
     mu = p["mu_eq"] + c0 - (p["c_l_co"] * phi0 + p["c_s_co"] * (1.0 - phi0))
@@ -465,8 +505,8 @@ def test_initial_populations_are_shifted_equilibria(oracle_mod, lattice, h_latti
     assert np.max(np.abs(h.sum(0) - c0)[inner]) < 1e-14
     m1g = analytic.first_moment(g, lattice)
     m1h = analytic.first_moment(h, lattice, light=bool(h_lattice))
-    cs2h = 0.25 if (lattice == 1 and h_lattice) else 1.0 / 3.0
-    want_g = -(kphi / 6.0)[..., None] * nrm
+    cs2h = 0.25 if (lattice == 1 and h_lattice) else analytic.lattice_cs2(lattice)
+    want_g = -(kphi * analytic.lattice_cs2(lattice) / 2.0)[..., None] * nrm
     want_h = F if h_scheme else -(p["gamma"] * cs2h / 2.0) * F
     assert np.max(np.abs(m1g - want_g)[inner]) < 1e-14
     assert np.max(np.abs(m1h - want_h)[inner]) < 1e-14

@@ -6,7 +6,7 @@ builds initial fields (phi0, c0) as float64 numpy arrays of shape
 (nz, ny, nx), x fastest, and parameter mappings in lattice units
 (dx = dt = 1).
 
-Parameter mappings carry the keys ``lattice`` (0 D2Q9, 1 D3Q19), ``shape``
+Parameter mappings carry the keys ``lattice`` (0 D2Q9, 1 D3Q19, 2 D2Q5, 3 D3Q7), ``shape``
 (nz, ny, nx), ``bc`` (x, y, z; 0 periodic, 1 zero flux), ``counter_term``,
 ``anti_trapping`` and the scalars W, M_phi, lam, D_l, D_s, gamma, a_at,
 c_s_co, c_l_co, mu_eq, eps_n.
@@ -18,6 +18,7 @@ import math
 import numpy as np
 
 D2Q9, D3Q19 = 0, 1
+D2Q5, D3Q7 = 2, 3  # g (and h) on the light lattices
 PERIODIC, ZERO_FLUX = 0, 1
 
 # Integrals of the thin-interface analysis as printed in Table 3 of the
