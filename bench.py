@@ -12,13 +12,13 @@ Printed: one JSON line with MLUPS (million node updates per second), the
 HBM roofline of the step kernel (algorithmic bytes per launch over the mean
 launch time, measured with HIP events on the stream the library launches on),
 the other forms of the same step beside it (FP32, FP16 and BF16 deviation
-storage; h on the light lattice D3Q7 / D2Q5 in FP64 and FP32; the alternative
+storage; h, or g and h, on the light lattice D3Q7 / D2Q5 in FP64 and FP32; the alternative
 equilibrium h^eq,alt and general quadratic free energies in FP64), the
 differentiation workload (adjoint / forward time), and the CPU oracle timed on
 a bounded crop of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--precision fp64|fp32|fp16dev|bf16dev]
-                    [--h-lattice full|light] [--h-scheme source|alt]
+                    [--h-lattice full|light|light-gh] [--h-scheme source|alt]
                     [--free-energy equal|quadratic] [--schedule auto|split|fused]
                     [--workload NAME] [--no-cpu-baseline] [--no-forms]
                     [--adjoint-steps K] [--variants]
@@ -55,9 +55,9 @@ def bytes_per_node_step(lattice_q: int, precision: str, lattice_qh: int | None =
 def form_name(precision: str, h_lattice: str = "full", h_scheme: str = "source",
               free_energy: str = "equal") -> str:
     """Label of a form of the step: the precision, with '_light_h' when h
-    runs on D3Q7 / D2Q5, '_alt_h' with h^eq,alt, '_quadratic' with general
-    quadratic free energies."""
-    return (precision + ("_light_h" if h_lattice == "light" else "")
+    runs on D3Q7 / D2Q5, '_light_gh' when g and h do, '_alt_h' with h^eq,alt,
+    '_quadratic' with general quadratic free energies."""
+    return (precision + {"full": "", "light": "_light_h", "light-gh": "_light_gh"}[h_lattice]
             + ("_alt_h" if h_scheme == "alt" else "")
             + ("_quadratic" if free_energy == "quadratic" else ""))
 
@@ -71,6 +71,8 @@ QUADRATIC = dict(free_energy=1, eps_s=1.0, eps_l=1.5)
 def form_params(p, h_lattice="full", h_scheme="source", free_energy="equal"):
     q = dict(p, h_lattice=1 if h_lattice == "light" else 0,
              h_scheme=1 if h_scheme == "alt" else 0)
+    if h_lattice == "light-gh":  # D2Q9 -> D2Q5, D3Q19 -> D3Q7
+        q["lattice"] = p["lattice"] + 2
     if free_energy == "quadratic":
         q.update(QUADRATIC, m_s=p["c_s_co"], m_l=p["c_l_co"], df_min=0.0)
     return q
@@ -301,7 +303,7 @@ def cpu_baseline(p, phi0, c0, log, budget_s=12.0):
     import oracle
     import workloads as wl
     oracle.build(force=False)
-    size = 128 if p["lattice"] == wl.D3Q19 else 512
+    size = 128 if p["lattice"] in (wl.D3Q19, wl.D3Q7) else 512
     q, a, b = wl.crop_zero_flux(p, phi0, c0, min(size, p["shape"][-1]))
     o = oracle.Oracle(q).init(a, b)
     n_nodes = int(np.prod(q["shape"]))
@@ -340,8 +342,9 @@ sys.path.insert(0, sys.argv[1])
 import numpy as np
 import oracle, workloads as wl
 lat, n = int(sys.argv[2]), int(sys.argv[3])
-shape = (n, n, n) if lat == wl.D3Q19 else (1, n, n)
-p = wl.base_params(lattice=lat, shape=shape, bc=(1, 1, 1 if lat == wl.D3Q19 else 0))
+three = lat in (wl.D3Q19, wl.D3Q7)
+shape = (n, n, n) if three else (1, n, n)
+p = wl.base_params(lattice=lat, shape=shape, bc=(1, 1, 1 if three else 0))
 phi0, c0 = wl.random_state_fields(shape, seed=1)
 o = oracle.Oracle(p).init(phi0, c0)
 o.step(1)
@@ -358,7 +361,8 @@ def cpu_single_thread(p, log):
     small random instance of the same lattice, about 3 s of stepping."""
     import subprocess
     env = dict(os.environ, OMP_NUM_THREADS="1")
-    n = 48 if p["lattice"] == 1 else 256
+    three = p["lattice"] in (1, 3)
+    n = 48 if three else 256
     try:
         out = subprocess.run([sys.executable, "-c", _SINGLE_THREAD, ROOT, str(p["lattice"]), str(n)],
                              env=env, capture_output=True, text=True, timeout=120, check=True)
@@ -368,7 +372,7 @@ def cpu_single_thread(p, log):
         return None
     log(f"cpu oracle, 1 thread: {float(v):.2f} MLUPS")
     return {"value": round(float(v), 3), "unit": "MLUPS", "threads": int(th),
-            "sample": f"{'x'.join([str(n)] * (3 if p['lattice'] == 1 else 2))} random fields, zero flux, ~3 s"}
+            "sample": f"{'x'.join([str(n)] * (3 if three else 2))} random fields, zero flux, ~3 s"}
 
 
 def main():
@@ -378,8 +382,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="porous3d_512_d3q19", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp16dev", "bf16dev"])
-    ap.add_argument("--h-lattice", default="full", choices=["full", "light"],
-                    help="h on the lattice of g, or on D3Q7 / D2Q5 (FP64 and FP32)")
+    ap.add_argument("--h-lattice", default="full", choices=["full", "light", "light-gh"],
+                    help="h on the lattice of g, h on D3Q7 / D2Q5, or g and h on D3Q7 / "
+                         "D2Q5 (FP64 and FP32)")
     ap.add_argument("--h-scheme", default="source", choices=["source", "alt"],
                     help="source H_k, or h^eq,alt (FP64 and FP32)")
     ap.add_argument("--free-energy", default="equal", choices=["equal", "quadratic"],
@@ -436,6 +441,7 @@ def main():
         precs = ("fp64", "fp32") + (("fp16dev", "bf16dev") if p["lattice"] == 1 else ())
         todo = ([(prec, "full", "source", "equal") for prec in precs]
                 + [("fp64", "light", "source", "equal"), ("fp32", "light", "source", "equal"),
+                   ("fp64", "light-gh", "source", "equal"), ("fp32", "light-gh", "source", "equal"),
                    ("fp64", "full", "alt", "equal"), ("fp64", "full", "source", "quadratic")])
         for prec, *var in todo:
             name = form_name(prec, *var)
@@ -492,9 +498,11 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": args.workload,
-            "lattice": "D3Q19" if p["lattice"] == 1 else "D2Q9",
+            "lattice": {(1, "light-gh"): "D3Q7", (0, "light-gh"): "D2Q5"}.get(
+                (p["lattice"], args.h_lattice), "D3Q19" if p["lattice"] == 1 else "D2Q9"),
             "h_lattice": {(1, "full"): "D3Q19", (1, "light"): "D3Q7", (0, "full"): "D2Q9",
-                          (0, "light"): "D2Q5"}[(p["lattice"], args.h_lattice)],
+                          (0, "light"): "D2Q5", (1, "light-gh"): "D3Q7",
+                          (0, "light-gh"): "D2Q5"}[(p["lattice"], args.h_lattice)],
             "h_scheme": args.h_scheme, "free_energy": args.free_energy,
             "grid": [nx, ny, nz],
             "bc": "periodic",

@@ -53,11 +53,18 @@ extern "C" {
 #define GPLBM_E_NONFINITE (-4) /* diagnostics found a non-finite phi or c */
 #define GPLBM_E_STATE (-5)     /* step / read before gplbm_init_fields */
 
-/* lattices of g (phi); h (c) runs on the same one or on the light one */
+/* lattices of g (phi).  D2Q5 / D3Q7 (Sec. 3.1 lists them among the usual
+ * sets): tau_g = M_phi / xi_s^2 (4 M_phi on D3Q7) and the gradient of
+ * Eqs. (DerivDirec_Grad), (Grad) with the factor 1 / xi_s^2, i.e. central
+ * differences; h then runs on the same lattice.  FP64 and FP32 only; no
+ * adjoint. */
 #define GPLBM_D2Q9 0
 #define GPLBM_D3Q19 1
+#define GPLBM_D2Q5 2
+#define GPLBM_D3Q7 3
 
-/* lattice of h.  LIGHT: D2Q5 under D2Q9, D3Q7 under D3Q19 (Sec. 3.3 leaves
+/* lattice of h under D2Q9 / D3Q19 (under D2Q5 / D3Q7, h always runs on the
+ * lattice of g).  LIGHT: D2Q5 under D2Q9, D3Q7 under D3Q19 (Sec. 3.3 leaves
  * the lattice of the c-LBE open; its equilibrium needs only the zeroth and
  * an isotropic second moment).  The relaxation time becomes
  * tau_h = 1 / (gamma xi_s^2) (3 / gamma, or 4 / gamma on D3Q7) so that the
@@ -107,8 +114,8 @@ extern "C" {
 #define GPLBM_SCHED_FUSED 2 /* one kernel per step (tile halo recompute) */
 
 typedef struct gplbm_params {
-  int32_t lattice;       /* GPLBM_D2Q9 or GPLBM_D3Q19 */
-  int32_t nx, ny, nz;    /* nodes; nz = 1 for D2Q9; node i = x + nx*(y + ny*z) */
+  int32_t lattice;       /* GPLBM_D2Q9, GPLBM_D3Q19, GPLBM_D2Q5 or GPLBM_D3Q7 (g) */
+  int32_t nx, ny, nz;    /* nodes; nz = 1 in 2-D; node i = x + nx*(y + ny*z) */
   int32_t bc[3];         /* per axis x, y, z: GPLBM_PERIODIC or GPLBM_ZERO_FLUX */
   int32_t precision;     /* GPLBM_FP64, GPLBM_FP32, GPLBM_FP16_DEV or GPLBM_BF16_DEV */
   int32_t counter_term;  /* 1: counter term G^ct_k (Eq. ModelA_EqPhi_CounterTerm); 0: G^dw */
@@ -118,7 +125,7 @@ typedef struct gplbm_params {
   int32_t h_scheme;      /* GPLBM_H_SOURCE or GPLBM_H_EQ_ALT */
   int32_t free_energy;   /* GPLBM_FE_EQUAL or GPLBM_FE_QUADRATIC */
   double W;              /* interface width */
-  double M_phi;          /* phase-field mobility; tau_g = 3 M_phi */
+  double M_phi;          /* phase-field mobility; tau_g = M_phi / xi_s^2 */
   double lambda;         /* coupling constant */
   double D_l, D_s;       /* diffusivities of liquid and solid */
   double gamma;          /* relaxation control of the c-LBE; tau_h = 1 / (gamma xi_s^2) */

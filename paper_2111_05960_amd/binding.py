@@ -25,7 +25,7 @@ GPLBM_E_DEVICE = -3
 GPLBM_E_NONFINITE = -4
 GPLBM_E_STATE = -5
 
-GPLBM_D2Q9, GPLBM_D3Q19 = 0, 1
+GPLBM_D2Q9, GPLBM_D3Q19, GPLBM_D2Q5, GPLBM_D3Q7 = 0, 1, 2, 3
 GPLBM_H_FULL, GPLBM_H_LIGHT = 0, 1
 GPLBM_H_SOURCE, GPLBM_H_EQ_ALT = 0, 1
 GPLBM_FE_EQUAL, GPLBM_FE_QUADRATIC = 0, 1
@@ -300,9 +300,10 @@ class Simulation:
         self.params = make_params(cfg, precision, schedule)
         self.shape = tuple(int(s) for s in cfg["shape"])
         self.N = self.shape[0] * self.shape[1] * self.shape[2]
-        self.Q = 9 if self.params.lattice == GPLBM_D2Q9 else 19
-        if self.params.h_lattice == GPLBM_H_LIGHT:
-            self.Qh = 5 if self.params.lattice == GPLBM_D2Q9 else 7
+        lat = self.params.lattice
+        self.Q = {GPLBM_D2Q9: 9, GPLBM_D3Q19: 19, GPLBM_D2Q5: 5, GPLBM_D3Q7: 7}[lat]
+        if self.params.h_lattice == GPLBM_H_LIGHT or lat in (GPLBM_D2Q5, GPLBM_D3Q7):
+            self.Qh = 5 if lat in (GPLBM_D2Q9, GPLBM_D2Q5) else 7
         else:
             self.Qh = self.Q
         nbytes = gplbm_state_bytes(self.params)

@@ -55,25 +55,41 @@ constexpr size_t kAlign = 256;
 
 size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-int lattice_q(int lattice) { return lattice == GPLBM_D2Q9 ? 9 : 19; }
+int lattice_q(int lattice) {
+  switch (lattice) {
+    case GPLBM_D2Q9: return D2Q9::Q;
+    case GPLBM_D3Q19: return D3Q19::Q;
+    case GPLBM_D2Q5: return D2Q5::Q;
+    default: return D3Q7::Q;
+  }
+}
+
+bool two_d(int lattice) { return lattice == GPLBM_D2Q9 || lattice == GPLBM_D2Q5; }
+bool light_g(int lattice) { return lattice == GPLBM_D2Q5 || lattice == GPLBM_D3Q7; }
+
+// h on the light lattice: asked for under D2Q9 / D3Q19, always under D2Q5 / D3Q7
+bool light_h(const gplbm_params& p) { return p.h_lattice == GPLBM_H_LIGHT || light_g(p.lattice); }
 
 int lattice_qh(const gplbm_params* p) {
-  if (p->h_lattice == GPLBM_H_LIGHT) return p->lattice == GPLBM_D2Q9 ? D2Q5::Q : D3Q7::Q;
+  if (light_h(*p)) return two_d(p->lattice) ? D2Q5::Q : D3Q7::Q;
   return lattice_q(p->lattice);
 }
 
 // xi_s^2 of the h lattice
 double lattice_cs2h(const gplbm_params& p) {
-  if (p.h_lattice == GPLBM_H_LIGHT) return p.lattice == GPLBM_D2Q9 ? D2Q5::cs2 : D3Q7::cs2;
+  if (light_h(p)) return two_d(p.lattice) ? D2Q5::cs2 : D3Q7::cs2;
   return p.lattice == GPLBM_D2Q9 ? D2Q9::cs2 : D3Q19::cs2;
 }
+
+// 1 / xi_s^2 of the g lattice, written exactly
+double lattice_inv_cs2g(int lattice) { return lattice == GPLBM_D3Q7 ? D3Q7::inv_cs2 : D3Q19::inv_cs2; }
 
 // Returns an error text, or nullptr when the parameters are acceptable.
 const char* check_params(const gplbm_params* p) {
   if (!p) return "null parameters";
-  if (p->lattice != GPLBM_D2Q9 && p->lattice != GPLBM_D3Q19) return "unknown lattice";
+  if (p->lattice < GPLBM_D2Q9 || p->lattice > GPLBM_D3Q7) return "unknown lattice";
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return "grid sizes must be >= 1";
-  if (p->lattice == GPLBM_D2Q9 && p->nz != 1) return "D2Q9 needs nz == 1";
+  if (two_d(p->lattice) && p->nz != 1) return "2-D lattices need nz == 1";
   for (int a = 0; a < 3; ++a)
     if (p->bc[a] != GPLBM_PERIODIC && p->bc[a] != GPLBM_ZERO_FLUX) return "unknown boundary";
   if (p->precision < GPLBM_FP64 || p->precision > GPLBM_BF16_DEV) return "unknown precision";
@@ -167,7 +183,8 @@ template <class C>
 Coef<C> make_coef(const gplbm_params& p) {
   Coef<C> K{};
   const double dc = p.c_s_co - p.c_l_co;
-  K.omega_g = C(1.0 / (3.0 * p.M_phi + 0.5));
+  // tau_g = M_phi / xi_s^2 (3 M_phi, or 4 M_phi on D3Q7)
+  K.omega_g = C(1.0 / (lattice_inv_cs2g(p.lattice) * p.M_phi + 0.5));
   // tau_h = 1 / (gamma xi_s^2): the diffusivity of the c-LBE is D(phi) on
   // every h lattice
   K.omega_h = C(1.0 / (1.0 / (p.gamma * lattice_cs2h(p)) + 0.5));
@@ -209,7 +226,7 @@ Geo make_geo(const gplbm_params& p) {
   g.nz = p.nz;
   g.bcx = p.bc[0];
   g.bcy = p.bc[1];
-  g.bcz = p.lattice == GPLBM_D2Q9 ? GPLBM_PERIODIC : p.bc[2];
+  g.bcz = two_d(p.lattice) ? GPLBM_PERIODIC : p.bc[2];
   g.N = (int64_t)p.nx * p.ny * p.nz;
   return g;
 }
@@ -385,11 +402,18 @@ int dispatch(gplbm_ctx* ctx, Args... args) {
   if (ctx->p.precision == GPLBM_BF16_DEV)
     return Fn<DevAdapter<BF16Codec>, void, void, void>::run(ctx, args...);
   const bool light = ctx->p.h_lattice == GPLBM_H_LIGHT;
-  if (ctx->p.lattice == GPLBM_D2Q9)
-    return light ? dispatch_prec<Fn, D2Q9, D2Q5>(ctx, args...)
-                 : dispatch_prec<Fn, D2Q9, D2Q9>(ctx, args...);
-  return light ? dispatch_prec<Fn, D3Q19, D3Q7>(ctx, args...)
-               : dispatch_prec<Fn, D3Q19, D3Q19>(ctx, args...);
+  switch (ctx->p.lattice) {
+    case GPLBM_D2Q9:
+      return light ? dispatch_prec<Fn, D2Q9, D2Q5>(ctx, args...)
+                   : dispatch_prec<Fn, D2Q9, D2Q9>(ctx, args...);
+    case GPLBM_D3Q19:
+      return light ? dispatch_prec<Fn, D3Q19, D3Q7>(ctx, args...)
+                   : dispatch_prec<Fn, D3Q19, D3Q19>(ctx, args...);
+    case GPLBM_D2Q5:
+      return dispatch_prec<Fn, D2Q5, D2Q5>(ctx, args...);
+    default:
+      return dispatch_prec<Fn, D3Q7, D3Q7>(ctx, args...);
+  }
 }
 
 template <class L, class LH, class S, class C>
@@ -434,7 +458,7 @@ struct DiagFn<A, void, void, void> {
 
 int choose_schedule(const gplbm_params& p) {
   const bool fused_ok = p.precision >= GPLBM_FP16_DEV ? dev_fused_supported(p.nx, p.ny, p.nz, p.bc)
-                        : p.lattice == GPLBM_D2Q9    ? fused2d_supported(p.nx, p.ny)
+                        : two_d(p.lattice)           ? fused2d_supported(p.nx, p.ny)
                                                      : fused3d_supported(p.nx, p.ny, p.nz, p.bc);
   if (p.schedule == GPLBM_SCHED_SPLIT) return GPLBM_SCHED_SPLIT;
   if (p.schedule == GPLBM_SCHED_FUSED) return fused_ok ? GPLBM_SCHED_FUSED : -1;
@@ -477,7 +501,7 @@ int gplbm_create(const gplbm_params* p, void* dev_buf, uint64_t bytes, void* str
   if (sched < 0) return GPLBM_E_INVALID;
   gplbm_ctx* ctx = new gplbm_ctx();
   ctx->p = *p;
-  if (ctx->p.lattice == GPLBM_D2Q9) ctx->p.bc[2] = GPLBM_PERIODIC;
+  if (two_d(ctx->p.lattice)) ctx->p.bc[2] = GPLBM_PERIODIC;
   ctx->Q = lattice_q(p->lattice);
   ctx->Qh = lattice_qh(p);
   ctx->N = (int64_t)p->nx * p->ny * p->nz;
@@ -751,7 +775,7 @@ struct AdjFinishFn {
 // The adjoint is written for h on the lattice of g with the source scheme and
 // equal curvatures, in FP64 or FP32.
 bool adjoint_supported(const gplbm_params& p) {
-  return (p.precision == GPLBM_FP64 || p.precision == GPLBM_FP32) && p.h_lattice == GPLBM_H_FULL &&
+  return (p.precision == GPLBM_FP64 || p.precision == GPLBM_FP32) && !light_h(p) &&
          p.h_scheme == GPLBM_H_SOURCE && p.free_energy == GPLBM_FE_EQUAL;
 }
 

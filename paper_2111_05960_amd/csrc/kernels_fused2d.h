@@ -1,5 +1,5 @@
 // Fused schedule in 2-D: one kernel per time step n -> n+1.  g runs on
-// D2Q9 (L), h on D2Q9 or D2Q5 (LH).
+// D2Q9 or D2Q5 (L), h on D2Q9 or D2Q5 (LH).
 //
 // A block owns an output tile T of TX x TY nodes (x-aligned, tiles.h) and
 // computes T grown by one node on each side (T+1).  Every thread of T+1:

@@ -1,5 +1,5 @@
 // Fused schedule in 3-D: one kernel per time step n -> n+1, marching in z.
-// g runs on D3Q19, h on D3Q19 or D3Q7 (LH).
+// g runs on D3Q19 or D3Q7 (L), h on D3Q19 or D3Q7 (LH).
 //
 // A block owns an x-y output tile T of TX x TY nodes and a chunk of ZC planes,
 // and computes the tile grown by one node in x and y (the region, BX x BY).
@@ -98,24 +98,38 @@ __device__ __forceinline__ void fetch_pops(const S* base, int zp, int nz, int pl
 // after the pull, which frees 2Q registers in FP64.
 enum class Carry { kRegisters, kLds };
 
-template <class S>
+
+template <class L, class S>
 struct Fused3DConfig;
 template <>
-struct Fused3DConfig<double> {
+struct Fused3DConfig<D3Q19, double> {
   static constexpr int TX = 64, TY = 6, ZC = 32;
   static constexpr Carry carry = Carry::kLds;
 };
 template <>
-struct Fused3DConfig<float> {
+struct Fused3DConfig<D3Q19, float> {
   static constexpr int TX = 64, TY = 12, ZC = 32;
   static constexpr Carry carry = Carry::kRegisters;
 };
+// g on D3Q7: 7 populations carried in registers; tile heights measured on
+// the 512^3 step (FP64: 12 rows 7.05 ms, 8 rows 7.79, 6 rows 8.36; FP32: 8
+// rows 4.05 ms, 12 rows 4.40, 6 rows 4.18)
+template <>
+struct Fused3DConfig<D3Q7, double> {
+  static constexpr int TX = 64, TY = 12, ZC = 32;
+  static constexpr Carry carry = Carry::kRegisters;
+};
+template <>
+struct Fused3DConfig<D3Q7, float> {
+  static constexpr int TX = 64, TY = 8, ZC = 32;
+  static constexpr Carry carry = Carry::kRegisters;
+};
 
-template <int TX, int TY, int ZC, Carry kCarryMode, class LH, class S, class C, bool kGen>
+template <int TX, int TY, int ZC, Carry kCarryMode, class L, class LH, class S, class C,
+          bool kGen>
 __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     k_fused3d(Geo g, Coef<C> Kin, StepBufs<S> b, int tiles_x, int tiles_xy, int ntiles) {
   const Coef<C> K = variant<kGen>(Kin);
-  using L = D3Q19;
   using Shape = TileShape<TX, TY>;
   constexpr int Q = L::Q, QH = LH::Q;
   // e_z layers of the h lattice: +1 at [0, NU), 0 at [NU, NU+NM), -1 after
@@ -308,19 +322,20 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   }
 }
 
-// 32-bit offsets inside a z plane group: Q * nx * ny * 8 bytes must fit.
+// 32-bit offsets inside a z plane group: Q * nx * ny * 8 bytes must fit
+// (checked for the larger lattice, 19 populations).
 inline bool fused3d_supported(int nx, int ny, int nz, const int* bc) {
   return bc[0] == 0 && bc[1] == 0 && bc[2] == 0 && (int64_t)nx * ny * 19 * 8 < ((int64_t)1 << 32) &&
          (int64_t)nx * ny * nz < ((int64_t)1 << 31);
 }
 
-template <class LH, class S, class C, bool kGen>
+template <class L, class LH, class S, class C, bool kGen>
 struct Fused3D {
   static int launch(const Geo& g, const Coef<C>& K, const StepBufs<S>& b, hipStream_t st) {
-    using Cfg = Fused3DConfig<S>;
+    using Cfg = Fused3DConfig<L, S>;
     constexpr int TX = Cfg::TX, TY = Cfg::TY, ZC = Cfg::ZC;
     constexpr int NT = TileShape<TX, TY>::NT;
-    auto kernel = k_fused3d<TX, TY, ZC, Cfg::carry, LH, S, C, kGen>;
+    auto kernel = k_fused3d<TX, TY, ZC, Cfg::carry, L, LH, S, C, kGen>;
     const int tiles_x = (g.nx + TX - 1) / TX;
     const int tiles_y = (g.ny + TY - 1) / TY;
     const int chunks = (g.nz + ZC - 1) / ZC;
@@ -340,7 +355,7 @@ struct FusedLaunch {
     if constexpr (L::D == 2)
       return Fused2D<L, LH, S, C, kGen>::launch(g, K, b, st);
     else
-      return Fused3D<LH, S, C, kGen>::launch(g, K, b, st);
+      return Fused3D<L, LH, S, C, kGen>::launch(g, K, b, st);
   }
 };
 

@@ -1,5 +1,6 @@
-// Velocity sets.  g (for phi) runs on D2Q9 or D3Q19; h (for c) on the same
-// lattice or on the light one of the same dimension, D2Q5 or D3Q7.
+// Velocity sets.  g (for phi) runs on D2Q9, D3Q19, D2Q5 or D3Q7; h (for c)
+// on the lattice of g or, under D2Q9 / D3Q19, on the light one of the same
+// dimension, D2Q5 or D3Q7.
 //
 // D2Q9 is numbered as in Sec. 3.1 of the paper: rest, the four axis
 // vectors (+x, +y, -x, -y), the four diagonals (+x+y, -x+y, -x-y, +x-y);
@@ -15,8 +16,10 @@
 // D2Q5 is the rest and the four axis vectors of D2Q9 (same order); weights
 // 1/3, 1/6.  D3Q7 is numbered by layers of e_z like D3Q19: (0,0,1), rest,
 // +x, -x, +y, -y, (0,0,-1); weights 1/4 (rest), 1/8.  cs2 is xi_s^2, the
-// second moment of the weights (1/3, except 1/4 for D3Q7); the relaxation
-// time of h is 1 / (gamma cs2).
+// second moment of the weights (1/3, except 1/4 for D3Q7), inv_cs2 its
+// inverse written exactly (3 or 4); the relaxation times are
+// tau_g = M_phi inv_cs2 and tau_h = 1 / (gamma cs2), and the gradient is
+// inv_cs2 sum_k w_k e_k d_k.
 #pragma once
 
 #include <cstdint>
@@ -26,6 +29,7 @@ namespace gplbm {
 struct D2Q9 {
   static constexpr int Q = 9;
   static constexpr double cs2 = 1.0 / 3.0;
+  static constexpr double inv_cs2 = 3.0;
   static constexpr int D = 2;
   static constexpr int REST = 0;
   static constexpr int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -40,6 +44,7 @@ struct D2Q9 {
 struct D3Q19 {
   static constexpr int Q = 19;
   static constexpr double cs2 = 1.0 / 3.0;
+  static constexpr double inv_cs2 = 3.0;
   static constexpr int D = 3;
   static constexpr int REST = 5;
   static constexpr int ex[19] = {0, 1, -1, 0, 0, 0, 1, -1, 0, 0,
@@ -60,6 +65,7 @@ struct D3Q19 {
 struct D2Q5 {
   static constexpr int Q = 5;
   static constexpr double cs2 = 1.0 / 3.0;
+  static constexpr double inv_cs2 = 3.0;
   static constexpr int D = 2;
   static constexpr int REST = 0;
   static constexpr int ex[5] = {0, 1, 0, -1, 0};
@@ -72,6 +78,7 @@ struct D2Q5 {
 struct D3Q7 {
   static constexpr int Q = 7;
   static constexpr double cs2 = 1.0 / 4.0;
+  static constexpr double inv_cs2 = 4.0;
   static constexpr int D = 3;
   static constexpr int REST = 1;
   static constexpr int ex[7] = {0, 0, 1, -1, 0, 0, 0};

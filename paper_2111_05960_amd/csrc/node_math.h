@@ -12,8 +12,8 @@
 //                     general quadratic free energies, Eq. (Closure):
 //                     mu = (sqrt(eps_s eps_l) / (eps_s phi + eps_l (1 - phi)))
 //                          ((c - phi m_l) - (1 - phi) m_s)
-//   gradient          grad = 3 sum_k w_k e_k d_k, d_k = (phi(x+e_k) - phi(x-e_k))/2
-//                     Eqs. (DerivDirec_Grad), (Grad)
+//   gradient          grad = (1/xi_s^2) sum_k w_k e_k d_k, d_k = (phi(x+e_k) - phi(x-e_k))/2
+//                     Eqs. (DerivDirec_Grad), (Grad); central differences on D2Q5 / D3Q7
 //   normal            n = grad / sqrt(|grad|^2 + eps_n^2)
 //   phi sources       G^st = kst S_phi, S_phi = 6 phi(1-phi) dc (mu - mu_eq),
 //                     kst = -lambda M / W^2               Eqs. (SourceG_ST), (SourceTerm_Coexistence)
@@ -23,7 +23,7 @@
 //                     G^dw = kdw 2 phi(1-phi)(1-2phi), kdw = -8 M / W^2   Eq. (SourceG_dw)
 //                     G_k = w_k (G^st + G^curv)           Eq. (TermG)
 //   g collision       g* = (g - omega_g ((g - w_k phi) + G_k/2)) + G_k
-//                     Eq. (LBE_PhaseField_Eq), omega_g = 1/(3 M + 1/2)
+//                     Eq. (LBE_PhaseField_Eq), omega_g = 1/(M / xi_s^2 + 1/2)
 //   h source          F = (mu (D_l - D_s)) grad + (a W dc) dphi/dt n,
 //                     H_k = (gamma w_k) e_k.F             Eq. (SourceTerm_LBE_h)
 //                     general: dc -> (ks mu + m_s) - m_l,
@@ -144,9 +144,9 @@ __device__ __forceinline__ void gradient_normal(const F& phi_at, C eps2, C g[3],
       if (L::ez[k] < 0) a2 = a2 - wd;
     }
   }
-  g[0] = C(3) * a0;
-  g[1] = C(3) * a1;
-  g[2] = C(3) * a2;
+  g[0] = C(L::inv_cs2) * a0;
+  g[1] = C(L::inv_cs2) * a1;
+  g[2] = C(L::inv_cs2) * a2;
   C nn = g[0] * g[0] + g[1] * g[1];
   if (L::D == 3) nn = nn + g[2] * g[2];
   C den = sqrt(nn + eps2);

@@ -88,7 +88,7 @@ def test_adjoint_rejects_light_h(lib):
 
 @pytest.mark.parametrize("field,value", [
     ("M_phi", 0.0), ("M_phi", -1.0), ("gamma", 0.0), ("W", 0.0), ("nz", 2), ("nx", 0),
-    ("lattice", 7), ("precision", 9), ("schedule", 5), ("lam", float("nan")),
+    ("lattice", 7), ("lattice", 4), ("precision", 9), ("schedule", 5), ("lam", float("nan")),
     ("h_lattice", 2), ("h_lattice", -1),
 ])
 def test_invalid_parameters_rejected(lib, field, value):
@@ -150,3 +150,22 @@ def test_variant_parameters_validated(lib, field, value):
     with pytest.raises(B.GplbmError) as e:
         B.gplbm_state_bytes(cp)
     assert e.value.code == B.GPLBM_E_INVALID
+
+
+@pytest.mark.parametrize("lattice,shape,q", [(wl.D2Q5, (1, 12, 10), 5), (wl.D3Q7, (6, 12, 10), 7)])
+def test_state_bytes_layout_light_g(lib, lattice, shape, q):
+    """g on D2Q5 / D3Q7: both distributions hold Q populations of that lattice."""
+    p = wl.base_params(lattice=lattice, shape=shape, bc=(0, 0, 0))
+    n = shape[0] * shape[1] * shape[2]
+    rnd = lambda v: (v + 255) // 256 * 256
+    cp = B.make_params(p, "fp64")
+    assert B.gplbm_checkpoint_bytes(cp) == 2 * rnd(q * n * 8) + rnd(n * 8)
+    out = ctypes.c_uint64()
+    assert lib.gplbm_adjoint_bytes(ctypes.byref(cp), ctypes.byref(out)) == B.GPLBM_E_INVALID
+    for prec in ("fp16dev", "bf16dev"):
+        with pytest.raises(B.GplbmError):
+            B.gplbm_state_bytes(B.make_params(p, prec))
+    bad = B.make_params(dict(p, shape=(2,) + shape[1:]) if lattice == wl.D2Q5 else p, "fp64")
+    if lattice == wl.D2Q5:
+        with pytest.raises(B.GplbmError):
+            B.gplbm_state_bytes(bad)

@@ -198,7 +198,7 @@ def crop_zero_flux(p: dict, phi0, c0, size: int = 64):
     """Crop [0, size)^d of a periodic workload, run with zero flux on every
     face."""
     q = dict(p)
-    if q["lattice"] == D3Q19:
+    if q["lattice"] in (D3Q19, D3Q7):
         q["shape"] = (size, size, size)
         q["bc"] = (ZERO_FLUX, ZERO_FLUX, ZERO_FLUX)
         return q, phi0[:size, :size, :size].copy(), c0[:size, :size, :size].copy()
