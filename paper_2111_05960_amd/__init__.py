@@ -9,3 +9,4 @@ from .binding import (Simulation, GplbmError, load, make_params,  # noqa: F401
                       gplbm_set_stream, gplbm_init_fields, gplbm_step, gplbm_step_count,
                       gplbm_read_fields, gplbm_diagnostics, gplbm_save_state,
                       gplbm_load_state, gplbm_schedule, gplbm_last_error, gplbm_destroy)
+from .units import lattice_steps, to_lattice_units  # noqa: F401

@@ -169,3 +169,22 @@ def test_state_bytes_layout_light_g(lib, lattice, shape, q):
     if lattice == wl.D2Q5:
         with pytest.raises(B.GplbmError):
             B.gplbm_state_bytes(bad)
+
+
+def test_unit_conversion_matches_the_paper_runs():
+    """The physical parameters of the Sec. 4.2 dissolution run (M_phi = 1.2,
+    D_l = 1, D_s = 0, W = 5e-3, dx = 1e-4, dt = 5e-9) convert to the lattice
+    parameters the validation workload states directly (M, D x 0.5, W = 50
+    cells), and t = 5e-4 is 1e5 steps."""
+    from paper_2111_05960_amd import units
+    p, _, _ = wl.paper_validation("dissolution")
+    phys = dict(p, M_phi=1.2, D_l=1.0, D_s=0.0, W=5e-3)
+    del phys["gamma"]
+    lat = units.to_lattice_units(phys, wl.PAPER_DX, wl.PAPER_DT)
+    for k in ("M_phi", "D_l", "D_s", "W", "gamma", "lam", "c_s_co", "c_l_co", "mu_eq"):
+        assert abs(lat[k] - p[k]) <= 1e-12 * max(abs(p[k]), 1.0), k
+    assert units.lattice_steps(5e-4, wl.PAPER_DT) == 100000
+    with pytest.raises(ValueError):
+        units.lattice_steps(5e-4 + 1e-9, wl.PAPER_DT)
+    back = units.to_lattice_units(dict(gamma=2.0), 0.5, 0.25)
+    assert back["gamma"] == 2.0 / (0.25 / 0.25)
