@@ -142,6 +142,66 @@ def time_gpu(p, phi0, c0, precision, schedule, steps, warmup, log, h_lattice="fu
     return res
 
 
+def adjoint_bytes_per_node(Q: int, D: int, precision: str) -> int:
+    """Algorithmic HBM bytes of one reverse step (the two reverse kernels) per
+    node: every array the step reads or writes, once.  Adjoint arrays are
+    FP64; the forward states (H pulls and phi at n and n+1) are in the
+    context's precision.
+      first kernel:  reads  H^{n+1} (Q), phi^{n+1}, A1 and B2, B3 (D), B4 of the
+                     previous step, the lambda accumulator;
+                     writes A1 (Q), A2 (D), A3, A4, the lambda accumulator
+      second kernel: reads  B1 of the previous step (Q), A3, A4, A2 (D),
+                     H^n (Q), phi^n, phi^{n+1}, both accumulators;
+                     writes B1 (Q), B2, B3 (D), B4, both accumulators"""
+    fwd = 8 if precision == "fp64" else 4
+    adj_values = (Q + 1 + D + 1 + 1) + (Q + D + 1 + 1 + 1) \
+        + (Q + 1 + 1 + D + 2) + (Q + 1 + D + 1 + 2)
+    fwd_values = (Q + 1) + (Q + 1 + 1)
+    return 8 * adj_values + fwd * fwd_values
+
+
+def time_reverse_steps(n, precision, log, reps=200):
+    """Mean time of one reverse step (both reverse kernels) on the n^2 D2Q9
+    porous workload, timed with HIP events on the stream the library launches
+    on, between two saved states."""
+    import torch
+    import workloads as wl
+    from paper_2111_05960_amd import Simulation
+    from paper_2111_05960_amd import binding as B
+
+    p, phi0, c0, _ = wl.config_porous2d(n=n)
+    sim = Simulation(p, precision).init(phi0, c0)
+    s0, _ = sim.checkpoint()
+    sim.step(1)
+    s1, _ = sim.checkpoint()
+    nb = B.gplbm_adjoint_bytes(sim.params)
+    work = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    base = (work.data_ptr() + 255) // 256 * 256
+    pb = torch.zeros(sim.N, dtype=torch.float64, device="cuda")
+    B.gplbm_adjoint_begin(sim.ctx, base, nb, pb.data_ptr(), 0)
+    for _ in range(10):
+        B.gplbm_adjoint_step(sim.ctx, s0.data_ptr(), s1.data_ptr())
+    stream = sim.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        B.gplbm_adjoint_step(sim.ctx, s0.data_ptr(), s1.data_ptr())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    balg = adjoint_bytes_per_node(9, 2, precision)
+    res = {"ms_per_reverse_step": round(ms, 5), "mlups": round(sim.N / (ms * 1e-3) / 1e6, 1),
+           "bytes_per_node_step": balg,
+           "achieved_gbs": round(balg * sim.N / (ms * 1e-3) / 1e9, 1),
+           "hbm_frac": round(balg * sim.N / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    log(f"reverse step {precision}: {ms:.4f} ms, {res['mlups']} MLUPS, {res['achieved_gbs']} GB/s "
+        f"algorithmic ({balg} B/node)")
+    del sim, work
+    torch.cuda.empty_cache()
+    return res
+
+
 def time_adjoint(K, log, n=512, precision="fp64"):
     """Differentiation workload: 2-D porous medium n^2 (D2Q9, periodic), K
     steps (FP64, or FP32 forward states with the FP64 reverse sweep);
@@ -183,8 +243,11 @@ def time_adjoint(K, log, n=512, precision="fp64"):
            "forward_s": round(fwd, 4), "backward_s": round(bwd, 4),
            "adjoint_forward_ratio": round(bwd / fwd, 3),
            "peak_memory_gb": round(peak / 1e9, 3),
+           "forward_mlups": round(n * n * K / fwd / 1e6, 1),
+           "backward_mlups": round(n * n * K / bwd / 1e6, 1),
            "J1": J1.item(), "dJ1_dlambda": g_lam.grad.item(), "dJ1_dDl": g_dl.grad.item(),
            "dJ1_dphi0_norm": float(g_phi0.grad.norm().item())}
+    res["reverse_step"] = time_reverse_steps(n, precision, log)
     log(f"adjoint {res['workload']} {precision} K={K}: forward {fwd:.3f} s, backward {bwd:.3f} s "
         f"(ratio {bwd / fwd:.2f}), peak {peak / 1e9:.2f} GB")
     return res
