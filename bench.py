@@ -99,7 +99,10 @@ def make_workload(name):
 
 
 def time_gpu(p, phi0, c0, precision, schedule, steps, warmup, log, h_lattice="full",
-             h_scheme="source", free_energy="equal"):
+             h_scheme="source", free_energy="equal", ref_phi=None, keep_phi=False):
+    """Times `steps` steps after `warmup` untimed ones.  ref_phi: phi of an
+    FP64 run of the same form and step count (device), against which the
+    final phi is compared; keep_phi: return this run's final phi as well."""
     import torch
     from paper_2111_05960_amd import Simulation
 
@@ -137,9 +140,21 @@ def time_gpu(p, phi0, c0, precision, schedule, steps, warmup, log, h_lattice="fu
     log(f"gpu {form_name(precision, h_lattice, h_scheme, free_energy)} {sim.schedule}: "
         f"{res['mlups']:.1f} MLUPS, {ms_step:.3f} ms/step, "
         f"{res['achieved_gbs']:.0f} GB/s algorithmic, mass drift {res['mass_drift_rel']:.2e}")
+    phi_end = None
+    if ref_phi is not None or keep_phi:
+        phi_end = sim.fields_device()[0]
+    if ref_phi is not None:
+        res["vs_fp64"] = {"phi_linf": float((phi_end - ref_phi).abs().max().item()),
+                          "solid_fraction_diff": abs(d1["solid_fraction"] - float(
+                              1.0 - ref_phi.mean().item())),
+                          "steps": warmup + steps}
+        log(f"  vs FP64 after {warmup + steps} steps: max|phi - phi_fp64| = "
+            f"{res['vs_fp64']['phi_linf']:.2e}")
     del sim
+    if not keep_phi:
+        phi_end = None
     torch.cuda.empty_cache()
-    return res
+    return (res, phi_end) if keep_phi else res
 
 
 def adjoint_bytes_per_node(Q: int, D: int, precision: str) -> int:
@@ -496,8 +511,12 @@ def main():
 
     variant = (args.h_lattice, args.h_scheme, args.free_energy)
     main_form = form_name(args.precision, *variant)
+    keep = args.precision == "fp64" and not args.no_forms
     main_res = time_gpu(p, phi0, c0, args.precision, args.schedule, args.steps, args.warmup, log,
-                        *variant)
+                        *variant, keep_phi=keep)
+    ref_phi = None
+    if keep:
+        main_res, ref_phi = main_res
     # the other forms of the same step, side by side (auto schedule)
     forms = {}
     if not args.no_forms:
@@ -510,7 +529,10 @@ def main():
             name = form_name(prec, *var)
             if name == main_form:
                 continue
-            r = time_gpu(p, phi0, c0, prec, "auto", args.steps, args.warmup, log, *var)
+            # the precision forms of the main variant are compared with its FP64 phi
+            same = tuple(var) == variant and prec in ("fp32", "fp16dev", "bf16dev")
+            r = time_gpu(p, phi0, c0, prec, "auto", args.steps, args.warmup, log, *var,
+                         ref_phi=ref_phi if same else None)
             t = stored_traffic(args.workload, name, r["schedule"])
             forms[name] = {
                 "mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
@@ -519,6 +541,10 @@ def main():
                 "hbm_frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
                 "traffic_gb_per_step": None if t is None else round(t["bytes_per_step"] / 1e9, 3),
                 "mass_drift_rel": r["mass_drift_rel"]}
+            if "vs_fp64" in r:
+                forms[name]["vs_fp64"] = r["vs_fp64"]
+    ref_phi = None
+    torch.cuda.empty_cache()
     variants = []
     if args.variants:
         precs = ("fp64", "fp32") + (("fp16dev", "bf16dev") if p["lattice"] == 1 else ())
