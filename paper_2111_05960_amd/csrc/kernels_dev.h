@@ -321,7 +321,6 @@ __global__ void __launch_bounds__(256) k_dev_fields(Geo g, double cl, double cs,
 template <class Codec>
 __global__ void __launch_bounds__(kDiagThreads) k_dev_diag_partial(Geo g, DevState s,
                                                                    double* __restrict__ part) {
-  __shared__ double red[kDiagVals][kDiagThreads];
   double v[kDiagVals] = {0.0, 0.0, 0.0, 0.0, INFINITY, -INFINITY, 0.0, 0.0};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.N; i += stride) {
@@ -343,22 +342,9 @@ __global__ void __launch_bounds__(kDiagThreads) k_dev_diag_partial(Geo g, DevSta
     v[5] = fmax(v[5], phi);
     if (!isfinite(c) || !isfinite(phi)) v[6] = 1.0;
   }
-  for (int j = 0; j < kDiagVals; ++j) red[j][threadIdx.x] = v[j];
-  __syncthreads();
-  for (int s2 = kDiagThreads / 2; s2 > 0; s2 >>= 1) {
-    if ((int)threadIdx.x < s2) {
-      const int t = threadIdx.x;
-      red[0][t] = red[0][t] + red[0][t + s2];
-      red[1][t] = red[1][t] + red[1][t + s2];
-      red[2][t] = red[2][t] + red[2][t + s2];
-      red[3][t] = red[3][t] + red[3][t + s2];
-      red[4][t] = fmin(red[4][t], red[4][t + s2]);
-      red[5][t] = fmax(red[5][t], red[5][t + s2]);
-      red[6][t] = fmax(red[6][t], red[6][t + s2]);
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < kDiagVals) part[blockIdx.x * kDiagVals + threadIdx.x] = red[threadIdx.x][0];
+  diag_block_reduce(v);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < kDiagVals; ++j) part[blockIdx.x * kDiagVals + j] = v[j];
 }
 
 // ---------------------------------------------------------------------------

@@ -213,18 +213,54 @@ __global__ void __launch_bounds__(256) k_fields(Geo g, ClosureK q, const S* __re
 }
 
 // ---------------------------------------------------------------------------
-// Diagnostics: fixed-shape two-pass reduction in double (deterministic: the
-// association of every sum depends only on the launch shape).
+// Diagnostics: fixed-shape two-pass reduction in double, wavefront shuffles
+// inside each block (deterministic: the association of every sum depends
+// only on the launch shape).
 
 constexpr int kDiagThreads = 256;
 constexpr int kDiagBlocks = 1024;
 constexpr int kDiagVals = 8;  // mass, solid, count, sum phi, min, max, nonfinite, spare
+constexpr int kDiagWaves = kDiagThreads / 64;
+
+// Combination of two partial diagnostics (sums, min, max, flag).
+__device__ __forceinline__ void diag_combine(double* v, const double* u) {
+  v[0] = v[0] + u[0];
+  v[1] = v[1] + u[1];
+  v[2] = v[2] + u[2];
+  v[3] = v[3] + u[3];
+  v[4] = fmin(v[4], u[4]);
+  v[5] = fmax(v[5], u[5]);
+  v[6] = fmax(v[6], u[6]);
+}
+
+// Block reduction of the per-thread partials: within each wavefront by
+// shuffles with halving offsets (lane l takes lane l + off), then the
+// wavefront results in wave order.  The association depends only on the
+// launch shape, so the result is deterministic.  Thread 0 returns the total.
+__device__ __forceinline__ void diag_block_reduce(double* v) {
+  __shared__ double wred[kDiagWaves][kDiagVals];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    double u[kDiagVals];
+#pragma unroll
+    for (int j = 0; j < kDiagVals; ++j) u[j] = __shfl_down(v[j], off, 64);
+    diag_combine(v, u);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < kDiagVals; ++j) wred[wave][j] = v[j];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kDiagWaves; ++w) diag_combine(v, wred[w]);
+  }
+}
 
 template <class L, class S>
 __global__ void __launch_bounds__(kDiagThreads) k_diag_partial(Geo g, const S* __restrict__ H,
                                                                const S* __restrict__ PHI,
                                                                double* __restrict__ part) {
-  __shared__ double red[kDiagVals][kDiagThreads];
   double v[kDiagVals] = {0.0, 0.0, 0.0, 0.0, INFINITY, -INFINITY, 0.0, 0.0};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.N; i += stride) {
@@ -246,27 +282,13 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag_partial(Geo g, const S* _
     v[5] = fmax(v[5], phi);
     if (!isfinite(c) || !isfinite(phi)) v[6] = 1.0;
   }
-  for (int j = 0; j < kDiagVals; ++j) red[j][threadIdx.x] = v[j];
-  __syncthreads();
-  for (int s = kDiagThreads / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      const int t = threadIdx.x;
-      red[0][t] = red[0][t] + red[0][t + s];
-      red[1][t] = red[1][t] + red[1][t + s];
-      red[2][t] = red[2][t] + red[2][t + s];
-      red[3][t] = red[3][t] + red[3][t + s];
-      red[4][t] = fmin(red[4][t], red[4][t + s]);
-      red[5][t] = fmax(red[5][t], red[5][t + s]);
-      red[6][t] = fmax(red[6][t], red[6][t + s]);
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < kDiagVals) part[blockIdx.x * kDiagVals + threadIdx.x] = red[threadIdx.x][0];
+  diag_block_reduce(v);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < kDiagVals; ++j) part[blockIdx.x * kDiagVals + j] = v[j];
 }
 
 __global__ void __launch_bounds__(kDiagThreads) k_diag_final(const double* __restrict__ part,
                                                              int nblocks, double* __restrict__ out) {
-  __shared__ double red[kDiagVals][kDiagThreads];
   double v[kDiagVals] = {0.0, 0.0, 0.0, 0.0, INFINITY, -INFINITY, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblocks; b += kDiagThreads) {
     const double* p = part + b * kDiagVals;
@@ -278,22 +300,9 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag_final(const double* __res
     v[5] = fmax(v[5], p[5]);
     v[6] = fmax(v[6], p[6]);
   }
-  for (int j = 0; j < kDiagVals; ++j) red[j][threadIdx.x] = v[j];
-  __syncthreads();
-  for (int s = kDiagThreads / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      const int t = threadIdx.x;
-      red[0][t] = red[0][t] + red[0][t + s];
-      red[1][t] = red[1][t] + red[1][t + s];
-      red[2][t] = red[2][t] + red[2][t + s];
-      red[3][t] = red[3][t] + red[3][t + s];
-      red[4][t] = fmin(red[4][t], red[4][t + s]);
-      red[5][t] = fmax(red[5][t], red[5][t + s]);
-      red[6][t] = fmax(red[6][t], red[6][t + s]);
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < kDiagVals) out[threadIdx.x] = red[threadIdx.x][0];
+  diag_block_reduce(v);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < kDiagVals; ++j) out[j] = v[j];
 }
 
 }  // namespace gplbm
