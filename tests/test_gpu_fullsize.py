@@ -1,4 +1,5 @@
-"""Parity at full workload size, in the launch configuration bench.py times.
+"""Parity at full workload size, in the launch configuration bench.py times
+(the base step and the variant forms the benchmark reports beside it).
 
 The oracle cannot step a 512^3 grid, but one step at a node depends only on
 the state within 3 nodes (the phi stencil of the h collision at a neighbour),
@@ -94,3 +95,21 @@ def test_fullsize_porous512_fp32(porous512):
 def test_fullsize_grain1024_fp64():
     p, phi0, c0, _ = wl.config1()
     _check(p, phi0, c0, "fp64", 0.0)
+
+
+# the variant forms of the 512^3 step that bench.py times (FP64, bit-exact):
+# h on D3Q7; g and h on D3Q7; h^eq,alt; general free energies with
+# eps_l / eps_s = 1.5 and the minima at the coexistence compositions
+VARIANTS = {
+    "light_h": lambda p: dict(p, h_lattice=1),
+    "light_gh": lambda p: dict(p, lattice=wl.D3Q7),
+    "alt_h": lambda p: dict(p, h_scheme=1),
+    "quadratic": lambda p: dict(p, free_energy=1, eps_s=1.0, eps_l=1.5, m_s=p["c_s_co"],
+                                m_l=p["c_l_co"], df_min=0.0),
+}
+
+
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
+def test_fullsize_porous512_variants_fp64(porous512, variant):
+    p, phi0, c0 = porous512
+    _check(VARIANTS[variant](p), phi0, c0, "fp64", 0.0)
