@@ -56,8 +56,8 @@ extern "C" {
 /* lattices of g (phi).  D2Q5 / D3Q7 (Sec. 3.1 lists them among the usual
  * sets): tau_g = M_phi / xi_s^2 (4 M_phi on D3Q7) and the gradient of
  * Eqs. (DerivDirec_Grad), (Grad) with the factor 1 / xi_s^2, i.e. central
- * differences; h then runs on the same lattice.  FP64 and FP32 only; no
- * adjoint. */
+ * differences; h then runs on the same lattice.  FP64 and FP32 only (the
+ * adjoint included). */
 #define GPLBM_D2Q9 0
 #define GPLBM_D3Q19 1
 #define GPLBM_D2Q5 2
@@ -69,7 +69,7 @@ extern "C" {
  * an isotropic second moment).  The relaxation time becomes
  * tau_h = 1 / (gamma xi_s^2) (3 / gamma, or 4 / gamma on D3Q7) so that the
  * diffusivity stays D(phi); H_k = gamma w_k e_k . F on the h lattice.  FP64
- * and FP32 only; no adjoint. */
+ * and FP32 only (the adjoint included). */
 #define GPLBM_H_FULL 0
 #define GPLBM_H_LIGHT 1
 
@@ -225,8 +225,9 @@ int gplbm_load_state(gplbm_ctx* ctx, const void* dev_src, int64_t step);
  *   writes dJ/dphi0 and dJ/dc0 (device, N doubles) and dJ/dlambda, dJ/dD_l into
  *   dJ_dparams (host, 2 doubles).  Parameter sums are reduced in a fixed
  *   order.  Synchronises the stream.
- * Return GPLBM_E_INVALID for FP16/BF16-deviation or GPLBM_H_LIGHT contexts
- * or null pointers, GPLBM_E_SIZE for a short workspace, GPLBM_E_STATE out of
+ * Every lattice combination is supported.  Return GPLBM_E_INVALID for
+ * FP16/BF16-deviation contexts, GPLBM_H_EQ_ALT or GPLBM_FE_QUADRATIC, or null
+ * pointers, GPLBM_E_SIZE for a short workspace, GPLBM_E_STATE out of
  * order. */
 int gplbm_adjoint_bytes(const gplbm_params* p, uint64_t* bytes);
 int gplbm_adjoint_begin(gplbm_ctx* ctx, void* work, uint64_t bytes, const double* phi_bar,

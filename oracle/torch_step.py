@@ -25,16 +25,32 @@ D3Q19_E = [(0, 0, 1), (1, 0, 1), (-1, 0, 1), (0, 1, 1), (0, -1, 1), (0, 0, 0),
            (0, 1, -1)]
 D3Q19_W = [1 / 18, 1 / 36, 1 / 36, 1 / 36, 1 / 36, 1 / 3, 1 / 18, 1 / 18, 1 / 18, 1 / 18,
            1 / 36, 1 / 36, 1 / 36, 1 / 36, 1 / 18, 1 / 36, 1 / 36, 1 / 36, 1 / 36]
+# the light sets: D2Q5 = rest and axes of D2Q9; D3Q7 grouped by e_z
+D2Q5_E = D2Q9_E[:5]
+D2Q5_W = [1 / 3, 1 / 6, 1 / 6, 1 / 6, 1 / 6]
+D3Q7_E = [(0, 0, 1), (0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, -1)]
+D3Q7_W = [1 / 8, 1 / 4, 1 / 8, 1 / 8, 1 / 8, 1 / 8, 1 / 8]
 
 
 class Lattice:
     """Velocity set, weights and the index maps of streaming and of the
-    gradient stencil for one grid (periodic wrap / zero-flux walls)."""
+    gradient stencil for one grid (periodic wrap / zero-flux walls).  role
+    "g" or "h": the lattice of that distribution (lattice 0 D2Q9, 1 D3Q19,
+    2 D2Q5, 3 D3Q7 for g; h on D2Q5 / D3Q7 under g on a light lattice or with
+    h_lattice = 1).  cs2 = xi_s^2 of the set, inv_cs2 its inverse (3 or 4)."""
 
-    def __init__(self, cfg):
-        self.d3 = int(cfg["lattice"]) == 1
-        self.e = D3Q19_E if self.d3 else D2Q9_E
-        self.w = torch.tensor(D3Q19_W if self.d3 else D2Q9_W, dtype=torch.float64)
+    def __init__(self, cfg, role="g"):
+        lat = int(cfg["lattice"])
+        self.d3 = lat in (1, 3)
+        light = lat in (2, 3) or (role == "h" and int(cfg.get("h_lattice", 0)) == 1)
+        if self.d3:
+            e, w = (D3Q7_E, D3Q7_W) if light else (D3Q19_E, D3Q19_W)
+        else:
+            e, w = (D2Q5_E, D2Q5_W) if light else (D2Q9_E, D2Q9_W)
+        self.e = e
+        self.w = torch.tensor(w, dtype=torch.float64)
+        self.cs2 = 0.25 if (self.d3 and light) else 1.0 / 3.0
+        self.inv_cs2 = 4.0 if (self.d3 and light) else 3.0
         self.Q = len(self.e)
         self.D = 3 if self.d3 else 2
         self.rest = self.e.index((0, 0, 0))
@@ -102,7 +118,7 @@ def gradient_normal(L, phi, eps_n):
         for a in range(L.D):
             if L.e[k][a] != 0:
                 acc[a] = acc[a] + (float(L.w[k]) * float(L.e[k][a])) * d
-    g = torch.stack([3.0 * acc[a] for a in range(3)])
+    g = torch.stack([L.inv_cs2 * acc[a] for a in range(3)])
     den = torch.sqrt((g[:L.D] ** 2).sum(0) + eps_n * eps_n)
     return g, g / den
 
@@ -133,23 +149,25 @@ def h_parts(L, P, c, phi, mu, F):
     return heq, H
 
 
-def init(L, P, phi0, c0):
-    """Initial natural state (g, h, phi) from flat phi0, c0 (N,)."""
+def init(L, Lh, P, phi0, c0):
+    """Initial natural state (g, h, phi) from flat phi0, c0 (N,); L, Lh the
+    lattices of g and h."""
     mu = closure(P, c0, phi0)
     gr, n = gradient_normal(L, phi0, P["eps_n"])
     G, _ = sources(L, P, phi0, mu, n)
     g = L.w[:, None] * phi0[None, :] - 0.5 * G
     F = (mu * (P["D_l"] - P["D_s"]))[None, :] * gr
-    heq, H = h_parts(L, P, c0, phi0, mu, F)
+    heq, H = h_parts(Lh, P, c0, phi0, mu, F)
     h = heq - 0.5 * H
     return g, h, phi0
 
 
-def step(L, P, g, h, phi):
-    """One step S1-S9 on flat (Q, N) / (N,) tensors."""
+def step(L, Lh, P, g, h, phi):
+    """One step S1-S9 on flat (Q, N) / (N,) tensors; L, Lh the lattices of g
+    and h."""
     Q, N = L.Q, L.N
-    omega_g = 1.0 / (3.0 * P["M_phi"] + 0.5)
-    omega_h = 1.0 / (3.0 / P["gamma"] + 0.5)
+    omega_g = 1.0 / (L.inv_cs2 * P["M_phi"] + 0.5)
+    omega_h = 1.0 / (1.0 / (P["gamma"] * Lh.cs2) + 0.5)
     dc = P["c_s_co"] - P["c_l_co"]
     c = h.sum(0)
     mu = closure(P, c, phi)
@@ -161,24 +179,24 @@ def step(L, P, g, h, phi):
     F = (mu * (P["D_l"] - P["D_s"]))[None, :] * gr
     if P["anti_trapping"]:
         F = F + ((P["a_at"] * P["W"]) * dc) * (phi1 - phi)[None, :] * n
-    heq, H = h_parts(L, P, c, phi, mu, F)
+    heq, H = h_parts(Lh, P, c, phi, mu, F)
     hs = h - omega_h * ((h - heq) + 0.5 * H) + H
-    h1 = hs.reshape(-1)[L.stream_src].reshape(Q, N)
+    h1 = hs.reshape(-1)[Lh.stream_src].reshape(Lh.Q, N)
     return g1, h1, phi1
 
 
 def run(cfg, phi0, c0, nsteps, lam=None, D_l=None):
     """phi^K and c^K (flat) after nsteps from (phi0, c0); lam and D_l may be
     tensors (with requires_grad) that replace the mapping's values."""
-    L = Lattice(cfg)
+    L, Lh = Lattice(cfg, "g"), Lattice(cfg, "h")
     P = dict(cfg)
     if lam is not None:
         P["lam"] = lam
     if D_l is not None:
         P["D_l"] = D_l
-    g, h, phi = init(L, P, phi0, c0)
+    g, h, phi = init(L, Lh, P, phi0, c0)
     for _ in range(nsteps):
-        g, h, phi = step(L, P, g, h, phi)
+        g, h, phi = step(L, Lh, P, g, h, phi)
     return phi, h.sum(0)
 
 

@@ -683,23 +683,23 @@ void gplbm_destroy(gplbm_ctx* ctx) { delete ctx; }
 namespace {
 
 struct AdjLayout {
-  size_t pop, fld, vec, red, total;
+  size_t pop, hpop, fld, vec, red, total;
 };
 
 AdjLayout adj_layout(const gplbm_params* p) {
   AdjLayout l{};
   const int64_t N = (int64_t)p->nx * p->ny * p->nz;
-  const int Q = lattice_q(p->lattice);
-  l.pop = round_up((size_t)Q * N * 8);
+  l.pop = round_up((size_t)lattice_q(p->lattice) * N * 8);  // A1: g populations
+  l.hpop = round_up((size_t)lattice_qh(p) * N * 8);         // B1: h populations
   l.fld = round_up((size_t)N * 8);
   l.vec = round_up((size_t)3 * N * 8);
   l.red = round_up(sizeof(double) * (2 * kDiagBlocks + 2));
   // two sets (A1, B1, B2, B3, B4), A2..A4, two accumulators, reduction
-  l.total = 2 * (2 * l.pop + 2 * l.fld + l.vec) + (l.vec + 2 * l.fld) + 2 * l.fld + l.red;
+  l.total = 2 * (l.pop + l.hpop + 2 * l.fld + l.vec) + (l.vec + 2 * l.fld) + 2 * l.fld + l.red;
   return l;
 }
 
-template <class L, class S>
+template <class L, class LH, class S>
 struct AdjOps {
   static dim3 block() { return dim3(64, 4, 1); }
   static dim3 grid(const gplbm_ctx* ctx) {
@@ -713,7 +713,7 @@ struct AdjOps {
   }
   static int seed(gplbm_ctx* ctx, const double* phib, const double* cb) {
     const Geo g = make_geo(ctx->p);
-    hipLaunchKernelGGL((k_adj_seed<L>), grid(ctx), block(), 0, ctx->stream, g, phib, cb,
+    hipLaunchKernelGGL((k_adj_seed<L, LH>), grid(ctx), block(), 0, ctx->stream, g, phib, cb,
                        ctx->adj.set[ctx->adj_cur], ctx->adj);
     return check_launch(ctx, "adjoint seed");
   }
@@ -722,9 +722,9 @@ struct AdjOps {
     const Coef<double> K = make_coef<double>(ctx->p);
     const int a = ctx->adj_cur, b = 1 - a;
     const FwdState<S> S0 = fwd(ctx, s0), S1 = fwd(ctx, s1);
-    hipLaunchKernelGGL((k_adj_ra<L, S>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx),
+    hipLaunchKernelGGL((k_adj_ra<L, LH, S>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx),
                        S1, ctx->adj.set[a], ctx->adj.set[b], ctx->adj);
-    hipLaunchKernelGGL((k_adj_rb<L, S>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx),
+    hipLaunchKernelGGL((k_adj_rb<L, LH, S>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx),
                        S0, S1, ctx->adj.set[a], ctx->adj.set[b], ctx->adj);
     int rc = check_launch(ctx, "adjoint step");
     if (rc) return rc;
@@ -736,7 +736,7 @@ struct AdjOps {
     const Geo g = make_geo(ctx->p);
     const Coef<double> K = make_coef<double>(ctx->p);
     const int a = ctx->adj_cur, b = 1 - a;
-    hipLaunchKernelGGL((k_adj_init_a<L>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx),
+    hipLaunchKernelGGL((k_adj_init_a<L, LH>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx),
                        phi0, c0, ctx->adj.set[a], ctx->adj.set[b], ctx->adj, c0b);
     hipLaunchKernelGGL((k_adj_init_b<L>), grid(ctx), block(), 0, ctx->stream, g, ctx->adj.set[b],
                        phi0b);
@@ -748,34 +748,51 @@ struct AdjOps {
   }
 };
 
-template <template <class, class> class Fn, class... Args>
-int adj_dispatch(gplbm_ctx* ctx, Args... args) {
-  const bool f64 = ctx->p.precision == GPLBM_FP64;
-  if (ctx->p.lattice == GPLBM_D2Q9)
-    return f64 ? Fn<D2Q9, double>::run(ctx, args...) : Fn<D2Q9, float>::run(ctx, args...);
-  return f64 ? Fn<D3Q19, double>::run(ctx, args...) : Fn<D3Q19, float>::run(ctx, args...);
+template <template <class, class, class> class Fn, class L, class LH, class... Args>
+int adj_dispatch_prec(gplbm_ctx* ctx, Args... args) {
+  if (ctx->p.precision == GPLBM_FP64) return Fn<L, LH, double>::run(ctx, args...);
+  return Fn<L, LH, float>::run(ctx, args...);
 }
-template <class L, class S>
+
+template <template <class, class, class> class Fn, class... Args>
+int adj_dispatch(gplbm_ctx* ctx, Args... args) {
+  const bool light = ctx->p.h_lattice == GPLBM_H_LIGHT;
+  switch (ctx->p.lattice) {
+    case GPLBM_D2Q9:
+      return light ? adj_dispatch_prec<Fn, D2Q9, D2Q5>(ctx, args...)
+                   : adj_dispatch_prec<Fn, D2Q9, D2Q9>(ctx, args...);
+    case GPLBM_D3Q19:
+      return light ? adj_dispatch_prec<Fn, D3Q19, D3Q7>(ctx, args...)
+                   : adj_dispatch_prec<Fn, D3Q19, D3Q19>(ctx, args...);
+    case GPLBM_D2Q5:
+      return adj_dispatch_prec<Fn, D2Q5, D2Q5>(ctx, args...);
+    default:
+      return adj_dispatch_prec<Fn, D3Q7, D3Q7>(ctx, args...);
+  }
+}
+template <class L, class LH, class S>
 struct AdjSeedFn {
   static int run(gplbm_ctx* c, const double* a, const double* b) {
-    return AdjOps<L, S>::seed(c, a, b);
+    return AdjOps<L, LH, S>::seed(c, a, b);
   }
 };
-template <class L, class S>
+template <class L, class LH, class S>
 struct AdjStepFn {
-  static int run(gplbm_ctx* c, const void* a, const void* b) { return AdjOps<L, S>::step(c, a, b); }
+  static int run(gplbm_ctx* c, const void* a, const void* b) {
+    return AdjOps<L, LH, S>::step(c, a, b);
+  }
 };
-template <class L, class S>
+template <class L, class LH, class S>
 struct AdjFinishFn {
   static int run(gplbm_ctx* c, const double* a, const double* b, double* d, double* e) {
-    return AdjOps<L, S>::finish(c, a, b, d, e);
+    return AdjOps<L, LH, S>::finish(c, a, b, d, e);
   }
 };
 
-// The adjoint is written for h on the lattice of g with the source scheme and
-// equal curvatures, in FP64 or FP32.
+// The adjoint is written for the source scheme and equal curvatures, on every
+// lattice combination, in FP64 or FP32.
 bool adjoint_supported(const gplbm_params& p) {
-  return (p.precision == GPLBM_FP64 || p.precision == GPLBM_FP32) && !light_h(p) &&
+  return (p.precision == GPLBM_FP64 || p.precision == GPLBM_FP32) &&
          p.h_scheme == GPLBM_H_SOURCE && p.free_energy == GPLBM_FE_EQUAL;
 }
 
@@ -794,8 +811,8 @@ int gplbm_adjoint_begin(gplbm_ctx* ctx, void* work, uint64_t bytes, const double
   if (!ctx || !work || ((uintptr_t)work) % kAlign) return GPLBM_E_INVALID;
   if (!adjoint_supported(ctx->p))
     return fail(ctx, GPLBM_E_INVALID,
-                "adjoint needs an FP64 or FP32 context with h on the g lattice, the source "
-                "scheme and equal curvatures");
+                "adjoint needs an FP64 or FP32 context with the source scheme and equal "
+                "curvatures");
   const AdjLayout l = adj_layout(&ctx->p);
   if (bytes < l.total) return fail(ctx, GPLBM_E_SIZE, "adjoint workspace too small");
   if (int rc = use_device(ctx)) return rc;
@@ -803,7 +820,7 @@ int gplbm_adjoint_begin(gplbm_ctx* ctx, void* work, uint64_t bytes, const double
   AdjWork& w = ctx->adj;
   for (int a = 0; a < 2; ++a) {
     w.set[a].A1 = (double*)b; b += l.pop;
-    w.set[a].B1 = (double*)b; b += l.pop;
+    w.set[a].B1 = (double*)b; b += l.hpop;
     w.set[a].B2 = (double*)b; b += l.fld;
     w.set[a].B3 = (double*)b; b += l.vec;
     w.set[a].B4 = (double*)b; b += l.fld;

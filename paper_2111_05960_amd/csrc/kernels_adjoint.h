@@ -89,14 +89,14 @@ struct NodeFwd {
   double c, mu, phi, g[3], n[3], s;  // s = sqrt(|grad|^2 + eps^2)
 };
 
-template <class L, class S>
+template <class L, class LH, class S>
 __device__ __forceinline__ NodeFwd<L> node_fwd(const Geo& g, const Coef<double>& K, const FwdState<S>& F,
                                                int x, int y, int z) {
   NodeFwd<L> f;
   double c = 0.0;
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k) {
-    const double v = double(pull<L>(g, F.H, k, x, y, z));
+  for (int k = 0; k < LH::Q; ++k) {
+    const double v = double(pull<LH>(g, F.H, k, x, y, z));
     c = k == 0 ? v : c + v;
   }
   f.c = c;
@@ -163,7 +163,7 @@ __device__ __forceinline__ void normal_adj(const NodeFwd<L>& f, const double nb[
 
 // Gather of the transposed gradient stencil at node (x, y, z):
 // sum over k != rest and over the nodes q with stencil(q + e_k) = (x, y, z)
-// of 3 w_k e_k . gb(q).
+// of (1 / xi_s^2) w_k e_k . gb(q).
 __device__ __forceinline__ int preimage(int z, int e, int n, int bc, int out[2]) {
   if (!bc) {
     int v = z - e;
@@ -200,7 +200,7 @@ __device__ __forceinline__ double stencil_adj_gather(const Geo& g, const double*
         for (int c = 0; c < mz; ++c) {
           const int64_t q = node_index(g, px[a], py[b], pz[c]);
           const double e_g = edot<L, double>(k, gb3[q], gb3[g.N + q], L::D == 3 ? gb3[2 * g.N + q] : 0.0);
-          acc += 3.0 * L::w[k] * e_g;
+          acc += L::inv_cs2 * L::w[k] * e_g;
         }
   }
   return acc;
@@ -216,7 +216,7 @@ __device__ __forceinline__ double gather_Gb(const Geo& g, const AdjSet& P, int k
   return P.A1[pop_index<L>(g, kk, dx, dy, dz)] + P.B2[node_index(g, dx, dy, dz)];
 }
 
-template <class L, class S>
+template <class L, class LH, class S>
 __global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> K, double lam_M_W2,
                                                 FwdState<S> S1, AdjSet P, AdjSet C, AdjWork w) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -224,7 +224,7 @@ __global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> K, double la
   const int z = blockIdx.z;
   if (x >= g.nx || y >= g.ny) return;
   const int64_t i = node_index(g, x, y, z);
-  const NodeFwd<L> f = node_fwd<L, S>(g, K, S1, x, y, z);  // c^{n+1}, mu^{n+1}, ...
+  const NodeFwd<L> f = node_fwd<L, LH, S>(g, K, S1, x, y, z);  // c^{n+1}, mu^{n+1}, ...
   const double om = K.omega_g;
   double Gb[L::Q];
   double phi_b = 0.0, mu_b = 0.0, nb[3] = {0.0, 0.0, 0.0};
@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> K, double la
   w.lamb[i] += lb;
 }
 
-template <class L, class S>
+template <class L, class LH, class S>
 __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> K, double lam_M_W2,
                                                 FwdState<S> S0, FwdState<S> S1, AdjSet P, AdjSet C,
                                                 AdjWork w) {
@@ -258,38 +258,38 @@ __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> K, double la
   if (x >= g.nx || y >= g.ny) return;
   const int64_t i = node_index(g, x, y, z);
   // total adjoint of h~*^n in this node's slots
-  double Hb[L::Q];
+  double Hb[LH::Q];
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k) {
+  for (int k = 0; k < LH::Q; ++k) {
     int dx, dy, dz;
-    const int kk = push_dest<L>(g, k, x, y, z, dx, dy, dz);
-    Hb[k] = P.B1[pop_index<L>(g, kk, dx, dy, dz)] + w.A3[node_index(g, dx, dy, dz)];
+    const int kk = push_dest<LH>(g, k, x, y, z, dx, dy, dz);
+    Hb[k] = P.B1[pop_index<LH>(g, kk, dx, dy, dz)] + w.A3[node_index(g, dx, dy, dz)];
   }
   // adjoint of phi^{n+1} at this node (A2, A4 hold both collisions' parts)
   double p1b = w.A4[i] + stencil_adj_gather<L>(g, w.A2, x, y, z);
   // forward quantities of step n
-  const NodeFwd<L> f = node_fwd<L, S>(g, K, S0, x, y, z);
+  const NodeFwd<L> f = node_fwd<L, LH, S>(g, K, S0, x, y, z);
   const double phi1 = double(S1.PHI[i]);
   const double dtphi = phi1 - f.phi;
   const double oh = K.omega_h;
   const double Dp = K.Dp;
   const double D = (K.Dl * f.phi) + (K.Ds * (1.0 - f.phi));
   // reverse of h* = (1 - oh) h + oh heq + (1 - oh/2) H
-  double hb[L::Q];
+  double hb[LH::Q];
   double c_b = 0.0, lam_b = 0.0, Fb[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k) {
+  for (int k = 0; k < LH::Q; ++k) {
     hb[k] = (1.0 - oh) * Hb[k];
     const double heq_b = oh * Hb[k];
-    if (k == L::REST) {
+    if (k == LH::REST) {
       c_b += heq_b;
-      lam_b += -(1.0 - L::w[k]) * heq_b;
+      lam_b += -(1.0 - LH::w[k]) * heq_b;
     } else {
-      lam_b += L::w[k] * heq_b;
-      const double HHb = (1.0 - 0.5 * oh) * Hb[k] * (K.gamma * L::w[k]);
-      if (L::ex[k]) Fb[0] += (L::ex[k] > 0 ? HHb : -HHb);
-      if (L::ey[k]) Fb[1] += (L::ey[k] > 0 ? HHb : -HHb);
-      if (L::D == 3 && L::ez[k]) Fb[2] += (L::ez[k] > 0 ? HHb : -HHb);
+      lam_b += LH::w[k] * heq_b;
+      const double HHb = (1.0 - 0.5 * oh) * Hb[k] * (K.gamma * LH::w[k]);
+      if (LH::ex[k]) Fb[0] += (LH::ex[k] > 0 ? HHb : -HHb);
+      if (LH::ey[k]) Fb[1] += (LH::ey[k] > 0 ? HHb : -HHb);
+      if (LH::D == 3 && LH::ez[k]) Fb[2] += (LH::ez[k] > 0 ? HHb : -HHb);
     }
   }
   double mu_b = 0.0, phi_b = 0.0, dl_b = 0.0, gb[3] = {0.0, 0.0, 0.0}, nb[3] = {0.0, 0.0, 0.0};
@@ -317,7 +317,7 @@ __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> K, double la
   c_b += mu_b;
   phi_b += (K.cs - K.cl) * mu_b;
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k) C.B1[pop_index<L>(g, k, x, y, z)] = hb[k] + c_b;
+  for (int k = 0; k < LH::Q; ++k) C.B1[pop_index<LH>(g, k, x, y, z)] = hb[k] + c_b;
   C.B2[i] = p1b;
   for (int a = 0; a < 3; ++a) C.B3[a * g.N + i] = gb[a];
   C.B4[i] = phi_b;
@@ -328,7 +328,7 @@ __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> K, double la
 // Seed: the adjoint of S_K from dJ/dphi^K and dJ/dc^K (c^K = sum of the
 // pulled H), written as a set the first reverse step gathers from:
 // Gb = 0, Hb(slot) = dJ/dc^K(dest), Pb = dJ/dphi^K.
-template <class L>
+template <class L, class LH>
 __global__ void __launch_bounds__(256) k_adj_seed(Geo g, const double* __restrict__ phib,
                                                   const double* __restrict__ cb, AdjSet P, AdjWork w) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -338,10 +338,9 @@ __global__ void __launch_bounds__(256) k_adj_seed(Geo g, const double* __restric
   const int64_t i = node_index(g, x, y, z);
   const double cv = cb ? cb[i] : 0.0;
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k) {
-    P.A1[pop_index<L>(g, k, x, y, z)] = 0.0;
-    P.B1[pop_index<L>(g, k, x, y, z)] = cv;
-  }
+  for (int k = 0; k < L::Q; ++k) P.A1[pop_index<L>(g, k, x, y, z)] = 0.0;
+#pragma unroll
+  for (int k = 0; k < LH::Q; ++k) P.B1[pop_index<LH>(g, k, x, y, z)] = cv;
   P.B2[i] = 0.0;
   for (int a = 0; a < 3; ++a) P.B3[a * g.N + i] = 0.0;
   P.B4[i] = phib ? phib[i] : 0.0;
@@ -352,7 +351,7 @@ __global__ void __launch_bounds__(256) k_adj_seed(Geo g, const double* __restric
 // Adjoint of the initialisation (phi0, c0) -> S_0, local part: writes the
 // adjoint of c0 and, in B4 / B3, the local part of the adjoint of phi0 and the
 // adjoint of grad phi0.
-template <class L>
+template <class L, class LH>
 __global__ void __launch_bounds__(256) k_adj_init_a(Geo g, Coef<double> K, double lam_M_W2,
                                                     const double* __restrict__ phi0,
                                                     const double* __restrict__ c0, AdjSet P,
@@ -378,20 +377,21 @@ __global__ void __launch_bounds__(256) k_adj_init_a(Geo g, Coef<double> K, doubl
   const double lam = h_lambda<double>(K, phi, mu0);
   double c = 0.0;
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k) {
-    const double hv = h_eq<L, double>(k, cin, lam) - 0.5 * h_source<L, double>(K, k, F);
+  for (int k = 0; k < LH::Q; ++k) {
+    const double hv = h_eq<LH, double>(k, cin, lam) - 0.5 * h_source<LH, double>(K, k, F);
     c = k == 0 ? hv : c + hv;
   }
   const double mu = closure(K.cl, K.cs, K.mueq, c, phi);
   // adjoints of the pulled h~^0 (from H of S_0) and of G of S_0
-  double hb[L::Q], Gb[L::Q], g0b[L::Q];
+  double hb[LH::Q], Gb[L::Q], g0b[L::Q];
   double phi_b = P.B4[i] + stencil_adj_gather<L>(g, P.B3, x, y, z);
   double mu_b = 0.0, mu0_b = 0.0, nb[3] = {0.0, 0.0, 0.0};
   double lb = 0.0;
   const double om = K.omega_g;
 #pragma unroll
+  for (int k = 0; k < LH::Q; ++k) hb[k] = P.B1[pop_index<LH>(g, k, x, y, z)];  // gathered Hb
+#pragma unroll
   for (int k = 0; k < L::Q; ++k) {
-    hb[k] = P.B1[pop_index<L>(g, k, x, y, z)];  // pull of the gathered Hb
     const double gsb = gather_Gb<L>(g, P, k, x, y, z);
     g0b[k] = (1.0 - om) * gsb;
     Gb[k] = (1.0 - 0.5 * om) * gsb;
@@ -412,17 +412,17 @@ __global__ void __launch_bounds__(256) k_adj_init_a(Geo g, Coef<double> K, doubl
   // h~^0 = heq(c0, Lambda0) - H^0 / 2
   double cin_b = 0.0, lam_b = 0.0, Fb[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k) {
+  for (int k = 0; k < LH::Q; ++k) {
     const double hk = hb[k] + c_b;
-    if (k == L::REST) {
+    if (k == LH::REST) {
       cin_b += hk;
-      lam_b += -(1.0 - L::w[k]) * hk;
+      lam_b += -(1.0 - LH::w[k]) * hk;
     } else {
-      lam_b += L::w[k] * hk;
-      const double HHb = -0.5 * hk * (K.gamma * L::w[k]);
-      if (L::ex[k]) Fb[0] += (L::ex[k] > 0 ? HHb : -HHb);
-      if (L::ey[k]) Fb[1] += (L::ey[k] > 0 ? HHb : -HHb);
-      if (L::D == 3 && L::ez[k]) Fb[2] += (L::ez[k] > 0 ? HHb : -HHb);
+      lam_b += LH::w[k] * hk;
+      const double HHb = -0.5 * hk * (K.gamma * LH::w[k]);
+      if (LH::ex[k]) Fb[0] += (LH::ex[k] > 0 ? HHb : -HHb);
+      if (LH::ey[k]) Fb[1] += (LH::ey[k] > 0 ? HHb : -HHb);
+      if (LH::D == 3 && LH::ez[k]) Fb[2] += (LH::ez[k] > 0 ? HHb : -HHb);
     }
   }
   const double D = (K.Dl * phi) + (K.Ds * (1.0 - phi));

@@ -5,8 +5,9 @@ with sqrt(K) checkpointing) against
     (pinned to the C oracle) differentiated by autograd, for a linear
     objective sum(a phi^K) + sum(b c^K) with seeded weights, on small grids
     covering both lattices, walls and periodic axes, counter term and
-    anti-trapping on and off: relative agreement 1e-9 (same derivative,
-    different summation orders, ~1e3 operations deep);
+    anti-trapping on and off, h on D2Q5 / D3Q7 and g and h on them: relative
+    agreement 1e-9 (same derivative, different summation orders, ~1e3
+    operations deep);
   - central finite differences of the GPU forward (h = 1e-6) for the two
     objectives of the differentiation workload, J1 (final solid fraction) and
     J2 (mean recession distance), with respect to lambda, D_l and a seeded
@@ -35,26 +36,33 @@ def _rel(a, b):
 
 
 CASES = [
-    (0, (1, 20, 26), (0, 0, 0), 1, 1),
-    (0, (1, 17, 23), (1, 0, 0), 1, 1),
-    (0, (1, 16, 18), (1, 1, 0), 0, 1),
-    (0, (1, 15, 21), (0, 1, 0), 1, 0),
-    (1, (8, 9, 10), (0, 0, 0), 1, 1),
-    (1, (7, 8, 9), (1, 0, 1), 0, 1),
+    # lattice, shape, bc, counter term, anti-trapping, h on the light lattice
+    (0, (1, 20, 26), (0, 0, 0), 1, 1, 0),
+    (0, (1, 17, 23), (1, 0, 0), 1, 1, 0),
+    (0, (1, 16, 18), (1, 1, 0), 0, 1, 0),
+    (0, (1, 15, 21), (0, 1, 0), 1, 0, 0),
+    (1, (8, 9, 10), (0, 0, 0), 1, 1, 0),
+    (1, (7, 8, 9), (1, 0, 1), 0, 1, 0),
+    (0, (1, 17, 23), (1, 0, 0), 1, 1, 1),
+    (1, (8, 9, 10), (0, 1, 0), 1, 1, 1),
+    (2, (1, 16, 18), (1, 1, 0), 1, 1, 0),
+    (3, (7, 8, 9), (1, 0, 1), 0, 1, 0),
 ]
 
 
 @pytest.mark.parametrize("case", CASES)
 def test_adjoint_matches_oracle_autograd(adj, case):
     from oracle import torch_step as ts
-    lattice, shape, bc, ct, at = case
-    p = wl.base_params(lattice=lattice, shape=shape, bc=bc, counter_term=ct, anti_trapping=at)
+    lattice, shape, bc, ct, at, hl = case
+    p = wl.base_params(lattice=lattice, shape=shape, bc=bc, counter_term=ct, anti_trapping=at,
+                       h_lattice=hl)
     phi0, c0 = wl.random_state_fields(shape, seed=31)
     rng = np.random.default_rng(32)
     a = rng.standard_normal(shape)
     b = rng.standard_normal(shape)
     K = 7
-    print(f"adjoint case lattice={lattice} shape={shape} bc={bc} ct={ct} at={at} K={K}", flush=True)
+    print(f"adjoint case lattice={lattice} shape={shape} bc={bc} ct={ct} at={at} hl={hl} K={K}",
+          flush=True)
     # oracle adjoint (CPU autograd)
     t_phi0 = torch.tensor(phi0.ravel(), requires_grad=True)
     t_c0 = torch.tensor(c0.ravel(), requires_grad=True)

@@ -77,13 +77,20 @@ def test_light_h_rejected_with_deviation_storage(lib, prec):
     assert e.value.code == B.GPLBM_E_INVALID
 
 
-def test_adjoint_rejects_light_h(lib):
-    cp = B.make_params(wl.base_params(lattice=wl.D3Q19, shape=(8, 8, 8), bc=(0, 0, 0),
-                                      h_lattice=1), "fp64")
+def test_adjoint_workspace_light_h(lib):
+    """With h on D3Q7 the adjoint of the h populations (B1) holds 7 values
+    per node, the adjoint of the g populations (A1) 19."""
+    shape = (8, 8, 8)
+    n = 8 * 8 * 8
+    rnd = lambda v: (v + 255) // 256 * 256
     out = ctypes.c_uint64()
-    assert lib.gplbm_adjoint_bytes(ctypes.byref(cp), ctypes.byref(out)) == B.GPLBM_E_INVALID
-    cp.h_lattice = 0
-    assert lib.gplbm_adjoint_bytes(ctypes.byref(cp), ctypes.byref(out)) == B.GPLBM_OK
+    full = B.make_params(wl.base_params(lattice=wl.D3Q19, shape=shape, bc=(0, 0, 0)), "fp64")
+    light = B.make_params(wl.base_params(lattice=wl.D3Q19, shape=shape, bc=(0, 0, 0),
+                                         h_lattice=1), "fp64")
+    assert lib.gplbm_adjoint_bytes(ctypes.byref(full), ctypes.byref(out)) == B.GPLBM_OK
+    bf = out.value
+    assert lib.gplbm_adjoint_bytes(ctypes.byref(light), ctypes.byref(out)) == B.GPLBM_OK
+    assert bf - out.value == 2 * (rnd(19 * n * 8) - rnd(7 * n * 8))
 
 
 @pytest.mark.parametrize("field,value", [
@@ -161,7 +168,7 @@ def test_state_bytes_layout_light_g(lib, lattice, shape, q):
     cp = B.make_params(p, "fp64")
     assert B.gplbm_checkpoint_bytes(cp) == 2 * rnd(q * n * 8) + rnd(n * 8)
     out = ctypes.c_uint64()
-    assert lib.gplbm_adjoint_bytes(ctypes.byref(cp), ctypes.byref(out)) == B.GPLBM_E_INVALID
+    assert lib.gplbm_adjoint_bytes(ctypes.byref(cp), ctypes.byref(out)) == B.GPLBM_OK
     for prec in ("fp16dev", "bf16dev"):
         with pytest.raises(B.GplbmError):
             B.gplbm_state_bytes(B.make_params(p, prec))

@@ -9,15 +9,22 @@ import workloads as wl
 from oracle import torch_step as ts
 
 
-@pytest.mark.parametrize("lattice,shape,bc,ct,at", [
-    (0, (1, 20, 30), (1, 0, 0), 1, 1),
-    (0, (1, 17, 23), (0, 0, 0), 0, 1),
-    (0, (1, 12, 14), (1, 1, 0), 1, 0),
-    (1, (8, 9, 10), (1, 0, 1), 1, 1),
-    (1, (7, 8, 9), (0, 0, 0), 0, 0),
+@pytest.mark.parametrize("lattice,shape,bc,ct,at,hl", [
+    (0, (1, 20, 30), (1, 0, 0), 1, 1, 0),
+    (0, (1, 17, 23), (0, 0, 0), 0, 1, 0),
+    (0, (1, 12, 14), (1, 1, 0), 1, 0, 0),
+    (1, (8, 9, 10), (1, 0, 1), 1, 1, 0),
+    (1, (7, 8, 9), (0, 0, 0), 0, 0, 0),
+    (0, (1, 20, 30), (1, 0, 0), 1, 1, 1),
+    (1, (8, 9, 10), (1, 0, 1), 1, 1, 1),
+    (2, (1, 17, 23), (1, 1, 0), 1, 1, 0),
+    (3, (8, 9, 10), (0, 1, 0), 0, 1, 0),
 ])
-def test_torch_restatement_equals_c_oracle(oracle_mod, lattice, shape, bc, ct, at):
-    p = wl.base_params(lattice=lattice, shape=shape, bc=bc, counter_term=ct, anti_trapping=at)
+def test_torch_restatement_equals_c_oracle(oracle_mod, lattice, shape, bc, ct, at, hl):
+    """Also with h on D2Q5 / D3Q7 (hl = 1) and with g and h on them
+    (lattice 2, 3)."""
+    p = wl.base_params(lattice=lattice, shape=shape, bc=bc, counter_term=ct, anti_trapping=at,
+                       h_lattice=hl)
     phi0, c0 = wl.random_state_fields(shape, seed=4)
     o = oracle_mod.Oracle(p).init(phi0, c0).step(25)
     phiK, cK = ts.run(p, torch.from_numpy(phi0.ravel()), torch.from_numpy(c0.ravel()), 25)
@@ -26,9 +33,12 @@ def test_torch_restatement_equals_c_oracle(oracle_mod, lattice, shape, bc, ct, a
     assert np.max(np.abs(cK.numpy() - c.ravel())) < 1e-13
 
 
-@pytest.mark.parametrize("lattice,shape,bc", [(0, (1, 14, 16), (1, 0, 0)), (1, (6, 7, 8), (0, 0, 0))])
-def test_torch_adjoint_matches_finite_differences(lattice, shape, bc):
-    p = wl.base_params(lattice=lattice, shape=shape, bc=bc)
+@pytest.mark.parametrize("lattice,shape,bc,hl", [(0, (1, 14, 16), (1, 0, 0), 0),
+                                                (1, (6, 7, 8), (0, 0, 0), 0),
+                                                (1, (6, 7, 8), (1, 0, 0), 1),
+                                                (3, (6, 7, 8), (0, 0, 1), 0)])
+def test_torch_adjoint_matches_finite_differences(lattice, shape, bc, hl):
+    p = wl.base_params(lattice=lattice, shape=shape, bc=bc, h_lattice=hl)
     phi0, c0 = wl.random_state_fields(shape, seed=8)
     K = 10
     t_lam = torch.tensor(p["lam"], dtype=torch.float64, requires_grad=True)
