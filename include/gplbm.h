@@ -78,7 +78,7 @@ extern "C" {
  * flux F = mu D' grad phi + j_at folded into the moving populations of the
  * equilibrium, w_k (gamma D mu + e_k . F / xi_s^2), no source; the initial
  * populations are that equilibrium (no variable-change shift).  FP64 and
- * FP32 only; no adjoint. */
+ * FP32 only (the adjoint included). */
 #define GPLBM_H_SOURCE 0
 #define GPLBM_H_EQ_ALT 1
 
@@ -89,7 +89,8 @@ extern "C" {
  * eps_s != eps_l, parameterised by eps_s, eps_l, m_s, m_l, df_min (closure
  * Eq. (Closure), source Eq. (SourceTerm), anti-trapping
  * Eq. (Anti-Trapping_Quadratic)), with the interpolations h(phi) = phi,
- * q(phi) and a of the equal case.  FP64 and FP32 only; no adjoint. */
+ * q(phi) and a of the equal case.  FP64 and FP32 only (the adjoint
+ * included). */
 #define GPLBM_FE_EQUAL 0
 #define GPLBM_FE_QUADRATIC 1
 
@@ -225,8 +226,9 @@ int gplbm_load_state(gplbm_ctx* ctx, const void* dev_src, int64_t step);
  *   writes dJ/dphi0 and dJ/dc0 (device, N doubles) and dJ/dlambda, dJ/dD_l into
  *   dJ_dparams (host, 2 doubles).  Parameter sums are reduced in a fixed
  *   order.  Synchronises the stream.
- * Every lattice combination is supported.  Return GPLBM_E_INVALID for
- * FP16/BF16-deviation contexts, GPLBM_H_EQ_ALT or GPLBM_FE_QUADRATIC, or null
+ * Every lattice combination, both h schemes and both free-energy forms are
+ * supported (the quadratic constants eps_s, eps_l, m_s, m_l, df_min held
+ * fixed).  Return GPLBM_E_INVALID for FP16/BF16-deviation contexts or null
  * pointers, GPLBM_E_SIZE for a short workspace, GPLBM_E_STATE out of
  * order. */
 int gplbm_adjoint_bytes(const gplbm_params* p, uint64_t* bytes);

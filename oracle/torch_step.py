@@ -123,10 +123,30 @@ def gradient_normal(L, phi, eps_n):
     return g, g / den
 
 
+def _quadratic(P):
+    return int(P.get("free_energy", 0)) == 1
+
+
+def coupling(P, mu):
+    """S_phi / p'(phi): dc (mu - mu_eq), or for general quadratic free
+    energies ((eps_l - eps_s)/sqrt(eps_l eps_s)) mu^2/2 - (m_l - m_s) mu - df_min."""
+    if _quadratic(P):
+        k2 = (P["eps_l"] - P["eps_s"]) / math.sqrt(P["eps_l"] * P["eps_s"])
+        return (k2 * mu * mu) * 0.5 - (P["m_l"] - P["m_s"]) * mu - P["df_min"]
+    return (P["c_s_co"] - P["c_l_co"]) * (mu - P["mu_eq"])
+
+
+def at_jump(P, mu):
+    """Composition jump of the anti-trapping current."""
+    if _quadratic(P):
+        ks = -((P["eps_s"] - P["eps_l"]) / math.sqrt(P["eps_s"] * P["eps_l"]))
+        return ks * mu + P["m_s"] - P["m_l"]
+    return P["c_s_co"] - P["c_l_co"]
+
+
 def sources(L, P, phi, mu, n):
-    dc = P["c_s_co"] - P["c_l_co"]
     pp = phi * (1.0 - phi)
-    Gst = -((P["lam"] * P["M_phi"]) / (P["W"] * P["W"])) * ((6.0 * pp * dc) * (mu - P["mu_eq"]))
+    Gst = -((P["lam"] * P["M_phi"]) / (P["W"] * P["W"])) * ((6.0 * pp) * coupling(P, mu))
     if P["counter_term"]:
         kphi = (4.0 / P["W"]) * pp
         G = torch.stack([float(L.w[k]) * (Gst + kphi * _edot(L, k, n)) for k in range(L.Q)])
@@ -137,14 +157,30 @@ def sources(L, P, phi, mu, n):
 
 
 def closure(P, c, phi):
+    if _quadratic(P):
+        fac = math.sqrt(P["eps_s"] * P["eps_l"]) / (P["eps_s"] * phi + P["eps_l"] * (1.0 - phi))
+        return fac * (c - phi * P["m_l"] - (1.0 - phi) * P["m_s"])
     return P["mu_eq"] + (c - (P["c_l_co"] * phi + P["c_s_co"] * (1.0 - phi)))
 
 
 def h_parts(L, P, c, phi, mu, F):
+    """Equilibrium and source of h.  With h^eq,alt (h_scheme = 1) the flux is
+    folded into the moving populations, w_k (Lambda + e_k . F / xi_s^2), and
+    the source is zero."""
     D = P["D_l"] * phi + P["D_s"] * (1.0 - phi)
     lam_ = (P["gamma"] * D) * mu
-    heq = torch.stack([c - (1.0 - float(L.w[k])) * lam_ if k == L.rest else float(L.w[k]) * lam_
-                       for k in range(L.Q)])
+    alt = int(P.get("h_scheme", 0)) == 1
+    heq = []
+    for k in range(L.Q):
+        if k == L.rest:
+            heq.append(c - (1.0 - float(L.w[k])) * lam_)
+        elif alt:
+            heq.append(float(L.w[k]) * (lam_ + _edot(L, k, F) / L.cs2))
+        else:
+            heq.append(float(L.w[k]) * lam_)
+    heq = torch.stack(heq)
+    if alt:
+        return heq, torch.zeros_like(heq)
     H = torch.stack([(P["gamma"] * float(L.w[k])) * _edot(L, k, F) for k in range(L.Q)])
     return heq, H
 
@@ -168,7 +204,6 @@ def step(L, Lh, P, g, h, phi):
     Q, N = L.Q, L.N
     omega_g = 1.0 / (L.inv_cs2 * P["M_phi"] + 0.5)
     omega_h = 1.0 / (1.0 / (P["gamma"] * Lh.cs2) + 0.5)
-    dc = P["c_s_co"] - P["c_l_co"]
     c = h.sum(0)
     mu = closure(P, c, phi)
     gr, n = gradient_normal(L, phi, P["eps_n"])
@@ -178,7 +213,8 @@ def step(L, Lh, P, g, h, phi):
     phi1 = g1.sum(0) + 0.5 * sbar
     F = (mu * (P["D_l"] - P["D_s"]))[None, :] * gr
     if P["anti_trapping"]:
-        F = F + ((P["a_at"] * P["W"]) * dc) * (phi1 - phi)[None, :] * n
+        jat = ((P["a_at"] * P["W"]) * at_jump(P, mu)) * (phi1 - phi)
+        F = F + jat[None, :] * n
     heq, H = h_parts(Lh, P, c, phi, mu, F)
     hs = h - omega_h * ((h - heq) + 0.5 * H) + H
     h1 = hs.reshape(-1)[Lh.stream_src].reshape(Lh.Q, N)

@@ -789,11 +789,10 @@ struct AdjFinishFn {
   }
 };
 
-// The adjoint is written for the source scheme and equal curvatures, on every
+// The adjoint covers both h schemes, both free-energy forms and every
 // lattice combination, in FP64 or FP32.
 bool adjoint_supported(const gplbm_params& p) {
-  return (p.precision == GPLBM_FP64 || p.precision == GPLBM_FP32) &&
-         p.h_scheme == GPLBM_H_SOURCE && p.free_energy == GPLBM_FE_EQUAL;
+  return p.precision == GPLBM_FP64 || p.precision == GPLBM_FP32;
 }
 
 }  // namespace

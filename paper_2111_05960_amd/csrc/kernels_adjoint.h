@@ -101,12 +101,43 @@ __device__ __forceinline__ NodeFwd<L> node_fwd(const Geo& g, const Coef<double>&
   }
   f.c = c;
   f.phi = double(F.PHI[node_index(g, x, y, z)]);
-  f.mu = closure(K.cl, K.cs, K.mueq, c, f.phi);
+  f.mu = closure(K.q, c, f.phi);
   gradient_normal<L, double>(GlobalPhi<S, double>{g, F.PHI, x, y, z}, K.eps2, f.g, f.n);
   double nn = f.g[0] * f.g[0] + f.g[1] * f.g[1];
   if (L::D == 3) nn = nn + f.g[2] * f.g[2];
   f.s = sqrt(nn + K.eps2);
   return f;
+}
+
+// Derivatives of the closure mu(c, phi): 1 and c_s - c_l for equal
+// curvatures; for general quadratic free energies, with
+// mu = fac (c - phi m_l - (1 - phi) m_s), fac = E / (eps_s phi + eps_l (1 - phi)):
+// d mu / dc = fac, d mu / dphi = -fac (eps_s - eps_l) / den r + fac (m_s - m_l).
+__device__ __forceinline__ void closure_grad(const Coef<double>& K, double c, double phi,
+                                             double& dmu_dc, double& dmu_dphi) {
+  if (K.q.quad) {
+    const double den = (K.q.eps_s * phi) + (K.q.eps_l * (1.0 - phi));
+    const double fac = K.q.efac / den;
+    const double r = (c - phi * K.q.m_l) - (1.0 - phi) * K.q.m_s;
+    dmu_dc = fac;
+    dmu_dphi = -fac * (K.q.eps_s - K.q.eps_l) / den * r + fac * (K.q.m_s - K.q.m_l);
+  } else {
+    dmu_dc = 1.0;
+    dmu_dphi = K.cs - K.cl;
+  }
+}
+
+// Bracket B(mu) of S_phi = p'(phi) B and its slope B'(mu): dc (mu - mu_eq) and
+// dc, or k2 mu^2 / 2 - (m_l - m_s) mu - df_min and k2 mu - (m_l - m_s).
+__device__ __forceinline__ void bracket_and_slope(const Coef<double>& K, double mu, double& B,
+                                                  double& Bp) {
+  if (K.fe_quad) {
+    B = ((K.k2 * (mu * mu)) * 0.5 - (K.dml * mu)) - K.dfm;
+    Bp = K.k2 * mu - K.dml;
+  } else {
+    B = K.dc * (mu - K.mueq_c);
+    Bp = K.dc;
+  }
 }
 
 // Adjoint of the phi sources G_k (given their adjoints Gb_k) and of the
@@ -143,9 +174,11 @@ __device__ __forceinline__ double sources_adj(const Coef<double>& K, double lam_
     Gst_b += s;
     Gdw_b = s + sbar_b;
   }
-  const double Sphi = (6.0 * pp * K.dc) * (mu - K.mueq_c);
-  double pp_b = (K.kst * 6.0 * K.dc * (mu - K.mueq_c)) * Gst_b + K.k4w * kphi_b;
-  mu_b += (K.kst * 6.0 * pp * K.dc) * Gst_b;
+  double B, Bp;
+  bracket_and_slope(K, mu, B, Bp);
+  const double Sphi = (6.0 * pp) * B;
+  double pp_b = (K.kst * 6.0 * B) * Gst_b + K.k4w * kphi_b;
+  mu_b += (K.kst * 6.0 * pp * Bp) * Gst_b;
   if (!K.counter_term) {
     pp_b += K.kdw * 2.0 * (1.0 - 2.0 * phi) * Gdw_b;
     phi_b += K.kdw * 2.0 * pp * (-2.0) * Gdw_b;
@@ -242,8 +275,10 @@ __global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> K, double la
   // and phi^{n+1}: their adjoints are added here, so that rb applies the
   // transposed stencil once
   for (int a = 0; a < L::D; ++a) w.A2[a * g.N + i] = gb[a] + P.B3[a * g.N + i];
-  w.A3[i] = mu_b;                      // adjoint of c^{n+1}
-  phi_b += (K.cs - K.cl) * mu_b;       // closure
+  double dmu_dc, dmu_dphi;
+  closure_grad(K, f.c, f.phi, dmu_dc, dmu_dphi);
+  w.A3[i] = dmu_dc * mu_b;             // adjoint of c^{n+1}
+  phi_b += dmu_dphi * mu_b;            // closure
   w.A4[i] = phi_b + P.B4[i];
   w.lamb[i] += lb;
 }
@@ -286,7 +321,10 @@ __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> K, double la
       lam_b += -(1.0 - LH::w[k]) * heq_b;
     } else {
       lam_b += LH::w[k] * heq_b;
-      const double HHb = (1.0 - 0.5 * oh) * Hb[k] * (K.gamma * LH::w[k]);
+      // the flux enters through H_k = gamma w_k e_k.F (source scheme) or
+      // through h^eq,alt_k = w_k (Lambda + e_k.F / xi_s^2)
+      const double HHb = K.h_alt ? heq_b * (LH::w[k] * LH::inv_cs2)
+                                 : (1.0 - 0.5 * oh) * Hb[k] * (K.gamma * LH::w[k]);
       if (LH::ex[k]) Fb[0] += (LH::ex[k] > 0 ? HHb : -HHb);
       if (LH::ey[k]) Fb[1] += (LH::ey[k] > 0 ? HHb : -HHb);
       if (LH::D == 3 && LH::ez[k]) Fb[2] += (LH::ez[k] > 0 ? HHb : -HHb);
@@ -305,8 +343,11 @@ __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> K, double la
   for (int a = 0; a < L::D; ++a) gb[a] += f.mu * Dp * Fb[a];
   if (K.anti_trapping) {
     const double nF = f.n[0] * Fb[0] + f.n[1] * Fb[1] + (L::D == 3 ? f.n[2] * Fb[2] : 0.0);
-    const double dt_b = K.jfac * nF;
-    for (int a = 0; a < L::D; ++a) nb[a] += K.jfac * dtphi * Fb[a];
+    // j_at = jf dphi/dt n, jf = a W dc, or a W (ks mu + m_s - m_l)
+    const double jf = K.fe_quad ? K.aW * ((K.ks * f.mu + K.ms) - K.ml) : K.jfac;
+    const double dt_b = jf * nF;
+    for (int a = 0; a < L::D; ++a) nb[a] += jf * dtphi * Fb[a];
+    if (K.fe_quad) mu_b += K.aW * K.ks * dtphi * nF;
     p1b += dt_b;
     phi_b -= dt_b;
   }
@@ -314,8 +355,12 @@ __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> K, double la
   const double lb = sources_adj<L>(K, lam_M_W2, f.phi, f.mu, f.n, nullptr, 0.5 * p1b, phi_b, mu_b, nb);
   normal_adj<L>(f, nb, gb);
   // closure and c^n = sum h~^n
-  c_b += mu_b;
-  phi_b += (K.cs - K.cl) * mu_b;
+  {
+    double dmu_dc, dmu_dphi;
+    closure_grad(K, f.c, f.phi, dmu_dc, dmu_dphi);
+    c_b += dmu_dc * mu_b;
+    phi_b += dmu_dphi * mu_b;
+  }
 #pragma unroll
   for (int k = 0; k < LH::Q; ++k) C.B1[pop_index<LH>(g, k, x, y, z)] = hb[k] + c_b;
   C.B2[i] = p1b;
@@ -370,7 +415,7 @@ __global__ void __launch_bounds__(256) k_adj_init_a(Geo g, Coef<double> K, doubl
     if (L::D == 3) nn = nn + f.g[2] * f.g[2];
     f.s = sqrt(nn + K.eps2);
   }
-  const double mu0 = closure(K.cl, K.cs, K.mueq, cin, phi);
+  const double mu0 = closure(K.q, cin, phi);
   // forward h~^0 and c^0
   double F[3];
   h_flux<L, double>(K, mu0, f.g, f.n, 0.0, false, F);
@@ -378,10 +423,10 @@ __global__ void __launch_bounds__(256) k_adj_init_a(Geo g, Coef<double> K, doubl
   double c = 0.0;
 #pragma unroll
   for (int k = 0; k < LH::Q; ++k) {
-    const double hv = h_eq<LH, double>(k, cin, lam) - 0.5 * h_source<LH, double>(K, k, F);
+    const double hv = h_initial<LH, double>(K, k, cin, lam, F);
     c = k == 0 ? hv : c + hv;
   }
-  const double mu = closure(K.cl, K.cs, K.mueq, c, phi);
+  const double mu = closure(K.q, c, phi);
   // adjoints of the pulled h~^0 (from H of S_0) and of G of S_0
   double hb[LH::Q], Gb[L::Q], g0b[L::Q];
   double phi_b = P.B4[i] + stencil_adj_gather<L>(g, P.B3, x, y, z);
@@ -399,8 +444,10 @@ __global__ void __launch_bounds__(256) k_adj_init_a(Geo g, Coef<double> K, doubl
   }
   // g collision at time 0 (sources at phi, mu(c^0), n)
   lb += sources_adj<L>(K, lam_M_W2, phi, mu, f.n, Gb, 0.0, phi_b, mu_b, nb);
-  const double c_b = mu_b;  // c^0 = sum h~^0
-  phi_b += (K.cs - K.cl) * mu_b;
+  double dmu_dc, dmu_dphi;
+  closure_grad(K, c, phi, dmu_dc, dmu_dphi);
+  const double c_b = dmu_dc * mu_b;  // c^0 = sum h~^0
+  phi_b += dmu_dphi * mu_b;
   // g~^0 = w phi - G^0 / 2
   double G0b[L::Q];
 #pragma unroll
@@ -419,7 +466,8 @@ __global__ void __launch_bounds__(256) k_adj_init_a(Geo g, Coef<double> K, doubl
       lam_b += -(1.0 - LH::w[k]) * hk;
     } else {
       lam_b += LH::w[k] * hk;
-      const double HHb = -0.5 * hk * (K.gamma * LH::w[k]);
+      // h~^0 = h^eq - H/2, or h^eq,alt
+      const double HHb = K.h_alt ? hk * (LH::w[k] * LH::inv_cs2) : -0.5 * hk * (K.gamma * LH::w[k]);
       if (LH::ex[k]) Fb[0] += (LH::ex[k] > 0 ? HHb : -HHb);
       if (LH::ey[k]) Fb[1] += (LH::ey[k] > 0 ? HHb : -HHb);
       if (LH::D == 3 && LH::ez[k]) Fb[2] += (LH::ez[k] > 0 ? HHb : -HHb);
@@ -437,8 +485,9 @@ __global__ void __launch_bounds__(256) k_adj_init_a(Geo g, Coef<double> K, doubl
   for (int d = 0; d < L::D; ++d) gb[d] += mu0 * K.Dp * Fb[d];
   normal_adj<L>(f, nb, gb);
   // mu0 = closure(c0, phi0)
-  cin_b += mu0_b;
-  phi_b += (K.cs - K.cl) * mu0_b;
+  closure_grad(K, cin, phi, dmu_dc, dmu_dphi);
+  cin_b += dmu_dc * mu0_b;
+  phi_b += dmu_dphi * mu0_b;
   c0b[i] = cin_b;
   C.B4[i] = phi_b;
   for (int d = 0; d < 3; ++d) C.B3[d * g.N + i] = gb[d];

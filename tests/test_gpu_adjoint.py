@@ -5,7 +5,9 @@ with sqrt(K) checkpointing) against
     (pinned to the C oracle) differentiated by autograd, for a linear
     objective sum(a phi^K) + sum(b c^K) with seeded weights, on small grids
     covering both lattices, walls and periodic axes, counter term and
-    anti-trapping on and off, h on D2Q5 / D3Q7 and g and h on them: relative
+    anti-trapping on and off, h on D2Q5 / D3Q7 and g and h on them, h^eq,alt
+    (Eqs. LBE_Concent_Alt, Seq_Concent_Alt) and general quadratic free
+    energies (Eqs. Closure, SourceTerm, Anti-Trapping_Quadratic): relative
     agreement 1e-9 (same derivative, different summation orders, ~1e3
     operations deep);
   - central finite differences of the GPU forward (h = 1e-6) for the two
@@ -35,8 +37,28 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
+# general quadratic free energies for the variant cases: eps_l / eps_s = 2.3
+QUAD = dict(free_energy=1, eps_s=1.0, eps_l=2.3, m_s=0.9, m_l=0.12, df_min=0.02)
+
+
+def _variant(v):
+    """h_lattice as an int, or a variant name: alt (h^eq,alt), quad, alt+quad;
+    gamma=6 keeps the light-lattice rest equilibrium of h positive under the
+    quadratic closure."""
+    if not isinstance(v, str):
+        return {"h_lattice": v}
+    over = {}
+    if "alt" in v:
+        over["h_scheme"] = 1
+    if "quad" in v:
+        over.update(QUAD)
+    if "gamma6" in v:
+        over["gamma"] = 6.0
+    return over
+
+
 CASES = [
-    # lattice, shape, bc, counter term, anti-trapping, h on the light lattice
+    # lattice, shape, bc, counter term, anti-trapping, h lattice or variant
     (0, (1, 20, 26), (0, 0, 0), 1, 1, 0),
     (0, (1, 17, 23), (1, 0, 0), 1, 1, 0),
     (0, (1, 16, 18), (1, 1, 0), 0, 1, 0),
@@ -47,6 +69,12 @@ CASES = [
     (1, (8, 9, 10), (0, 1, 0), 1, 1, 1),
     (2, (1, 16, 18), (1, 1, 0), 1, 1, 0),
     (3, (7, 8, 9), (1, 0, 1), 0, 1, 0),
+    (0, (1, 17, 23), (1, 0, 0), 1, 1, "alt"),
+    (1, (8, 9, 10), (0, 1, 0), 1, 1, "alt"),
+    (0, (1, 16, 18), (0, 1, 0), 0, 1, "quad"),
+    (1, (7, 8, 9), (1, 0, 1), 1, 1, "quad"),
+    (0, (1, 20, 26), (1, 1, 0), 1, 1, "alt+quad"),
+    (3, (8, 9, 10), (0, 0, 1), 1, 1, "alt+quad+gamma6"),
 ]
 
 
@@ -55,7 +83,7 @@ def test_adjoint_matches_oracle_autograd(adj, case):
     from oracle import torch_step as ts
     lattice, shape, bc, ct, at, hl = case
     p = wl.base_params(lattice=lattice, shape=shape, bc=bc, counter_term=ct, anti_trapping=at,
-                       h_lattice=hl)
+                       **_variant(hl))
     phi0, c0 = wl.random_state_fields(shape, seed=31)
     rng = np.random.default_rng(32)
     a = rng.standard_normal(shape)

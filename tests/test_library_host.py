@@ -140,9 +140,21 @@ def test_variants_rejected_with_deviation_storage(lib, prec, over):
 
 
 @pytest.mark.parametrize("over", [dict(h_scheme=1), dict(free_energy=1, eps_s=1.0, eps_l=2.0)])
-def test_adjoint_rejects_variants(lib, over):
+def test_adjoint_workspace_variants(lib, over):
+    """The scheme variants change no array of the adjoint: same workspace as
+    the base scheme."""
+    base = B.make_params(wl.base_params(lattice=wl.D2Q9, shape=(1, 8, 8), bc=(0, 0, 0)), "fp64")
     cp = B.make_params(wl.base_params(lattice=wl.D2Q9, shape=(1, 8, 8), bc=(0, 0, 0), **over),
                        "fp64")
+    a, b = ctypes.c_uint64(), ctypes.c_uint64()
+    assert lib.gplbm_adjoint_bytes(ctypes.byref(base), ctypes.byref(a)) == B.GPLBM_OK
+    assert lib.gplbm_adjoint_bytes(ctypes.byref(cp), ctypes.byref(b)) == B.GPLBM_OK
+    assert a.value == b.value > 0
+
+
+@pytest.mark.parametrize("prec", ["fp16dev", "bf16dev"])
+def test_adjoint_rejects_deviation_storage(lib, prec):
+    cp = B.make_params(wl.base_params(lattice=wl.D3Q19, shape=(8, 8, 8), bc=(0, 0, 0)), prec)
     out = ctypes.c_uint64()
     assert B.gplbm_state_bytes(cp) > 0
     assert lib.gplbm_adjoint_bytes(ctypes.byref(cp), ctypes.byref(out)) == B.GPLBM_E_INVALID

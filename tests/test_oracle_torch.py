@@ -8,6 +8,21 @@ import torch
 import workloads as wl
 from oracle import torch_step as ts
 
+# general quadratic free energies for the variant cases: eps_l / eps_s = 2.3
+QUAD = dict(free_energy=1, eps_s=1.0, eps_l=2.3, m_s=0.9, m_l=0.12, df_min=0.02)
+
+
+def _variant(v):
+    """h_lattice as an int, or a variant name: alt (h^eq,alt), quad, alt+quad."""
+    if not isinstance(v, str):
+        return {"h_lattice": v}
+    over = {}
+    if "alt" in v:
+        over["h_scheme"] = 1
+    if "quad" in v:
+        over.update(QUAD)
+    return over
+
 
 @pytest.mark.parametrize("lattice,shape,bc,ct,at,hl", [
     (0, (1, 20, 30), (1, 0, 0), 1, 1, 0),
@@ -19,12 +34,15 @@ from oracle import torch_step as ts
     (1, (8, 9, 10), (1, 0, 1), 1, 1, 1),
     (2, (1, 17, 23), (1, 1, 0), 1, 1, 0),
     (3, (8, 9, 10), (0, 1, 0), 0, 1, 0),
+    (0, (1, 20, 30), (1, 0, 0), 1, 1, "alt"),
+    (1, (8, 9, 10), (0, 0, 1), 1, 1, "quad"),
+    (0, (1, 17, 23), (0, 1, 0), 0, 1, "alt+quad"),
 ])
 def test_torch_restatement_equals_c_oracle(oracle_mod, lattice, shape, bc, ct, at, hl):
-    """Also with h on D2Q5 / D3Q7 (hl = 1) and with g and h on them
-    (lattice 2, 3)."""
+    """Also with h on D2Q5 / D3Q7 (hl = 1), with g and h on them (lattice 2,
+    3), with h^eq,alt and with general quadratic free energies."""
     p = wl.base_params(lattice=lattice, shape=shape, bc=bc, counter_term=ct, anti_trapping=at,
-                       h_lattice=hl)
+                       **_variant(hl))
     phi0, c0 = wl.random_state_fields(shape, seed=4)
     o = oracle_mod.Oracle(p).init(phi0, c0).step(25)
     phiK, cK = ts.run(p, torch.from_numpy(phi0.ravel()), torch.from_numpy(c0.ravel()), 25)
@@ -36,9 +54,10 @@ def test_torch_restatement_equals_c_oracle(oracle_mod, lattice, shape, bc, ct, a
 @pytest.mark.parametrize("lattice,shape,bc,hl", [(0, (1, 14, 16), (1, 0, 0), 0),
                                                 (1, (6, 7, 8), (0, 0, 0), 0),
                                                 (1, (6, 7, 8), (1, 0, 0), 1),
-                                                (3, (6, 7, 8), (0, 0, 1), 0)])
+                                                (3, (6, 7, 8), (0, 0, 1), 0),
+                                                (0, (1, 14, 16), (1, 0, 0), "alt+quad")])
 def test_torch_adjoint_matches_finite_differences(lattice, shape, bc, hl):
-    p = wl.base_params(lattice=lattice, shape=shape, bc=bc, h_lattice=hl)
+    p = wl.base_params(lattice=lattice, shape=shape, bc=bc, **_variant(hl))
     phi0, c0 = wl.random_state_fields(shape, seed=8)
     K = 10
     t_lam = torch.tensor(p["lam"], dtype=torch.float64, requires_grad=True)
