@@ -56,6 +56,9 @@ constexpr int kMov = 18;
 
 __device__ __forceinline__ constexpr int mslot(int k) { return k < LD::REST ? k : k - 1; }
 
+// slot of plane q in a ring of four planes (q >= -8)
+__device__ __forceinline__ int ring4(int q) { return (q + 8) & 3; }
+
 __device__ __forceinline__ int64_t mov_index(const Geo& g, int k, int x, int y, int z) {
   const int64_t plane = (int64_t)g.nx * g.ny;
   return ((int64_t)z * kMov + mslot(k)) * plane + (int64_t)y * g.nx + x;
@@ -375,10 +378,15 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   constexpr int BX = Shape::BX, BY = Shape::BY;
   constexpr int AX = BX + 2, AY = BY + 2;
   constexpr int NT = Shape::NT;
-  __shared__ float phiA[3][AY][AX];  // phi^n, planes p-1, p, p+1
-  __shared__ float lamA[3][AY][AX];  // Lambda^{n-1}, planes p-1, p, p+1
-  __shared__ float phiB[3][BY][BX];  // phi^{n+1}, planes p-2, p-1, p
-  __shared__ double acc[3][BY][BX];  // c^{n+1}
+  // Rings of four planes and a double-buffered exchange, so that one barrier
+  // per plane orders every LDS access: the tile of plane p + 2 is loaded, and
+  // the next plane's exchange written, while other waves still read the
+  // planes of p (see the hazards noted at the barrier).
+  __shared__ float phiA[4][AY][AX];          // phi^n, planes p-1 .. p+2
+  __shared__ float lamA[4][AY][AX];          // Lambda^{n-1}, planes p-1 .. p+2
+  __shared__ float phiB[4][BY][BX];          // phi^{n+1}, planes p-3 .. p
+  __shared__ uint16_t hxe[2][kMov][BY][BX];  // h*^n of plane p: 16-bit codes
+  __shared__ float hxl[2][BY][BX];           // and Lambda^n, the reference of the codes
 
   int tx, ty;
   bool valid;
@@ -410,21 +418,25 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     for (int l = threadIdx.x; l < AX * AY; l += NT) {
       const int lx = l % AX, ly = l / AX;
       const int gx = wrap_coord(X0 - 2 + lx, nx), gy = wrap_coord(Y0 - 2 + ly, ny);
-      phiA[ring3(p)][ly][lx] = b.cur.PHI[zoff + gy * nx + gx];
-      lamA[ring3(p)][ly][lx] = b.cur.LAM[zoff + gy * nx + gx];
+      phiA[ring4(p)][ly][lx] = b.cur.PHI[zoff + gy * nx + gx];
+      lamA[ring4(p)][ly][lx] = b.cur.LAM[zoff + gy * nx + gx];
     }
   };
   load_tiles(z0 - 2);
   load_tiles(z0 - 1);
+  load_tiles(z0);
+  __syncthreads();
 
   float g_old[Q];
 #pragma unroll
   for (int k = 0; k < Q; ++k) g_old[k] = 0.0f;
+  // c^{n+1} of this thread's node on planes p - 1 and p, partly summed: the
+  // five e_z = +1 populations arrive one plane early, the five e_z = -1 ones
+  // one plane late, each group gathered in ascending k
+  const bool inner = valid && tx >= 1 && tx <= TX && ty >= 1 && ty <= TY;
+  double acc_dn = 0.0, acc_mid = 0.0;
 
   for (int p = z0 - 1; p <= z1; ++p) {
-    load_tiles(p + 1);
-    __syncthreads();
-
     const int zp = wrap_coord(p, nz);
     const int zo[3] = {(zp == 0 ? nz - 1 : zp - 1), zp, (zp == nz - 1 ? 0 : zp + 1)};
     __amdgpu_buffer_rsrc_t Hz[3], Gz[3];
@@ -445,7 +457,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
         v = b.cur.H.rest[selfnode];
       } else {
         const float ref = float(LD::w[k]) *
-                          lamA[ring3(p - LD::ez[k])][ty + 1 - LD::ey[k]][tx + 1 - LD::ex[k]];
+                          lamA[ring4(p - LD::ez[k])][ty + 1 - LD::ey[k]][tx + 1 - LD::ex[k]];
         v = dev_decode<Codec>(bload16(Hz[1 - LD::ez[k]], xyb[1 - LD::ey[k]][1 - LD::ex[k]],
                                       mslot(k) * planeB), ref);
       }
@@ -459,18 +471,18 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
         v = b.cur.G.rest[selfnode];
       } else {
         const float ref = float(LD::w[k]) *
-                          phiA[ring3(p - LD::ez[k])][ty + 1 - LD::ey[k]][tx + 1 - LD::ex[k]];
+                          phiA[ring4(p - LD::ez[k])][ty + 1 - LD::ey[k]][tx + 1 - LD::ex[k]];
         v = dev_decode<Codec>(bload16(Gz[1 - LD::ez[k]], xyb[1 - LD::ey[k]][1 - LD::ex[k]],
                                       mslot(k) * planeB), ref);
       }
       g_new[k] = v;
       sg = k == 0 ? double(v) : sg + double(v);
     }
-    const int sA = ring3(p);
+    const int sA = ring4(p);
     const float phi = phiA[sA][ty + 1][tx + 1];
     const float mu = float(closure(K.cl, K.cs, K.mueq, c, double(phi)));
     auto atA = [&](int dx, int dy, int dz) -> float {
-      return phiA[ring3(p + dz)][ty + 1 + dy][tx + 1 + dx];
+      return phiA[ring4(p + dz)][ty + 1 + dy][tx + 1 + dx];
     };
     float gr[3], n[3];
     gradient_normal<LD, float>(atA, K.eps2, gr, n);
@@ -501,44 +513,55 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
       __builtin_nontemporal_store(phin, &b.nxt.PHI[selfnode]);
     }
 
-    const bool up_ok = p + 1 >= z0 && p + 1 < z1, dn_ok = p - 1 >= z0 && p - 1 < z1;
+    // streaming of h* inside the block: every region node publishes its
+    // codes and Lambda, then each inner node gathers from x - e_k and decodes
+    // (the same arithmetic as the writer's, so the same values), keeping the
+    // population order of a pull without ordered passes
+    const int xb = p & 1;
+    if (valid) {
 #pragma unroll
-    for (int j = 0; j < 9; ++j) {
-      if (j < 5 && up_ok) {
-        const int k = j;
-        const int tx2 = tx + LD::ex[k], ty2 = ty + LD::ey[k];
-        if (valid && tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
-          double& a = acc[ring3(p + 1)][ty2][tx2];
-          a = k == 0 ? double(hdec[k]) : a + double(hdec[k]);
+      for (int k = 0; k < Q; ++k)
+        if (k != LD::REST) hxe[xb][mslot(k)][ty][tx] = enc[k];
+      hxl[xb][ty][tx] = lam;
+    }
+    load_tiles(p + 2);
+    // The one barrier of the plane.  Before it: reads of the phi / Lambda
+    // planes p-1 .. p+1, writes of phi^{n+1}(p), of the exchange (p & 1) and
+    // of the tile p+2.  After it: reads of the exchange (p & 1) and of
+    // phi^{n+1}(p-2 .. p).  The slot of tile p+2 was last read before the
+    // previous barrier, that of phi^{n+1}(p) after the barrier three planes
+    // back, and the exchange buffer (p & 1) after the barrier two planes back.
+    __syncthreads();
+    const bool dn_ok = p - 1 >= z0 && p - 1 < z1;
+    double acc_up = 0.0;
+    if (inner) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        double v;
+        if (k == LD::REST) {
+          v = double(hdec[k]);
+        } else {
+          const int sy = ty - LD::ey[k], sx = tx - LD::ex[k];
+          const float ref = float(LD::w[k]) * hxl[xb][sy][sx];
+          v = double(dev_decode<Codec>(hxe[xb][mslot(k)][sy][sx], ref));
         }
+        if (LD::ez[k] > 0)
+          acc_up = k == 0 ? v : acc_up + v;
+        else if (LD::ez[k] == 0)
+          acc_mid = acc_mid + v;
+        else
+          acc_dn = acc_dn + v;
       }
-      if (own_p) {
-        const int k = 5 + j;
-        const int tx2 = tx + LD::ex[k], ty2 = ty + LD::ey[k];
-        if (valid && tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
-          double& a = acc[sA][ty2][tx2];
-          a = a + double(hdec[k]);
-        }
-      }
-      if (j < 5 && dn_ok) {
-        const int k = 14 + j;
-        const int tx2 = tx + LD::ex[k], ty2 = ty + LD::ey[k];
-        if (valid && tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY) {
-          double& a = acc[ring3(p - 1)][ty2][tx2];
-          a = a + double(hdec[k]);
-        }
-      }
-      __syncthreads();
     }
 
     if (out && dn_ok) {
       const int zq = zo[0];
-      const int sB = ring3(p - 1);
-      const double c1 = acc[sB][ty][tx];
+      const int sB = ring4(p - 1);
+      const double c1 = acc_dn;
       const float phi1 = phiB[sB][ty][tx];
       const float mu1 = float(closure(K.cl, K.cs, K.mueq, c1, double(phi1)));
       auto atB = [&](int dx, int dy, int dz) -> float {
-        return phiB[ring3(p - 1 + dz)][ty + dy][tx + dx];
+        return phiB[ring4(p - 1 + dz)][ty + dy][tx + dx];
       };
       float gr1[3], n1[3];
       gradient_normal<LD, float>(atB, K.eps2, gr1, n1);
@@ -557,6 +580,8 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     }
 #pragma unroll
     for (int k = 0; k < Q; ++k) g_old[k] = g_new[k];
+    acc_dn = acc_mid;
+    acc_mid = acc_up;
   }
   __syncthreads();  // the LDS rings are refilled by the next tile
   }
