@@ -202,16 +202,17 @@ int gplbm_diagnostics(gplbm_ctx* ctx, gplbm_diag* out);
 int gplbm_save_state(gplbm_ctx* ctx, void* dev_dst);
 int gplbm_load_state(gplbm_ctx* ctx, const void* dev_src, int64_t step);
 
-/* Adjoint (reverse mode) of gplbm_init_fields followed by K steps, for FP64
- * and FP32 contexts: gradients of a scalar objective J(phi^K, c^K) with
+/* Adjoint (reverse mode) of gplbm_init_fields followed by K steps, for every
+ * context: gradients of a scalar objective J(phi^K, c^K) with
  * respect to phi0, c0, lambda and D_l (gamma, M_phi, W and a_at held fixed;
  * D' = D_l - D_s and D(phi) follow D_l).  It differentiates the discrete map
  * of the step in FP64 arithmetic (every operation of the collisions,
  * sources, closure, normal, anti-trapping current, streaming and boundaries)
  * at the forward values recomputed from saved states; for an FP64 context
  * that is exactly the map gplbm_step computes, for an FP32 context the same
- * map taken at the FP32 states (the reverse sweep and all accumulations are
- * FP64 in both).  The caller drives the reverse sweep (e.g. with sqrt(K)
+ * map taken at the FP32 states, for an FP16/BF16-deviation context the same
+ * map taken at the decoded states (the reverse sweep and all accumulations
+ * are FP64 in all).  The caller drives the reverse sweep (e.g. with sqrt(K)
  * checkpointing of gplbm_save_state snapshots).
  *
  * gplbm_adjoint_bytes: size of the FP64 device workspace (adjoint state,
@@ -226,11 +227,11 @@ int gplbm_load_state(gplbm_ctx* ctx, const void* dev_src, int64_t step);
  *   writes dJ/dphi0 and dJ/dc0 (device, N doubles) and dJ/dlambda, dJ/dD_l into
  *   dJ_dparams (host, 2 doubles).  Parameter sums are reduced in a fixed
  *   order.  Synchronises the stream.
- * Every lattice combination, both h schemes and both free-energy forms are
- * supported (the quadratic constants eps_s, eps_l, m_s, m_l, df_min held
- * fixed).  Return GPLBM_E_INVALID for FP16/BF16-deviation contexts or null
- * pointers, GPLBM_E_SIZE for a short workspace, GPLBM_E_STATE out of
- * order. */
+ * Every lattice combination, both h schemes, both free-energy forms (the
+ * quadratic constants eps_s, eps_l, m_s, m_l, df_min held fixed) and the
+ * deviation formats are supported.  Return GPLBM_E_INVALID for invalid
+ * parameters or null pointers, GPLBM_E_SIZE for a short workspace,
+ * GPLBM_E_STATE out of order. */
 int gplbm_adjoint_bytes(const gplbm_params* p, uint64_t* bytes);
 int gplbm_adjoint_begin(gplbm_ctx* ctx, void* work, uint64_t bytes, const double* phi_bar,
                         const double* c_bar);

@@ -9,7 +9,9 @@ torch objective J(phiK, cK) can then be differentiated: backward returns
 dJ/dphi0, dJ/dc0, dJ/dlambda and dJ/dD_l, all computed by the GPU kernels of
 libgplbm.so (this module only schedules them).  precision "fp32" runs the
 forward (and its re-computation) in FP32 storage and arithmetic; the reverse
-sweep stays FP64, taken at the FP32 states.
+sweep stays FP64, taken at the FP32 states.  "fp16dev" / "bf16dev" (D3Q19)
+run the forward in a deviation storage format and the FP64 reverse sweep at
+its decoded states.
 
 Checkpointing: forward keeps the state every s = ceil(sqrt(K)) steps;
 backward rebuilds each segment from its checkpoint (gplbm_step_to, no copies)
@@ -84,9 +86,9 @@ class _Run(torch.autograd.Function):
 
 def gplbm_run(phi0, c0, lam, D_l, cfg, K, seg=None, precision="fp64"):
     """(phi^K, c^K) after K steps; differentiable in phi0, c0, lam and D_l.
-    precision: "fp64" or "fp32" (forward storage and arithmetic)."""
-    if precision not in ("fp64", "fp32"):
-        raise ValueError("the adjoint runs over FP64 or FP32 forward states")
+    precision: "fp64", "fp32", "fp16dev" or "bf16dev" (forward storage)."""
+    if precision not in ("fp64", "fp32", "fp16dev", "bf16dev"):
+        raise ValueError(f"unknown precision {precision!r}")
     return _Run.apply(phi0, c0, lam, D_l, cfg, K, seg, precision)
 
 

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 
 #include "gplbm.h"
 #include "kernels_adjoint.h"
@@ -678,7 +679,8 @@ void gplbm_destroy(gplbm_ctx* ctx) { delete ctx; }
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// Adjoint: FP64 reverse sweep over FP64 or FP32 forward states.
+// Adjoint: FP64 reverse sweep over FP64, FP32 or deviation-format forward
+// states.
 
 namespace {
 
@@ -699,18 +701,38 @@ AdjLayout adj_layout(const gplbm_params* p) {
   return l;
 }
 
-template <class L, class LH, class S>
+// A saved state (gplbm_save_state layout: G | H | PHI | LAM) as the forward
+// state type FS of the reverse kernels.
+template <class FS>
+struct FwdFromState;
+template <class S>
+struct FwdFromState<FwdState<S>> {
+  static FwdState<S> get(const gplbm_ctx* ctx, const void* ck) {
+    const char* b = (const char*)ck;
+    return FwdState<S>{(const S*)b, (const S*)(b + ctx->pop_bytes),
+                       (const S*)(b + ctx->pop_bytes + ctx->hpop_bytes)};
+  }
+};
+template <class Codec>
+struct FwdFromState<DevFwdState<Codec>> {
+  static DevFwdState<Codec> get(const gplbm_ctx* ctx, const void* ck) {
+    char* b = (char*)const_cast<void*>(ck);
+    DevFwdState<Codec> f;
+    f.H.mov = (uint16_t*)(b + ctx->pop_bytes);
+    f.H.rest = (float*)(b + ctx->pop_bytes + ctx->mov_bytes);
+    f.PHI = (const float*)(b + ctx->pop_bytes + ctx->hpop_bytes);
+    f.LAM = (const float*)(b + ctx->pop_bytes + ctx->hpop_bytes + ctx->phi_bytes);
+    return f;
+  }
+};
+
+template <class L, class LH, class FS>
 struct AdjOps {
   static dim3 block() { return dim3(64, 4, 1); }
   static dim3 grid(const gplbm_ctx* ctx) {
     return dim3((ctx->p.nx + 63) / 64, (ctx->p.ny + 3) / 4, ctx->p.nz);
   }
   static double lam_M_W2(const gplbm_ctx* ctx) { return ctx->p.M_phi / (ctx->p.W * ctx->p.W); }
-  static FwdState<S> fwd(const gplbm_ctx* ctx, const void* ck) {
-    const char* b = (const char*)ck;
-    return FwdState<S>{(const S*)b, (const S*)(b + ctx->pop_bytes),
-                       (const S*)(b + ctx->pop_bytes + ctx->hpop_bytes)};
-  }
   static int seed(gplbm_ctx* ctx, const double* phib, const double* cb) {
     const Geo g = make_geo(ctx->p);
     hipLaunchKernelGGL((k_adj_seed<L, LH>), grid(ctx), block(), 0, ctx->stream, g, phib, cb,
@@ -721,10 +743,10 @@ struct AdjOps {
     const Geo g = make_geo(ctx->p);
     const Coef<double> K = make_coef<double>(ctx->p);
     const int a = ctx->adj_cur, b = 1 - a;
-    const FwdState<S> S0 = fwd(ctx, s0), S1 = fwd(ctx, s1);
-    hipLaunchKernelGGL((k_adj_ra<L, LH, S>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx),
+    const FS S0 = FwdFromState<FS>::get(ctx, s0), S1 = FwdFromState<FS>::get(ctx, s1);
+    hipLaunchKernelGGL((k_adj_ra<L, LH, FS>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx),
                        S1, ctx->adj.set[a], ctx->adj.set[b], ctx->adj);
-    hipLaunchKernelGGL((k_adj_rb<L, LH, S>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx),
+    hipLaunchKernelGGL((k_adj_rb<L, LH, FS>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx),
                        S0, S1, ctx->adj.set[a], ctx->adj.set[b], ctx->adj);
     int rc = check_launch(ctx, "adjoint step");
     if (rc) return rc;
@@ -750,8 +772,20 @@ struct AdjOps {
 
 template <template <class, class, class> class Fn, class L, class LH, class... Args>
 int adj_dispatch_prec(gplbm_ctx* ctx, Args... args) {
-  if (ctx->p.precision == GPLBM_FP64) return Fn<L, LH, double>::run(ctx, args...);
-  return Fn<L, LH, float>::run(ctx, args...);
+  switch (ctx->p.precision) {
+    case GPLBM_FP64:
+      return Fn<L, LH, FwdState<double>>::run(ctx, args...);
+    case GPLBM_FP32:
+      return Fn<L, LH, FwdState<float>>::run(ctx, args...);
+    default:
+      // deviation formats exist for g and h on D3Q19 only
+      if constexpr (std::is_same_v<L, D3Q19> && std::is_same_v<LH, D3Q19>) {
+        if (ctx->p.precision == GPLBM_FP16_DEV)
+          return Fn<L, LH, DevFwdState<F16Codec>>::run(ctx, args...);
+        return Fn<L, LH, DevFwdState<BF16Codec>>::run(ctx, args...);
+      }
+      return GPLBM_E_INVALID;
+  }
 }
 
 template <template <class, class, class> class Fn, class... Args>
@@ -770,30 +804,29 @@ int adj_dispatch(gplbm_ctx* ctx, Args... args) {
       return adj_dispatch_prec<Fn, D3Q7, D3Q7>(ctx, args...);
   }
 }
-template <class L, class LH, class S>
+template <class L, class LH, class FS>
 struct AdjSeedFn {
   static int run(gplbm_ctx* c, const double* a, const double* b) {
-    return AdjOps<L, LH, S>::seed(c, a, b);
+    return AdjOps<L, LH, FS>::seed(c, a, b);
   }
 };
-template <class L, class LH, class S>
+template <class L, class LH, class FS>
 struct AdjStepFn {
   static int run(gplbm_ctx* c, const void* a, const void* b) {
-    return AdjOps<L, LH, S>::step(c, a, b);
+    return AdjOps<L, LH, FS>::step(c, a, b);
   }
 };
-template <class L, class LH, class S>
+template <class L, class LH, class FS>
 struct AdjFinishFn {
   static int run(gplbm_ctx* c, const double* a, const double* b, double* d, double* e) {
-    return AdjOps<L, LH, S>::finish(c, a, b, d, e);
+    return AdjOps<L, LH, FS>::finish(c, a, b, d, e);
   }
 };
 
-// The adjoint covers both h schemes, both free-energy forms and every
-// lattice combination, in FP64 or FP32.
-bool adjoint_supported(const gplbm_params& p) {
-  return p.precision == GPLBM_FP64 || p.precision == GPLBM_FP32;
-}
+// The adjoint covers every context the parameters allow: both h schemes,
+// both free-energy forms and every lattice combination in FP64 or FP32, and
+// the deviation formats (D3Q19, source scheme, equal curvatures).
+bool adjoint_supported(const gplbm_params& p) { return check_params(&p) == nullptr; }
 
 }  // namespace
 

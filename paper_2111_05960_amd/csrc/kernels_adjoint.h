@@ -27,6 +27,7 @@
 // not follow D_l).
 #pragma once
 
+#include "kernels_dev.h"
 #include "kernels_split.h"
 
 namespace gplbm {
@@ -59,6 +60,16 @@ struct FwdState {
   const S* G;
   const S* H;
   const S* PHI;
+};
+
+// A forward state in a deviation format (D3Q19): the h populations decode
+// with the Lambda field of the state, phi is FP32.  The reverse kernels take
+// the decoded values as the state and differentiate the FP64 step there.
+template <class Codec>
+struct DevFwdState {
+  DevDist H;
+  const float* PHI;
+  const float* LAM;
 };
 
 // Destination of the value stored in slot (k, x, y, z) under the pull
@@ -103,6 +114,27 @@ __device__ __forceinline__ NodeFwd<L> node_fwd(const Geo& g, const Coef<double>&
   f.phi = double(F.PHI[node_index(g, x, y, z)]);
   f.mu = closure(K.q, c, f.phi);
   gradient_normal<L, double>(GlobalPhi<S, double>{g, F.PHI, x, y, z}, K.eps2, f.g, f.n);
+  double nn = f.g[0] * f.g[0] + f.g[1] * f.g[1];
+  if (L::D == 3) nn = nn + f.g[2] * f.g[2];
+  f.s = sqrt(nn + K.eps2);
+  return f;
+}
+
+template <class L, class LH, class Codec>
+__device__ __forceinline__ NodeFwd<L> node_fwd(const Geo& g, const Coef<double>& K,
+                                               const DevFwdState<Codec>& F, int x, int y, int z) {
+  static_assert(L::Q == 19 && LH::Q == 19, "deviation formats are D3Q19");
+  NodeFwd<L> f;
+  double c = 0.0;
+#pragma unroll
+  for (int k = 0; k < LH::Q; ++k) {
+    const double v = double(pull_dev<Codec>(g, F.H, F.LAM, k, x, y, z));
+    c = k == 0 ? v : c + v;
+  }
+  f.c = c;
+  f.phi = double(F.PHI[node_index(g, x, y, z)]);
+  f.mu = closure(K.q, c, f.phi);
+  gradient_normal<L, double>(GlobalPhi<float, double>{g, F.PHI, x, y, z}, K.eps2, f.g, f.n);
   double nn = f.g[0] * f.g[0] + f.g[1] * f.g[1];
   if (L::D == 3) nn = nn + f.g[2] * f.g[2];
   f.s = sqrt(nn + K.eps2);
@@ -249,15 +281,15 @@ __device__ __forceinline__ double gather_Gb(const Geo& g, const AdjSet& P, int k
   return P.A1[pop_index<L>(g, kk, dx, dy, dz)] + P.B2[node_index(g, dx, dy, dz)];
 }
 
-template <class L, class LH, class S>
+template <class L, class LH, class FS>
 __global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> K, double lam_M_W2,
-                                                FwdState<S> S1, AdjSet P, AdjSet C, AdjWork w) {
+                                                FS S1, AdjSet P, AdjSet C, AdjWork w) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= g.nx || y >= g.ny) return;
   const int64_t i = node_index(g, x, y, z);
-  const NodeFwd<L> f = node_fwd<L, LH, S>(g, K, S1, x, y, z);  // c^{n+1}, mu^{n+1}, ...
+  const NodeFwd<L> f = node_fwd<L, LH>(g, K, S1, x, y, z);  // c^{n+1}, mu^{n+1}, ...
   const double om = K.omega_g;
   double Gb[L::Q];
   double phi_b = 0.0, mu_b = 0.0, nb[3] = {0.0, 0.0, 0.0};
@@ -283,10 +315,9 @@ __global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> K, double la
   w.lamb[i] += lb;
 }
 
-template <class L, class LH, class S>
+template <class L, class LH, class FS>
 __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> K, double lam_M_W2,
-                                                FwdState<S> S0, FwdState<S> S1, AdjSet P, AdjSet C,
-                                                AdjWork w) {
+                                                FS S0, FS S1, AdjSet P, AdjSet C, AdjWork w) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
@@ -303,7 +334,7 @@ __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> K, double la
   // adjoint of phi^{n+1} at this node (A2, A4 hold both collisions' parts)
   double p1b = w.A4[i] + stencil_adj_gather<L>(g, w.A2, x, y, z);
   // forward quantities of step n
-  const NodeFwd<L> f = node_fwd<L, LH, S>(g, K, S0, x, y, z);
+  const NodeFwd<L> f = node_fwd<L, LH>(g, K, S0, x, y, z);
   const double phi1 = double(S1.PHI[i]);
   const double dtphi = phi1 - f.phi;
   const double oh = K.omega_h;

@@ -153,11 +153,22 @@ def test_adjoint_workspace_variants(lib, over):
 
 
 @pytest.mark.parametrize("prec", ["fp16dev", "bf16dev"])
-def test_adjoint_rejects_deviation_storage(lib, prec):
-    cp = B.make_params(wl.base_params(lattice=wl.D3Q19, shape=(8, 8, 8), bc=(0, 0, 0)), prec)
+def test_adjoint_workspace_deviation_storage(lib, prec):
+    """The reverse sweep is FP64 whatever the forward storage: a deviation
+    context needs the FP64 context's workspace."""
+    p = wl.base_params(lattice=wl.D3Q19, shape=(8, 8, 8), bc=(0, 0, 0))
+    a, b = ctypes.c_uint64(), ctypes.c_uint64()
+    assert lib.gplbm_adjoint_bytes(ctypes.byref(B.make_params(p, "fp64")), ctypes.byref(a)) == B.GPLBM_OK
+    assert lib.gplbm_adjoint_bytes(ctypes.byref(B.make_params(p, prec)), ctypes.byref(b)) == B.GPLBM_OK
+    assert a.value == b.value > 0
+
+
+def test_adjoint_bytes_rejects_invalid_parameters(lib):
+    p = wl.base_params(lattice=wl.D3Q19, shape=(8, 8, 8), bc=(0, 0, 0), h_lattice=1)
     out = ctypes.c_uint64()
-    assert B.gplbm_state_bytes(cp) > 0
-    assert lib.gplbm_adjoint_bytes(ctypes.byref(cp), ctypes.byref(out)) == B.GPLBM_E_INVALID
+    # deviation storage exists for g and h on D3Q19 only
+    assert lib.gplbm_adjoint_bytes(ctypes.byref(B.make_params(p, "fp16dev")),
+                                   ctypes.byref(out)) == B.GPLBM_E_INVALID
 
 
 @pytest.mark.parametrize("field,value", [("h_scheme", 2), ("free_energy", 3), ("eps_s", 0.0),
