@@ -141,9 +141,19 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   constexpr int NT = Shape::NT;
   constexpr int PHI_PER_THREAD = (AX * AY + NT - 1) / NT;
   constexpr bool kRegs = kCarryMode == Carry::kRegisters;
-  __shared__ C phiA[3][AY][AX];      // phi^n, planes p-1, p, p+1
-  __shared__ C phiB[3][BY][BX];      // phi^{n+1}, planes p-2, p-1, p
-  __shared__ double acc[3][BY][BX];  // c^{n+1} being accumulated
+  // In-block streaming of h*: where the LDS and the registers allow it (a
+  // register carry and one lattice lighter than D3Q19), the post-collision
+  // h* of the plane go to an LDS exchange that the readers gather from after
+  // one barrier, keeping their partial sums of c^{n+1} in registers;
+  // otherwise they are pushed into an accumulator ring in NPASS ordered
+  // passes.  Both sum every c^{n+1} in population order.
+  constexpr bool kGather = kRegs && !(Q == 19 && QH == 19);
+  __shared__ C phiA[3][AY][AX];  // phi^n, planes p-1, p, p+1
+  __shared__ C phiB[3][BY][BX];  // phi^{n+1}, planes p-2, p-1, p
+  // c^{n+1} being accumulated (push passes)
+  __shared__ double acc[kGather ? 1 : 3][kGather ? 1 : BY][kGather ? 1 : BX];
+  // h* of plane p, moving populations (gather)
+  __shared__ C hx[kGather ? QH : 1][kGather ? BY : 1][kGather ? BX : 1];
   // pulled g~^{n+1} of the output nodes by plane parity (LDS carry)
   __shared__ C gkeep[kRegs ? 1 : 2][kRegs ? 1 : Q][kRegs ? 1 : TY][kRegs ? 1 : TX];
 
@@ -198,6 +208,11 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     C g_old[kRegs ? Q : 1];
 #pragma unroll
     for (int k = 0; k < (kRegs ? Q : 1); ++k) g_old[k] = C(0);
+    // gather: c^{n+1} of this thread's node on planes p-1 and p, partly
+    // summed (the e_z = +1 populations arrive one plane early, the e_z = -1
+    // ones one plane late, each layer in ascending k)
+    const bool inner = valid && tx >= 1 && tx <= TX && ty >= 1 && ty <= TY;
+    double acc_dn = 0.0, acc_mid = 0.0;
 
     for (int p = z0 - 1; p <= z1; ++p) {
       load_phi(p + 1);
@@ -255,12 +270,37 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
         __builtin_nontemporal_store(S(phin_c), &b.PHIn[(int64_t)zp * plane + y * nx + x]);
       }
 
-      // in-block streaming of h* into the accumulator ring, NPASS passes:
-      // pass j carries population j (e_z=+1, to plane p+1), population NU+j
-      // (e_z=0, to plane p) and population NU+NM+j (e_z=-1, to plane p-1)
       const bool up_ok = p + 1 >= z0 && p + 1 < z1, dn_ok = p - 1 >= z0 && p - 1 < z1;
+      double acc_up = 0.0;
+      if constexpr (kGather) {
+        // every region node publishes its moving h*, then each inner node
+        // gathers from x - e_k in population order
+        if (valid) {
 #pragma unroll
-      for (int j = 0; j < NPASS; ++j) {
+          for (int k = 0; k < QH; ++k)
+            if (k != LH::REST) hx[k][ty][tx] = hs[k];
+        }
+        __syncthreads();
+        if (inner) {
+#pragma unroll
+          for (int k = 0; k < QH; ++k) {
+            const double v = k == LH::REST ? double(hs[k])
+                                           : double(hx[k][ty - LH::ey[k]][tx - LH::ex[k]]);
+            if (LH::ez[k] > 0)
+              acc_up = k == 0 ? v : acc_up + v;
+            else if (LH::ez[k] == 0)
+              acc_mid = acc_mid + v;
+            else
+              acc_dn = acc_dn + v;
+          }
+        }
+      }
+      // push form: in-block streaming of h* into the accumulator ring, NPASS
+      // passes: pass j carries population j (e_z=+1, to plane p+1),
+      // population NU+j (e_z=0, to plane p) and population NU+NM+j (e_z=-1,
+      // to plane p-1)
+#pragma unroll
+      for (int j = 0; j < (kGather ? 0 : NPASS); ++j) {
         if (j < NU && up_ok) {
           const int k = j;
           const int tx2 = tx + LH::ex[k], ty2 = ty + LH::ey[k];
@@ -292,7 +332,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
       if (out && dn_ok) {
         const int zq = wrap_coord(p - 1, nz);
         const int sB = ring3(p - 1);
-        const double c1 = acc[sB][ty][tx];
+        const double c1 = kGather ? acc_dn : acc[kGather ? 0 : sB][ty][tx];
         const C phi1 = phiB[sB][ty][tx];
         const C mu1 = C(closure(K.q, c1, double(phi1)));
         auto atB = [&](int dx, int dy, int dz) -> C {
@@ -316,6 +356,10 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
       if constexpr (kRegs) {
 #pragma unroll
         for (int k = 0; k < Q; ++k) g_old[k] = g_new[k];
+      }
+      if constexpr (kGather) {
+        acc_dn = acc_mid;
+        acc_mid = acc_up;
       }
     }
     __syncthreads();  // the LDS rings are refilled by the next tile
