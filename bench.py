@@ -414,8 +414,11 @@ def cpu_model() -> str:
     return "unknown"
 
 
-_SINGLE_THREAD = """
-import sys, time
+
+def cpu_single_thread(p, log):
+    """The oracle on one thread (OMP_NUM_THREADS=1, a child process), on a
+    small random instance of the same lattice, about 3 s of stepping."""
+    script = """import sys, time
 sys.path.insert(0, sys.argv[1])
 import numpy as np
 import oracle, workloads as wl
@@ -432,17 +435,12 @@ while time.perf_counter() - t0 < 3.0:
     k += 1
 print(np.prod(shape) * k / (time.perf_counter() - t0) / 1e6, oracle.threads())
 """
-
-
-def cpu_single_thread(p, log):
-    """The oracle on one thread (OMP_NUM_THREADS=1, a child process), on a
-    small random instance of the same lattice, about 3 s of stepping."""
     import subprocess
     env = dict(os.environ, OMP_NUM_THREADS="1")
     three = p["lattice"] in (1, 3)
     n = 48 if three else 256
     try:
-        out = subprocess.run([sys.executable, "-c", _SINGLE_THREAD, ROOT, str(p["lattice"]), str(n)],
+        out = subprocess.run([sys.executable, "-c", script, ROOT, str(p["lattice"]), str(n)],
                              env=env, capture_output=True, text=True, timeout=120, check=True)
         v, th = out.stdout.split()
     except (subprocess.SubprocessError, ValueError) as e:

@@ -218,3 +218,23 @@ def test_unit_conversion_matches_the_paper_runs():
         units.lattice_steps(5e-4 + 1e-9, wl.PAPER_DT)
     back = units.to_lattice_units(dict(gamma=2.0), 0.5, 0.25)
     assert back["gamma"] == 2.0 / (0.25 / 0.25)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """With the library absent the binding raises instead of falling back to
+    any other implementation (there is none)."""
+    import subprocess
+    import sys
+    code = (
+        "from paper_2111_05960_amd import binding\n"
+        "try:\n"
+        "    binding.load()\n"
+        "except RuntimeError as e:\n"
+        "    assert 'missing' in str(e) and 'no fallback' in str(e), e\n"
+        "    print('raised')\n"
+    )
+    env = dict(os.environ, GPLBM_LIBRARY=str(tmp_path / "absent.so"))
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip() == "raised"
