@@ -92,6 +92,16 @@ def test_fullsize_porous512_fp32(porous512):
     _check(p, phi0, c0, "fp32", 1e-5)
 
 
+# FP16 / BF16 deviation storage: a stored deviation of size ~1e-2 keeps 11
+# (8) significant bits, ~2.4e-6 (2e-5) per population; over the 19
+# populations of a moment and 3 steps that bounds phi, c and mu within 1e-4
+# (1e-3) of the oracle (measured over 55 steps: 2.7e-5 and 2.7e-4 in phi)
+@pytest.mark.parametrize("prec,tol", [("fp16dev", 1e-4), ("bf16dev", 1e-3)])
+def test_fullsize_porous512_deviation_storage(porous512, prec, tol):
+    p, phi0, c0 = porous512
+    _check(p, phi0, c0, prec, tol)
+
+
 def test_fullsize_grain1024_fp64():
     p, phi0, c0, _ = wl.config1()
     _check(p, phi0, c0, "fp64", 0.0)
