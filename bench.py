@@ -518,7 +518,7 @@ def main():
     # the other forms of the same step, side by side (auto schedule)
     forms = {}
     if not args.no_forms:
-        precs = ("fp64", "fp32") + (("fp16dev", "bf16dev") if p["lattice"] == 1 else ())
+        precs = ("fp64", "fp32", "fp16dev", "bf16dev")
         todo = ([(prec, "full", "source", "equal") for prec in precs]
                 + [("fp64", "light", "source", "equal"), ("fp32", "light", "source", "equal"),
                    ("fp64", "light-gh", "source", "equal"), ("fp32", "light-gh", "source", "equal"),
@@ -545,7 +545,7 @@ def main():
     torch.cuda.empty_cache()
     variants = []
     if args.variants:
-        precs = ("fp64", "fp32") + (("fp16dev", "bf16dev") if p["lattice"] == 1 else ())
+        precs = ("fp64", "fp32", "fp16dev", "bf16dev")
         for prec in precs:
             for sch in ("split", "auto"):
                 if prec == args.precision and sch == args.schedule:

@@ -101,7 +101,8 @@ extern "C" {
 /* storage / arithmetic precision of the populations and of phi */
 #define GPLBM_FP64 0 /* everything in double */
 #define GPLBM_FP32 1 /* float storage and collision; moments and closure in double */
-/* D3Q19 only: the 18 moving populations of g and h stored as 16-bit deviations
+/* D2Q9 or D3Q19, h on the lattice of g, source scheme, equal curvatures: the
+ * Q - 1 moving populations of g and h stored as 16-bit deviations
  * from the writing node's equilibrium (w_k phi for g, w_k gamma D(phi) mu for
  * h), rest populations, phi and gamma D(phi) mu as float; float collision,
  * double moments and closure; solute mass balanced through the rest

@@ -94,8 +94,8 @@ const char* check_params(const gplbm_params* p) {
   for (int a = 0; a < 3; ++a)
     if (p->bc[a] != GPLBM_PERIODIC && p->bc[a] != GPLBM_ZERO_FLUX) return "unknown boundary";
   if (p->precision < GPLBM_FP64 || p->precision > GPLBM_BF16_DEV) return "unknown precision";
-  if (p->precision >= GPLBM_FP16_DEV && p->lattice != GPLBM_D3Q19)
-    return "deviation storage is implemented for D3Q19";
+  if (p->precision >= GPLBM_FP16_DEV && p->lattice != GPLBM_D3Q19 && p->lattice != GPLBM_D2Q9)
+    return "deviation storage is implemented for D2Q9 and D3Q19";
   if (p->schedule < GPLBM_SCHED_AUTO || p->schedule > GPLBM_SCHED_FUSED) return "unknown schedule";
   if (p->h_lattice != GPLBM_H_FULL && p->h_lattice != GPLBM_H_LIGHT) return "unknown h lattice";
   if (p->h_lattice == GPLBM_H_LIGHT && p->precision >= GPLBM_FP16_DEV)
@@ -319,8 +319,9 @@ struct Ops {
   }
 };
 
-// Operations in the deviation storage formats (D3Q19 only).
-template <class Codec>
+// Operations in the deviation storage formats (D2Q9 or D3Q19; the fused
+// schedules are the D3Q19 z-march and the D2Q9 tile kernel).
+template <class Codec, class L>
 struct DevOps {
   static dim3 block() { return dim3(64, 4, 1); }
   static dim3 grid(const gplbm_ctx* ctx) {
@@ -341,7 +342,7 @@ struct DevOps {
     const Coef<float> K = make_coef<float>(ctx->p);
     const DevState s = state(ctx, ctx->cur);
     hipLaunchKernelGGL(k_dev_init_fields, grid(ctx), block(), 0, ctx->stream, g, K, phi0, c0, s);
-    hipLaunchKernelGGL((k_dev_init<Codec>), grid(ctx), block(), 0, ctx->stream, g, K, c0, s);
+    hipLaunchKernelGGL((k_dev_init<Codec, L>), grid(ctx), block(), 0, ctx->stream, g, K, c0, s);
     return check_launch(ctx, "init");
   }
   static int step(gplbm_ctx* ctx, int64_t nsteps) {
@@ -351,11 +352,12 @@ struct DevOps {
       const int a = ctx->cur, b = 1 - a;
       const DevStep st{state(ctx, a), state(ctx, b)};
       if (ctx->sched == GPLBM_SCHED_FUSED) {
-        if (DevFused3D<Codec>::launch(g, K, st, ctx->stream))
-          return fail(ctx, GPLBM_E_DEVICE, "fused step launch failed");
+        const int rc = std::is_same_v<L, D3Q19> ? DevFused3D<Codec>::launch(g, K, st, ctx->stream)
+                                                : DevFused2D<Codec>::launch(g, K, st, ctx->stream);
+        if (rc) return fail(ctx, GPLBM_E_DEVICE, "fused step launch failed");
       } else {
-        hipLaunchKernelGGL((k_dev_split_h<Codec>), grid(ctx), block(), 0, ctx->stream, g, K, st);
-        hipLaunchKernelGGL((k_dev_split_g<Codec>), grid(ctx), block(), 0, ctx->stream, g, K, st);
+        hipLaunchKernelGGL((k_dev_split_h<Codec, L>), grid(ctx), block(), 0, ctx->stream, g, K, st);
+        hipLaunchKernelGGL((k_dev_split_g<Codec, L>), grid(ctx), block(), 0, ctx->stream, g, K, st);
       }
       int rc = check_launch(ctx, "step");
       if (rc) return rc;
@@ -366,7 +368,7 @@ struct DevOps {
   }
   static int fields(gplbm_ctx* ctx, double* phi, double* c, double* mu) {
     const Geo g = make_geo(ctx->p);
-    hipLaunchKernelGGL((k_dev_fields<Codec>), grid(ctx), block(), 0, ctx->stream, g, ctx->p.c_l_co,
+    hipLaunchKernelGGL((k_dev_fields<Codec, L>), grid(ctx), block(), 0, ctx->stream, g, ctx->p.c_l_co,
                        ctx->p.c_s_co, ctx->p.mu_eq, state(ctx, ctx->cur), phi, c, mu);
     return check_launch(ctx, "read fields");
   }
@@ -374,7 +376,7 @@ struct DevOps {
     const Geo g = make_geo(ctx->p);
     double* part = ctx->red;
     double* out = ctx->red + kDiagBlocks * kDiagVals;
-    hipLaunchKernelGGL((k_dev_diag_partial<Codec>), dim3(kDiagBlocks), dim3(kDiagThreads), 0,
+    hipLaunchKernelGGL((k_dev_diag_partial<Codec, L>), dim3(kDiagBlocks), dim3(kDiagThreads), 0,
                        ctx->stream, g, state(ctx, ctx->cur), part);
     hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagThreads), 0, ctx->stream,
                        (const double*)part, kDiagBlocks, out);
@@ -382,12 +384,12 @@ struct DevOps {
   }
 };
 
-template <class Codec>
+template <class Codec, class L>
 struct DevAdapter {
-  static int init(gplbm_ctx* c, const double* a, const double* b) { return DevOps<Codec>::init(c, a, b); }
-  static int step(gplbm_ctx* c, int64_t n) { return DevOps<Codec>::step(c, n); }
-  static int fields(gplbm_ctx* c, double* a, double* b, double* d) { return DevOps<Codec>::fields(c, a, b, d); }
-  static int diag(gplbm_ctx* c) { return DevOps<Codec>::diag(c); }
+  static int init(gplbm_ctx* c, const double* a, const double* b) { return DevOps<Codec, L>::init(c, a, b); }
+  static int step(gplbm_ctx* c, int64_t n) { return DevOps<Codec, L>::step(c, n); }
+  static int fields(gplbm_ctx* c, double* a, double* b, double* d) { return DevOps<Codec, L>::fields(c, a, b, d); }
+  static int diag(gplbm_ctx* c) { return DevOps<Codec, L>::diag(c); }
 };
 
 template <template <class, class, class, class> class Fn, class L, class LH, class... Args>
@@ -398,10 +400,13 @@ int dispatch_prec(gplbm_ctx* ctx, Args... args) {
 
 template <template <class, class, class, class> class Fn, class... Args>
 int dispatch(gplbm_ctx* ctx, Args... args) {
+  const bool d2 = ctx->p.lattice == GPLBM_D2Q9;
   if (ctx->p.precision == GPLBM_FP16_DEV)
-    return Fn<DevAdapter<F16Codec>, void, void, void>::run(ctx, args...);
+    return d2 ? Fn<DevAdapter<F16Codec, D2Q9>, void, void, void>::run(ctx, args...)
+              : Fn<DevAdapter<F16Codec, D3Q19>, void, void, void>::run(ctx, args...);
   if (ctx->p.precision == GPLBM_BF16_DEV)
-    return Fn<DevAdapter<BF16Codec>, void, void, void>::run(ctx, args...);
+    return d2 ? Fn<DevAdapter<BF16Codec, D2Q9>, void, void, void>::run(ctx, args...)
+              : Fn<DevAdapter<BF16Codec, D3Q19>, void, void, void>::run(ctx, args...);
   const bool light = ctx->p.h_lattice == GPLBM_H_LIGHT;
   switch (ctx->p.lattice) {
     case GPLBM_D2Q9:
@@ -458,7 +463,8 @@ struct DiagFn<A, void, void, void> {
 };
 
 int choose_schedule(const gplbm_params& p) {
-  const bool fused_ok = p.precision >= GPLBM_FP16_DEV ? dev_fused_supported(p.nx, p.ny, p.nz, p.bc)
+  const bool fused_ok = p.precision >= GPLBM_FP16_DEV
+                            ? (p.lattice == GPLBM_D2Q9 || dev_fused_supported(p.nx, p.ny, p.nz, p.bc))
                         : two_d(p.lattice)           ? fused2d_supported(p.nx, p.ny)
                                                      : fused3d_supported(p.nx, p.ny, p.nz, p.bc);
   if (p.schedule == GPLBM_SCHED_SPLIT) return GPLBM_SCHED_SPLIT;
@@ -778,8 +784,8 @@ int adj_dispatch_prec(gplbm_ctx* ctx, Args... args) {
     case GPLBM_FP32:
       return Fn<L, LH, FwdState<float>>::run(ctx, args...);
     default:
-      // deviation formats exist for g and h on D3Q19 only
-      if constexpr (std::is_same_v<L, D3Q19> && std::is_same_v<LH, D3Q19>) {
+      // deviation formats exist for g and h on D2Q9 or on D3Q19
+      if constexpr (std::is_same_v<L, LH> && (std::is_same_v<L, D3Q19> || std::is_same_v<L, D2Q9>)) {
         if (ctx->p.precision == GPLBM_FP16_DEV)
           return Fn<L, LH, DevFwdState<F16Codec>>::run(ctx, args...);
         return Fn<L, LH, DevFwdState<BF16Codec>>::run(ctx, args...);

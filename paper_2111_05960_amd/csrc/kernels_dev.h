@@ -1,5 +1,5 @@
-// Reduced-precision storage of the D3Q19 state: the 18 moving populations of
-// each distribution are stored as FP16 or BF16 deviations from the local
+// Reduced-precision storage of the D2Q9 or D3Q19 state: the Q - 1 moving
+// populations of each distribution are stored as FP16 or BF16 deviations from the local
 // equilibrium of the node that wrote them, the rest populations, phi and
 // Lambda = gamma D(phi) mu as FP32.  Collision arithmetic is FP32; the moments
 // (c, phi) and the closure mu(c, phi) are FP64.
@@ -16,9 +16,10 @@
 // to the c it received - the collision conserves c exactly in arithmetic, so
 // this only removes the rounding of the 16-bit encodings from the balance.
 //
-// Layout of one distribution: moving populations u16[z][m][y][x] (m = k for
-// k < 5, k - 1 after the rest vector), then the rest populations
-// f32[z][y][x].
+// Layout of one distribution: moving populations u16[z][m][y][x] (m = k
+// before the rest vector, k - 1 after it), then the rest populations
+// f32[z][y][x].  The per-node kernels take the lattice as a template
+// argument (D3Q19 by default); the fused z-march is D3Q19.
 #pragma once
 
 #include "kernels_fused3d.h"
@@ -51,17 +52,20 @@ struct DevStep {
   DevState nxt;  // written: G = g~*^{n+1}, H = h~*^n, PHI = phi^{n+1}, LAM = Lambda^n
 };
 
-using LD = D3Q19;
+using LD = D3Q19;  // lattice of the fused deviation z-march
 constexpr int kMov = 18;
 
-__device__ __forceinline__ constexpr int mslot(int k) { return k < LD::REST ? k : k - 1; }
+// slot of moving population k among the Q - 1 of lattice L
+template <class L = LD>
+__device__ __forceinline__ constexpr int mslot(int k) { return k < L::REST ? k : k - 1; }
 
 // slot of plane q in a ring of four planes (q >= -8)
 __device__ __forceinline__ int ring4(int q) { return (q + 8) & 3; }
 
+template <class L = LD>
 __device__ __forceinline__ int64_t mov_index(const Geo& g, int k, int x, int y, int z) {
   const int64_t plane = (int64_t)g.nx * g.ny;
-  return ((int64_t)z * kMov + mslot(k)) * plane + (int64_t)y * g.nx + x;
+  return ((int64_t)z * (L::Q - 1) + mslot<L>(k)) * plane + (int64_t)y * g.nx + x;
 }
 
 template <class Codec>
@@ -75,46 +79,46 @@ __device__ __forceinline__ uint16_t dev_encode(float v, float ref) {
 
 // Pull of population k at (x, y, z) from a distribution in the deviation
 // format; ref is the field (phi for g, Lambda for h) of the source node.
-template <class Codec>
+template <class Codec, class L = LD>
 __device__ __forceinline__ float pull_dev(const Geo& g, const DevDist& d, const float* reff, int k,
                                           int x, int y, int z) {
-  if (k == LD::REST) return d.rest[node_index(g, x, y, z)];
+  if (k == L::REST) return d.rest[node_index(g, x, y, z)];
   int sx = x, sy = y, sz = z;
-  const bool in = pull_axis(sx, LD::ex[k], g.nx, g.bcx) && pull_axis(sy, LD::ey[k], g.ny, g.bcy) &&
-                  pull_axis(sz, LD::ez[k], g.nz, g.bcz);
-  const int kk = in ? k : LD::opp[k];
+  const bool in = pull_axis(sx, L::ex[k], g.nx, g.bcx) && pull_axis(sy, L::ey[k], g.ny, g.bcy) &&
+                  pull_axis(sz, L::ez[k], g.nz, g.bcz);
+  const int kk = in ? k : L::opp[k];
   if (!in) sx = x, sy = y, sz = z;
-  const float ref = float(LD::w[kk]) * reff[node_index(g, sx, sy, sz)];
-  return dev_decode<Codec>(d.mov[mov_index(g, kk, sx, sy, sz)], ref);
+  const float ref = float(L::w[kk]) * reff[node_index(g, sx, sy, sz)];
+  return dev_decode<Codec>(d.mov[mov_index<L>(g, kk, sx, sy, sz)], ref);
 }
 
 // Encode the post-collision h of one node with the mass balance of the rest
 // population; hdec receives the decoded values (what readers will see).
-template <class Codec>
-__device__ __forceinline__ void encode_h(const float hs[19], float lam, double c_in,
-                                         uint16_t enc[19], float hdec[19]) {
+template <class Codec, class L = LD>
+__device__ __forceinline__ void encode_h(const float hs[L::Q], float lam, double c_in,
+                                         uint16_t enc[L::Q], float hdec[L::Q]) {
   double s = 0.0;
 #pragma unroll
-  for (int k = 0; k < 19; ++k) {
-    if (k == LD::REST) continue;
-    const float ref = float(LD::w[k]) * lam;
+  for (int k = 0; k < L::Q; ++k) {
+    if (k == L::REST) continue;
+    const float ref = float(L::w[k]) * lam;
     enc[k] = dev_encode<Codec>(hs[k], ref);
     hdec[k] = dev_decode<Codec>(enc[k], ref);
     s = s + double(hdec[k]);
   }
-  hdec[LD::REST] = float(c_in - s);
+  hdec[L::REST] = float(c_in - s);
 }
 
-template <class Codec>
-__device__ __forceinline__ void encode_g(const float gs[19], float phi, uint16_t enc[19],
-                                         float gdec[19]) {
+template <class Codec, class L = LD>
+__device__ __forceinline__ void encode_g(const float gs[L::Q], float phi, uint16_t enc[L::Q],
+                                         float gdec[L::Q]) {
 #pragma unroll
-  for (int k = 0; k < 19; ++k) {
-    if (k == LD::REST) {
+  for (int k = 0; k < L::Q; ++k) {
+    if (k == L::REST) {
       gdec[k] = gs[k];
       continue;
     }
-    const float ref = float(LD::w[k]) * phi;
+    const float ref = float(L::w[k]) * phi;
     enc[k] = dev_encode<Codec>(gs[k], ref);
     gdec[k] = dev_decode<Codec>(enc[k], ref);
   }
@@ -150,7 +154,7 @@ __global__ void __launch_bounds__(256) k_dev_init_fields(Geo g, Coef<float> K,
   s.LAM[i] = h_lambda<float>(K, phi, mu0);
 }
 
-template <class Codec>
+template <class Codec, class L>
 __global__ void __launch_bounds__(256) k_dev_init(Geo g, Coef<float> K,
                                                   const double* __restrict__ c0, DevState s) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -161,109 +165,109 @@ __global__ void __launch_bounds__(256) k_dev_init(Geo g, Coef<float> K,
   const float phi = s.PHI[i];
   const double cin = c0[i];
   float gr[3], n[3];
-  gradient_normal<LD, float>(DevGlobalPhi{g, s.PHI, x, y, z}, K.eps2, gr, n);
+  gradient_normal<L, float>(DevGlobalPhi{g, s.PHI, x, y, z}, K.eps2, gr, n);
   const float mu0 = float(closure(K.cl, K.cs, K.mueq, cin, double(phi)));
-  float G0[19];
-  phi_sources<LD, float>(K, phi, mu0, n, G0);
+  float G0[L::Q];
+  phi_sources<L, float>(K, phi, mu0, n, G0);
   float F[3];
-  h_flux<LD, float>(K, mu0, gr, n, 0.0f, false, F);
+  h_flux<L, float>(K, mu0, gr, n, 0.0f, false, F);
   const float lam = s.LAM[i];
   // h~^0, encoded for the slot (x - e_k, k) or (x, opp k) at a wall
   double c = 0.0;
 #pragma unroll
-  for (int k = 0; k < 19; ++k) {
-    const float hv = h_eq<LD, float>(k, float(cin), lam) - 0.5f * h_source<LD, float>(K, k, F);
+  for (int k = 0; k < L::Q; ++k) {
+    const float hv = h_eq<L, float>(k, float(cin), lam) - 0.5f * h_source<L, float>(K, k, F);
     float dec;
-    if (k == LD::REST) {
+    if (k == L::REST) {
       s.H.rest[i] = hv;
       dec = hv;
     } else {
       int dx = x, dy = y, dz = z;
-      const bool in = pull_axis(dx, LD::ex[k], g.nx, g.bcx) &&
-                      pull_axis(dy, LD::ey[k], g.ny, g.bcy) &&
-                      pull_axis(dz, LD::ez[k], g.nz, g.bcz);
-      const int kk = in ? k : LD::opp[k];
+      const bool in = pull_axis(dx, L::ex[k], g.nx, g.bcx) &&
+                      pull_axis(dy, L::ey[k], g.ny, g.bcy) &&
+                      pull_axis(dz, L::ez[k], g.nz, g.bcz);
+      const int kk = in ? k : L::opp[k];
       if (!in) dx = x, dy = y, dz = z;
-      const float ref = float(LD::w[kk]) * s.LAM[node_index(g, dx, dy, dz)];
+      const float ref = float(L::w[kk]) * s.LAM[node_index(g, dx, dy, dz)];
       const uint16_t e = dev_encode<Codec>(hv, ref);
-      s.H.mov[mov_index(g, kk, dx, dy, dz)] = e;
+      s.H.mov[mov_index<L>(g, kk, dx, dy, dz)] = e;
       dec = dev_decode<Codec>(e, ref);
     }
     c = k == 0 ? double(dec) : c + double(dec);
   }
   // collision of g at time 0 with c^0 = sum of the decoded h~^0
   const float mu = float(closure(K.cl, K.cs, K.mueq, c, double(phi)));
-  float Gk[19], gs[19];
-  phi_sources<LD, float>(K, phi, mu, n, Gk);
+  float Gk[L::Q], gs[L::Q];
+  phi_sources<L, float>(K, phi, mu, n, Gk);
 #pragma unroll
-  for (int k = 0; k < 19; ++k) {
-    const float g0 = float(LD::w[k]) * phi - 0.5f * G0[k];
-    gs[k] = g_collide<LD, float>(K, k, g0, phi, Gk[k]);
+  for (int k = 0; k < L::Q; ++k) {
+    const float g0 = float(L::w[k]) * phi - 0.5f * G0[k];
+    gs[k] = g_collide<L, float>(K, k, g0, phi, Gk[k]);
   }
-  uint16_t enc[19];
-  float gdec[19];
-  encode_g<Codec>(gs, phi, enc, gdec);
+  uint16_t enc[L::Q];
+  float gdec[L::Q];
+  encode_g<Codec, L>(gs, phi, enc, gdec);
 #pragma unroll
-  for (int k = 0; k < 19; ++k) {
-    if (k == LD::REST)
+  for (int k = 0; k < L::Q; ++k) {
+    if (k == L::REST)
       s.G.rest[i] = gdec[k];
     else
-      s.G.mov[mov_index(g, k, x, y, z)] = enc[k];
+      s.G.mov[mov_index<L>(g, k, x, y, z)] = enc[k];
   }
 }
 
 // ---------------------------------------------------------------------------
 // Split schedule in the deviation format (any boundaries).
 
-template <class Codec>
+template <class Codec, class L>
 __global__ void __launch_bounds__(256) k_dev_split_h(Geo g, Coef<float> K, DevStep b) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= g.nx || y >= g.ny) return;
   const int64_t i = node_index(g, x, y, z);
-  float h[19];
+  float h[L::Q];
   double c = 0.0;
 #pragma unroll
-  for (int k = 0; k < 19; ++k) {
-    h[k] = pull_dev<Codec>(g, b.cur.H, b.cur.LAM, k, x, y, z);
+  for (int k = 0; k < L::Q; ++k) {
+    h[k] = pull_dev<Codec, L>(g, b.cur.H, b.cur.LAM, k, x, y, z);
     c = k == 0 ? double(h[k]) : c + double(h[k]);
   }
   const float phi = b.cur.PHI[i];
   const float mu = float(closure(K.cl, K.cs, K.mueq, c, double(phi)));
   float gr[3], n[3];
-  gradient_normal<LD, float>(DevGlobalPhi{g, b.cur.PHI, x, y, z}, K.eps2, gr, n);
+  gradient_normal<L, float>(DevGlobalPhi{g, b.cur.PHI, x, y, z}, K.eps2, gr, n);
   const float sbar = source_moment<float>(K, phi, mu);
   double sg = 0.0;
 #pragma unroll
-  for (int k = 0; k < 19; ++k) {
-    const double v = double(pull_dev<Codec>(g, b.cur.G, b.cur.PHI, k, x, y, z));
+  for (int k = 0; k < L::Q; ++k) {
+    const double v = double(pull_dev<Codec, L>(g, b.cur.G, b.cur.PHI, k, x, y, z));
     sg = k == 0 ? v : sg + v;
   }
   const float phin = float(sg + 0.5 * double(sbar));
   float F[3];
-  h_flux<LD, float>(K, mu, gr, n, phin - phi, K.anti_trapping != 0, F);
+  h_flux<L, float>(K, mu, gr, n, phin - phi, K.anti_trapping != 0, F);
   const float lam = h_lambda<float>(K, phi, mu);
   const float cc = float(c);
-  float hs[19];
+  float hs[L::Q];
 #pragma unroll
-  for (int k = 0; k < 19; ++k)
-    hs[k] = h_collide<LD, float>(K, k, h[k], h_eq<LD, float>(k, cc, lam), h_source<LD, float>(K, k, F));
-  uint16_t enc[19];
-  float hdec[19];
-  encode_h<Codec>(hs, lam, c, enc, hdec);
+  for (int k = 0; k < L::Q; ++k)
+    hs[k] = h_collide<L, float>(K, k, h[k], h_eq<L, float>(k, cc, lam), h_source<L, float>(K, k, F));
+  uint16_t enc[L::Q];
+  float hdec[L::Q];
+  encode_h<Codec, L>(hs, lam, c, enc, hdec);
 #pragma unroll
-  for (int k = 0; k < 19; ++k) {
-    if (k == LD::REST)
+  for (int k = 0; k < L::Q; ++k) {
+    if (k == L::REST)
       b.nxt.H.rest[i] = hdec[k];
     else
-      b.nxt.H.mov[mov_index(g, k, x, y, z)] = enc[k];
+      b.nxt.H.mov[mov_index<L>(g, k, x, y, z)] = enc[k];
   }
   b.nxt.LAM[i] = lam;
   b.nxt.PHI[i] = phin;
 }
 
-template <class Codec>
+template <class Codec, class L>
 __global__ void __launch_bounds__(256) k_dev_split_g(Geo g, Coef<float> K, DevStep b) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -272,35 +276,35 @@ __global__ void __launch_bounds__(256) k_dev_split_g(Geo g, Coef<float> K, DevSt
   const int64_t i = node_index(g, x, y, z);
   double c = 0.0;
 #pragma unroll
-  for (int k = 0; k < 19; ++k) {
-    const double v = double(pull_dev<Codec>(g, b.nxt.H, b.nxt.LAM, k, x, y, z));
+  for (int k = 0; k < L::Q; ++k) {
+    const double v = double(pull_dev<Codec, L>(g, b.nxt.H, b.nxt.LAM, k, x, y, z));
     c = k == 0 ? v : c + v;
   }
   const float phi = b.nxt.PHI[i];
   const float mu = float(closure(K.cl, K.cs, K.mueq, c, double(phi)));
   float gr[3], n[3];
-  gradient_normal<LD, float>(DevGlobalPhi{g, b.nxt.PHI, x, y, z}, K.eps2, gr, n);
-  float G[19], gs[19];
-  phi_sources<LD, float>(K, phi, mu, n, G);
+  gradient_normal<L, float>(DevGlobalPhi{g, b.nxt.PHI, x, y, z}, K.eps2, gr, n);
+  float G[L::Q], gs[L::Q];
+  phi_sources<L, float>(K, phi, mu, n, G);
 #pragma unroll
-  for (int k = 0; k < 19; ++k) {
-    const float gk = pull_dev<Codec>(g, b.cur.G, b.cur.PHI, k, x, y, z);
-    gs[k] = g_collide<LD, float>(K, k, gk, phi, G[k]);
+  for (int k = 0; k < L::Q; ++k) {
+    const float gk = pull_dev<Codec, L>(g, b.cur.G, b.cur.PHI, k, x, y, z);
+    gs[k] = g_collide<L, float>(K, k, gk, phi, G[k]);
   }
-  uint16_t enc[19];
-  float gdec[19];
-  encode_g<Codec>(gs, phi, enc, gdec);
+  uint16_t enc[L::Q];
+  float gdec[L::Q];
+  encode_g<Codec, L>(gs, phi, enc, gdec);
 #pragma unroll
-  for (int k = 0; k < 19; ++k) {
-    if (k == LD::REST)
+  for (int k = 0; k < L::Q; ++k) {
+    if (k == L::REST)
       b.nxt.G.rest[i] = gdec[k];
     else
-      b.nxt.G.mov[mov_index(g, k, x, y, z)] = enc[k];
+      b.nxt.G.mov[mov_index<L>(g, k, x, y, z)] = enc[k];
   }
 }
 
 // read-out and diagnostics in the deviation format
-template <class Codec>
+template <class Codec, class L>
 __global__ void __launch_bounds__(256) k_dev_fields(Geo g, double cl, double cs, double mueq,
                                                     DevState s, double* phi_out, double* c_out,
                                                     double* mu_out) {
@@ -311,8 +315,8 @@ __global__ void __launch_bounds__(256) k_dev_fields(Geo g, double cl, double cs,
   const int64_t i = node_index(g, x, y, z);
   double c = 0.0;
 #pragma unroll
-  for (int k = 0; k < 19; ++k) {
-    const double v = double(pull_dev<Codec>(g, s.H, s.LAM, k, x, y, z));
+  for (int k = 0; k < L::Q; ++k) {
+    const double v = double(pull_dev<Codec, L>(g, s.H, s.LAM, k, x, y, z));
     c = k == 0 ? v : c + v;
   }
   const double phi = double(s.PHI[i]);
@@ -321,7 +325,7 @@ __global__ void __launch_bounds__(256) k_dev_fields(Geo g, double cl, double cs,
   if (mu_out) mu_out[i] = closure(cl, cs, mueq, c, phi);
 }
 
-template <class Codec>
+template <class Codec, class L>
 __global__ void __launch_bounds__(kDiagThreads) k_dev_diag_partial(Geo g, DevState s,
                                                                    double* __restrict__ part) {
   double v[kDiagVals] = {0.0, 0.0, 0.0, 0.0, INFINITY, -INFINITY, 0.0, 0.0};
@@ -332,8 +336,8 @@ __global__ void __launch_bounds__(kDiagThreads) k_dev_diag_partial(Geo g, DevSta
     const int z = int(i / ((int64_t)g.nx * g.ny));
     double c = 0.0;
 #pragma unroll
-    for (int k = 0; k < 19; ++k) {
-      const double hv = double(pull_dev<Codec>(g, s.H, s.LAM, k, x, y, z));
+    for (int k = 0; k < L::Q; ++k) {
+      const double hv = double(pull_dev<Codec, L>(g, s.H, s.LAM, k, x, y, z));
       c = k == 0 ? hv : c + hv;
     }
     const double phi = double(s.PHI[i]);
@@ -602,6 +606,203 @@ struct DevFused3D {
     const int grid = resident_grid(kernel, NT, ntiles, resident);
     if (grid <= 0) return -1;
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(NT), 0, st, g, K, b, tiles_x, tiles_xy, ntiles);
+    return 0;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Fused schedule in the deviation format on D2Q9 (any boundaries): one kernel
+// per step, the 2-D tiling of the FP32 / FP64 fused kernel.  A block owns an
+// output tile T (x-aligned, tiles.h) and computes T grown by one node (T+1):
+//   - phi^n and Lambda^{n-1} of T+2 are staged in LDS; every pull decodes
+//     with the reference (w_k phi or w_k Lambda) of its source node, or of the
+//     node itself for a population bounced back at a wall;
+//   - the threads of T+1 run the h collision of step n, write the 16-bit
+//     codes (nodes of T) and publish the decoded h* to an LDS exchange;
+//   - after one barrier each node of T gathers c^{n+1} from x - e_k in
+//     population order (its own h*_{opp k} where x - e_k lies beyond a
+//     wall), then runs the g collision of step n+1.
+// The values and the order of every sum are those of the split kernels, so
+// the two schedules give identical bits.
+template <int TX, int TY, class Codec>
+__global__ void __launch_bounds__((TileShape<TX, TY>::NT))
+    k_dev_fused2d(Geo g, Coef<float> K, DevStep b, int tiles_x, int ntiles) {
+  using L = D2Q9;
+  constexpr int Q = L::Q;
+  using Shape = TileShape<TX, TY>;
+  constexpr int BX = Shape::BX, BY = Shape::BY, NT = Shape::NT;
+  constexpr int AX = BX + 2, AY = BY + 2;
+  __shared__ float phiA[AY][AX];  // phi^n on T+2
+  __shared__ float lamA[AY][AX];  // Lambda^{n-1} on T+2
+  __shared__ float phiB[BY][BX];  // phi^{n+1} on T+1
+  __shared__ float hx[Q][BY][BX];  // decoded h*^n of T+1 (moving populations)
+
+  int tx, ty;
+  bool valid;
+  Shape::node(threadIdx.x, tx, ty, valid);
+
+  for (int tile = first_tile(); tile < ntiles; tile += gridDim.x) {
+  const int X0 = (tile % tiles_x) * TX, Y0 = (tile / tiles_x) * TY;
+  for (int l = threadIdx.x; l < AX * AY; l += NT) {
+    const int lx = l % AX, ly = l / AX;
+    int vx = X0 - 2 + lx, vy = Y0 - 2 + ly;
+    vx = g.bcx ? min(max(vx, 0), g.nx - 1) : wrap_coord(vx, g.nx);
+    vy = g.bcy ? min(max(vy, 0), g.ny - 1) : wrap_coord(vy, g.ny);
+    const int64_t j = node_index(g, vx, vy, 0);
+    phiA[ly][lx] = b.cur.PHI[j];
+    lamA[ly][lx] = b.cur.LAM[j];
+  }
+
+  const int ux = X0 - 1 + tx, uy = Y0 - 1 + ty;  // unwrapped node of this thread
+  const bool in_x = ux >= 0 && ux < g.nx, in_y = uy >= 0 && uy < g.ny;
+  const bool active = valid && (in_x || !g.bcx) && (in_y || !g.bcy);
+  const bool out = valid && in_x && in_y && tx >= 1 && tx <= TX && ty >= 1 && ty <= TY;
+  const int x = g.bcx ? ux : wrap_coord(ux, g.nx);
+  const int y = g.bcy ? uy : wrap_coord(uy, g.ny);
+  const int64_t i = active ? node_index(g, x, y, 0) : 0;
+  const int xm = (g.bcx && ux == 0) ? 0 : -1, xp = (g.bcx && ux == g.nx - 1) ? 0 : 1;
+  const int ym = (g.bcy && uy == 0) ? 0 : -1, yp = (g.bcy && uy == g.ny - 1) ? 0 : 1;
+  // population k of this node comes from x - e_k, or bounces back at a wall
+  auto inside = [&](int k) {
+    const int sx = ux - L::ex[k], sy = uy - L::ey[k];
+    return !((g.bcx && (sx < 0 || sx >= g.nx)) || (g.bcy && (sy < 0 || sy >= g.ny)));
+  };
+  // pull of population k from a distribution in the deviation format, the
+  // reference field of the source node read from its T+2 tile
+  auto pull_tile = [&](const DevDist& d, const float (*ref)[AX], int k) -> float {
+    if (k == L::REST) return d.rest[i];
+    int sx = x, sy = y, kk = k, rx = tx + 1, ry = ty + 1;
+    if (inside(k)) {
+      pull_axis(sx, L::ex[k], g.nx, g.bcx);
+      pull_axis(sy, L::ey[k], g.ny, g.bcy);
+      rx -= L::ex[k];
+      ry -= L::ey[k];
+    } else {
+      kk = L::opp[k];
+    }
+    const float r = float(L::w[kk]) * ref[ry][rx];
+    return dev_decode<Codec>(d.mov[mov_index<L>(g, kk, sx, sy, 0)], r);
+  };
+  __syncthreads();
+
+  float gn[Q];          // g~^{n+1}
+  float hdec[Q];        // h~*^n as readers decode it
+  float phin = 0.0f;
+  if (active) {
+    float h[Q];
+    double c = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      h[k] = pull_tile(b.cur.H, lamA, k);
+      c = k == 0 ? double(h[k]) : c + double(h[k]);
+    }
+    double sg = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      gn[k] = pull_tile(b.cur.G, phiA, k);
+      sg = k == 0 ? double(gn[k]) : sg + double(gn[k]);
+    }
+    const float phi = phiA[ty + 1][tx + 1];
+    const float mu = float(closure(K.cl, K.cs, K.mueq, c, double(phi)));
+    auto at = [&](int dx, int dy, int) -> float {
+      const int ox = dx < 0 ? xm : (dx > 0 ? xp : 0);
+      const int oy = dy < 0 ? ym : (dy > 0 ? yp : 0);
+      return phiA[ty + 1 + oy][tx + 1 + ox];
+    };
+    float gr[3], n[3];
+    gradient_normal<L, float>(at, K.eps2, gr, n);
+    const float sbar = source_moment<float>(K, phi, mu);
+    phin = float(sg + 0.5 * double(sbar));
+    float F[3];
+    h_flux<L, float>(K, mu, gr, n, phin - phi, K.anti_trapping != 0, F);
+    const float lam = h_lambda<float>(K, phi, mu);
+    const float cc = float(c);
+    float hs[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      hs[k] = h_collide<L, float>(K, k, h[k], h_eq<L, float>(k, cc, lam), h_source<L, float>(K, k, F));
+    uint16_t enc[Q];
+    encode_h<Codec, L>(hs, lam, c, enc, hdec);
+    if (out) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+        if (k != L::REST) b.nxt.H.mov[mov_index<L>(g, k, x, y, 0)] = enc[k];
+      b.nxt.H.rest[i] = hdec[L::REST];
+      b.nxt.LAM[i] = lam;
+      b.nxt.PHI[i] = phin;
+    }
+  }
+  if (valid) {
+    phiB[ty][tx] = phin;
+    if (active) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+        if (k != L::REST) hx[k][ty][tx] = hdec[k];
+    }
+  }
+  __syncthreads();
+
+  if (out) {
+    double c1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      float v;
+      if (k == L::REST)
+        v = hdec[k];
+      else if (inside(k))
+        v = hx[k][ty - L::ey[k]][tx - L::ex[k]];
+      else
+        v = hdec[L::opp[k]];
+      c1 = k == 0 ? double(v) : c1 + double(v);
+    }
+    const float phi1 = phiB[ty][tx];
+    const float mu1 = float(closure(K.cl, K.cs, K.mueq, c1, double(phi1)));
+    auto at1 = [&](int dx, int dy, int) -> float {
+      const int ox = dx < 0 ? xm : (dx > 0 ? xp : 0);
+      const int oy = dy < 0 ? ym : (dy > 0 ? yp : 0);
+      return phiB[ty + oy][tx + ox];
+    };
+    float gr[3], n[3];
+    gradient_normal<L, float>(at1, K.eps2, gr, n);
+    float G[Q], gs[Q];
+    phi_sources<L, float>(K, phi1, mu1, n, G);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) gs[k] = g_collide<L, float>(K, k, gn[k], phi1, G[k]);
+    uint16_t genc[Q];
+    float gdec[Q];
+    encode_g<Codec, L>(gs, phi1, genc, gdec);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      if (k == L::REST)
+        b.nxt.G.rest[i] = gdec[k];
+      else
+        b.nxt.G.mov[mov_index<L>(g, k, x, y, 0)] = genc[k];
+    }
+  }
+  __syncthreads();  // the LDS tiles are refilled by the next tile
+  }
+}
+
+// output rows per tile of the fused 2-D deviation kernel: 64 x 13 outputs,
+// 1024 threads, one block per CU (1024^2 step: 55 us, against 62 / 70 / 74 /
+// 78 us at 12 / 8 / 5 / 4 rows, the last two with two blocks per CU)
+#ifndef GPLBM_DEV2_TY
+#define GPLBM_DEV2_TY 13
+#endif
+
+template <class Codec>
+struct DevFused2D {
+  static int launch(const Geo& g, const Coef<float>& K, const DevStep& b, hipStream_t st) {
+    constexpr int TX = 64, TY = GPLBM_DEV2_TY;
+    constexpr int NT = TileShape<TX, TY>::NT;
+    auto kernel = k_dev_fused2d<TX, TY, Codec>;
+    const int tiles_x = (g.nx + TX - 1) / TX;
+    const int tiles_y = (g.ny + TY - 1) / TY;
+    const int ntiles = tiles_x * tiles_y;
+    static int resident[64] = {0};
+    const int grid = resident_grid(kernel, NT, ntiles, resident);
+    if (grid <= 0) return -1;
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(NT), 0, st, g, K, b, tiles_x, ntiles);
     return 0;
   }
 };

@@ -194,16 +194,19 @@ def test_fp32_forward_gradients_close_to_fp64(adj):
 
 
 @pytest.mark.parametrize("prec,bar", [("fp16dev", 1e-3), ("bf16dev", 1e-2)])
-@pytest.mark.parametrize("geom", ["periodic48", "crop32"])
+@pytest.mark.parametrize("geom", ["periodic48", "crop32", "porous2d96"])
 def test_deviation_forward_gradients_close_to_fp64(adj, prec, bar, geom):
-    """Forward in a deviation storage format (D3Q19), FP64 reverse sweep at
-    the decoded states: the gradients of J1 and J2 agree with the FP64 run's.
-    The periodic box runs the fused deviation kernel, the zero-flux crop the
-    split kernels.  Bar: after 55 steps the FP16 (BF16) trajectory departs
+    """Forward in a deviation storage format, FP64 reverse sweep at the
+    decoded states: the gradients of J1 and J2 agree with the FP64 run's.
+    The periodic D3Q19 box runs the fused deviation kernel, the zero-flux
+    crop and the D2Q9 porous medium (96^2, periodic) the split kernels.  Bar: after 55 steps the FP16 (BF16) trajectory departs
     from the FP64 one by ~3e-5 (~3e-4) in phi and the gradient is a smooth
     function of the states, so 1e-3 (1e-2) relative over 100 steps leaves
     more than an order of magnitude of margin."""
-    p, phi0, c0 = wl.config_porous3d(48)
+    if geom == "porous2d96":
+        p, phi0, c0, _ = wl.config_porous2d(n=96)
+    else:
+        p, phi0, c0 = wl.config_porous3d(48)
     if geom == "crop32":
         p, phi0, c0 = wl.crop_zero_flux(p, phi0, c0, 32)
     K = 100

@@ -1,8 +1,10 @@
-"""FP16 / BF16 deviation storage of the D3Q19 state, through the C ABI.
+"""FP16 / BF16 deviation storage of the D3Q19 and D2Q9 states, through the
+C ABI.
 
 Bars:
   - the fused and the split schedule give identical bits (same float
-    arithmetic on the same decoded values);
+    arithmetic on the same decoded values; the D3Q19 z-march and the D2Q9
+    tile kernel);
   - against the FP64 oracle, the interface-position error
     d_int = max over 0.1 < phi < 0.9 of |phi_dev - phi_ref| / |grad phi_ref|
     stays below 1e-3 lattice units with FP16 storage.  BF16 keeps 8
@@ -49,11 +51,16 @@ def test_dev_fused_equals_split(gp, prec):
         assert np.array_equal(x, y)
 
 
+def _lattice(shape):
+    return wl.D2Q9 if shape[0] == 1 else wl.D3Q19
+
+
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("case", [((32, 32, 32), (0, 0, 0)), ((24, 20, 28), (1, 1, 1))])
+@pytest.mark.parametrize("case", [((32, 32, 32), (0, 0, 0)), ((24, 20, 28), (1, 1, 1)),
+                                  ((1, 96, 128), (0, 0, 0)), ((1, 70, 90), (1, 1, 0))])
 def test_dev_against_oracle(gp, oracle_mod, prec, case):
     shape, bc = case
-    p = wl.base_params(lattice=wl.D3Q19, shape=shape, bc=bc)
+    p = wl.base_params(lattice=_lattice(shape), shape=shape, bc=bc)
     phi0, c0 = wl.random_state_fields(shape, seed=23)
     steps = 300
     sim = gp.Simulation(p, prec).init(phi0, c0)
@@ -75,9 +82,25 @@ def test_dev_against_oracle(gp, oracle_mod, prec, case):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_dev_checkpoint_resume(gp, prec):
-    shape = (16, 20, 24)
-    p = wl.base_params(lattice=wl.D3Q19, shape=shape, bc=(0, 0, 0))
+@pytest.mark.parametrize("case", [((1, 70, 150), (0, 0, 0)), ((1, 53, 91), (1, 1, 0)),
+                                  ((1, 40, 130), (1, 0, 0)), ((1, 33, 64), (0, 1, 0))])
+def test_dev_d2q9_fused_equals_split(gp, prec, case):
+    """D2Q9 deviation storage: the fused tile kernel (walls handled in the
+    block) and the split kernels give identical bits; ragged tiles."""
+    shape, bc = case
+    p = wl.base_params(lattice=wl.D2Q9, shape=shape, bc=bc)
+    phi0, c0 = wl.random_state_fields(shape, seed=27)
+    a = gp.Simulation(p, prec, "split").init(phi0, c0).step(15)
+    b = gp.Simulation(p, prec, "fused").init(phi0, c0).step(15)
+    assert b.schedule == "fused" and a.schedule == "split"
+    for x, y in zip(a.fields(), b.fields()):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("shape", [(16, 20, 24), (1, 40, 52)])
+def test_dev_checkpoint_resume(gp, prec, shape):
+    p = wl.base_params(lattice=_lattice(shape), shape=shape, bc=(0, 0, 0))
     phi0, c0 = wl.random_state_fields(shape, seed=25)
     a = gp.Simulation(p, prec).init(phi0, c0).step(5)
     ck = a.checkpoint()

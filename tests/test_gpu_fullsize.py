@@ -107,6 +107,12 @@ def test_fullsize_grain1024_fp64():
     _check(p, phi0, c0, "fp64", 0.0)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp16dev", 1e-4), ("bf16dev", 1e-3)])
+def test_fullsize_grain1024_deviation_storage(prec, tol):
+    p, phi0, c0, _ = wl.config1()
+    _check(p, phi0, c0, prec, tol)
+
+
 # the variant forms of the 512^3 step that bench.py times (FP64, bit-exact):
 # h on D3Q7; g and h on D3Q7; h^eq,alt; general free energies with
 # eps_l / eps_s = 1.5 and the minima at the coexistence compositions

@@ -51,6 +51,31 @@ def test_state_bytes_layout(lib):
         assert B.gplbm_state_bytes(cp) >= 4 * pop + 2 * phi
 
 
+@pytest.mark.parametrize("prec", ["fp16dev", "bf16dev"])
+@pytest.mark.parametrize("lattice,shape,q", [(wl.D3Q19, (16, 12, 10), 19), (wl.D2Q9, (1, 12, 10), 9)])
+def test_state_bytes_layout_deviation(lib, prec, lattice, shape, q):
+    """Deviation formats: each distribution is Q - 1 16-bit moving
+    populations and an FP32 rest population per node; phi and Lambda FP32."""
+    n = shape[0] * shape[1] * shape[2]
+    rnd = lambda v: (v + 255) // 256 * 256
+    cp = B.make_params(wl.base_params(lattice=lattice, shape=shape, bc=(0, 0, 0)), prec)
+    dist = rnd((q - 1) * n * 2) + rnd(n * 4)
+    assert B.gplbm_checkpoint_bytes(cp) == 2 * dist + 2 * rnd(n * 4)
+    assert B.gplbm_state_bytes(cp) >= 4 * dist + 4 * rnd(n * 4)
+
+
+@pytest.mark.parametrize("prec", ["fp16dev", "bf16dev"])
+def test_deviation_storage_accepted_on_d2q9_and_d3q19_only(lib, prec):
+    for lattice, shape in ((wl.D2Q9, (1, 64, 64)), (wl.D3Q19, (8, 8, 8))):
+        p = wl.base_params(lattice=lattice, shape=shape, bc=(0, 0, 0))
+        assert B.gplbm_state_bytes(B.make_params(p, prec)) > 0
+    for lattice, shape in ((wl.D2Q5, (1, 64, 64)), (wl.D3Q7, (8, 8, 8))):
+        p = wl.base_params(lattice=lattice, shape=shape, bc=(0, 0, 0))
+        with pytest.raises(B.GplbmError) as e:
+            B.gplbm_state_bytes(B.make_params(p, prec))
+        assert e.value.code == B.GPLBM_E_INVALID
+
+
 @pytest.mark.parametrize("lattice,shape,qg,qh", [
     (wl.D3Q19, (16, 12, 10), 19, 7), (wl.D2Q9, (1, 12, 10), 9, 5)])
 def test_state_bytes_layout_light_h(lib, lattice, shape, qg, qh):
