@@ -167,10 +167,14 @@ def adjoint_bytes_per_node(Q: int, D: int, precision: str) -> int:
                      writes A1 (Q), A2 (D), A3, A4, the lambda accumulator
       second kernel: reads  B1 of the previous step (Q), A3, A4, A2 (D),
                      H^n (Q), phi^n, phi^{n+1}, both accumulators;
-                     writes B1 (Q), B2, B3 (D), B4, both accumulators"""
-    fwd = 8 if precision == "fp64" else 4
+                     writes B1 (Q), B2, B3 (D), B4, both accumulators
+    A deviation-format state is read as Q - 1 16-bit codes, the FP32 rest
+    population and the FP32 Lambda the decode needs per H read, FP32 phi."""
     adj_values = (Q + 1 + D + 1 + 1) + (Q + D + 1 + 1 + 1) \
         + (Q + 1 + 1 + D + 2) + (Q + 1 + D + 1 + 2)
+    if precision in ("fp16dev", "bf16dev"):
+        return 8 * adj_values + 2 * ((Q - 1) * 2 + 4 + 4) + 3 * 4
+    fwd = 8 if precision == "fp64" else 4
     fwd_values = (Q + 1) + (Q + 1 + 1)
     return 8 * adj_values + fwd * fwd_values
 
@@ -219,7 +223,8 @@ def time_reverse_steps(n, precision, log, reps=200):
 
 def time_adjoint(K, log, n=512, precision="fp64"):
     """Differentiation workload: 2-D porous medium n^2 (D2Q9, periodic), K
-    steps (FP64, or FP32 forward states with the FP64 reverse sweep);
+    steps (FP64, or FP32 / FP16-deviation forward states with the FP64
+    reverse sweep);
     gradients of the final solid fraction with respect to lambda, D_l and
     phi0 through the hand-written adjoint with sqrt(K) checkpointing.
     Returns forward and backward wall times (the backward phase rebuilds each
@@ -558,6 +563,7 @@ def main():
     if args.adjoint_steps > 0:
         adj = time_adjoint(args.adjoint_steps, log)
         adj["fp32_forward"] = time_adjoint(args.adjoint_steps, log, precision="fp32")
+        adj["fp16dev_forward"] = time_adjoint(args.adjoint_steps, log, precision="fp16dev")
 
     if args.calibration_copy:
         calibration_copy(log)
