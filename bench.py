@@ -324,6 +324,32 @@ def calibration_copy(log, gib=4):
     torch.cuda.empty_cache()
 
 
+def stream_ceiling(log, gib=4, reps=10):
+    """Rate of a plain read + write stream on this GPU (one elementwise
+    negation, gib GiB in and gib GiB out, FP64), timed with HIP events over
+    reps launches: the practical ceiling for a kernel that reads and writes
+    in similar amounts, beside the 8 TB/s peak."""
+    import torch
+    n = gib * (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.neg(a, out=b)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        torch.neg(a, out=b)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = 2 * n * 8 / (ms * 1e-3) / 1e9
+    log(f"stream ceiling: {gbs:.0f} GB/s ({gib} GiB read + {gib} GiB written, {ms:.3f} ms)")
+    del a, b
+    torch.cuda.empty_cache()
+    return round(gbs, 1)
+
+
 def summarize_profile(kind, dbs, out, workload, precision, schedule):
     """Turn rocprofv3 database(s) into the text/JSON summaries kept under
     profiles/.  kind: 'trace' (kernel trace statistics) or 'traffic'
@@ -572,6 +598,11 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(form_params(p, *variant), phi0, c0, log)
     traffic = stored_traffic(args.workload, main_form, main_res["schedule"])
+    ceiling = stream_ceiling(log)
+    # rate of the bytes the step actually moves (the profiled counters), over
+    # the stream ceiling measured here
+    traffic_rate = None if traffic is None else \
+        traffic["bytes_per_step"] / (main_res["ms_per_step"] * 1e-3) / 1e9
 
     nz, ny, nx = p["shape"]
     achieved = main_res["achieved_gbs"]
@@ -617,6 +648,10 @@ def main():
             "kernel": "step (all launches of one time step)",
             "bytes_per_node_step": main_res["bytes_per_node_step"],
             "launches_per_step": main_res["launches_per_step"],
+            "stream_ceiling_gbs": ceiling,
+            "stream_ceiling_kernel": "FP64 negation, 4 GiB read + 4 GiB written (torch.neg)",
+            "traffic_rate_gbs": None if traffic_rate is None else round(traffic_rate, 1),
+            "traffic_rate_frac_of_ceiling": None if traffic_rate is None else round(traffic_rate / ceiling, 4),
         },
         "cpu_baseline": cpu,
         "checks": {"mass_drift_rel": main_res["mass_drift_rel"], "nonfinite": main_res["nonfinite"]},
