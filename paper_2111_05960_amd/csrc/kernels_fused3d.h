@@ -141,13 +141,14 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   constexpr int NT = Shape::NT;
   constexpr int PHI_PER_THREAD = (AX * AY + NT - 1) / NT;
   constexpr bool kRegs = kCarryMode == Carry::kRegisters;
-  // In-block streaming of h*: where the LDS and the registers allow it (a
-  // register carry and one lattice lighter than D3Q19), the post-collision
-  // h* of the plane go to an LDS exchange that the readers gather from after
-  // one barrier, keeping their partial sums of c^{n+1} in registers;
-  // otherwise they are pushed into an accumulator ring in NPASS ordered
-  // passes.  Both sum every c^{n+1} in population order.
-  constexpr bool kGather = kRegs && !(Q == 19 && QH == 19);
+  // In-block streaming of h*: with the register carry of g the LDS has room
+  // for an exchange of the post-collision h* of the plane, which the readers
+  // gather from after one barrier, keeping their partial sums of c^{n+1} in
+  // registers (g and h on D3Q19 in FP32 spills 8-11 VGPRs doing so and is
+  // still faster, 10.0 against 10.6 ms at 512^3); with the LDS carry (FP64
+  // D3Q19) they are pushed into an accumulator ring in NPASS ordered passes.
+  // Both sum every c^{n+1} in population order.
+  constexpr bool kGather = kRegs;
   __shared__ C phiA[3][AY][AX];  // phi^n, planes p-1, p, p+1
   __shared__ C phiB[3][BY][BX];  // phi^{n+1}, planes p-2, p-1, p
   // c^{n+1} being accumulated (push passes)
