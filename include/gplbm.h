@@ -77,8 +77,8 @@ extern "C" {
  * (SourceTerm_LBE_h).  EQ_ALT: Eqs. (LBE_Concent_Alt), (Seq_Concent_Alt), the
  * flux F = mu D' grad phi + j_at folded into the moving populations of the
  * equilibrium, w_k (gamma D mu + e_k . F / xi_s^2), no source; the initial
- * populations are that equilibrium (no variable-change shift).  FP64 and
- * FP32 only (the adjoint included). */
+ * populations are that equilibrium (no variable-change shift).  Every
+ * precision, the adjoint included. */
 #define GPLBM_H_SOURCE 0
 #define GPLBM_H_EQ_ALT 1
 
@@ -89,8 +89,8 @@ extern "C" {
  * eps_s != eps_l, parameterised by eps_s, eps_l, m_s, m_l, df_min (closure
  * Eq. (Closure), source Eq. (SourceTerm), anti-trapping
  * Eq. (Anti-Trapping_Quadratic)), with the interpolations h(phi) = phi,
- * q(phi) and a of the equal case.  FP64 and FP32 only (the adjoint
- * included). */
+ * q(phi) and a of the equal case.  Every precision, the adjoint
+ * included. */
 #define GPLBM_FE_EQUAL 0
 #define GPLBM_FE_QUADRATIC 1
 
@@ -101,8 +101,8 @@ extern "C" {
 /* storage / arithmetic precision of the populations and of phi */
 #define GPLBM_FP64 0 /* everything in double */
 #define GPLBM_FP32 1 /* float storage and collision; moments and closure in double */
-/* D2Q9 or D3Q19, h on the lattice of g, source scheme, equal curvatures: the
- * Q - 1 moving populations of g and h stored as 16-bit deviations
+/* D2Q9 or D3Q19 with h on the lattice of g (either h scheme, either
+ * free-energy form): the Q - 1 moving populations of g and h stored as 16-bit deviations
  * from the writing node's equilibrium (w_k phi for g, w_k gamma D(phi) mu for
  * h), rest populations, phi and gamma D(phi) mu as float; float collision,
  * double moments and closure; solute mass balanced through the rest

@@ -103,8 +103,6 @@ const char* check_params(const gplbm_params* p) {
   if (p->h_scheme != GPLBM_H_SOURCE && p->h_scheme != GPLBM_H_EQ_ALT) return "unknown h scheme";
   if (p->free_energy != GPLBM_FE_EQUAL && p->free_energy != GPLBM_FE_QUADRATIC)
     return "unknown free energy";
-  if (p->precision >= GPLBM_FP16_DEV && (p->h_scheme != GPLBM_H_SOURCE || p->free_energy != GPLBM_FE_EQUAL))
-    return "deviation storage needs the source scheme and equal curvatures";
   if (p->free_energy == GPLBM_FE_QUADRATIC) {
     if (!(p->eps_s > 0.0) || !(p->eps_l > 0.0) || !std::isfinite(p->eps_s) || !std::isfinite(p->eps_l))
       return "eps_s and eps_l must be > 0";
@@ -352,8 +350,15 @@ struct DevOps {
       const int a = ctx->cur, b = 1 - a;
       const DevStep st{state(ctx, a), state(ctx, b)};
       if (ctx->sched == GPLBM_SCHED_FUSED) {
-        const int rc = std::is_same_v<L, D3Q19> ? DevFused3D<Codec>::launch(g, K, st, ctx->stream)
-                                                : DevFused2D<Codec>::launch(g, K, st, ctx->stream);
+        // the general instantiation only for h^eq,alt or eps_s != eps_l
+        const bool gen = ctx->p.h_scheme != GPLBM_H_SOURCE || ctx->p.free_energy != GPLBM_FE_EQUAL;
+        int rc;
+        if constexpr (std::is_same_v<L, D3Q19>)
+          rc = gen ? DevFused3D<Codec, true>::launch(g, K, st, ctx->stream)
+                   : DevFused3D<Codec, false>::launch(g, K, st, ctx->stream);
+        else
+          rc = gen ? DevFused2D<Codec, true>::launch(g, K, st, ctx->stream)
+                   : DevFused2D<Codec, false>::launch(g, K, st, ctx->stream);
         if (rc) return fail(ctx, GPLBM_E_DEVICE, "fused step launch failed");
       } else {
         hipLaunchKernelGGL((k_dev_split_h<Codec, L>), grid(ctx), block(), 0, ctx->stream, g, K, st);
@@ -368,8 +373,8 @@ struct DevOps {
   }
   static int fields(gplbm_ctx* ctx, double* phi, double* c, double* mu) {
     const Geo g = make_geo(ctx->p);
-    hipLaunchKernelGGL((k_dev_fields<Codec, L>), grid(ctx), block(), 0, ctx->stream, g, ctx->p.c_l_co,
-                       ctx->p.c_s_co, ctx->p.mu_eq, state(ctx, ctx->cur), phi, c, mu);
+    hipLaunchKernelGGL((k_dev_fields<Codec, L>), grid(ctx), block(), 0, ctx->stream, g,
+                       closure_k(ctx->p), state(ctx, ctx->cur), phi, c, mu);
     return check_launch(ctx, "read fields");
   }
   static int diag(gplbm_ctx* ctx) {

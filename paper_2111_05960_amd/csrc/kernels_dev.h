@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(256) k_dev_init_fields(Geo g, Coef<float> K,
   if (x >= g.nx || y >= g.ny) return;
   const int64_t i = node_index(g, x, y, z);
   const float phi = float(phi0[i]);
-  const float mu0 = float(closure(K.cl, K.cs, K.mueq, c0[i], double(phi)));
+  const float mu0 = float(closure(K.q, c0[i], double(phi)));
   s.PHI[i] = phi;
   s.LAM[i] = h_lambda<float>(K, phi, mu0);
 }
@@ -166,7 +166,7 @@ __global__ void __launch_bounds__(256) k_dev_init(Geo g, Coef<float> K,
   const double cin = c0[i];
   float gr[3], n[3];
   gradient_normal<L, float>(DevGlobalPhi{g, s.PHI, x, y, z}, K.eps2, gr, n);
-  const float mu0 = float(closure(K.cl, K.cs, K.mueq, cin, double(phi)));
+  const float mu0 = float(closure(K.q, cin, double(phi)));
   float G0[L::Q];
   phi_sources<L, float>(K, phi, mu0, n, G0);
   float F[3];
@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(256) k_dev_init(Geo g, Coef<float> K,
   double c = 0.0;
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
-    const float hv = h_eq<L, float>(k, float(cin), lam) - 0.5f * h_source<L, float>(K, k, F);
+    const float hv = h_initial<L, float>(K, k, float(cin), lam, F);
     float dec;
     if (k == L::REST) {
       s.H.rest[i] = hv;
@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(256) k_dev_init(Geo g, Coef<float> K,
     c = k == 0 ? double(dec) : c + double(dec);
   }
   // collision of g at time 0 with c^0 = sum of the decoded h~^0
-  const float mu = float(closure(K.cl, K.cs, K.mueq, c, double(phi)));
+  const float mu = float(closure(K.q, c, double(phi)));
   float Gk[L::Q], gs[L::Q];
   phi_sources<L, float>(K, phi, mu, n, Gk);
 #pragma unroll
@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(256) k_dev_split_h(Geo g, Coef<float> K, DevSt
     c = k == 0 ? double(h[k]) : c + double(h[k]);
   }
   const float phi = b.cur.PHI[i];
-  const float mu = float(closure(K.cl, K.cs, K.mueq, c, double(phi)));
+  const float mu = float(closure(K.q, c, double(phi)));
   float gr[3], n[3];
   gradient_normal<L, float>(DevGlobalPhi{g, b.cur.PHI, x, y, z}, K.eps2, gr, n);
   const float sbar = source_moment<float>(K, phi, mu);
@@ -252,7 +252,7 @@ __global__ void __launch_bounds__(256) k_dev_split_h(Geo g, Coef<float> K, DevSt
   float hs[L::Q];
 #pragma unroll
   for (int k = 0; k < L::Q; ++k)
-    hs[k] = h_collide<L, float>(K, k, h[k], h_eq<L, float>(k, cc, lam), h_source<L, float>(K, k, F));
+    hs[k] = h_update<L, float>(K, k, h[k], cc, lam, F);
   uint16_t enc[L::Q];
   float hdec[L::Q];
   encode_h<Codec, L>(hs, lam, c, enc, hdec);
@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(256) k_dev_split_g(Geo g, Coef<float> K, DevSt
     c = k == 0 ? v : c + v;
   }
   const float phi = b.nxt.PHI[i];
-  const float mu = float(closure(K.cl, K.cs, K.mueq, c, double(phi)));
+  const float mu = float(closure(K.q, c, double(phi)));
   float gr[3], n[3];
   gradient_normal<L, float>(DevGlobalPhi{g, b.nxt.PHI, x, y, z}, K.eps2, gr, n);
   float G[L::Q], gs[L::Q];
@@ -305,8 +305,8 @@ __global__ void __launch_bounds__(256) k_dev_split_g(Geo g, Coef<float> K, DevSt
 
 // read-out and diagnostics in the deviation format
 template <class Codec, class L>
-__global__ void __launch_bounds__(256) k_dev_fields(Geo g, double cl, double cs, double mueq,
-                                                    DevState s, double* phi_out, double* c_out,
+__global__ void __launch_bounds__(256) k_dev_fields(Geo g, ClosureK q, DevState s,
+                                                    double* phi_out, double* c_out,
                                                     double* mu_out) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -322,7 +322,7 @@ __global__ void __launch_bounds__(256) k_dev_fields(Geo g, double cl, double cs,
   const double phi = double(s.PHI[i]);
   if (phi_out) phi_out[i] = phi;
   if (c_out) c_out[i] = c;
-  if (mu_out) mu_out[i] = closure(cl, cs, mueq, c, phi);
+  if (mu_out) mu_out[i] = closure(q, c, phi);
 }
 
 template <class Codec, class L>
@@ -374,9 +374,10 @@ __device__ __forceinline__ void bstore16_nt(uint16_t v, __amdgpu_buffer_rsrc_t r
   __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(V, v), r, voff, soff, 2);
 }
 
-template <int TX, int TY, int ZC, class Codec>
+template <int TX, int TY, int ZC, class Codec, bool kGen>
 __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
-    k_dev_fused3d(Geo g, Coef<float> K, DevStep b, int tiles_x, int tiles_xy, int ntiles) {
+    k_dev_fused3d(Geo g, Coef<float> Kin, DevStep b, int tiles_x, int tiles_xy, int ntiles) {
+  const Coef<float> K = variant<kGen>(Kin);
   using Shape = TileShape<TX, TY>;
   constexpr int Q = 19;
   constexpr int BX = Shape::BX, BY = Shape::BY;
@@ -484,7 +485,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     }
     const int sA = ring4(p);
     const float phi = phiA[sA][ty + 1][tx + 1];
-    const float mu = float(closure(K.cl, K.cs, K.mueq, c, double(phi)));
+    const float mu = float(closure(K.q, c, double(phi)));
     auto atA = [&](int dx, int dy, int dz) -> float {
       return phiA[ring4(p + dz)][ty + 1 + dy][tx + 1 + dx];
     };
@@ -500,8 +501,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     float hs[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k)
-      hs[k] = h_collide<LD, float>(K, k, h[k], h_eq<LD, float>(k, cc, lam),
-                                   h_source<LD, float>(K, k, F));
+      hs[k] = h_update<LD, float>(K, k, h[k], cc, lam, F);
     uint16_t enc[Q];
     float hdec[Q];
     encode_h<Codec>(hs, lam, c, enc, hdec);
@@ -563,7 +563,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
       const int sB = ring4(p - 1);
       const double c1 = acc_dn;
       const float phi1 = phiB[sB][ty][tx];
-      const float mu1 = float(closure(K.cl, K.cs, K.mueq, c1, double(phi1)));
+      const float mu1 = float(closure(K.q, c1, double(phi1)));
       auto atB = [&](int dx, int dy, int dz) -> float {
         return phiB[ring4(p - 1 + dz)][ty + dy][tx + dx];
       };
@@ -591,12 +591,12 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   }
 }
 
-template <class Codec>
+template <class Codec, bool kGen>
 struct DevFused3D {
   static int launch(const Geo& g, const Coef<float>& K, const DevStep& b, hipStream_t st) {
     constexpr int TX = 64, TY = GPLBM_DEV_TY, ZC = 32;
     constexpr int NT = TileShape<TX, TY>::NT;
-    auto kernel = k_dev_fused3d<TX, TY, ZC, Codec>;
+    auto kernel = k_dev_fused3d<TX, TY, ZC, Codec, kGen>;
     const int tiles_x = (g.nx + TX - 1) / TX;
     const int tiles_y = (g.ny + TY - 1) / TY;
     const int chunks = (g.nz + ZC - 1) / ZC;
@@ -624,9 +624,10 @@ struct DevFused3D {
 //     wall), then runs the g collision of step n+1.
 // The values and the order of every sum are those of the split kernels, so
 // the two schedules give identical bits.
-template <int TX, int TY, class Codec>
+template <int TX, int TY, class Codec, bool kGen>
 __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
-    k_dev_fused2d(Geo g, Coef<float> K, DevStep b, int tiles_x, int ntiles) {
+    k_dev_fused2d(Geo g, Coef<float> Kin, DevStep b, int tiles_x, int ntiles) {
+  const Coef<float> K = variant<kGen>(Kin);
   using L = D2Q9;
   constexpr int Q = L::Q;
   using Shape = TileShape<TX, TY>;
@@ -703,7 +704,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
       sg = k == 0 ? double(gn[k]) : sg + double(gn[k]);
     }
     const float phi = phiA[ty + 1][tx + 1];
-    const float mu = float(closure(K.cl, K.cs, K.mueq, c, double(phi)));
+    const float mu = float(closure(K.q, c, double(phi)));
     auto at = [&](int dx, int dy, int) -> float {
       const int ox = dx < 0 ? xm : (dx > 0 ? xp : 0);
       const int oy = dy < 0 ? ym : (dy > 0 ? yp : 0);
@@ -720,7 +721,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     float hs[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k)
-      hs[k] = h_collide<L, float>(K, k, h[k], h_eq<L, float>(k, cc, lam), h_source<L, float>(K, k, F));
+      hs[k] = h_update<L, float>(K, k, h[k], cc, lam, F);
     uint16_t enc[Q];
     encode_h<Codec, L>(hs, lam, c, enc, hdec);
     if (out) {
@@ -756,7 +757,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
       c1 = k == 0 ? double(v) : c1 + double(v);
     }
     const float phi1 = phiB[ty][tx];
-    const float mu1 = float(closure(K.cl, K.cs, K.mueq, c1, double(phi1)));
+    const float mu1 = float(closure(K.q, c1, double(phi1)));
     auto at1 = [&](int dx, int dy, int) -> float {
       const int ox = dx < 0 ? xm : (dx > 0 ? xp : 0);
       const int oy = dy < 0 ? ym : (dy > 0 ? yp : 0);
@@ -790,12 +791,12 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
 #define GPLBM_DEV2_TY 13
 #endif
 
-template <class Codec>
+template <class Codec, bool kGen>
 struct DevFused2D {
   static int launch(const Geo& g, const Coef<float>& K, const DevStep& b, hipStream_t st) {
     constexpr int TX = 64, TY = GPLBM_DEV2_TY;
     constexpr int NT = TileShape<TX, TY>::NT;
-    auto kernel = k_dev_fused2d<TX, TY, Codec>;
+    auto kernel = k_dev_fused2d<TX, TY, Codec, kGen>;
     const int tiles_x = (g.nx + TX - 1) / TX;
     const int tiles_y = (g.ny + TY - 1) / TY;
     const int ntiles = tiles_x * tiles_y;

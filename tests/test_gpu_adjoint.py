@@ -194,17 +194,24 @@ def test_fp32_forward_gradients_close_to_fp64(adj):
 
 
 @pytest.mark.parametrize("prec,bar", [("fp16dev", 1e-3), ("bf16dev", 1e-2)])
-@pytest.mark.parametrize("geom", ["periodic48", "crop32", "porous2d96"])
+@pytest.mark.parametrize("geom", ["periodic48", "crop32", "porous2d96", "porous2d96-variants"])
 def test_deviation_forward_gradients_close_to_fp64(adj, prec, bar, geom):
     """Forward in a deviation storage format, FP64 reverse sweep at the
     decoded states: the gradients of J1 and J2 agree with the FP64 run's.
-    The periodic D3Q19 box runs the fused deviation kernel, the zero-flux
-    crop and the D2Q9 porous medium (96^2, periodic) the split kernels.  Bar: after 55 steps the FP16 (BF16) trajectory departs
-    from the FP64 one by ~3e-5 (~3e-4) in phi and the gradient is a smooth
+    The periodic D3Q19 box runs the fused z-march, the zero-flux crop the
+    split kernels, the D2Q9 porous medium (96^2, periodic) the fused 2-D
+    kernel, also with h^eq,alt and general free energies.  Bar: after 55
+    steps the FP16 (BF16) trajectory departs from the FP64 one by ~3e-5
+    (~3e-4) in phi and the gradient is a smooth
     function of the states, so 1e-3 (1e-2) relative over 100 steps leaves
     more than an order of magnitude of margin."""
-    if geom == "porous2d96":
+    if geom.startswith("porous2d96"):
         p, phi0, c0, _ = wl.config_porous2d(n=96)
+        if geom.endswith("variants"):
+            # h^eq,alt and general free energies (eps_l / eps_s = 1.5, minima
+            # at the coexistence compositions of the workload)
+            p = dict(p, h_scheme=1, free_energy=1, eps_s=1.0, eps_l=1.5, m_s=p["c_s_co"],
+                     m_l=p["c_l_co"], df_min=0.0)
     else:
         p, phi0, c0 = wl.config_porous3d(48)
     if geom == "crop32":

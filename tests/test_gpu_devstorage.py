@@ -108,3 +108,54 @@ def test_dev_checkpoint_resume(gp, prec, shape):
     b = gp.Simulation(p, prec).init(phi0, c0).restore(ck).step(7)
     for x, y in zip(a.fields(), b.fields()):
         assert np.array_equal(x, y)
+
+
+# the scheme variants in the deviation formats: h^eq,alt (Eqs. LBE_Concent_Alt,
+# Seq_Concent_Alt) and general quadratic free energies (Eqs. Closure,
+# SourceTerm, Anti-Trapping_Quadratic), eps_l / eps_s = 2.3; same bars and the
+# same seeded instance as the base-scheme test (seed 23).  The interface metric
+# divides by |grad phi| over 0.1 < phi < 0.9 and is ill-conditioned on some
+# geometries: on the 70 x 90 walled case with seed 29 the base scheme itself
+# reads 1.9e-3 in FP16 and FP32 reads 1.3e-4 (4x its value elsewhere), with
+# every variant at or below the base scheme there.
+QUAD = dict(free_energy=1, eps_s=1.0, eps_l=2.3, m_s=0.9, m_l=0.12, df_min=0.02)
+VARIANTS = {"alt": dict(h_scheme=1), "quad": QUAD, "alt+quad": dict(QUAD, h_scheme=1)}
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("case", [((32, 32, 32), (0, 0, 0)), ((1, 70, 90), (1, 1, 0))])
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
+def test_dev_variants_against_oracle(gp, oracle_mod, prec, case, variant):
+    shape, bc = case
+    p = wl.base_params(lattice=_lattice(shape), shape=shape, bc=bc, **VARIANTS[variant])
+    phi0, c0 = wl.random_state_fields(shape, seed=23)
+    steps = 300
+    sim = gp.Simulation(p, prec).init(phi0, c0)
+    m0 = sim.diagnostics()["total_mass"]
+    sim.step(steps)
+    m1 = sim.diagnostics()["total_mass"]
+    ref = oracle_mod.Oracle(p).init(phi0, c0).step(steps)
+    phi_r, _, _ = ref.fields()
+    grad_r, _ = ref.gradient()
+    phi_d, _, _ = sim.fields()
+    dint = interface_error(phi_d, phi_r, grad_r)
+    drift = abs(m1 - m0) / abs(m0)
+    print(f"{variant} {prec} {shape} bc={bc}: d_int={dint:.3e} "
+          f"Linf(phi)={np.max(np.abs(phi_d - phi_r)):.3e} mass drift={drift:.3e} "
+          f"schedule={sim.schedule}", flush=True)
+    assert dint <= (1e-3 if prec == "fp16dev" else 1e-2)
+    assert drift <= 1e-6
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("case", [((24, 30, 70), (0, 0, 0)), ((1, 53, 91), (1, 1, 0))])
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
+def test_dev_variants_fused_equals_split(gp, prec, case, variant):
+    shape, bc = case
+    p = wl.base_params(lattice=_lattice(shape), shape=shape, bc=bc, **VARIANTS[variant])
+    phi0, c0 = wl.random_state_fields(shape, seed=31)
+    a = gp.Simulation(p, prec, "split").init(phi0, c0).step(12)
+    b = gp.Simulation(p, prec, "fused").init(phi0, c0).step(12)
+    assert b.schedule == "fused" and a.schedule == "split"
+    for x, y in zip(a.fields(), b.fields()):
+        assert np.array_equal(x, y)
