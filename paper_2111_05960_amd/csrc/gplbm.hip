@@ -755,10 +755,18 @@ struct AdjOps {
     const Coef<double> K = make_coef<double>(ctx->p);
     const int a = ctx->adj_cur, b = 1 - a;
     const FS S0 = FwdFromState<FS>::get(ctx, s0), S1 = FwdFromState<FS>::get(ctx, s1);
-    hipLaunchKernelGGL((k_adj_ra<L, LH, FS>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx),
-                       S1, ctx->adj.set[a], ctx->adj.set[b], ctx->adj);
-    hipLaunchKernelGGL((k_adj_rb<L, LH, FS>), grid(ctx), block(), 0, ctx->stream, g, K, lam_M_W2(ctx),
-                       S0, S1, ctx->adj.set[a], ctx->adj.set[b], ctx->adj);
+    // the general reverse kernels only for h^eq,alt or eps_s != eps_l
+    if (ctx->p.h_scheme != GPLBM_H_SOURCE || ctx->p.free_energy != GPLBM_FE_EQUAL) {
+      hipLaunchKernelGGL((k_adj_ra<L, LH, FS, true>), grid(ctx), block(), 0, ctx->stream, g, K,
+                         lam_M_W2(ctx), S1, ctx->adj.set[a], ctx->adj.set[b], ctx->adj);
+      hipLaunchKernelGGL((k_adj_rb<L, LH, FS, true>), grid(ctx), block(), 0, ctx->stream, g, K,
+                         lam_M_W2(ctx), S0, S1, ctx->adj.set[a], ctx->adj.set[b], ctx->adj);
+    } else {
+      hipLaunchKernelGGL((k_adj_ra<L, LH, FS, false>), grid(ctx), block(), 0, ctx->stream, g, K,
+                         lam_M_W2(ctx), S1, ctx->adj.set[a], ctx->adj.set[b], ctx->adj);
+      hipLaunchKernelGGL((k_adj_rb<L, LH, FS, false>), grid(ctx), block(), 0, ctx->stream, g, K,
+                         lam_M_W2(ctx), S0, S1, ctx->adj.set[a], ctx->adj.set[b], ctx->adj);
+    }
     int rc = check_launch(ctx, "adjoint step");
     if (rc) return rc;
     ctx->adj_cur = b;

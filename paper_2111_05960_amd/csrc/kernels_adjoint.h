@@ -281,9 +281,12 @@ __device__ __forceinline__ double gather_Gb(const Geo& g, const AdjSet& P, int k
   return P.A1[pop_index<L>(g, kk, dx, dy, dz)] + P.B2[node_index(g, dx, dy, dz)];
 }
 
-template <class L, class LH, class FS>
-__global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> K, double lam_M_W2,
+// kGen: the general instantiation keeps the scheme flags (h^eq,alt, general
+// free energies) of the run; the basic one fixes them off at compile time.
+template <class L, class LH, class FS, bool kGen>
+__global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> Kin, double lam_M_W2,
                                                 FS S1, AdjSet P, AdjSet C, AdjWork w) {
+  const Coef<double> K = variant<kGen>(Kin);
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
@@ -315,9 +318,10 @@ __global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> K, double la
   w.lamb[i] += lb;
 }
 
-template <class L, class LH, class FS>
-__global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> K, double lam_M_W2,
+template <class L, class LH, class FS, bool kGen>
+__global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> Kin, double lam_M_W2,
                                                 FS S0, FS S1, AdjSet P, AdjSet C, AdjWork w) {
+  const Coef<double> K = variant<kGen>(Kin);
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
