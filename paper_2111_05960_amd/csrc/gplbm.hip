@@ -198,9 +198,6 @@ Coef<C> make_coef(const gplbm_params& p) {
   K.gamma = C(p.gamma);
   K.eps2 = C(p.eps_n * p.eps_n);
   K.mueq_c = C(p.mu_eq);
-  K.cl = p.c_l_co;
-  K.cs = p.c_s_co;
-  K.mueq = p.mu_eq;
   K.counter_term = p.counter_term ? 1 : 0;
   K.anti_trapping = p.anti_trapping ? 1 : 0;
   K.h_alt = p.h_scheme == GPLBM_H_EQ_ALT ? 1 : 0;

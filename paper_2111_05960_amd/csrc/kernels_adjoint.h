@@ -155,7 +155,7 @@ __device__ __forceinline__ void closure_grad(const Coef<double>& K, double c, do
     dmu_dphi = -fac * (K.q.eps_s - K.q.eps_l) / den * r + fac * (K.q.m_s - K.q.m_l);
   } else {
     dmu_dc = 1.0;
-    dmu_dphi = K.cs - K.cl;
+    dmu_dphi = K.q.cs - K.q.cl;
   }
 }
 

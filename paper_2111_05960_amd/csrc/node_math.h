@@ -75,7 +75,6 @@ struct Coef {
   C Dl, Ds, gamma;
   C eps2;              // eps_n^2
   C mueq_c;            // mu_eq in C
-  double cl, cs, mueq; // closure constants (always double)
   int counter_term, anti_trapping;
   int h_alt;           // 1: relaxation to h^eq,alt without source
   int fe_quad;         // 1: general quadratic free energies
@@ -97,12 +96,6 @@ __device__ __forceinline__ Coef<C> variant(const Coef<C>& K) {
     R.q.quad = 0;
   }
   return R;
-}
-
-__device__ __forceinline__ double closure(double cl, double cs, double mueq, double c,
-                                          double phi) {
-  double cco = (cl * phi) + (cs * (1.0 - phi));
-  return mueq + (c - cco);
 }
 
 // e_k . v with the zero components skipped and -1 as a negation.
