@@ -8,10 +8,11 @@
 //     normal, source moment), forms phi^{n+1} and writes it to an LDS tile,
 //   - runs the h collision of step n (anti-trapping current from
 //     phi^{n+1} - phi^n).
-// The post-collision h* of T+1 are then streamed inside the block: Qh passes,
-// one per population in index order, each adding the population that arrives
-// at every node of T into an LDS accumulator, so that c^{n+1} is summed in the
-// same order as a pull would sum it.  Finally the threads of T run the g
+// The post-collision h* of T+1 are then streamed inside the block: they go to
+// an LDS exchange, and after one barrier every node of T gathers the
+// population k arriving from x - e_k (its own h*_{opp k} where x - e_k lies
+// beyond a wall) in index order, so that c^{n+1} is summed in the same order
+// as a pull would sum it.  Finally the threads of T run the g
 // collision of step n+1 (gradient of phi^{n+1} from the LDS tile) and write
 // g~*^{n+1}, h~*^n and phi^{n+1}.
 //
@@ -35,7 +36,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT), (sizeof(S) == 4 ? 6 :
   constexpr int AX = BX + 2, AY = BY + 2;  // phi^n tile with a 2-node halo
   __shared__ C phiA[AY][AX];
   __shared__ C phiB[BY][BX];
-  __shared__ double acc[BY][BX];
+  __shared__ C hx[LH::Q][BY][BX];  // h*^n of T+1 (moving populations)
 
   int tx, ty;
   bool valid;
@@ -104,35 +105,32 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT), (sizeof(S) == 4 ? 6 :
 #pragma unroll
     for (int k = 0; k < LH::Q; ++k) hs[k] = C(S(h_update<LH, C>(K, k, h[k], cc, lam, F)));
   }
-  if (valid) phiB[ty][tx] = phin_c;
+  if (valid) {
+    phiB[ty][tx] = phin_c;
+    if (active) {
+#pragma unroll
+      for (int k = 0; k < LH::Q; ++k)
+        if (k != LH::REST) hx[k][ty][tx] = hs[k];
+    }
+  }
   __syncthreads();
 
-  // streaming of h* inside the tile: pass k adds the population k arriving
-  // at every output node (from x - e_k, or bounced back at a wall)
+  if (out) {
+  // streaming of h* inside the tile: population k arrives from x - e_k, or
+  // is this node's own h*_{opp k} bounced back where x - e_k is beyond a wall
+  double c1 = 0.0;
 #pragma unroll
   for (int k = 0; k < LH::Q; ++k) {
-    if (active) {
-      const int tx2 = tx + LH::ex[k], ty2 = ty + LH::ey[k];
-      const int vx = ux + LH::ex[k], vy = uy + LH::ey[k];
-      const bool tgt_in = tx2 >= 1 && tx2 <= TX && ty2 >= 1 && ty2 <= TY && vx >= 0 &&
-                          vx < g.nx && vy >= 0 && vy < g.ny;
-      if (tgt_in) {
-        const double v = double(hs[k]);
-        if (k == 0) acc[ty2][tx2] = v;
-        else acc[ty2][tx2] = acc[ty2][tx2] + v;
-      }
-      // population k of this node bounced back: its source x - e_k is beyond a wall
-      if (out && k != LH::REST) {
-        const bool wall = (g.bcx && (ux - LH::ex[k] < 0 || ux - LH::ex[k] >= g.nx)) ||
-                          (g.bcy && (uy - LH::ey[k] < 0 || uy - LH::ey[k] >= g.ny));
-        if (wall) acc[ty][tx] = acc[ty][tx] + double(hs[LH::opp[k]]);
-      }
+    C v;
+    if (k == LH::REST) {
+      v = hs[k];
+    } else {
+      const bool wall = (g.bcx && (ux - LH::ex[k] < 0 || ux - LH::ex[k] >= g.nx)) ||
+                        (g.bcy && (uy - LH::ey[k] < 0 || uy - LH::ey[k] >= g.ny));
+      v = wall ? hs[LH::opp[k]] : hx[k][ty - LH::ey[k]][tx - LH::ex[k]];
     }
-    __syncthreads();
+    c1 = k == 0 ? double(v) : c1 + double(v);
   }
-
-  if (out) {
-  const double c1 = acc[ty][tx];
   const C phi1 = phiB[ty][tx];
   const C mu1 = C(closure(K.q, c1, double(phi1)));
   auto at1 = [&](int dx, int dy, int) -> C {
