@@ -12,7 +12,8 @@ Printed: one JSON line with MLUPS (million node updates per second), the
 HBM roofline of the step kernel (algorithmic bytes per launch over the mean
 launch time, measured with HIP events on the stream the library launches on),
 the other forms of the same step beside it (FP32, FP16 and BF16 deviation
-storage; h, or g and h, on the light lattice D3Q7 / D2Q5 in FP64 and FP32; the alternative
+storage; h, or g and h, on the light lattice D3Q7 / D2Q5 in FP64 and FP32, h on it
+in FP16 deviations; the alternative
 equilibrium h^eq,alt and general quadratic free energies in FP64), the
 differentiation workload (adjoint / forward time), and the CPU oracle timed on
 a bounded crop of the same workload.
@@ -46,8 +47,9 @@ def bytes_per_node_step(lattice_q: int, precision: str, lattice_qh: int | None =
     their h references need)."""
     qh = lattice_q if lattice_qh is None else lattice_qh
     if precision in ("fp16dev", "bf16dev"):
-        dist = (lattice_q - 1) * 2 + 4          # 16-bit moving + FP32 rest
-        return 2 * (2 * dist + 4 + 4)
+        dist_g = (lattice_q - 1) * 2 + 4        # 16-bit moving + FP32 rest
+        dist_h = (qh - 1) * 2 + 4
+        return 2 * (dist_g + dist_h + 4 + 4)
     elem = 8 if precision == "fp64" else 4
     return (2 * lattice_q + 2 * qh + 2) * elem
 
@@ -494,11 +496,11 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp16dev", "bf16dev"])
     ap.add_argument("--h-lattice", default="full", choices=["full", "light", "light-gh"],
                     help="h on the lattice of g, h on D3Q7 / D2Q5, or g and h on D3Q7 / "
-                         "D2Q5 (FP64 and FP32)")
+                         "D2Q5 (the last in FP64 and FP32)")
     ap.add_argument("--h-scheme", default="source", choices=["source", "alt"],
-                    help="source H_k, or h^eq,alt (FP64 and FP32)")
+                    help="source H_k, or h^eq,alt")
     ap.add_argument("--free-energy", default="equal", choices=["equal", "quadratic"],
-                    help="equal curvatures, or general quadratic (FP64 and FP32)")
+                    help="equal curvatures, or general quadratic")
     ap.add_argument("--schedule", default="auto", choices=["auto", "split", "fused"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
@@ -555,6 +557,7 @@ def main():
         precs = ("fp64", "fp32", "fp16dev", "bf16dev")
         todo = ([(prec, "full", "source", "equal") for prec in precs]
                 + [("fp64", "light", "source", "equal"), ("fp32", "light", "source", "equal"),
+                   ("fp16dev", "light", "source", "equal"),
                    ("fp64", "light-gh", "source", "equal"), ("fp32", "light-gh", "source", "equal"),
                    ("fp64", "full", "alt", "equal"), ("fp64", "full", "source", "quadratic")])
         for prec, *var in todo:

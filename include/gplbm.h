@@ -68,8 +68,8 @@ extern "C" {
  * the lattice of the c-LBE open; its equilibrium needs only the zeroth and
  * an isotropic second moment).  The relaxation time becomes
  * tau_h = 1 / (gamma xi_s^2) (3 / gamma, or 4 / gamma on D3Q7) so that the
- * diffusivity stays D(phi); H_k = gamma w_k e_k . F on the h lattice.  FP64
- * and FP32 only (the adjoint included). */
+ * diffusivity stays D(phi); H_k = gamma w_k e_k . F on the h lattice.  Every
+ * precision, the adjoint included. */
 #define GPLBM_H_FULL 0
 #define GPLBM_H_LIGHT 1
 
@@ -101,8 +101,9 @@ extern "C" {
 /* storage / arithmetic precision of the populations and of phi */
 #define GPLBM_FP64 0 /* everything in double */
 #define GPLBM_FP32 1 /* float storage and collision; moments and closure in double */
-/* D2Q9 or D3Q19 with h on the lattice of g (either h scheme, either
- * free-energy form): the Q - 1 moving populations of g and h stored as 16-bit deviations
+/* g on D2Q9 or D3Q19, h on the lattice of g or on the light one (either h
+ * scheme, either free-energy form): the Q - 1 (Qh - 1) moving populations of
+ * g (h) stored as 16-bit deviations
  * from the writing node's equilibrium (w_k phi for g, w_k gamma D(phi) mu for
  * h), rest populations, phi and gamma D(phi) mu as float; float collision,
  * double moments and closure; solute mass balanced through the rest

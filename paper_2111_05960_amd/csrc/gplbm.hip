@@ -29,7 +29,8 @@ struct gplbm_ctx {
   size_t elem;        // bytes per stored phi value
   size_t pop_bytes;   // the g distribution (rounded up)
   size_t hpop_bytes;  // the h distribution (rounded up)
-  size_t mov_bytes;   // deviation formats: the 16-bit moving part of a distribution
+  size_t mov_bytes;   // deviation formats: the 16-bit moving part of the g distribution
+  size_t hmov_bytes;  // and of the h distribution
   size_t phi_bytes;   // N*elem rounded up
   size_t lam_bytes;   // deviation formats: the Lambda field
   char* G[2];
@@ -98,8 +99,6 @@ const char* check_params(const gplbm_params* p) {
     return "deviation storage is implemented for D2Q9 and D3Q19";
   if (p->schedule < GPLBM_SCHED_AUTO || p->schedule > GPLBM_SCHED_FUSED) return "unknown schedule";
   if (p->h_lattice != GPLBM_H_FULL && p->h_lattice != GPLBM_H_LIGHT) return "unknown h lattice";
-  if (p->h_lattice == GPLBM_H_LIGHT && p->precision >= GPLBM_FP16_DEV)
-    return "deviation storage needs h on the lattice of g";
   if (p->h_scheme != GPLBM_H_SOURCE && p->h_scheme != GPLBM_H_EQ_ALT) return "unknown h scheme";
   if (p->free_energy != GPLBM_FE_EQUAL && p->free_energy != GPLBM_FE_QUADRATIC)
     return "unknown free energy";
@@ -123,7 +122,7 @@ const char* check_params(const gplbm_params* p) {
 // Borrowed buffer: G[0], G[1], H[0], H[1], PHI[0], PHI[1], LAM[0], LAM[1],
 // reduction scratch.  A saved state: G, H, PHI, LAM.
 struct Layout {
-  size_t elem, pop, hpop, mov, phi, lam, red, total, ckpt;
+  size_t elem, pop, hpop, mov, hmov, phi, lam, red, total, ckpt;
 };
 
 Layout layout(const gplbm_params* p) {
@@ -134,11 +133,13 @@ Layout layout(const gplbm_params* p) {
     l.elem = 4;
     l.mov = round_up((size_t)(Q - 1) * N * 2);
     l.pop = l.mov + round_up((size_t)N * 4);
-    l.hpop = l.pop;
+    l.hmov = round_up((size_t)(lattice_qh(p) - 1) * N * 2);
+    l.hpop = l.hmov + round_up((size_t)N * 4);
     l.lam = round_up((size_t)N * 4);
   } else {
     l.elem = p->precision == GPLBM_FP64 ? 8 : 4;
     l.mov = 0;
+    l.hmov = 0;
     l.pop = round_up((size_t)Q * N * l.elem);
     l.hpop = round_up((size_t)lattice_qh(p) * N * l.elem);
     l.lam = 0;
@@ -316,7 +317,7 @@ struct Ops {
 
 // Operations in the deviation storage formats (D2Q9 or D3Q19; the fused
 // schedules are the D3Q19 z-march and the D2Q9 tile kernel).
-template <class Codec, class L>
+template <class Codec, class L, class LH>
 struct DevOps {
   static dim3 block() { return dim3(64, 4, 1); }
   static dim3 grid(const gplbm_ctx* ctx) {
@@ -327,7 +328,7 @@ struct DevOps {
     s.G.mov = (uint16_t*)ctx->G[a];
     s.G.rest = (float*)(ctx->G[a] + ctx->mov_bytes);
     s.H.mov = (uint16_t*)ctx->H[a];
-    s.H.rest = (float*)(ctx->H[a] + ctx->mov_bytes);
+    s.H.rest = (float*)(ctx->H[a] + ctx->hmov_bytes);
     s.PHI = (float*)ctx->PHI[a];
     s.LAM = (float*)ctx->LAM[a];
     return s;
@@ -337,7 +338,7 @@ struct DevOps {
     const Coef<float> K = make_coef<float>(ctx->p);
     const DevState s = state(ctx, ctx->cur);
     hipLaunchKernelGGL(k_dev_init_fields, grid(ctx), block(), 0, ctx->stream, g, K, phi0, c0, s);
-    hipLaunchKernelGGL((k_dev_init<Codec, L>), grid(ctx), block(), 0, ctx->stream, g, K, c0, s);
+    hipLaunchKernelGGL((k_dev_init<Codec, L, LH>), grid(ctx), block(), 0, ctx->stream, g, K, c0, s);
     return check_launch(ctx, "init");
   }
   static int step(gplbm_ctx* ctx, int64_t nsteps) {
@@ -351,15 +352,15 @@ struct DevOps {
         const bool gen = ctx->p.h_scheme != GPLBM_H_SOURCE || ctx->p.free_energy != GPLBM_FE_EQUAL;
         int rc;
         if constexpr (std::is_same_v<L, D3Q19>)
-          rc = gen ? DevFused3D<Codec, true>::launch(g, K, st, ctx->stream)
-                   : DevFused3D<Codec, false>::launch(g, K, st, ctx->stream);
+          rc = gen ? DevFused3D<Codec, LH, true>::launch(g, K, st, ctx->stream)
+                   : DevFused3D<Codec, LH, false>::launch(g, K, st, ctx->stream);
         else
-          rc = gen ? DevFused2D<Codec, true>::launch(g, K, st, ctx->stream)
-                   : DevFused2D<Codec, false>::launch(g, K, st, ctx->stream);
+          rc = gen ? DevFused2D<Codec, LH, true>::launch(g, K, st, ctx->stream)
+                   : DevFused2D<Codec, LH, false>::launch(g, K, st, ctx->stream);
         if (rc) return fail(ctx, GPLBM_E_DEVICE, "fused step launch failed");
       } else {
-        hipLaunchKernelGGL((k_dev_split_h<Codec, L>), grid(ctx), block(), 0, ctx->stream, g, K, st);
-        hipLaunchKernelGGL((k_dev_split_g<Codec, L>), grid(ctx), block(), 0, ctx->stream, g, K, st);
+        hipLaunchKernelGGL((k_dev_split_h<Codec, L, LH>), grid(ctx), block(), 0, ctx->stream, g, K, st);
+        hipLaunchKernelGGL((k_dev_split_g<Codec, L, LH>), grid(ctx), block(), 0, ctx->stream, g, K, st);
       }
       int rc = check_launch(ctx, "step");
       if (rc) return rc;
@@ -370,7 +371,7 @@ struct DevOps {
   }
   static int fields(gplbm_ctx* ctx, double* phi, double* c, double* mu) {
     const Geo g = make_geo(ctx->p);
-    hipLaunchKernelGGL((k_dev_fields<Codec, L>), grid(ctx), block(), 0, ctx->stream, g,
+    hipLaunchKernelGGL((k_dev_fields<Codec, LH>), grid(ctx), block(), 0, ctx->stream, g,
                        closure_k(ctx->p), state(ctx, ctx->cur), phi, c, mu);
     return check_launch(ctx, "read fields");
   }
@@ -378,7 +379,7 @@ struct DevOps {
     const Geo g = make_geo(ctx->p);
     double* part = ctx->red;
     double* out = ctx->red + kDiagBlocks * kDiagVals;
-    hipLaunchKernelGGL((k_dev_diag_partial<Codec, L>), dim3(kDiagBlocks), dim3(kDiagThreads), 0,
+    hipLaunchKernelGGL((k_dev_diag_partial<Codec, LH>), dim3(kDiagBlocks), dim3(kDiagThreads), 0,
                        ctx->stream, g, state(ctx, ctx->cur), part);
     hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagThreads), 0, ctx->stream,
                        (const double*)part, kDiagBlocks, out);
@@ -386,12 +387,13 @@ struct DevOps {
   }
 };
 
-template <class Codec, class L>
+template <class Codec, class L, class LH>
 struct DevAdapter {
-  static int init(gplbm_ctx* c, const double* a, const double* b) { return DevOps<Codec, L>::init(c, a, b); }
-  static int step(gplbm_ctx* c, int64_t n) { return DevOps<Codec, L>::step(c, n); }
-  static int fields(gplbm_ctx* c, double* a, double* b, double* d) { return DevOps<Codec, L>::fields(c, a, b, d); }
-  static int diag(gplbm_ctx* c) { return DevOps<Codec, L>::diag(c); }
+  using Ops = DevOps<Codec, L, LH>;
+  static int init(gplbm_ctx* c, const double* a, const double* b) { return Ops::init(c, a, b); }
+  static int step(gplbm_ctx* c, int64_t n) { return Ops::step(c, n); }
+  static int fields(gplbm_ctx* c, double* a, double* b, double* d) { return Ops::fields(c, a, b, d); }
+  static int diag(gplbm_ctx* c) { return Ops::diag(c); }
 };
 
 template <template <class, class, class, class> class Fn, class L, class LH, class... Args>
@@ -400,16 +402,24 @@ int dispatch_prec(gplbm_ctx* ctx, Args... args) {
   return Fn<L, LH, float, float>::run(ctx, args...);
 }
 
+// deviation formats: g on D2Q9 or D3Q19, h on the same lattice or the light
+// one of its dimension
+template <template <class, class, class, class> class Fn, class Codec, class... Args>
+int dispatch_dev(gplbm_ctx* ctx, Args... args) {
+  const bool light = ctx->p.h_lattice == GPLBM_H_LIGHT;
+  if (ctx->p.lattice == GPLBM_D2Q9)
+    return light ? Fn<DevAdapter<Codec, D2Q9, D2Q5>, void, void, void>::run(ctx, args...)
+                 : Fn<DevAdapter<Codec, D2Q9, D2Q9>, void, void, void>::run(ctx, args...);
+  return light ? Fn<DevAdapter<Codec, D3Q19, D3Q7>, void, void, void>::run(ctx, args...)
+               : Fn<DevAdapter<Codec, D3Q19, D3Q19>, void, void, void>::run(ctx, args...);
+}
+
 template <template <class, class, class, class> class Fn, class... Args>
 int dispatch(gplbm_ctx* ctx, Args... args) {
-  const bool d2 = ctx->p.lattice == GPLBM_D2Q9;
-  if (ctx->p.precision == GPLBM_FP16_DEV)
-    return d2 ? Fn<DevAdapter<F16Codec, D2Q9>, void, void, void>::run(ctx, args...)
-              : Fn<DevAdapter<F16Codec, D3Q19>, void, void, void>::run(ctx, args...);
-  if (ctx->p.precision == GPLBM_BF16_DEV)
-    return d2 ? Fn<DevAdapter<BF16Codec, D2Q9>, void, void, void>::run(ctx, args...)
-              : Fn<DevAdapter<BF16Codec, D3Q19>, void, void, void>::run(ctx, args...);
   const bool light = ctx->p.h_lattice == GPLBM_H_LIGHT;
+  if (ctx->p.precision >= GPLBM_FP16_DEV)
+    return ctx->p.precision == GPLBM_FP16_DEV ? dispatch_dev<Fn, F16Codec>(ctx, args...)
+                                              : dispatch_dev<Fn, BF16Codec>(ctx, args...);
   switch (ctx->p.lattice) {
     case GPLBM_D2Q9:
       return light ? dispatch_prec<Fn, D2Q9, D2Q5>(ctx, args...)
@@ -518,6 +528,7 @@ int gplbm_create(const gplbm_params* p, void* dev_buf, uint64_t bytes, void* str
   ctx->pop_bytes = lay.pop;
   ctx->hpop_bytes = lay.hpop;
   ctx->mov_bytes = lay.mov;
+  ctx->hmov_bytes = lay.hmov;
   ctx->phi_bytes = lay.phi;
   ctx->lam_bytes = lay.lam;
   char* b = (char*)dev_buf;
@@ -727,7 +738,7 @@ struct FwdFromState<DevFwdState<Codec>> {
     char* b = (char*)const_cast<void*>(ck);
     DevFwdState<Codec> f;
     f.H.mov = (uint16_t*)(b + ctx->pop_bytes);
-    f.H.rest = (float*)(b + ctx->pop_bytes + ctx->mov_bytes);
+    f.H.rest = (float*)(b + ctx->pop_bytes + ctx->hmov_bytes);
     f.PHI = (const float*)(b + ctx->pop_bytes + ctx->hpop_bytes);
     f.LAM = (const float*)(b + ctx->pop_bytes + ctx->hpop_bytes + ctx->phi_bytes);
     return f;
@@ -794,8 +805,9 @@ int adj_dispatch_prec(gplbm_ctx* ctx, Args... args) {
     case GPLBM_FP32:
       return Fn<L, LH, FwdState<float>>::run(ctx, args...);
     default:
-      // deviation formats exist for g and h on D2Q9 or on D3Q19
-      if constexpr (std::is_same_v<L, LH> && (std::is_same_v<L, D3Q19> || std::is_same_v<L, D2Q9>)) {
+      // deviation formats exist for g on D2Q9 or D3Q19 (h on it or on its
+      // light lattice)
+      if constexpr (std::is_same_v<L, D3Q19> || std::is_same_v<L, D2Q9>) {
         if (ctx->p.precision == GPLBM_FP16_DEV)
           return Fn<L, LH, DevFwdState<F16Codec>>::run(ctx, args...);
         return Fn<L, LH, DevFwdState<BF16Codec>>::run(ctx, args...);

@@ -62,7 +62,7 @@ struct FwdState {
   const S* PHI;
 };
 
-// A forward state in a deviation format (D2Q9 or D3Q19): the h populations decode
+// A forward state in a deviation format (g on D2Q9 or D3Q19): the h populations decode
 // with the Lambda field of the state, phi is FP32.  The reverse kernels take
 // the decoded values as the state and differentiate the FP64 step there.
 template <class Codec>
@@ -123,7 +123,6 @@ __device__ __forceinline__ NodeFwd<L> node_fwd(const Geo& g, const Coef<double>&
 template <class L, class LH, class Codec>
 __device__ __forceinline__ NodeFwd<L> node_fwd(const Geo& g, const Coef<double>& K,
                                                const DevFwdState<Codec>& F, int x, int y, int z) {
-  static_assert(L::Q == LH::Q, "deviation formats keep h on the lattice of g");
   NodeFwd<L> f;
   double c = 0.0;
 #pragma unroll

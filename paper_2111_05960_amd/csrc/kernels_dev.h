@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(256) k_dev_init_fields(Geo g, Coef<float> K,
   s.LAM[i] = h_lambda<float>(K, phi, mu0);
 }
 
-template <class Codec, class L>
+template <class Codec, class L, class LH>
 __global__ void __launch_bounds__(256) k_dev_init(Geo g, Coef<float> K,
                                                   const double* __restrict__ c0, DevState s) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -175,22 +175,22 @@ __global__ void __launch_bounds__(256) k_dev_init(Geo g, Coef<float> K,
   // h~^0, encoded for the slot (x - e_k, k) or (x, opp k) at a wall
   double c = 0.0;
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k) {
-    const float hv = h_initial<L, float>(K, k, float(cin), lam, F);
+  for (int k = 0; k < LH::Q; ++k) {
+    const float hv = h_initial<LH, float>(K, k, float(cin), lam, F);
     float dec;
-    if (k == L::REST) {
+    if (k == LH::REST) {
       s.H.rest[i] = hv;
       dec = hv;
     } else {
       int dx = x, dy = y, dz = z;
-      const bool in = pull_axis(dx, L::ex[k], g.nx, g.bcx) &&
-                      pull_axis(dy, L::ey[k], g.ny, g.bcy) &&
-                      pull_axis(dz, L::ez[k], g.nz, g.bcz);
-      const int kk = in ? k : L::opp[k];
+      const bool in = pull_axis(dx, LH::ex[k], g.nx, g.bcx) &&
+                      pull_axis(dy, LH::ey[k], g.ny, g.bcy) &&
+                      pull_axis(dz, LH::ez[k], g.nz, g.bcz);
+      const int kk = in ? k : LH::opp[k];
       if (!in) dx = x, dy = y, dz = z;
-      const float ref = float(L::w[kk]) * s.LAM[node_index(g, dx, dy, dz)];
+      const float ref = float(LH::w[kk]) * s.LAM[node_index(g, dx, dy, dz)];
       const uint16_t e = dev_encode<Codec>(hv, ref);
-      s.H.mov[mov_index<L>(g, kk, dx, dy, dz)] = e;
+      s.H.mov[mov_index<LH>(g, kk, dx, dy, dz)] = e;
       dec = dev_decode<Codec>(e, ref);
     }
     c = k == 0 ? double(dec) : c + double(dec);
@@ -219,18 +219,18 @@ __global__ void __launch_bounds__(256) k_dev_init(Geo g, Coef<float> K,
 // ---------------------------------------------------------------------------
 // Split schedule in the deviation format (any boundaries).
 
-template <class Codec, class L>
+template <class Codec, class L, class LH>
 __global__ void __launch_bounds__(256) k_dev_split_h(Geo g, Coef<float> K, DevStep b) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= g.nx || y >= g.ny) return;
   const int64_t i = node_index(g, x, y, z);
-  float h[L::Q];
+  float h[LH::Q];
   double c = 0.0;
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k) {
-    h[k] = pull_dev<Codec, L>(g, b.cur.H, b.cur.LAM, k, x, y, z);
+  for (int k = 0; k < LH::Q; ++k) {
+    h[k] = pull_dev<Codec, LH>(g, b.cur.H, b.cur.LAM, k, x, y, z);
     c = k == 0 ? double(h[k]) : c + double(h[k]);
   }
   const float phi = b.cur.PHI[i];
@@ -249,25 +249,25 @@ __global__ void __launch_bounds__(256) k_dev_split_h(Geo g, Coef<float> K, DevSt
   h_flux<L, float>(K, mu, gr, n, phin - phi, K.anti_trapping != 0, F);
   const float lam = h_lambda<float>(K, phi, mu);
   const float cc = float(c);
-  float hs[L::Q];
+  float hs[LH::Q];
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k)
-    hs[k] = h_update<L, float>(K, k, h[k], cc, lam, F);
-  uint16_t enc[L::Q];
-  float hdec[L::Q];
-  encode_h<Codec, L>(hs, lam, c, enc, hdec);
+  for (int k = 0; k < LH::Q; ++k)
+    hs[k] = h_update<LH, float>(K, k, h[k], cc, lam, F);
+  uint16_t enc[LH::Q];
+  float hdec[LH::Q];
+  encode_h<Codec, LH>(hs, lam, c, enc, hdec);
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k) {
-    if (k == L::REST)
+  for (int k = 0; k < LH::Q; ++k) {
+    if (k == LH::REST)
       b.nxt.H.rest[i] = hdec[k];
     else
-      b.nxt.H.mov[mov_index<L>(g, k, x, y, z)] = enc[k];
+      b.nxt.H.mov[mov_index<LH>(g, k, x, y, z)] = enc[k];
   }
   b.nxt.LAM[i] = lam;
   b.nxt.PHI[i] = phin;
 }
 
-template <class Codec, class L>
+template <class Codec, class L, class LH>
 __global__ void __launch_bounds__(256) k_dev_split_g(Geo g, Coef<float> K, DevStep b) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -276,8 +276,8 @@ __global__ void __launch_bounds__(256) k_dev_split_g(Geo g, Coef<float> K, DevSt
   const int64_t i = node_index(g, x, y, z);
   double c = 0.0;
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k) {
-    const double v = double(pull_dev<Codec, L>(g, b.nxt.H, b.nxt.LAM, k, x, y, z));
+  for (int k = 0; k < LH::Q; ++k) {
+    const double v = double(pull_dev<Codec, LH>(g, b.nxt.H, b.nxt.LAM, k, x, y, z));
     c = k == 0 ? v : c + v;
   }
   const float phi = b.nxt.PHI[i];
@@ -374,7 +374,7 @@ __device__ __forceinline__ void bstore16_nt(uint16_t v, __amdgpu_buffer_rsrc_t r
   __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(V, v), r, voff, soff, 2);
 }
 
-template <int TX, int TY, int ZC, class Codec, bool kGen>
+template <int TX, int TY, int ZC, class Codec, class LH, bool kGen>
 __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     k_dev_fused3d(Geo g, Coef<float> Kin, DevStep b, int tiles_x, int tiles_xy, int ntiles) {
   const Coef<float> K = variant<kGen>(Kin);
@@ -390,7 +390,8 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   __shared__ float phiA[4][AY][AX];          // phi^n, planes p-1 .. p+2
   __shared__ float lamA[4][AY][AX];          // Lambda^{n-1}, planes p-1 .. p+2
   __shared__ float phiB[4][BY][BX];          // phi^{n+1}, planes p-3 .. p
-  __shared__ uint16_t hxe[2][kMov][BY][BX];  // h*^n of plane p: 16-bit codes
+  constexpr int QH = LH::Q;  // h lattice (D3Q19 or D3Q7)
+  __shared__ uint16_t hxe[2][QH - 1][BY][BX];  // h*^n of plane p: 16-bit codes
   __shared__ float hxl[2][BY][BX];           // and Lambda^n, the reference of the codes
 
   int tx, ty;
@@ -399,7 +400,8 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int plane = nx * ny;
   const uint32_t planeB = uint32_t(plane) * 2u;            // one 16-bit population plane
-  const int64_t groupB = int64_t(plane) * kMov * 2;        // one z group of moving populations
+  const int64_t groupB = int64_t(plane) * kMov * 2;        // one z group of moving g populations
+  const int64_t groupBH = int64_t(plane) * (QH - 1) * 2;   // one z group of moving h populations
 
   for (int tile = first_tile(); tile < ntiles; tile += gridDim.x) {
   const int chunk = tile / tiles_xy, txy = tile % tiles_xy;
@@ -447,24 +449,24 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     __amdgpu_buffer_rsrc_t Hz[3], Gz[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      Hz[j] = make_rsrc(reinterpret_cast<const char*>(b.cur.H.mov) + zo[j] * groupB, uint32_t(groupB));
+      Hz[j] = make_rsrc(reinterpret_cast<const char*>(b.cur.H.mov) + zo[j] * groupBH, uint32_t(groupBH));
       Gz[j] = make_rsrc(reinterpret_cast<const char*>(b.cur.G.mov) + zo[j] * groupB, uint32_t(groupB));
     }
     const int64_t selfnode = (int64_t)zp * plane + self_xy;
 
     // pulls, decoded with the reference of the source node (LDS tiles)
-    float h[Q], g_new[Q];
+    float h[QH], g_new[Q];
     double c = 0.0, sg = 0.0;
 #pragma unroll
-    for (int k = 0; k < Q; ++k) {
+    for (int k = 0; k < QH; ++k) {
       float v;
-      if (k == LD::REST) {
+      if (k == LH::REST) {
         v = b.cur.H.rest[selfnode];
       } else {
-        const float ref = float(LD::w[k]) *
-                          lamA[ring4(p - LD::ez[k])][ty + 1 - LD::ey[k]][tx + 1 - LD::ex[k]];
-        v = dev_decode<Codec>(bload16(Hz[1 - LD::ez[k]], xyb[1 - LD::ey[k]][1 - LD::ex[k]],
-                                      mslot(k) * planeB), ref);
+        const float ref = float(LH::w[k]) *
+                          lamA[ring4(p - LH::ez[k])][ty + 1 - LH::ey[k]][tx + 1 - LH::ex[k]];
+        v = dev_decode<Codec>(bload16(Hz[1 - LH::ez[k]], xyb[1 - LH::ey[k]][1 - LH::ex[k]],
+                                      mslot<LH>(k) * planeB), ref);
       }
       h[k] = v;
       c = k == 0 ? double(v) : c + double(v);
@@ -498,21 +500,21 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     h_flux<LD, float>(K, mu, gr, n, phin - phi, K.anti_trapping != 0, F);
     const float lam = h_lambda<float>(K, phi, mu);
     const float cc = float(c);
-    float hs[Q];
+    float hs[QH];
 #pragma unroll
-    for (int k = 0; k < Q; ++k)
-      hs[k] = h_update<LD, float>(K, k, h[k], cc, lam, F);
-    uint16_t enc[Q];
-    float hdec[Q];
-    encode_h<Codec>(hs, lam, c, enc, hdec);
+    for (int k = 0; k < QH; ++k)
+      hs[k] = h_update<LH, float>(K, k, h[k], cc, lam, F);
+    uint16_t enc[QH];
+    float hdec[QH];
+    encode_h<Codec, LH>(hs, lam, c, enc, hdec);
 
     const bool own_p = p >= z0 && p < z1;
     if (out && own_p) {
-      const auto Hw = make_rsrc(reinterpret_cast<char*>(b.nxt.H.mov) + zp * groupB, uint32_t(groupB));
+      const auto Hw = make_rsrc(reinterpret_cast<char*>(b.nxt.H.mov) + zp * groupBH, uint32_t(groupBH));
 #pragma unroll
-      for (int k = 0; k < Q; ++k)
-        if (k != LD::REST) bstore16_nt(enc[k], Hw, selfB, mslot(k) * planeB);
-      __builtin_nontemporal_store(hdec[LD::REST], &b.nxt.H.rest[selfnode]);
+      for (int k = 0; k < QH; ++k)
+        if (k != LH::REST) bstore16_nt(enc[k], Hw, selfB, mslot<LH>(k) * planeB);
+      __builtin_nontemporal_store(hdec[LH::REST], &b.nxt.H.rest[selfnode]);
       __builtin_nontemporal_store(lam, &b.nxt.LAM[selfnode]);
       __builtin_nontemporal_store(phin, &b.nxt.PHI[selfnode]);
     }
@@ -524,8 +526,8 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     const int xb = p & 1;
     if (valid) {
 #pragma unroll
-      for (int k = 0; k < Q; ++k)
-        if (k != LD::REST) hxe[xb][mslot(k)][ty][tx] = enc[k];
+      for (int k = 0; k < QH; ++k)
+        if (k != LH::REST) hxe[xb][mslot<LH>(k)][ty][tx] = enc[k];
       hxl[xb][ty][tx] = lam;
     }
     load_tiles(p + 2);
@@ -540,18 +542,18 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     double acc_up = 0.0;
     if (inner) {
 #pragma unroll
-      for (int k = 0; k < Q; ++k) {
+      for (int k = 0; k < QH; ++k) {
         double v;
-        if (k == LD::REST) {
+        if (k == LH::REST) {
           v = double(hdec[k]);
         } else {
-          const int sy = ty - LD::ey[k], sx = tx - LD::ex[k];
-          const float ref = float(LD::w[k]) * hxl[xb][sy][sx];
-          v = double(dev_decode<Codec>(hxe[xb][mslot(k)][sy][sx], ref));
+          const int sy = ty - LH::ey[k], sx = tx - LH::ex[k];
+          const float ref = float(LH::w[k]) * hxl[xb][sy][sx];
+          v = double(dev_decode<Codec>(hxe[xb][mslot<LH>(k)][sy][sx], ref));
         }
-        if (LD::ez[k] > 0)
+        if (LH::ez[k] > 0)
           acc_up = k == 0 ? v : acc_up + v;
-        else if (LD::ez[k] == 0)
+        else if (LH::ez[k] == 0)
           acc_mid = acc_mid + v;
         else
           acc_dn = acc_dn + v;
@@ -591,12 +593,12 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   }
 }
 
-template <class Codec, bool kGen>
+template <class Codec, class LH, bool kGen>
 struct DevFused3D {
   static int launch(const Geo& g, const Coef<float>& K, const DevStep& b, hipStream_t st) {
     constexpr int TX = 64, TY = GPLBM_DEV_TY, ZC = 32;
     constexpr int NT = TileShape<TX, TY>::NT;
-    auto kernel = k_dev_fused3d<TX, TY, ZC, Codec, kGen>;
+    auto kernel = k_dev_fused3d<TX, TY, ZC, Codec, LH, kGen>;
     const int tiles_x = (g.nx + TX - 1) / TX;
     const int tiles_y = (g.ny + TY - 1) / TY;
     const int chunks = (g.nz + ZC - 1) / ZC;
@@ -624,19 +626,24 @@ struct DevFused3D {
 //     wall), then runs the g collision of step n+1.
 // The values and the order of every sum are those of the split kernels, so
 // the two schedules give identical bits.
-template <int TX, int TY, class Codec, bool kGen>
+template <class P>
+struct LatticeTag {
+  using type = P;
+};
+
+template <int TX, int TY, class Codec, class LH, bool kGen>
 __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     k_dev_fused2d(Geo g, Coef<float> Kin, DevStep b, int tiles_x, int ntiles) {
   const Coef<float> K = variant<kGen>(Kin);
-  using L = D2Q9;
-  constexpr int Q = L::Q;
+  using L = D2Q9;  // g; h on LH (D2Q9 or D2Q5)
+  constexpr int Q = L::Q, QH = LH::Q;
   using Shape = TileShape<TX, TY>;
   constexpr int BX = Shape::BX, BY = Shape::BY, NT = Shape::NT;
   constexpr int AX = BX + 2, AY = BY + 2;
   __shared__ float phiA[AY][AX];  // phi^n on T+2
   __shared__ float lamA[AY][AX];  // Lambda^{n-1} on T+2
   __shared__ float phiB[BY][BX];  // phi^{n+1} on T+1
-  __shared__ float hx[Q][BY][BX];  // decoded h*^n of T+1 (moving populations)
+  __shared__ float hx[QH][BY][BX];  // decoded h*^n of T+1 (moving populations)
 
   int tx, ty;
   bool valid;
@@ -663,44 +670,49 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   const int64_t i = active ? node_index(g, x, y, 0) : 0;
   const int xm = (g.bcx && ux == 0) ? 0 : -1, xp = (g.bcx && ux == g.nx - 1) ? 0 : 1;
   const int ym = (g.bcy && uy == 0) ? 0 : -1, yp = (g.bcy && uy == g.ny - 1) ? 0 : 1;
-  // population k of this node comes from x - e_k, or bounces back at a wall
-  auto inside = [&](int k) {
-    const int sx = ux - L::ex[k], sy = uy - L::ey[k];
+  // population k (of lattice P) of this node comes from x - e_k, or bounces
+  // back at a wall
+  auto inside = [&](auto tag, int k) {
+    using P = typename decltype(tag)::type;
+    const int sx = ux - P::ex[k], sy = uy - P::ey[k];
     return !((g.bcx && (sx < 0 || sx >= g.nx)) || (g.bcy && (sy < 0 || sy >= g.ny)));
   };
   // pull of population k from a distribution in the deviation format, the
   // reference field of the source node read from its T+2 tile
-  auto pull_tile = [&](const DevDist& d, const float (*ref)[AX], int k) -> float {
-    if (k == L::REST) return d.rest[i];
+  auto pull_tile = [&](auto tag, const DevDist& d, const float (*ref)[AX], int k) -> float {
+    using P = typename decltype(tag)::type;
+    if (k == P::REST) return d.rest[i];
     int sx = x, sy = y, kk = k, rx = tx + 1, ry = ty + 1;
-    if (inside(k)) {
-      pull_axis(sx, L::ex[k], g.nx, g.bcx);
-      pull_axis(sy, L::ey[k], g.ny, g.bcy);
-      rx -= L::ex[k];
-      ry -= L::ey[k];
+    if (inside(tag, k)) {
+      pull_axis(sx, P::ex[k], g.nx, g.bcx);
+      pull_axis(sy, P::ey[k], g.ny, g.bcy);
+      rx -= P::ex[k];
+      ry -= P::ey[k];
     } else {
-      kk = L::opp[k];
+      kk = P::opp[k];
     }
-    const float r = float(L::w[kk]) * ref[ry][rx];
-    return dev_decode<Codec>(d.mov[mov_index<L>(g, kk, sx, sy, 0)], r);
+    const float r = float(P::w[kk]) * ref[ry][rx];
+    return dev_decode<Codec>(d.mov[mov_index<P>(g, kk, sx, sy, 0)], r);
   };
+  const LatticeTag<L> tg{};
+  const LatticeTag<LH> th{};
   __syncthreads();
 
   float gn[Q];          // g~^{n+1}
-  float hdec[Q];        // h~*^n as readers decode it
+  float hdec[QH];       // h~*^n as readers decode it
   float phin = 0.0f;
   if (active) {
-    float h[Q];
+    float h[QH];
     double c = 0.0;
 #pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      h[k] = pull_tile(b.cur.H, lamA, k);
+    for (int k = 0; k < QH; ++k) {
+      h[k] = pull_tile(th, b.cur.H, lamA, k);
       c = k == 0 ? double(h[k]) : c + double(h[k]);
     }
     double sg = 0.0;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      gn[k] = pull_tile(b.cur.G, phiA, k);
+      gn[k] = pull_tile(tg, b.cur.G, phiA, k);
       sg = k == 0 ? double(gn[k]) : sg + double(gn[k]);
     }
     const float phi = phiA[ty + 1][tx + 1];
@@ -718,17 +730,17 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     h_flux<L, float>(K, mu, gr, n, phin - phi, K.anti_trapping != 0, F);
     const float lam = h_lambda<float>(K, phi, mu);
     const float cc = float(c);
-    float hs[Q];
+    float hs[QH];
 #pragma unroll
-    for (int k = 0; k < Q; ++k)
-      hs[k] = h_update<L, float>(K, k, h[k], cc, lam, F);
-    uint16_t enc[Q];
-    encode_h<Codec, L>(hs, lam, c, enc, hdec);
+    for (int k = 0; k < QH; ++k)
+      hs[k] = h_update<LH, float>(K, k, h[k], cc, lam, F);
+    uint16_t enc[QH];
+    encode_h<Codec, LH>(hs, lam, c, enc, hdec);
     if (out) {
 #pragma unroll
-      for (int k = 0; k < Q; ++k)
-        if (k != L::REST) b.nxt.H.mov[mov_index<L>(g, k, x, y, 0)] = enc[k];
-      b.nxt.H.rest[i] = hdec[L::REST];
+      for (int k = 0; k < QH; ++k)
+        if (k != LH::REST) b.nxt.H.mov[mov_index<LH>(g, k, x, y, 0)] = enc[k];
+      b.nxt.H.rest[i] = hdec[LH::REST];
       b.nxt.LAM[i] = lam;
       b.nxt.PHI[i] = phin;
     }
@@ -737,8 +749,8 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     phiB[ty][tx] = phin;
     if (active) {
 #pragma unroll
-      for (int k = 0; k < Q; ++k)
-        if (k != L::REST) hx[k][ty][tx] = hdec[k];
+      for (int k = 0; k < QH; ++k)
+        if (k != LH::REST) hx[k][ty][tx] = hdec[k];
     }
   }
   __syncthreads();
@@ -746,14 +758,14 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   if (out) {
     double c1 = 0.0;
 #pragma unroll
-    for (int k = 0; k < Q; ++k) {
+    for (int k = 0; k < QH; ++k) {
       float v;
-      if (k == L::REST)
+      if (k == LH::REST)
         v = hdec[k];
-      else if (inside(k))
-        v = hx[k][ty - L::ey[k]][tx - L::ex[k]];
+      else if (inside(th, k))
+        v = hx[k][ty - LH::ey[k]][tx - LH::ex[k]];
       else
-        v = hdec[L::opp[k]];
+        v = hdec[LH::opp[k]];
       c1 = k == 0 ? double(v) : c1 + double(v);
     }
     const float phi1 = phiB[ty][tx];
@@ -791,12 +803,12 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
 #define GPLBM_DEV2_TY 13
 #endif
 
-template <class Codec, bool kGen>
+template <class Codec, class LH, bool kGen>
 struct DevFused2D {
   static int launch(const Geo& g, const Coef<float>& K, const DevStep& b, hipStream_t st) {
     constexpr int TX = 64, TY = GPLBM_DEV2_TY;
     constexpr int NT = TileShape<TX, TY>::NT;
-    auto kernel = k_dev_fused2d<TX, TY, Codec, kGen>;
+    auto kernel = k_dev_fused2d<TX, TY, Codec, LH, kGen>;
     const int tiles_x = (g.nx + TX - 1) / TX;
     const int tiles_y = (g.ny + TY - 1) / TY;
     const int ntiles = tiles_x * tiles_y;

@@ -52,16 +52,21 @@ def test_state_bytes_layout(lib):
 
 
 @pytest.mark.parametrize("prec", ["fp16dev", "bf16dev"])
-@pytest.mark.parametrize("lattice,shape,q", [(wl.D3Q19, (16, 12, 10), 19), (wl.D2Q9, (1, 12, 10), 9)])
-def test_state_bytes_layout_deviation(lib, prec, lattice, shape, q):
-    """Deviation formats: each distribution is Q - 1 16-bit moving
-    populations and an FP32 rest population per node; phi and Lambda FP32."""
+@pytest.mark.parametrize("lattice,shape,q,hl,qh", [
+    (wl.D3Q19, (16, 12, 10), 19, 0, 19), (wl.D2Q9, (1, 12, 10), 9, 0, 9),
+    (wl.D3Q19, (16, 12, 10), 19, 1, 7), (wl.D2Q9, (1, 12, 10), 9, 1, 5)])
+def test_state_bytes_layout_deviation(lib, prec, lattice, shape, q, hl, qh):
+    """Deviation formats: each distribution is its lattice's Q - 1 16-bit
+    moving populations and an FP32 rest population per node (h on the light
+    lattice: Qh - 1 of them); phi and Lambda FP32."""
     n = shape[0] * shape[1] * shape[2]
     rnd = lambda v: (v + 255) // 256 * 256
-    cp = B.make_params(wl.base_params(lattice=lattice, shape=shape, bc=(0, 0, 0)), prec)
-    dist = rnd((q - 1) * n * 2) + rnd(n * 4)
-    assert B.gplbm_checkpoint_bytes(cp) == 2 * dist + 2 * rnd(n * 4)
-    assert B.gplbm_state_bytes(cp) >= 4 * dist + 4 * rnd(n * 4)
+    cp = B.make_params(wl.base_params(lattice=lattice, shape=shape, bc=(0, 0, 0), h_lattice=hl),
+                       prec)
+    dist_g = rnd((q - 1) * n * 2) + rnd(n * 4)
+    dist_h = rnd((qh - 1) * n * 2) + rnd(n * 4)
+    assert B.gplbm_checkpoint_bytes(cp) == dist_g + dist_h + 2 * rnd(n * 4)
+    assert B.gplbm_state_bytes(cp) >= 2 * (dist_g + dist_h) + 4 * rnd(n * 4)
 
 
 @pytest.mark.parametrize("prec", ["fp16dev", "bf16dev"])
@@ -91,15 +96,6 @@ def test_state_bytes_layout_light_h(lib, lattice, shape, qg, qh):
         assert B.gplbm_state_bytes(cp) >= 2 * pg + 2 * ph + 2 * phi
         full = B.make_params(dict(p, h_lattice=0), prec)
         assert B.gplbm_state_bytes(full) - B.gplbm_state_bytes(cp) == 2 * (pg - ph)
-
-
-@pytest.mark.parametrize("prec", ["fp16dev", "bf16dev"])
-def test_light_h_rejected_with_deviation_storage(lib, prec):
-    cp = B.make_params(wl.base_params(lattice=wl.D3Q19, shape=(8, 8, 8), bc=(0, 0, 0),
-                                      h_lattice=1), prec)
-    with pytest.raises(B.GplbmError) as e:
-        B.gplbm_state_bytes(cp)
-    assert e.value.code == B.GPLBM_E_INVALID
 
 
 def test_adjoint_workspace_light_h(lib):
@@ -189,11 +185,14 @@ def test_adjoint_workspace_deviation_storage(lib, prec):
 
 
 def test_adjoint_bytes_rejects_invalid_parameters(lib):
-    p = wl.base_params(lattice=wl.D3Q19, shape=(8, 8, 8), bc=(0, 0, 0), h_lattice=1)
     out = ctypes.c_uint64()
-    # deviation storage exists for g and h on D3Q19 only
+    # deviation storage exists for g on D2Q9 / D3Q19 only
+    p = wl.base_params(lattice=wl.D3Q7, shape=(8, 8, 8), bc=(0, 0, 0))
     assert lib.gplbm_adjoint_bytes(ctypes.byref(B.make_params(p, "fp16dev")),
                                    ctypes.byref(out)) == B.GPLBM_E_INVALID
+    p = wl.base_params(lattice=wl.D3Q19, shape=(8, 8, 8), bc=(0, 0, 0), h_lattice=1)
+    assert lib.gplbm_adjoint_bytes(ctypes.byref(B.make_params(p, "fp16dev")),
+                                   ctypes.byref(out)) == B.GPLBM_OK
 
 
 @pytest.mark.parametrize("field,value", [("h_scheme", 2), ("free_energy", 3), ("eps_s", 0.0),
