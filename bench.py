@@ -12,8 +12,8 @@ Printed: one JSON line with MLUPS (million node updates per second), the
 HBM roofline of the step kernel (algorithmic bytes per launch over the mean
 launch time, measured with HIP events on the stream the library launches on),
 the other forms of the same step beside it (FP32, FP16 and BF16 deviation
-storage; h, or g and h, on the light lattice D3Q7 / D2Q5 in FP64 and FP32, h on it
-in FP16 deviations; the alternative
+storage; h, or g and h, on the light lattice D3Q7 / D2Q5 in FP64, FP32 and FP16
+deviations; the alternative
 equilibrium h^eq,alt and general quadratic free energies in FP64), the
 differentiation workload (adjoint / forward time), and the CPU oracle timed on
 a bounded crop of the same workload.
@@ -496,8 +496,7 @@ def main():
     ap.add_argument("--workload", default="porous3d_512_d3q19", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp16dev", "bf16dev"])
     ap.add_argument("--h-lattice", default="full", choices=["full", "light", "light-gh"],
-                    help="h on the lattice of g, h on D3Q7 / D2Q5, or g and h on D3Q7 / "
-                         "D2Q5 (the last in FP64 and FP32)")
+                    help="h on the lattice of g, h on D3Q7 / D2Q5, or g and h on D3Q7 / D2Q5")
     ap.add_argument("--h-scheme", default="source", choices=["source", "alt"],
                     help="source H_k, or h^eq,alt")
     ap.add_argument("--free-energy", default="equal", choices=["equal", "quadratic"],
@@ -560,6 +559,7 @@ def main():
                 + [("fp64", "light", "source", "equal"), ("fp32", "light", "source", "equal"),
                    ("fp16dev", "light", "source", "equal"),
                    ("fp64", "light-gh", "source", "equal"), ("fp32", "light-gh", "source", "equal"),
+                   ("fp16dev", "light-gh", "source", "equal"),
                    ("fp64", "full", "alt", "equal"), ("fp64", "full", "source", "quadratic")])
         for prec, *var in todo:
             name = form_name(prec, *var)

@@ -56,8 +56,8 @@ extern "C" {
 /* lattices of g (phi).  D2Q5 / D3Q7 (Sec. 3.1 lists them among the usual
  * sets): tau_g = M_phi / xi_s^2 (4 M_phi on D3Q7) and the gradient of
  * Eqs. (DerivDirec_Grad), (Grad) with the factor 1 / xi_s^2, i.e. central
- * differences; h then runs on the same lattice.  FP64 and FP32 only (the
- * adjoint included). */
+ * differences; h then runs on the same lattice.  Every precision, the
+ * adjoint included. */
 #define GPLBM_D2Q9 0
 #define GPLBM_D3Q19 1
 #define GPLBM_D2Q5 2
@@ -101,9 +101,8 @@ extern "C" {
 /* storage / arithmetic precision of the populations and of phi */
 #define GPLBM_FP64 0 /* everything in double */
 #define GPLBM_FP32 1 /* float storage and collision; moments and closure in double */
-/* g on D2Q9 or D3Q19, h on the lattice of g or on the light one (either h
- * scheme, either free-energy form): the Q - 1 (Qh - 1) moving populations of
- * g (h) stored as 16-bit deviations
+/* any lattice combination, either h scheme, either free-energy form: the
+ * Q - 1 (Qh - 1) moving populations of g (h) stored as 16-bit deviations
  * from the writing node's equilibrium (w_k phi for g, w_k gamma D(phi) mu for
  * h), rest populations, phi and gamma D(phi) mu as float; float collision,
  * double moments and closure; solute mass balanced through the rest

@@ -95,8 +95,6 @@ const char* check_params(const gplbm_params* p) {
   for (int a = 0; a < 3; ++a)
     if (p->bc[a] != GPLBM_PERIODIC && p->bc[a] != GPLBM_ZERO_FLUX) return "unknown boundary";
   if (p->precision < GPLBM_FP64 || p->precision > GPLBM_BF16_DEV) return "unknown precision";
-  if (p->precision >= GPLBM_FP16_DEV && p->lattice != GPLBM_D3Q19 && p->lattice != GPLBM_D2Q9)
-    return "deviation storage is implemented for D2Q9 and D3Q19";
   if (p->schedule < GPLBM_SCHED_AUTO || p->schedule > GPLBM_SCHED_FUSED) return "unknown schedule";
   if (p->h_lattice != GPLBM_H_FULL && p->h_lattice != GPLBM_H_LIGHT) return "unknown h lattice";
   if (p->h_scheme != GPLBM_H_SOURCE && p->h_scheme != GPLBM_H_EQ_ALT) return "unknown h scheme";
@@ -315,8 +313,8 @@ struct Ops {
   }
 };
 
-// Operations in the deviation storage formats (D2Q9 or D3Q19; the fused
-// schedules are the D3Q19 z-march and the D2Q9 tile kernel).
+// Operations in the deviation storage formats (every lattice combination;
+// the fused schedules are the 3-D z-march and the 2-D tile kernel).
 template <class Codec, class L, class LH>
 struct DevOps {
   static dim3 block() { return dim3(64, 4, 1); }
@@ -351,12 +349,12 @@ struct DevOps {
         // the general instantiation only for h^eq,alt or eps_s != eps_l
         const bool gen = ctx->p.h_scheme != GPLBM_H_SOURCE || ctx->p.free_energy != GPLBM_FE_EQUAL;
         int rc;
-        if constexpr (std::is_same_v<L, D3Q19>)
-          rc = gen ? DevFused3D<Codec, LH, true>::launch(g, K, st, ctx->stream)
-                   : DevFused3D<Codec, LH, false>::launch(g, K, st, ctx->stream);
+        if constexpr (L::D == 3)
+          rc = gen ? DevFused3D<Codec, L, LH, true>::launch(g, K, st, ctx->stream)
+                   : DevFused3D<Codec, L, LH, false>::launch(g, K, st, ctx->stream);
         else
-          rc = gen ? DevFused2D<Codec, LH, true>::launch(g, K, st, ctx->stream)
-                   : DevFused2D<Codec, LH, false>::launch(g, K, st, ctx->stream);
+          rc = gen ? DevFused2D<Codec, L, LH, true>::launch(g, K, st, ctx->stream)
+                   : DevFused2D<Codec, L, LH, false>::launch(g, K, st, ctx->stream);
         if (rc) return fail(ctx, GPLBM_E_DEVICE, "fused step launch failed");
       } else {
         hipLaunchKernelGGL((k_dev_split_h<Codec, L, LH>), grid(ctx), block(), 0, ctx->stream, g, K, st);
@@ -402,16 +400,22 @@ int dispatch_prec(gplbm_ctx* ctx, Args... args) {
   return Fn<L, LH, float, float>::run(ctx, args...);
 }
 
-// deviation formats: g on D2Q9 or D3Q19, h on the same lattice or the light
-// one of its dimension
+// deviation formats: the lattice combinations of the other precisions
 template <template <class, class, class, class> class Fn, class Codec, class... Args>
 int dispatch_dev(gplbm_ctx* ctx, Args... args) {
   const bool light = ctx->p.h_lattice == GPLBM_H_LIGHT;
-  if (ctx->p.lattice == GPLBM_D2Q9)
-    return light ? Fn<DevAdapter<Codec, D2Q9, D2Q5>, void, void, void>::run(ctx, args...)
-                 : Fn<DevAdapter<Codec, D2Q9, D2Q9>, void, void, void>::run(ctx, args...);
-  return light ? Fn<DevAdapter<Codec, D3Q19, D3Q7>, void, void, void>::run(ctx, args...)
-               : Fn<DevAdapter<Codec, D3Q19, D3Q19>, void, void, void>::run(ctx, args...);
+  switch (ctx->p.lattice) {
+    case GPLBM_D2Q9:
+      return light ? Fn<DevAdapter<Codec, D2Q9, D2Q5>, void, void, void>::run(ctx, args...)
+                   : Fn<DevAdapter<Codec, D2Q9, D2Q9>, void, void, void>::run(ctx, args...);
+    case GPLBM_D3Q19:
+      return light ? Fn<DevAdapter<Codec, D3Q19, D3Q7>, void, void, void>::run(ctx, args...)
+                   : Fn<DevAdapter<Codec, D3Q19, D3Q19>, void, void, void>::run(ctx, args...);
+    case GPLBM_D2Q5:
+      return Fn<DevAdapter<Codec, D2Q5, D2Q5>, void, void, void>::run(ctx, args...);
+    default:
+      return Fn<DevAdapter<Codec, D3Q7, D3Q7>, void, void, void>::run(ctx, args...);
+  }
 }
 
 template <template <class, class, class, class> class Fn, class... Args>
@@ -476,7 +480,7 @@ struct DiagFn<A, void, void, void> {
 
 int choose_schedule(const gplbm_params& p) {
   const bool fused_ok = p.precision >= GPLBM_FP16_DEV
-                            ? (p.lattice == GPLBM_D2Q9 || dev_fused_supported(p.nx, p.ny, p.nz, p.bc))
+                            ? (two_d(p.lattice) || dev_fused_supported(p.nx, p.ny, p.nz, p.bc))
                         : two_d(p.lattice)           ? fused2d_supported(p.nx, p.ny)
                                                      : fused3d_supported(p.nx, p.ny, p.nz, p.bc);
   if (p.schedule == GPLBM_SCHED_SPLIT) return GPLBM_SCHED_SPLIT;
@@ -804,15 +808,10 @@ int adj_dispatch_prec(gplbm_ctx* ctx, Args... args) {
       return Fn<L, LH, FwdState<double>>::run(ctx, args...);
     case GPLBM_FP32:
       return Fn<L, LH, FwdState<float>>::run(ctx, args...);
+    case GPLBM_FP16_DEV:
+      return Fn<L, LH, DevFwdState<F16Codec>>::run(ctx, args...);
     default:
-      // deviation formats exist for g on D2Q9 or D3Q19 (h on it or on its
-      // light lattice)
-      if constexpr (std::is_same_v<L, D3Q19> || std::is_same_v<L, D2Q9>) {
-        if (ctx->p.precision == GPLBM_FP16_DEV)
-          return Fn<L, LH, DevFwdState<F16Codec>>::run(ctx, args...);
-        return Fn<L, LH, DevFwdState<BF16Codec>>::run(ctx, args...);
-      }
-      return GPLBM_E_INVALID;
+      return Fn<L, LH, DevFwdState<BF16Codec>>::run(ctx, args...);
   }
 }
 

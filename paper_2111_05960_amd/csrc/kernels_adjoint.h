@@ -62,7 +62,7 @@ struct FwdState {
   const S* PHI;
 };
 
-// A forward state in a deviation format (g on D2Q9 or D3Q19): the h populations decode
+// A forward state in a deviation format (any lattices): the h populations decode
 // with the Lambda field of the state, phi is FP32.  The reverse kernels take
 // the decoded values as the state and differentiate the FP64 step there.
 template <class Codec>

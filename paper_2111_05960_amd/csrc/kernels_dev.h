@@ -1,4 +1,4 @@
-// Reduced-precision storage of the D2Q9 or D3Q19 state: the Q - 1 moving
+// Reduced-precision storage of the state on any lattice: the Q - 1 moving
 // populations of each distribution are stored as FP16 or BF16 deviations from the local
 // equilibrium of the node that wrote them, the rest populations, phi and
 // Lambda = gamma D(phi) mu as FP32.  Collision arithmetic is FP32; the moments
@@ -18,8 +18,8 @@
 //
 // Layout of one distribution: moving populations u16[z][m][y][x] (m = k
 // before the rest vector, k - 1 after it), then the rest populations
-// f32[z][y][x].  The per-node kernels take the lattice as a template
-// argument (D3Q19 by default); the fused z-march is D3Q19.
+// f32[z][y][x].  Every kernel takes the lattices of g and h as template
+// arguments.
 #pragma once
 
 #include "kernels_fused3d.h"
@@ -52,8 +52,8 @@ struct DevStep {
   DevState nxt;  // written: G = g~*^{n+1}, H = h~*^n, PHI = phi^{n+1}, LAM = Lambda^n
 };
 
-using LD = D3Q19;  // lattice of the fused deviation z-march
-constexpr int kMov = 18;
+using LD = D3Q19;    // default lattice of the per-node helpers
+constexpr int kMov = 18;  // the most moving populations per node (D3Q19)
 
 // slot of moving population k among the Q - 1 of lattice L
 template <class L = LD>
@@ -374,12 +374,12 @@ __device__ __forceinline__ void bstore16_nt(uint16_t v, __amdgpu_buffer_rsrc_t r
   __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(V, v), r, voff, soff, 2);
 }
 
-template <int TX, int TY, int ZC, class Codec, class LH, bool kGen>
+template <int TX, int TY, int ZC, class Codec, class LG, class LH, bool kGen>
 __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     k_dev_fused3d(Geo g, Coef<float> Kin, DevStep b, int tiles_x, int tiles_xy, int ntiles) {
   const Coef<float> K = variant<kGen>(Kin);
   using Shape = TileShape<TX, TY>;
-  constexpr int Q = 19;
+  constexpr int Q = LG::Q;  // g lattice (D3Q19 or D3Q7)
   constexpr int BX = Shape::BX, BY = Shape::BY;
   constexpr int AX = BX + 2, AY = BY + 2;
   constexpr int NT = Shape::NT;
@@ -400,7 +400,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int plane = nx * ny;
   const uint32_t planeB = uint32_t(plane) * 2u;            // one 16-bit population plane
-  const int64_t groupB = int64_t(plane) * kMov * 2;        // one z group of moving g populations
+  const int64_t groupB = int64_t(plane) * (Q - 1) * 2;        // one z group of moving g populations
   const int64_t groupBH = int64_t(plane) * (QH - 1) * 2;   // one z group of moving h populations
 
   for (int tile = first_tile(); tile < ntiles; tile += gridDim.x) {
@@ -474,13 +474,13 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       float v;
-      if (k == LD::REST) {
+      if (k == LG::REST) {
         v = b.cur.G.rest[selfnode];
       } else {
-        const float ref = float(LD::w[k]) *
-                          phiA[ring4(p - LD::ez[k])][ty + 1 - LD::ey[k]][tx + 1 - LD::ex[k]];
-        v = dev_decode<Codec>(bload16(Gz[1 - LD::ez[k]], xyb[1 - LD::ey[k]][1 - LD::ex[k]],
-                                      mslot(k) * planeB), ref);
+        const float ref = float(LG::w[k]) *
+                          phiA[ring4(p - LG::ez[k])][ty + 1 - LG::ey[k]][tx + 1 - LG::ex[k]];
+        v = dev_decode<Codec>(bload16(Gz[1 - LG::ez[k]], xyb[1 - LG::ey[k]][1 - LG::ex[k]],
+                                      mslot<LG>(k) * planeB), ref);
       }
       g_new[k] = v;
       sg = k == 0 ? double(v) : sg + double(v);
@@ -492,12 +492,12 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
       return phiA[ring4(p + dz)][ty + 1 + dy][tx + 1 + dx];
     };
     float gr[3], n[3];
-    gradient_normal<LD, float>(atA, K.eps2, gr, n);
+    gradient_normal<LG, float>(atA, K.eps2, gr, n);
     const float sbar = source_moment<float>(K, phi, mu);
     const float phin = float(sg + 0.5 * double(sbar));
     if (valid) phiB[sA][ty][tx] = phin;
     float F[3];
-    h_flux<LD, float>(K, mu, gr, n, phin - phi, K.anti_trapping != 0, F);
+    h_flux<LG, float>(K, mu, gr, n, phin - phi, K.anti_trapping != 0, F);
     const float lam = h_lambda<float>(K, phi, mu);
     const float cc = float(c);
     float hs[QH];
@@ -570,19 +570,19 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
         return phiB[ring4(p - 1 + dz)][ty + dy][tx + dx];
       };
       float gr1[3], n1[3];
-      gradient_normal<LD, float>(atB, K.eps2, gr1, n1);
+      gradient_normal<LG, float>(atB, K.eps2, gr1, n1);
       float G[Q], gs[Q];
-      phi_sources<LD, float>(K, phi1, mu1, n1, G);
+      phi_sources<LG, float>(K, phi1, mu1, n1, G);
 #pragma unroll
-      for (int k = 0; k < Q; ++k) gs[k] = g_collide<LD, float>(K, k, g_old[k], phi1, G[k]);
+      for (int k = 0; k < Q; ++k) gs[k] = g_collide<LG, float>(K, k, g_old[k], phi1, G[k]);
       uint16_t genc[Q];
       float gdec[Q];
-      encode_g<Codec>(gs, phi1, genc, gdec);
+      encode_g<Codec, LG>(gs, phi1, genc, gdec);
       const auto Gw = make_rsrc(reinterpret_cast<char*>(b.nxt.G.mov) + zq * groupB, uint32_t(groupB));
 #pragma unroll
       for (int k = 0; k < Q; ++k)
-        if (k != LD::REST) bstore16_nt(genc[k], Gw, selfB, mslot(k) * planeB);
-      __builtin_nontemporal_store(gdec[LD::REST], &b.nxt.G.rest[(int64_t)zq * plane + self_xy]);
+        if (k != LG::REST) bstore16_nt(genc[k], Gw, selfB, mslot<LG>(k) * planeB);
+      __builtin_nontemporal_store(gdec[LG::REST], &b.nxt.G.rest[(int64_t)zq * plane + self_xy]);
     }
 #pragma unroll
     for (int k = 0; k < Q; ++k) g_old[k] = g_new[k];
@@ -593,12 +593,12 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   }
 }
 
-template <class Codec, class LH, bool kGen>
+template <class Codec, class LG, class LH, bool kGen>
 struct DevFused3D {
   static int launch(const Geo& g, const Coef<float>& K, const DevStep& b, hipStream_t st) {
     constexpr int TX = 64, TY = GPLBM_DEV_TY, ZC = 32;
     constexpr int NT = TileShape<TX, TY>::NT;
-    auto kernel = k_dev_fused3d<TX, TY, ZC, Codec, LH, kGen>;
+    auto kernel = k_dev_fused3d<TX, TY, ZC, Codec, LG, LH, kGen>;
     const int tiles_x = (g.nx + TX - 1) / TX;
     const int tiles_y = (g.ny + TY - 1) / TY;
     const int chunks = (g.nz + ZC - 1) / ZC;
@@ -631,11 +631,11 @@ struct LatticeTag {
   using type = P;
 };
 
-template <int TX, int TY, class Codec, class LH, bool kGen>
+template <int TX, int TY, class Codec, class L, class LH, bool kGen>
 __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     k_dev_fused2d(Geo g, Coef<float> Kin, DevStep b, int tiles_x, int ntiles) {
   const Coef<float> K = variant<kGen>(Kin);
-  using L = D2Q9;  // g; h on LH (D2Q9 or D2Q5)
+  // g on L (D2Q9 or D2Q5), h on LH (L, or D2Q5 under D2Q9)
   constexpr int Q = L::Q, QH = LH::Q;
   using Shape = TileShape<TX, TY>;
   constexpr int BX = Shape::BX, BY = Shape::BY, NT = Shape::NT;
@@ -803,12 +803,12 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
 #define GPLBM_DEV2_TY 13
 #endif
 
-template <class Codec, class LH, bool kGen>
+template <class Codec, class L, class LH, bool kGen>
 struct DevFused2D {
   static int launch(const Geo& g, const Coef<float>& K, const DevStep& b, hipStream_t st) {
     constexpr int TX = 64, TY = GPLBM_DEV2_TY;
     constexpr int NT = TileShape<TX, TY>::NT;
-    auto kernel = k_dev_fused2d<TX, TY, Codec, LH, kGen>;
+    auto kernel = k_dev_fused2d<TX, TY, Codec, L, LH, kGen>;
     const int tiles_x = (g.nx + TX - 1) / TX;
     const int tiles_y = (g.ny + TY - 1) / TY;
     const int ntiles = tiles_x * tiles_y;

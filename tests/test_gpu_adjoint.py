@@ -195,7 +195,7 @@ def test_fp32_forward_gradients_close_to_fp64(adj):
 
 @pytest.mark.parametrize("prec,bar", [("fp16dev", 1e-3), ("bf16dev", 1e-2)])
 @pytest.mark.parametrize("geom", ["periodic48", "crop32", "porous2d96", "porous2d96-variants",
-                                  "periodic48-light-h"])
+                                  "periodic48-light-h", "periodic48-light-gh"])
 def test_deviation_forward_gradients_close_to_fp64(adj, prec, bar, geom):
     """Forward in a deviation storage format, FP64 reverse sweep at the
     decoded states: the gradients of J1 and J2 agree with the FP64 run's.
@@ -217,6 +217,8 @@ def test_deviation_forward_gradients_close_to_fp64(adj, prec, bar, geom):
         p, phi0, c0 = wl.config_porous3d(48)
         if geom.endswith("light-h"):
             p = dict(p, h_lattice=1)  # h on D3Q7
+        elif geom.endswith("light-gh"):
+            p = dict(p, lattice=wl.D3Q7)  # g and h on D3Q7
     if geom == "crop32":
         p, phi0, c0 = wl.crop_zero_flux(p, phi0, c0, 32)
     K = 100

@@ -161,14 +161,22 @@ def test_dev_variants_fused_equals_split(gp, prec, case, variant):
         assert np.array_equal(x, y)
 
 
-# h on the light lattice (D3Q7 under D3Q19, D2Q5 under D2Q9) in the deviation
-# formats; same bars and instances as the base scheme
+# the light lattices in the deviation formats: h on D3Q7 under D3Q19 / D2Q5
+# under D2Q9 ("h"), or g and h both on D3Q7 / D2Q5 ("gh"); same bars and
+# instances as the base scheme
+def _light(shape, bc, which):
+    if which == "h":
+        return wl.base_params(lattice=_lattice(shape), shape=shape, bc=bc, h_lattice=1)
+    return wl.base_params(lattice=wl.D2Q5 if shape[0] == 1 else wl.D3Q7, shape=shape, bc=bc)
+
+
+@pytest.mark.parametrize("which", ["h", "gh"])
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("case", [((32, 32, 32), (0, 0, 0)), ((24, 20, 28), (1, 1, 1)),
                                   ((1, 96, 128), (0, 0, 0)), ((1, 70, 90), (1, 1, 0))])
-def test_dev_light_h_against_oracle(gp, oracle_mod, prec, case):
+def test_dev_light_h_against_oracle(gp, oracle_mod, prec, case, which):
     shape, bc = case
-    p = wl.base_params(lattice=_lattice(shape), shape=shape, bc=bc, h_lattice=1)
+    p = _light(shape, bc, which)
     phi0, c0 = wl.random_state_fields(shape, seed=23)
     steps = 300
     sim = gp.Simulation(p, prec).init(phi0, c0)
@@ -182,19 +190,20 @@ def test_dev_light_h_against_oracle(gp, oracle_mod, prec, case):
     phi_d, _, _ = sim.fields()
     dint = interface_error(phi_d, phi_r, grad_r)
     drift = abs(m1 - m0) / abs(m0)
-    print(f"light h {prec} {shape} bc={bc}: d_int={dint:.3e} "
+    print(f"light {which} {prec} {shape} bc={bc}: d_int={dint:.3e} "
           f"Linf(phi)={np.max(np.abs(phi_d - phi_r)):.3e} mass drift={drift:.3e} "
           f"schedule={sim.schedule}", flush=True)
     assert dint <= (1e-3 if prec == "fp16dev" else 1e-2)
     assert drift <= 1e-6
 
 
+@pytest.mark.parametrize("which", ["h", "gh"])
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("case", [((24, 30, 70), (0, 0, 0)), ((1, 53, 91), (1, 1, 0)),
                                   ((1, 70, 150), (0, 0, 0))])
-def test_dev_light_h_fused_equals_split(gp, prec, case):
+def test_dev_light_h_fused_equals_split(gp, prec, case, which):
     shape, bc = case
-    p = wl.base_params(lattice=_lattice(shape), shape=shape, bc=bc, h_lattice=1)
+    p = _light(shape, bc, which)
     phi0, c0 = wl.random_state_fields(shape, seed=33)
     a = gp.Simulation(p, prec, "split").init(phi0, c0).step(12)
     b = gp.Simulation(p, prec, "fused").init(phi0, c0).step(12)
@@ -203,10 +212,11 @@ def test_dev_light_h_fused_equals_split(gp, prec, case):
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("which", ["h", "gh"])
 @pytest.mark.parametrize("prec", PRECS)
-def test_dev_light_h_checkpoint_resume(gp, prec):
+def test_dev_light_h_checkpoint_resume(gp, prec, which):
     shape = (16, 20, 24)
-    p = wl.base_params(lattice=wl.D3Q19, shape=shape, bc=(0, 0, 0), h_lattice=1)
+    p = _light(shape, (0, 0, 0), which)
     phi0, c0 = wl.random_state_fields(shape, seed=35)
     a = gp.Simulation(p, prec).init(phi0, c0).step(5)
     ck = a.checkpoint()

@@ -70,15 +70,11 @@ def test_state_bytes_layout_deviation(lib, prec, lattice, shape, q, hl, qh):
 
 
 @pytest.mark.parametrize("prec", ["fp16dev", "bf16dev"])
-def test_deviation_storage_accepted_on_d2q9_and_d3q19_only(lib, prec):
-    for lattice, shape in ((wl.D2Q9, (1, 64, 64)), (wl.D3Q19, (8, 8, 8))):
+def test_deviation_storage_accepted_on_every_lattice(lib, prec):
+    for lattice, shape in ((wl.D2Q9, (1, 64, 64)), (wl.D3Q19, (8, 8, 8)), (wl.D2Q5, (1, 64, 64)),
+                           (wl.D3Q7, (8, 8, 8))):
         p = wl.base_params(lattice=lattice, shape=shape, bc=(0, 0, 0))
         assert B.gplbm_state_bytes(B.make_params(p, prec)) > 0
-    for lattice, shape in ((wl.D2Q5, (1, 64, 64)), (wl.D3Q7, (8, 8, 8))):
-        p = wl.base_params(lattice=lattice, shape=shape, bc=(0, 0, 0))
-        with pytest.raises(B.GplbmError) as e:
-            B.gplbm_state_bytes(B.make_params(p, prec))
-        assert e.value.code == B.GPLBM_E_INVALID
 
 
 @pytest.mark.parametrize("lattice,shape,qg,qh", [
@@ -186,13 +182,12 @@ def test_adjoint_workspace_deviation_storage(lib, prec):
 
 def test_adjoint_bytes_rejects_invalid_parameters(lib):
     out = ctypes.c_uint64()
-    # deviation storage exists for g on D2Q9 / D3Q19 only
-    p = wl.base_params(lattice=wl.D3Q7, shape=(8, 8, 8), bc=(0, 0, 0))
-    assert lib.gplbm_adjoint_bytes(ctypes.byref(B.make_params(p, "fp16dev")),
-                                   ctypes.byref(out)) == B.GPLBM_E_INVALID
     p = wl.base_params(lattice=wl.D3Q19, shape=(8, 8, 8), bc=(0, 0, 0), h_lattice=1)
     assert lib.gplbm_adjoint_bytes(ctypes.byref(B.make_params(p, "fp16dev")),
                                    ctypes.byref(out)) == B.GPLBM_OK
+    cp = B.make_params(p, "fp16dev")
+    cp.nz = 0
+    assert lib.gplbm_adjoint_bytes(ctypes.byref(cp), ctypes.byref(out)) == B.GPLBM_E_INVALID
 
 
 @pytest.mark.parametrize("field,value", [("h_scheme", 2), ("free_energy", 3), ("eps_s", 0.0),
@@ -217,8 +212,9 @@ def test_state_bytes_layout_light_g(lib, lattice, shape, q):
     out = ctypes.c_uint64()
     assert lib.gplbm_adjoint_bytes(ctypes.byref(cp), ctypes.byref(out)) == B.GPLBM_OK
     for prec in ("fp16dev", "bf16dev"):
-        with pytest.raises(B.GplbmError):
-            B.gplbm_state_bytes(B.make_params(p, prec))
+        # deviation formats: Q - 1 16-bit codes and an FP32 rest population
+        dist = rnd((q - 1) * n * 2) + rnd(n * 4)
+        assert B.gplbm_checkpoint_bytes(B.make_params(p, prec)) == 2 * dist + 2 * rnd(n * 4)
     bad = B.make_params(dict(p, shape=(2,) + shape[1:]) if lattice == wl.D2Q5 else p, "fp64")
     if lattice == wl.D2Q5:
         with pytest.raises(B.GplbmError):
