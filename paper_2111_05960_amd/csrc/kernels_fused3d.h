@@ -9,12 +9,15 @@
 //   - takes phi^n of planes p-1, p, p+1 from a 3-plane LDS ring (T+2 in x-y)
 //     for the gradient, writes phi^{n+1}(p) into a second ring,
 //   - runs the h collision of step n.
-// The post-collision h* are then streamed inside the block into a ring of
-// three LDS accumulator planes: the e_z = +1 populations go to plane p+1, the
-// in-plane ones to plane p, the e_z = -1 ones to plane p-1.  Because D3Q19 and
-// D3Q7 are numbered by layers of e_z (+1, 0, -1), every node's c^{n+1}
-// receives its populations in index order across the three planes, the order
-// of a pull.
+// The post-collision h* are then streamed inside the block, to three planes:
+// the e_z = +1 populations to plane p+1, the in-plane ones to plane p, the
+// e_z = -1 ones to plane p-1.  Where the g carry is in registers the h* go to
+// an LDS exchange and every node gathers its own contributions from x - e_k
+// into three rolling partial sums (one barrier); with the LDS g carry they
+// are pushed into a ring of three LDS accumulator planes in ordered passes.
+// Because D3Q19 and D3Q7 are numbered by layers of e_z (+1, 0, -1), every
+// node's c^{n+1} receives its populations in index order across the three
+// planes either way, the order of a pull.
 // After plane p, c^{n+1}(p-1) is complete and the threads of T run the g
 // collision of step n+1 at plane p-1, on the g~^{n+1} pulled one plane
 // earlier (kept in registers, or in LDS where registers are short).
