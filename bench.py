@@ -456,6 +456,54 @@ def cpu_baseline(p, phi0, c0, log, budget_s=12.0):
             "cpu_model": cpu_model(), "single_thread": single}
 
 
+_ORACLE_SAMPLE = """import sys, time
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+import bench, oracle, workloads as wl
+name, budget = sys.argv[2], float(sys.argv[3])
+p, phi0, c0 = bench.make_workload(name)
+if p["lattice"] in (wl.D3Q19, wl.D3Q7):
+    p, phi0, c0 = wl.crop_zero_flux(p, phi0, c0, 64)
+oracle.build(force=False)
+o = oracle.Oracle(p).init(phi0, c0)
+o.step(1)
+t0, k = time.perf_counter(), 0
+while time.perf_counter() - t0 < budget:
+    o.step(1)
+    k += 1
+print(np.prod(p["shape"]) * k / (time.perf_counter() - t0) / 1e6, oracle.threads(), k,
+      "x".join(map(str, p["shape"][::-1])))
+"""
+
+
+def cpu_table(log, budget_s=5.0):
+    """The FP64 oracle beside the FP64 GPU step on every workload: the GPU on
+    the full grid, the oracle (child processes, all host threads and one) on
+    the full 2-D grid or the 64^3 zero-flux crop of a 3-D one, each stepped
+    for about budget_s seconds."""
+    import subprocess
+    rows = []
+    for name in WORKLOADS:
+        p, phi0, c0 = make_workload(name)
+        g = time_gpu(p, phi0, c0, "fp64", "auto", 20, 5, log)
+        del phi0, c0
+        row = {"workload": name, "gpu_fp64_mlups": round(g["mlups"], 1),
+               "gpu_schedule": g["schedule"]}
+        for label, env in (("oracle", dict(os.environ)),
+                           ("oracle_1thread", dict(os.environ, OMP_NUM_THREADS="1"))):
+            out = subprocess.run([sys.executable, "-c", _ORACLE_SAMPLE, ROOT, name, str(budget_s)],
+                                 env=env, capture_output=True, text=True, timeout=600, check=True)
+            v, th, k, shape = out.stdout.split()[-4:]
+            row[label] = {"mlups": round(float(v), 3), "threads": int(th), "steps": int(k),
+                          "grid": shape}
+        row["gpu_over_oracle"] = round(row["gpu_fp64_mlups"] / row["oracle"]["mlups"], 1)
+        log(f"cpu table {name}: GPU {row['gpu_fp64_mlups']} MLUPS; oracle "
+            f"{row['oracle']['mlups']} MLUPS on {row['oracle']['threads']} threads, "
+            f"{row['oracle_1thread']['mlups']} on 1 ({row['oracle']['grid']})")
+        rows.append(row)
+    return rows
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -519,6 +567,9 @@ def main():
                     help="equal curvatures, or general quadratic")
     ap.add_argument("--schedule", default="auto", choices=["auto", "split", "fused"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-table", action="store_true",
+                    help="also time the FP64 oracle (all threads and one) beside the "
+                         "FP64 GPU step on every workload")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip timing the other precision forms of the step")
     ap.add_argument("--variants", action="store_true",
@@ -699,6 +750,8 @@ def main():
         line["adjoint"] = adj
     if variants:
         line["variants"] = variants
+    if args.cpu_table:
+        line["cpu_table"] = cpu_table(log)
     print(json.dumps(line), flush=True)
 
 
