@@ -63,6 +63,33 @@ def test_planar_dissolution_follows_stefan(gp, oracle_mod, prec):
             assert np.array_equal(a, b)
 
 
+def test_planar_lambda_reading(gp):
+    """The two values of lambda* (Sec. 4.2, Eq. Lambda-Star with Table 3): the
+    printed constants give 6.8211 for this planar case, the defining integral
+    of K evaluated for the model's own interpolation functions 7.9012.  The
+    printed value tracks the one-sided Stefan front more closely at every
+    sample (0.33% against 1.09% after 1000 steps, 0.45% against 0.81% after
+    4000), the error growing with lambda on both sides of it."""
+    errs = {}
+    for lam in (wl.config0()[0]["lam"], 7.901235):
+        p, phi0, c0, _ = wl.config0(lam=lam)
+        alpha = analytic.stefan_alpha(p["mu_eq"], p["mu_eq"] - p["c_l_co"],
+                                      p["c_s_co"] - p["c_l_co"])
+        sim = gp.Simulation(p, "fp64").init(phi0, c0)
+        x0 = analytic.front_position(sim.fields()[0][0])
+        errs[lam] = []
+        for t in (1000, 2000, 3000, 4000):
+            sim.step(1000)
+            exact = analytic.stefan_front(alpha, p["D_l"], t)
+            errs[lam].append(abs(analytic.front_position(sim.fields()[0][0]) - x0 - exact)
+                             / abs(exact))
+        print(f"lambda={lam:.6f}: relative front errors {['%.4f' % e for e in errs[lam]]}",
+              flush=True)
+    printed, literal = errs.values()
+    assert all(a < b for a, b in zip(printed, literal))
+    assert max(printed) < 0.006
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_grain_radius_with_and_without_counter_term(gp, prec):
     radii = {}
