@@ -9,9 +9,10 @@ torch objective J(phiK, cK) can then be differentiated: backward returns
 dJ/dphi0, dJ/dc0, dJ/dlambda and dJ/dD_l, all computed by the GPU kernels of
 libgplbm.so (this module only schedules them).  precision "fp32" runs the
 forward (and its re-computation) in FP32 storage and arithmetic; the reverse
-sweep stays FP64, taken at the FP32 states.  "fp16dev" / "bf16dev" (D3Q19)
-run the forward in a deviation storage format and the FP64 reverse sweep at
-its decoded states.
+sweep stays FP64, taken at the FP32 states.  "fp16dev" / "bf16dev" (every
+lattice combination, both h schemes, both free-energy forms) run the forward
+in a deviation storage format and the FP64 reverse sweep at its decoded
+states.
 
 Checkpointing: forward keeps the state every s = ceil(sqrt(K)) steps;
 backward rebuilds each segment from its checkpoint (gplbm_step_to, no copies)

@@ -260,7 +260,8 @@ def gplbm_adjoint_bytes(p: gplbm_params) -> int:
     out = ctypes.c_uint64()
     rc = load().gplbm_adjoint_bytes(ctypes.byref(p), ctypes.byref(out))
     if rc:
-        raise GplbmError(rc, "adjoint needs an FP64 context")
+        raise GplbmError(rc, "gplbm_adjoint_bytes rejected the parameters (see "
+                         "gplbm_state_bytes for the checks they must pass)")
     return out.value
 
 

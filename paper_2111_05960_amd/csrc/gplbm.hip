@@ -45,7 +45,7 @@ struct gplbm_ctx {
   hipStream_t stream;
   int device;
   std::string err;
-  // adjoint (FP64 contexts)
+  // adjoint (every context; FP64 reverse sweep)
   AdjWork adj;
   int adj_cur;
   bool adj_ready;
@@ -850,9 +850,9 @@ struct AdjFinishFn {
   }
 };
 
-// The adjoint covers every context the parameters allow: both h schemes,
-// both free-energy forms and every lattice combination in FP64 or FP32, and
-// the deviation formats (D3Q19, source scheme, equal curvatures).
+// The adjoint covers every context the parameters allow: every precision
+// (FP64, FP32, FP16 / BF16 deviations), every lattice combination, both h
+// schemes and both free-energy forms.
 bool adjoint_supported(const gplbm_params& p) { return check_params(&p) == nullptr; }
 
 }  // namespace
@@ -868,10 +868,10 @@ int gplbm_adjoint_bytes(const gplbm_params* p, uint64_t* bytes) {
 int gplbm_adjoint_begin(gplbm_ctx* ctx, void* work, uint64_t bytes, const double* phi_bar,
                         const double* c_bar) {
   if (!ctx || !work || ((uintptr_t)work) % kAlign) return GPLBM_E_INVALID;
-  if (!adjoint_supported(ctx->p))
-    return fail(ctx, GPLBM_E_INVALID,
-                "adjoint needs an FP64 or FP32 context with the source scheme and equal "
-                "curvatures");
+  if (!adjoint_supported(ctx->p)) {
+    const char* why = check_params(&ctx->p);
+    return fail(ctx, GPLBM_E_INVALID, std::string("adjoint: ") + (why ? why : "invalid parameters"));
+  }
   const AdjLayout l = adj_layout(&ctx->p);
   if (bytes < l.total) return fail(ctx, GPLBM_E_SIZE, "adjoint workspace too small");
   if (int rc = use_device(ctx)) return rc;

@@ -196,6 +196,15 @@ MUTANTS = [
     ("D3Q19 table: axis and diagonal weights swapped",
      "    1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,\n    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,\n    1.0 / 18.0,",
      "    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,\n    1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,\n    1.0 / 18.0,"),
+    ("diagnostics: phi <= 1/2 counted as solid",
+     "if (phi < 0.5) count = count + 1.0;",
+     "if (phi <= 0.5) count = count + 1.0;"),
+    ("diagnostics: min and max swapped",
+     "if (phi < mn) mn = phi;",
+     "if (phi > mn) mn = phi;"),
+    ("diagnostics: solid fraction from phi",
+     "solid = solid + (1.0 - phi);",
+     "solid = solid + phi;"),
 ]
 
 

@@ -621,6 +621,65 @@ def test_quadratic_stefan_front(oracle_mod, eps_s, eps_l):
 
 
 # --------------------------------------------------------------------------
+# Diagnostics on hand-computed fixtures
+
+
+@pytest.mark.parametrize("lattice", [0, 1])
+def test_diagnostics_hand_computed_fixture(oracle_mod, lattice):
+    """The reported quantities at time 0, where phi^0 = phi0 and c^0 equals
+    c0 up to the rounding of the equilibrium sums (the shifted equilibria
+    of the initial populations sum to c0, Eq. Heq_Composition, and the
+    source moments vanish): twelve phi0 values chosen by hand, dyadic so
+    that every sum below is exact.
+
+      phi0 = 0, 1/4, 1/2, 3/4, 1, 1/8, 7/8, 1/2 - 2^-20, 3/8, 5/8, 1/16, 1
+      phi < 1/2 (strictly): 0, 1/4, 1/8, 1/2 - 2^-20, 3/8, 1/16  -> 6 of 12
+      sum phi = 0 + 1/4 + 1/2 + 3/4 + 1 + 1/8 + 7/8 + (1/2 - 2^-20) + 3/8
+        + 5/8 + 1/16 + 1 = 97/16 - 2^-20
+      mean (1 - phi) = (12 - 97/16 + 2^-20) / 12 = (95/16 + 2^-20) / 12
+      min 0, max 1; c0 = 1/2 + phi0 / 4 sums to 6 + (97/16 - 2^-20) / 4
+    """
+    vals = np.array([0.0, 0.25, 0.5, 0.75, 1.0, 0.125, 0.875, 0.5 - 2.0 ** -20,
+                     0.375, 0.625, 0.0625, 1.0])
+    shape = (1, 3, 4) if lattice == 0 else (3, 2, 2)
+    p = wl.base_params(lattice=lattice, shape=shape, bc=(0, 0, 0))
+    phi0 = vals.reshape(shape)
+    c0 = 0.5 + 0.25 * phi0
+    d = oracle_mod.Oracle(p).init(phi0, c0).diagnostics()
+    assert d["step"] == 0 and not d["nonfinite"]
+    assert d["solid_fraction_count"] == 6.0 / 12.0
+    assert d["phi_min"] == 0.0 and d["phi_max"] == 1.0
+    assert d["sum_phi"] == 97.0 / 16.0 - 2.0 ** -20
+    assert d["solid_fraction"] == (95.0 / 16.0 + 2.0 ** -20) / 12.0
+    assert abs(d["total_mass"] - (6.0 + (97.0 / 16.0 - 2.0 ** -20) / 4.0)) < 1e-14
+
+
+def test_diagnostics_after_steps_and_nonfinite(oracle_mod):
+    """Pure liquid (phi = 1) with uniform c is stationary up to the rounding
+    of the weight sums: after 5 steps the diagnostics report step 5, no node
+    below 1/2, solid fraction 0, min = max = 1, the N values of phi and the
+    solute N c (to 1e-15 per node).  A NaN in phi0 or an infinite c0 raises
+    the non-finite flag."""
+    shape = (4, 3, 5)
+    N = 60
+    p = wl.base_params(lattice=1, shape=shape, bc=(1, 0, 1))
+    o = oracle_mod.Oracle(p).init(np.ones(shape), np.full(shape, 0.125)).step(5)
+    d = o.diagnostics()
+    assert d["step"] == 5 and not d["nonfinite"]
+    assert d["solid_fraction_count"] == 0.0 and abs(d["solid_fraction"]) < 1e-15
+    assert abs(d["phi_min"] - 1.0) < 1e-15 and abs(d["phi_max"] - 1.0) < 1e-15
+    assert d["phi_min"] <= d["phi_max"]
+    assert abs(d["sum_phi"] - N) < N * 1e-15
+    assert abs(d["total_mass"] - 0.125 * N) < N * 1e-15
+    phi0 = np.full(shape, 0.5)
+    phi0[1, 2, 3] = np.nan
+    assert oracle_mod.Oracle(p).init(phi0, np.zeros(shape)).diagnostics()["nonfinite"]
+    c0 = np.zeros(shape)
+    c0[3, 0, 0] = np.inf
+    assert oracle_mod.Oracle(p).init(np.full(shape, 0.5), c0).diagnostics()["nonfinite"]
+
+
+# --------------------------------------------------------------------------
 # Three-dimensional curvature flow (last: the slowest pins)
 
 
