@@ -197,6 +197,20 @@ int gplbm_read_fields(gplbm_ctx* ctx, double* phi, double* c, double* mu);
  * finite. */
 int gplbm_diagnostics(gplbm_ctx* ctx, gplbm_diag* out);
 
+/* For callers that cannot allocate device memory at all (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * diagnostics, bit-identical to gplbm_diagnostics, with the reduction
+ * partials in a static device array of the library instead of the context's
+ * buffer.  That array holds 8 * 1024 + 8 doubles (65.6 KB) per device, taken
+ * when the first context is created on the device and kept until the process
+ * ends; its size does not depend on the grid (the reduction grid is fixed),
+ * so every grid gplbm_create accepts fits and larger ones are rejected with
+ * GPLBM_E_SIZE.  Calls no allocating routine.  All calls on one device share
+ * the array: calls that overlap on one device (other threads, other streams)
+ * race and must be serialised by the caller.  Synchronises the stream;
+ * GPLBM_E_DEVICE if the array's device address could not be taken. */
+int gplbm_diagnostics_noalloc(gplbm_ctx* ctx, gplbm_diag* out);
+
 /* Copy the complete state (gplbm_checkpoint_bytes bytes) to / from device
  * memory; together with the step count it determines every later step
  * exactly.  Asynchronous on the context's stream. */

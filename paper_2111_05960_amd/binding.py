@@ -42,7 +42,8 @@ SYMBOLS = ("gplbm_state_bytes", "gplbm_checkpoint_bytes", "gplbm_create", "gplbm
            "gplbm_init_fields", "gplbm_step", "gplbm_step_count", "gplbm_read_fields",
            "gplbm_diagnostics", "gplbm_save_state", "gplbm_load_state", "gplbm_schedule",
            "gplbm_last_error", "gplbm_destroy", "gplbm_adjoint_bytes", "gplbm_adjoint_begin",
-           "gplbm_adjoint_step", "gplbm_adjoint_finish", "gplbm_step_to")
+           "gplbm_adjoint_step", "gplbm_adjoint_finish", "gplbm_step_to",
+           "gplbm_diagnostics_noalloc")
 
 
 class gplbm_params(ctypes.Structure):
@@ -108,6 +109,7 @@ def load():
     lib.gplbm_step_count.restype = i64
     lib.gplbm_read_fields.argtypes = [vp, vp, vp, vp]
     lib.gplbm_diagnostics.argtypes = [vp, P(gplbm_diag)]
+    lib.gplbm_diagnostics_noalloc.argtypes = [vp, P(gplbm_diag)]
     lib.gplbm_save_state.argtypes = [vp, vp]
     lib.gplbm_load_state.argtypes = [vp, vp, i64]
     lib.gplbm_schedule.argtypes = [vp]
@@ -123,7 +125,8 @@ def load():
     lib.gplbm_adjoint_finish.argtypes = [vp, vp, vp, vp, vp, P(ctypes.c_double)]
     for name in ("gplbm_state_bytes", "gplbm_checkpoint_bytes", "gplbm_create",
                  "gplbm_set_stream", "gplbm_init_fields", "gplbm_step", "gplbm_read_fields",
-                 "gplbm_diagnostics", "gplbm_save_state", "gplbm_load_state", "gplbm_schedule",
+                 "gplbm_diagnostics", "gplbm_diagnostics_noalloc", "gplbm_save_state",
+                 "gplbm_load_state", "gplbm_schedule",
                  "gplbm_adjoint_bytes", "gplbm_adjoint_begin", "gplbm_adjoint_step",
                  "gplbm_adjoint_finish"):
         getattr(lib, name).restype = ctypes.c_int
@@ -225,6 +228,16 @@ def gplbm_read_fields(ctx, phi_ptr, c_ptr, mu_ptr):
 def gplbm_diagnostics(ctx, allow_nonfinite: bool = False) -> dict:
     d = gplbm_diag()
     rc = load().gplbm_diagnostics(ctx, ctypes.byref(d))
+    if rc and not (rc == GPLBM_E_NONFINITE and allow_nonfinite):
+        _check(ctx, rc)
+    return {"step": d.step, "total_mass": d.total_mass, "solid_fraction": d.solid_fraction,
+            "solid_fraction_count": d.solid_fraction_count, "sum_phi": d.sum_phi,
+            "phi_min": d.phi_min, "phi_max": d.phi_max, "nonfinite": bool(d.nonfinite)}
+
+
+def gplbm_diagnostics_noalloc(ctx, allow_nonfinite: bool = False) -> dict:
+    d = gplbm_diag()
+    rc = load().gplbm_diagnostics_noalloc(ctx, ctypes.byref(d))
     if rc and not (rc == GPLBM_E_NONFINITE and allow_nonfinite):
         _check(ctx, rc)
     return {"step": d.step, "total_mass": d.total_mass, "solid_fraction": d.solid_fraction,

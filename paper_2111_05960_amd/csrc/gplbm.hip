@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 
@@ -300,11 +301,11 @@ struct Ops {
     return check_launch(ctx, "read fields");
   }
 
-  static int diag(gplbm_ctx* ctx) {
+  static int diag(gplbm_ctx* ctx, double* red) {
     const Geo g = make_geo(ctx->p);
     const int a = ctx->cur;
-    double* part = ctx->red;
-    double* out = ctx->red + kDiagBlocks * kDiagVals;
+    double* part = red;
+    double* out = red + kDiagBlocks * kDiagVals;
     hipLaunchKernelGGL((k_diag_partial<LH, S>), dim3(kDiagBlocks), dim3(kDiagThreads), 0,
                        ctx->stream, g, (const S*)ctx->H[a], (const S*)ctx->PHI[a], part);
     hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagThreads), 0, ctx->stream,
@@ -373,10 +374,10 @@ struct DevOps {
                        closure_k(ctx->p), state(ctx, ctx->cur), phi, c, mu);
     return check_launch(ctx, "read fields");
   }
-  static int diag(gplbm_ctx* ctx) {
+  static int diag(gplbm_ctx* ctx, double* red) {
     const Geo g = make_geo(ctx->p);
-    double* part = ctx->red;
-    double* out = ctx->red + kDiagBlocks * kDiagVals;
+    double* part = red;
+    double* out = red + kDiagBlocks * kDiagVals;
     hipLaunchKernelGGL((k_dev_diag_partial<Codec, LH>), dim3(kDiagBlocks), dim3(kDiagThreads), 0,
                        ctx->stream, g, state(ctx, ctx->cur), part);
     hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagThreads), 0, ctx->stream,
@@ -391,7 +392,7 @@ struct DevAdapter {
   static int init(gplbm_ctx* c, const double* a, const double* b) { return Ops::init(c, a, b); }
   static int step(gplbm_ctx* c, int64_t n) { return Ops::step(c, n); }
   static int fields(gplbm_ctx* c, double* a, double* b, double* d) { return Ops::fields(c, a, b, d); }
-  static int diag(gplbm_ctx* c) { return Ops::diag(c); }
+  static int diag(gplbm_ctx* c, double* r) { return Ops::diag(c, r); }
 };
 
 template <template <class, class, class, class> class Fn, class L, class LH, class... Args>
@@ -471,11 +472,11 @@ struct FieldsFn<A, void, void, void> {
 };
 template <class L, class LH, class S, class C>
 struct DiagFn {
-  static int run(gplbm_ctx* c) { return Ops<L, LH, S, C>::diag(c); }
+  static int run(gplbm_ctx* c, double* r) { return Ops<L, LH, S, C>::diag(c, r); }
 };
 template <class A>
 struct DiagFn<A, void, void, void> {
-  static int run(gplbm_ctx* c) { return A::diag(c); }
+  static int run(gplbm_ctx* c, double* r) { return A::diag(c, r); }
 };
 
 int choose_schedule(const gplbm_params& p) {
@@ -493,6 +494,65 @@ int use_device(gplbm_ctx* ctx) {
   if (hipGetDevice(&dev) != hipSuccess) return fail(ctx, GPLBM_E_DEVICE, "hipGetDevice failed");
   if (dev != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
     return fail(ctx, GPLBM_E_DEVICE, "hipSetDevice failed");
+  return GPLBM_OK;
+}
+
+// The reduction scratch of gplbm_diagnostics_noalloc: the partials of the
+// fixed reduction grid and the final values, the same amount the borrowed
+// buffer reserves for gplbm_diagnostics.  Every device holds its own copy for
+// the life of the process; its device address is taken once per device (with
+// that device current) when a context is created there, and only that address
+// is handed to kernels.
+constexpr int kMaxDevices = 64;
+constexpr size_t kScratchDoubles = (size_t)kDiagBlocks * kDiagVals + kDiagVals;
+std::mutex scratch_mu;
+double* scratch_ptr[kMaxDevices] = {};
+hipError_t scratch_err[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+// Device address of scratch on the current device `dev` (taken on the first
+// call per device); nullptr with the HIP error in *err when it cannot be had.
+double* scratch_on(int dev, hipError_t* err) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev] && scratch_err[dev] == hipSuccess) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      scratch_err[dev] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+    else
+      scratch_ptr[dev] = (double*)ptr;
+  }
+  *err = scratch_err[dev];
+  return scratch_ptr[dev];
+}
+
+// Copy the final reduction values from device memory and fill *out
+// (synchronises the stream).
+int finish_diagnostics(gplbm_ctx* ctx, const double* red, gplbm_diag* out) {
+  double v[kDiagVals];
+  hipError_t e = hipMemcpyAsync(v, red + kDiagBlocks * kDiagVals, sizeof(v),
+                                hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail(ctx, GPLBM_E_DEVICE, std::string("diagnostics copy: ") + hipGetErrorString(e));
+  out->step = ctx->step;
+  out->total_mass = v[0];
+  out->solid_fraction = v[1] / (double)ctx->N;
+  out->solid_fraction_count = v[2] / (double)ctx->N;
+  out->sum_phi = v[3];
+  out->phi_min = v[4];
+  out->phi_max = v[5];
+  out->nonfinite = v[6] != 0.0 ? 1 : 0;
+  out->reserved = 0;
+  if (out->nonfinite) return fail(ctx, GPLBM_E_NONFINITE, "non-finite phi or c");
   return GPLBM_OK;
 }
 
@@ -556,6 +616,10 @@ int gplbm_create(const gplbm_params* p, void* dev_buf, uint64_t bytes, void* str
     delete ctx;
     return GPLBM_E_DEVICE;
   }
+  // set-up of gplbm_diagnostics_noalloc on this device (a failure is
+  // reported by that call, not here)
+  hipError_t serr;
+  (void)scratch_on(ctx->device, &serr);
   *out = ctx;
   return GPLBM_OK;
 }
@@ -634,24 +698,31 @@ int gplbm_diagnostics(gplbm_ctx* ctx, gplbm_diag* out) {
   if (!ctx || !out) return GPLBM_E_INVALID;
   if (!ctx->ready) return fail(ctx, GPLBM_E_STATE, "diagnostics before init");
   if (int rc = use_device(ctx)) return rc;
-  int rc = dispatch<DiagFn>(ctx);
+  int rc = dispatch<DiagFn>(ctx, ctx->red);
   if (rc) return rc;
-  double v[kDiagVals];
-  hipError_t e = hipMemcpyAsync(v, ctx->red + kDiagBlocks * kDiagVals, sizeof(v),
-                                hipMemcpyDeviceToHost, ctx->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  if (e != hipSuccess) return fail(ctx, GPLBM_E_DEVICE, std::string("diagnostics copy: ") + hipGetErrorString(e));
-  out->step = ctx->step;
-  out->total_mass = v[0];
-  out->solid_fraction = v[1] / (double)ctx->N;
-  out->solid_fraction_count = v[2] / (double)ctx->N;
-  out->sum_phi = v[3];
-  out->phi_min = v[4];
-  out->phi_max = v[5];
-  out->nonfinite = v[6] != 0.0 ? 1 : 0;
-  out->reserved = 0;
-  if (out->nonfinite) return fail(ctx, GPLBM_E_NONFINITE, "non-finite phi or c");
-  return GPLBM_OK;
+  return finish_diagnostics(ctx, ctx->red, out);
+}
+
+int gplbm_diagnostics_noalloc(gplbm_ctx* ctx, gplbm_diag* out) {
+  if (!ctx || !out) return GPLBM_E_INVALID;
+  if (!ctx->ready) return fail(ctx, GPLBM_E_STATE, "diagnostics before init");
+  if (int rc = use_device(ctx)) return rc;
+  // the reduction grid is fixed, so the scratch fits every grid
+  // gplbm_create accepts; the check guards the layout it was sized for
+  static_assert(kScratchDoubles == (size_t)kDiagBlocks * kDiagVals + kDiagVals,
+                "scratch sized for the reduction grid");
+  if (ctx->N > ((int64_t)1 << 40))
+    return fail(ctx, GPLBM_E_SIZE, "diagnostics scratch: grid larger than 2^40 nodes");
+  hipError_t serr = hipSuccess;
+  double* red = scratch_on(ctx->device, &serr);
+  if (!red)
+    return fail(ctx, GPLBM_E_DEVICE,
+                std::string("diagnostics scratch address: ") + hipGetErrorString(serr));
+  // every partial and final value is written before it is read, so nothing
+  // left by an earlier call needs clearing
+  int rc = dispatch<DiagFn>(ctx, red);
+  if (rc) return rc;
+  return finish_diagnostics(ctx, red, out);
 }
 
 int gplbm_save_state(gplbm_ctx* ctx, void* dev_dst) {
