@@ -361,9 +361,20 @@ __global__ void __launch_bounds__(kDiagThreads) k_dev_diag_partial(Geo g, DevSta
 #define GPLBM_DEV_TY 13
 #endif
 
-// Fused z-marching schedule in the deviation format (periodic domains).  Same
-// structure as k_fused3d (x-aligned tiles, persistent grid, carry in registers); in addition a 3-plane LDS ring holds Lambda^{n-1}
-// on T+2 for the h references, and the phi^n ring serves the g references.
+// Fused z-marching schedule in the deviation format, periodic or with
+// zero-flux walls.  Same structure as k_fused3d (x-aligned tiles, persistent
+// grid, g carry in registers); in addition an LDS ring holds Lambda^{n-1} on
+// T+2 for the h references, and the phi^n ring serves the g references.
+//
+// Walls (kWalls, any axis): a pull whose source lies beyond a wall reads the
+// node's own opposite population, decoded with the node's own reference; the
+// T+2 tiles are loaded with clamped coordinates (the mirror ghost of the
+// gradient); the phi^{n+1} stencil of the g collision takes mirrored offsets;
+// and the in-block h streaming keeps the index order of the pull sum: the
+// e_z = +1 contributions gathered for the plane above are held apart (they
+// may be replaced by the node's own bounced values of that plane), the node's
+// own e_z = +1 values of a plane are held for the e_z = -1 bounces of the
+// plane below, and a closing plane past a top wall finishes the last plane.
 
 __device__ __forceinline__ uint16_t bload16(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
   return __builtin_bit_cast(uint16_t, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
@@ -374,7 +385,7 @@ __device__ __forceinline__ void bstore16_nt(uint16_t v, __amdgpu_buffer_rsrc_t r
   __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(V, v), r, voff, soff, 2);
 }
 
-template <int TX, int TY, int ZC, class Codec, class LG, class LH, bool kGen>
+template <int TX, int TY, int ZC, class Codec, class LG, class LH, bool kGen, bool kWalls>
 __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     k_dev_fused3d(Geo g, Coef<float> Kin, DevStep b, int tiles_x, int tiles_xy, int ntiles) {
   const Coef<float> K = variant<kGen>(Kin);
@@ -391,6 +402,8 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   __shared__ float lamA[4][AY][AX];          // Lambda^{n-1}, planes p-1 .. p+2
   __shared__ float phiB[4][BY][BX];          // phi^{n+1}, planes p-3 .. p
   constexpr int QH = LH::Q;  // h lattice (D3Q19 or D3Q7)
+  // e_z layers of the h lattice: +1 at [0, NU), 0 at [NU, NU + NM), -1 after
+  constexpr int NU = count_ez<LH>(1), NM = count_ez<LH>(0);
   __shared__ uint16_t hxe[2][QH - 1][BY][BX];  // h*^n of plane p: 16-bit codes
   __shared__ float hxl[2][BY][BX];           // and Lambda^n, the reference of the codes
 
@@ -402,6 +415,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   const uint32_t planeB = uint32_t(plane) * 2u;            // one 16-bit population plane
   const int64_t groupB = int64_t(plane) * (Q - 1) * 2;        // one z group of moving g populations
   const int64_t groupBH = int64_t(plane) * (QH - 1) * 2;   // one z group of moving h populations
+  const bool wz = kWalls && g.bcz;
 
   for (int tile = first_tile(); tile < ntiles; tile += gridDim.x) {
   const int chunk = tile / tiles_xy, txy = tile % tiles_xy;
@@ -409,7 +423,14 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   const int z0 = chunk * ZC, z1 = min(z0 + ZC, nz);
   const int ux = X0 - 1 + tx, uy = Y0 - 1 + ty;
   const bool out = valid && ux < nx && uy < ny && tx >= 1 && tx <= TX && ty >= 1 && ty <= TY;
-  const int x = wrap_coord(ux, nx), y = wrap_coord(uy, ny);
+  // region nodes beyond a wall take no part (with walls only)
+  bool active = valid;
+  if constexpr (kWalls)
+    active = valid && (!g.bcx || (ux >= 0 && ux < nx)) && (!g.bcy || (uy >= 0 && uy < ny));
+  const int x = kWalls ? tile_coord(ux, nx, g.bcx) : wrap_coord(ux, nx);
+  const int y = kWalls ? tile_coord(uy, ny, g.bcy) : wrap_coord(uy, ny);
+  // source offsets wrap also on wall axes: a source beyond a wall is never
+  // read (its population bounces), the wrapped address only keeps it in range
   const int xo[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
   const int yo[3] = {(y == 0 ? ny - 1 : y - 1) * nx, y * nx, (y == ny - 1 ? 0 : y + 1) * nx};
   uint32_t xyb[3][3];
@@ -419,33 +440,67 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     for (int c = 0; c < 3; ++c) xyb[a][c] = uint32_t(yo[a] + xo[c]) * 2u;
   const uint32_t selfB = xyb[1][1];
   const int self_xy = y * nx + x;
+  // populations arriving from beyond an x or y wall (bit k), and the mirror
+  // offsets of the phi^{n+1} stencil
+  uint32_t bmh = 0, bmg = 0;
+  int xm = -1, xp = 1, ym = -1, yp = 1;
+  if constexpr (kWalls) {
+    bmh = xy_bounce_mask<LH>(g, ux, uy);
+    bmg = xy_bounce_mask<LG>(g, ux, uy);
+    xm = (g.bcx && ux == 0) ? 0 : -1;
+    xp = (g.bcx && ux == nx - 1) ? 0 : 1;
+    ym = (g.bcy && uy == 0) ? 0 : -1;
+    yp = (g.bcy && uy == ny - 1) ? 0 : 1;
+  }
 
   auto load_tiles = [&](int p) {
-    const int64_t zoff = (int64_t)wrap_coord(p, nz) * plane;
+    const int64_t zoff = (int64_t)(kWalls ? tile_coord(p, nz, g.bcz) : wrap_coord(p, nz)) * plane;
     for (int l = threadIdx.x; l < AX * AY; l += NT) {
       const int lx = l % AX, ly = l / AX;
-      const int gx = wrap_coord(X0 - 2 + lx, nx), gy = wrap_coord(Y0 - 2 + ly, ny);
+      const int gx = kWalls ? tile_coord(X0 - 2 + lx, nx, g.bcx) : wrap_coord(X0 - 2 + lx, nx);
+      const int gy = kWalls ? tile_coord(Y0 - 2 + ly, ny, g.bcy) : wrap_coord(Y0 - 2 + ly, ny);
       phiA[ring4(p)][ly][lx] = b.cur.PHI[zoff + gy * nx + gx];
       lamA[ring4(p)][ly][lx] = b.cur.LAM[zoff + gy * nx + gx];
     }
   };
-  load_tiles(z0 - 2);
-  load_tiles(z0 - 1);
-  load_tiles(z0);
+  // first plane: the halo plane below the chunk, or the bottom plane at a z wall
+  const int pfirst = (wz && z0 == 0) ? 0 : z0 - 1;
+  load_tiles(pfirst - 1);
+  load_tiles(pfirst);
+  load_tiles(pfirst + 1);
   __syncthreads();
 
   float g_old[Q];
 #pragma unroll
   for (int k = 0; k < Q; ++k) g_old[k] = 0.0f;
   // c^{n+1} of this thread's node on planes p - 1 and p, partly summed: the
-  // five e_z = +1 populations arrive one plane early, the five e_z = -1 ones
-  // one plane late, each group gathered in ascending k
+  // e_z = +1 populations arrive one plane early, the e_z = -1 ones one plane
+  // late, each group gathered in ascending k
   const bool inner = valid && tx >= 1 && tx <= TX && ty >= 1 && ty <= TY;
   double acc_dn = 0.0, acc_mid = 0.0;
+  // walls: e_z = +1 contributions gathered for the plane above, and this
+  // node's own e_z = +1 post-collision values of the plane below
+  float up_v[kWalls ? NU : 1], own_prev[kWalls ? NU : 1];
+#pragma unroll
+  for (int k = 0; k < (kWalls ? NU : 1); ++k) up_v[k] = own_prev[k] = 0.0f;
 
-  for (int p = z0 - 1; p <= z1; ++p) {
-    const int zp = wrap_coord(p, nz);
-    const int zo[3] = {(zp == 0 ? nz - 1 : zp - 1), zp, (zp == nz - 1 ? 0 : zp + 1)};
+  for (int p = pfirst; p <= z1; ++p) {
+    // past a top wall: no plane, only the completion of plane nz - 1
+    const bool closing = wz && p == nz;
+    const int zp = wz ? min(p, nz - 1) : wrap_coord(p, nz);
+    int zo[3];
+    if (wz) {
+      // a plane beyond the wall is never read (its populations bounce)
+      zo[0] = max(zp - 1, 0);
+      zo[1] = zp;
+      zo[2] = min(zp + 1, nz - 1);
+    } else {
+      zo[0] = zp == 0 ? nz - 1 : zp - 1;
+      zo[1] = zp;
+      zo[2] = zp == nz - 1 ? 0 : zp + 1;
+    }
+    // all e_z = +1 (-1) sources of this plane lie beyond the bottom (top) wall
+    const bool bz_up = wz && p == 0, bz_dn = wz && p == nz - 1;
     __amdgpu_buffer_rsrc_t Hz[3], Gz[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -453,60 +508,79 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
       Gz[j] = make_rsrc(reinterpret_cast<const char*>(b.cur.G.mov) + zo[j] * groupB, uint32_t(groupB));
     }
     const int64_t selfnode = (int64_t)zp * plane + self_xy;
-
-    // pulls, decoded with the reference of the source node (LDS tiles)
-    float h[QH], g_new[Q];
-    double c = 0.0, sg = 0.0;
-#pragma unroll
-    for (int k = 0; k < QH; ++k) {
-      float v;
-      if (k == LH::REST) {
-        v = b.cur.H.rest[selfnode];
-      } else {
-        const float ref = float(LH::w[k]) *
-                          lamA[ring4(p - LH::ez[k])][ty + 1 - LH::ey[k]][tx + 1 - LH::ex[k]];
-        v = dev_decode<Codec>(bload16(Hz[1 - LH::ez[k]], xyb[1 - LH::ey[k]][1 - LH::ex[k]],
-                                      mslot<LH>(k) * planeB), ref);
-      }
-      h[k] = v;
-      c = k == 0 ? double(v) : c + double(v);
-    }
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      float v;
-      if (k == LG::REST) {
-        v = b.cur.G.rest[selfnode];
-      } else {
-        const float ref = float(LG::w[k]) *
-                          phiA[ring4(p - LG::ez[k])][ty + 1 - LG::ey[k]][tx + 1 - LG::ex[k]];
-        v = dev_decode<Codec>(bload16(Gz[1 - LG::ez[k]], xyb[1 - LG::ey[k]][1 - LG::ex[k]],
-                                      mslot<LG>(k) * planeB), ref);
-      }
-      g_new[k] = v;
-      sg = k == 0 ? double(v) : sg + double(v);
-    }
     const int sA = ring4(p);
-    const float phi = phiA[sA][ty + 1][tx + 1];
-    const float mu = float(closure(K.q, c, double(phi)));
-    auto atA = [&](int dx, int dy, int dz) -> float {
-      return phiA[ring4(p + dz)][ty + 1 + dy][tx + 1 + dx];
-    };
-    float gr[3], n[3];
-    gradient_normal<LG, float>(atA, K.eps2, gr, n);
-    const float sbar = source_moment<float>(K, phi, mu);
-    const float phin = float(sg + 0.5 * double(sbar));
-    if (valid) phiB[sA][ty][tx] = phin;
-    float F[3];
-    h_flux<LG, float>(K, mu, gr, n, phin - phi, K.anti_trapping != 0, F);
-    const float lam = h_lambda<float>(K, phi, mu);
-    const float cc = float(c);
-    float hs[QH];
-#pragma unroll
-    for (int k = 0; k < QH; ++k)
-      hs[k] = h_update<LH, float>(K, k, h[k], cc, lam, F);
-    uint16_t enc[QH];
+
+    float g_new[Q];
     float hdec[QH];
-    encode_h<Codec, LH>(hs, lam, c, enc, hdec);
+    float phin = 0.0f, lam = 0.0f;
+    uint16_t enc[QH];
+    if (!kWalls || (active && !closing)) {
+      // pulls, decoded with the reference of the source node (LDS tiles), or
+      // of the node itself for a population bounced back at a wall
+      float h[QH];
+      double c = 0.0, sg = 0.0;
+#pragma unroll
+      for (int k = 0; k < QH; ++k) {
+        float v;
+        if (k == LH::REST) {
+          v = b.cur.H.rest[selfnode];
+        } else {
+          const bool bz = (LH::ez[k] > 0 && bz_up) || (LH::ez[k] < 0 && bz_dn);
+          const int ko = LH::opp[k];
+          if (kWalls && (bz || ((bmh >> k) & 1u))) {
+            v = dev_decode<Codec>(bload16(Hz[1], selfB, mslot<LH>(ko) * planeB),
+                                  float(LH::w[ko]) * lamA[sA][ty + 1][tx + 1]);
+          } else {
+            const float ref = float(LH::w[k]) *
+                              lamA[ring4(p - LH::ez[k])][ty + 1 - LH::ey[k]][tx + 1 - LH::ex[k]];
+            v = dev_decode<Codec>(bload16(Hz[1 - LH::ez[k]], xyb[1 - LH::ey[k]][1 - LH::ex[k]],
+                                          mslot<LH>(k) * planeB), ref);
+          }
+        }
+        h[k] = v;
+        c = k == 0 ? double(v) : c + double(v);
+      }
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        float v;
+        if (k == LG::REST) {
+          v = b.cur.G.rest[selfnode];
+        } else {
+          const bool bz = (LG::ez[k] > 0 && bz_up) || (LG::ez[k] < 0 && bz_dn);
+          const int ko = LG::opp[k];
+          if (kWalls && (bz || ((bmg >> k) & 1u))) {
+            v = dev_decode<Codec>(bload16(Gz[1], selfB, mslot<LG>(ko) * planeB),
+                                  float(LG::w[ko]) * phiA[sA][ty + 1][tx + 1]);
+          } else {
+            const float ref = float(LG::w[k]) *
+                              phiA[ring4(p - LG::ez[k])][ty + 1 - LG::ey[k]][tx + 1 - LG::ex[k]];
+            v = dev_decode<Codec>(bload16(Gz[1 - LG::ez[k]], xyb[1 - LG::ey[k]][1 - LG::ex[k]],
+                                          mslot<LG>(k) * planeB), ref);
+          }
+        }
+        g_new[k] = v;
+        sg = k == 0 ? double(v) : sg + double(v);
+      }
+      const float phi = phiA[sA][ty + 1][tx + 1];
+      const float mu = float(closure(K.q, c, double(phi)));
+      auto atA = [&](int dx, int dy, int dz) -> float {
+        return phiA[ring4(p + dz)][ty + 1 + dy][tx + 1 + dx];
+      };
+      float gr[3], n[3];
+      gradient_normal<LG, float>(atA, K.eps2, gr, n);
+      const float sbar = source_moment<float>(K, phi, mu);
+      phin = float(sg + 0.5 * double(sbar));
+      float F[3];
+      h_flux<LG, float>(K, mu, gr, n, phin - phi, K.anti_trapping != 0, F);
+      lam = h_lambda<float>(K, phi, mu);
+      const float cc = float(c);
+      float hs[QH];
+#pragma unroll
+      for (int k = 0; k < QH; ++k)
+        hs[k] = h_update<LH, float>(K, k, h[k], cc, lam, F);
+      encode_h<Codec, LH>(hs, lam, c, enc, hdec);
+    }
+    if (active && !closing) phiB[sA][ty][tx] = phin;
 
     const bool own_p = p >= z0 && p < z1;
     if (out && own_p) {
@@ -524,7 +598,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     // (the same arithmetic as the writer's, so the same values), keeping the
     // population order of a pull without ordered passes
     const int xb = p & 1;
-    if (valid) {
+    if (active && !closing) {
 #pragma unroll
       for (int k = 0; k < QH; ++k)
         if (k != LH::REST) hxe[xb][mslot<LH>(k)][ty][tx] = enc[k];
@@ -539,35 +613,81 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     // back, and the exchange buffer (p & 1) after the barrier two planes back.
     __syncthreads();
     const bool dn_ok = p - 1 >= z0 && p - 1 < z1;
+    // decoded h* that population k of this node receives from x - e_k in the
+    // exchange of plane p
+    auto xchg = [&](int k) -> double {
+      const int sy = ty - LH::ey[k], sx = tx - LH::ex[k];
+      const float ref = float(LH::w[k]) * hxl[xb][sy][sx];
+      return double(dev_decode<Codec>(hxe[xb][mslot<LH>(k)][sy][sx], ref));
+    };
     double acc_up = 0.0;
-    if (inner) {
+    if constexpr (!kWalls) {
+      if (inner) {
 #pragma unroll
-      for (int k = 0; k < QH; ++k) {
-        double v;
-        if (k == LH::REST) {
-          v = double(hdec[k]);
-        } else {
-          const int sy = ty - LH::ey[k], sx = tx - LH::ex[k];
-          const float ref = float(LH::w[k]) * hxl[xb][sy][sx];
-          v = double(dev_decode<Codec>(hxe[xb][mslot<LH>(k)][sy][sx], ref));
+        for (int k = 0; k < QH; ++k) {
+          const double v = k == LH::REST ? double(hdec[k]) : xchg(k);
+          if (LH::ez[k] > 0)
+            acc_up = k == 0 ? v : acc_up + v;
+          else if (LH::ez[k] == 0)
+            acc_mid = acc_mid + v;
+          else
+            acc_dn = acc_dn + v;
         }
-        if (LH::ez[k] > 0)
-          acc_up = k == 0 ? v : acc_up + v;
-        else if (LH::ez[k] == 0)
-          acc_mid = acc_mid + v;
-        else
+      }
+    } else if (inner && active) {
+      if (!closing) {
+        // c^{n+1}(p) through its in-plane layer: the e_z = +1 layer gathered
+        // at the plane below, or bounced (the node's own opposite values)
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < NU; ++k) {
+          const bool bnc = bz_up || ((bmh >> k) & 1u);
+          const double v = bnc ? double(hdec[LH::opp[k]]) : double(up_v[k]);
+          a = k == 0 ? v : a + v;
+        }
+#pragma unroll
+        for (int k = NU; k < NU + NM; ++k) {
+          double v;
+          if (k == LH::REST)
+            v = double(hdec[k]);
+          else if ((bmh >> k) & 1u)
+            v = double(hdec[LH::opp[k]]);
+          else
+            v = xchg(k);
+          a = a + v;
+        }
+        // c^{n+1}(p - 1): its e_z = -1 layer, from this plane or bounced
+        // (this node's own e_z = +1 values of plane p - 1)
+#pragma unroll
+        for (int k = NU + NM; k < QH; ++k) {
+          const double v = ((bmh >> k) & 1u) ? double(own_prev[LH::opp[k]]) : xchg(k);
           acc_dn = acc_dn + v;
+        }
+        // the e_z = +1 layer of plane p + 1, and this plane's own values
+#pragma unroll
+        for (int k = 0; k < NU; ++k) {
+          up_v[k] = float(xchg(k));
+          own_prev[k] = hdec[k];
+        }
+        acc_up = a;
+      } else {
+        // past the top wall every e_z = -1 population of plane nz - 1 bounces
+#pragma unroll
+        for (int k = NU + NM; k < QH; ++k) acc_dn = acc_dn + double(own_prev[LH::opp[k]]);
       }
     }
 
     if (out && dn_ok) {
-      const int zq = zo[0];
-      const int sB = ring4(p - 1);
+      const int zq = wrap_coord(p - 1, nz);
       const double c1 = acc_dn;
-      const float phi1 = phiB[sB][ty][tx];
+      const float phi1 = phiB[ring4(p - 1)][ty][tx];
       const float mu1 = float(closure(K.q, c1, double(phi1)));
+      const int zm = (wz && p - 1 == 0) ? 0 : -1, zpl = (wz && p - 1 == nz - 1) ? 0 : 1;
       auto atB = [&](int dx, int dy, int dz) -> float {
-        return phiB[ring4(p - 1 + dz)][ty + dy][tx + dx];
+        const int ox = dx < 0 ? xm : (dx > 0 ? xp : 0);
+        const int oy = dy < 0 ? ym : (dy > 0 ? yp : 0);
+        const int oz = dz < 0 ? zm : (dz > 0 ? zpl : 0);
+        return phiB[ring4(p - 1 + oz)][ty + oy][tx + ox];
       };
       float gr1[3], n1[3];
       gradient_normal<LG, float>(atB, K.eps2, gr1, n1);
@@ -586,8 +706,12 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     }
 #pragma unroll
     for (int k = 0; k < Q; ++k) g_old[k] = g_new[k];
-    acc_dn = acc_mid;
-    acc_mid = acc_up;
+    if constexpr (kWalls) {
+      acc_dn = acc_up;
+    } else {
+      acc_dn = acc_mid;
+      acc_mid = acc_up;
+    }
   }
   __syncthreads();  // the LDS rings are refilled by the next tile
   }
@@ -595,10 +719,11 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
 
 template <class Codec, class LG, class LH, bool kGen>
 struct DevFused3D {
-  static int launch(const Geo& g, const Coef<float>& K, const DevStep& b, hipStream_t st) {
+  template <bool kWalls>
+  static int run(const Geo& g, const Coef<float>& K, const DevStep& b, hipStream_t st) {
     constexpr int TX = 64, TY = GPLBM_DEV_TY, ZC = 32;
     constexpr int NT = TileShape<TX, TY>::NT;
-    auto kernel = k_dev_fused3d<TX, TY, ZC, Codec, LG, LH, kGen>;
+    auto kernel = k_dev_fused3d<TX, TY, ZC, Codec, LG, LH, kGen, kWalls>;
     const int tiles_x = (g.nx + TX - 1) / TX;
     const int tiles_y = (g.ny + TY - 1) / TY;
     const int chunks = (g.nz + ZC - 1) / ZC;
@@ -609,6 +734,9 @@ struct DevFused3D {
     if (grid <= 0) return -1;
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(NT), 0, st, g, K, b, tiles_x, tiles_xy, ntiles);
     return 0;
+  }
+  static int launch(const Geo& g, const Coef<float>& K, const DevStep& b, hipStream_t st) {
+    return (g.bcx || g.bcy || g.bcz) ? run<true>(g, K, b, st) : run<false>(g, K, b, st);
   }
 };
 
@@ -820,8 +948,9 @@ struct DevFused2D {
   }
 };
 
-inline bool dev_fused_supported(int nx, int ny, int nz, const int* bc) {
-  return bc[0] == 0 && bc[1] == 0 && bc[2] == 0 && (int64_t)nx * ny * kMov * 2 < ((int64_t)1 << 31) &&
+// 32-bit offsets inside a z plane group of moving populations; any boundary
+inline bool dev_fused_supported(int nx, int ny, int nz, const int*) {
+  return (int64_t)nx * ny * kMov * 2 < ((int64_t)1 << 31) &&
          (int64_t)nx * ny * nz < ((int64_t)1 << 31);
 }
 

@@ -34,9 +34,16 @@
 // population plane k*nx*ny is the uniform offset and the (x, y) source the
 // per-lane offset, so a load costs no vector address arithmetic.
 //
-// Only periodic domains take this path (a wall would bounce some +z
-// populations into a plane one step later than the index order allows); the
-// split schedule serves the others.
+// Zero-flux walls (kWalls): a pull from beyond a wall reads the node's own
+// opposite population; the phi^n tiles are loaded with clamped coordinates
+// (the mirror ghost) and the phi^{n+1} stencil takes mirrored offsets.  A
+// population that bounces at an x or y wall reaches its node from the node's
+// own plane, not from the plane below or above, so the gather form keeps the
+// index order of the pull sum by taking the e_z = +1 layer of a node's c^{n+1}
+// at the node's own plane from a second, parity-buffered exchange of the
+// plane below (or the node's own bounced values), and the bounced e_z = -1
+// values from the node's own entries there; past a top wall a closing plane
+// finishes the last one.
 #pragma once
 
 #include "kernels_fused2d.h"
@@ -101,6 +108,31 @@ __device__ __forceinline__ void fetch_pops(const S* base, int zp, int nz, int pl
 // after the pull, which frees 2Q registers in FP64.
 enum class Carry { kRegisters, kLds };
 
+// Zero-flux walls in the z-marching kernels.  A population whose source
+// x - e_k lies beyond a wall is the node's own opposite population (halfway
+// bounce-back); the gradient stencils use the mirror ghost, which the T+2
+// tiles get by loading clamped coordinates along wall axes.
+//
+// Coordinate of a tile node along one axis: wrapped on a periodic axis,
+// clamped (mirror ghost) on a wall axis.
+__device__ __forceinline__ int tile_coord(int u, int n, int bc) {
+  return bc ? min(max(u, 0), n - 1) : wrap_coord(u, n);
+}
+
+// Bit k set when population k of lattice P reaches the node at unwrapped
+// coordinates (ux, uy) from beyond an x or a y wall.
+template <class P>
+__device__ __forceinline__ uint32_t xy_bounce_mask(const Geo& g, int ux, int uy) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int k = 0; k < P::Q; ++k) {
+    const int sx = ux - P::ex[k], sy = uy - P::ey[k];
+    const bool b = (g.bcx && (sx < 0 || sx >= g.nx)) || (g.bcy && (sy < 0 || sy >= g.ny));
+    m |= b ? (1u << k) : 0u;
+  }
+  return m;
+}
+
 
 template <class L, class S>
 struct Fused3DConfig;
@@ -129,7 +161,7 @@ struct Fused3DConfig<D3Q7, float> {
 };
 
 template <int TX, int TY, int ZC, Carry kCarryMode, class L, class LH, class S, class C,
-          bool kGen>
+          bool kGen, bool kWalls>
 __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     k_fused3d(Geo g, Coef<C> Kin, StepBufs<S> b, int tiles_x, int tiles_xy, int ntiles) {
   const Coef<C> K = variant<kGen>(Kin);
@@ -152,12 +184,18 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   // D3Q19) they are pushed into an accumulator ring in NPASS ordered passes.
   // Both sum every c^{n+1} in population order.
   constexpr bool kGather = kRegs;
+  static_assert(!kWalls || kGather, "walls need the gather form");
   __shared__ C phiA[3][AY][AX];  // phi^n, planes p-1, p, p+1
   __shared__ C phiB[3][BY][BX];  // phi^{n+1}, planes p-2, p-1, p
   // c^{n+1} being accumulated (push passes)
   __shared__ double acc[kGather ? 1 : 3][kGather ? 1 : BY][kGather ? 1 : BX];
   // h* of plane p, moving populations (gather)
   __shared__ C hx[kGather ? QH : 1][kGather ? BY : 1][kGather ? BX : 1];
+  // With walls the e_z = +1 layer of the exchange is kept for one more plane
+  // (by plane parity): the plane above gathers it after its own barrier, and
+  // a node's own values in it are the bounce of its e_z = -1 populations.
+  // The plane's two barriers order the reuse of a parity buffer.
+  __shared__ C hxu[kWalls ? 2 : 1][kWalls ? NU : 1][kWalls ? BY : 1][kWalls ? BX : 1];
   // pulled g~^{n+1} of the output nodes by plane parity (LDS carry)
   __shared__ C gkeep[kRegs ? 1 : 2][kRegs ? 1 : Q][kRegs ? 1 : TY][kRegs ? 1 : TX];
 
@@ -169,6 +207,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   const uint32_t planeB = uint32_t(plane) * sizeof(S);     // one population plane
   const int64_t groupB = int64_t(plane) * Q * sizeof(S);   // one z plane group of g
   const int64_t groupH = int64_t(plane) * QH * sizeof(S);  // one z plane group of h
+  const bool wz = kWalls && g.bcz;
 
   for (int tile = first_tile(); tile < ntiles; tile += gridDim.x) {
     const int chunk = tile / tiles_xy, txy = tile % tiles_xy;
@@ -177,7 +216,14 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
 
     const int ux = X0 - 1 + tx, uy = Y0 - 1 + ty;
     const bool out = valid && ux < nx && uy < ny && tx >= 1 && tx <= TX && ty >= 1 && ty <= TY;
-    const int x = wrap_coord(ux, nx), y = wrap_coord(uy, ny);
+    // region nodes beyond a wall take no part (with walls only)
+    bool active = valid;
+    if constexpr (kWalls)
+      active = valid && (!g.bcx || (ux >= 0 && ux < nx)) && (!g.bcy || (uy >= 0 && uy < ny));
+    const int x = kWalls ? tile_coord(ux, nx, g.bcx) : wrap_coord(ux, nx);
+    const int y = kWalls ? tile_coord(uy, ny, g.bcy) : wrap_coord(uy, ny);
+    // source offsets wrap also on wall axes: a source beyond a wall is never
+    // read (its population bounces), the wrapped address keeps it in range
     const int xo[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
     const int yo[3] = {(y == 0 ? ny - 1 : y - 1) * nx, y * nx, (y == ny - 1 ? 0 : y + 1) * nx};
     // byte offset, inside a population plane, of the source x - e_k (by e_x, e_y)
@@ -187,16 +233,31 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
 #pragma unroll
       for (int c = 0; c < 3; ++c) xyb[a][c] = uint32_t(yo[a] + xo[c]) * sizeof(S);
     const uint32_t selfB = xyb[1][1];
-    // phi^n tile positions this thread loads (T+2 in x-y)
+    // populations arriving from beyond an x or y wall (bit k), and the mirror
+    // offsets of the phi^{n+1} stencil
+    uint32_t bmh = 0, bmg = 0;
+    int xm = -1, xp = 1, ym = -1, yp = 1;
+    if constexpr (kWalls) {
+      bmh = xy_bounce_mask<LH>(g, ux, uy);
+      bmg = xy_bounce_mask<L>(g, ux, uy);
+      xm = (g.bcx && ux == 0) ? 0 : -1;
+      xp = (g.bcx && ux == nx - 1) ? 0 : 1;
+      ym = (g.bcy && uy == 0) ? 0 : -1;
+      yp = (g.bcy && uy == ny - 1) ? 0 : 1;
+    }
+    // phi^n tile positions this thread loads (T+2 in x-y; clamped along wall
+    // axes, the mirror ghost)
     uint32_t phi_off[PHI_PER_THREAD];
 #pragma unroll
     for (int j = 0; j < PHI_PER_THREAD; ++j) {
       const int l = min((int)threadIdx.x + j * NT, AX * AY - 1);
-      const int gx = wrap_coord(X0 - 2 + l % AX, nx), gy = wrap_coord(Y0 - 2 + l / AX, ny);
+      const int gx = kWalls ? tile_coord(X0 - 2 + l % AX, nx, g.bcx) : wrap_coord(X0 - 2 + l % AX, nx);
+      const int gy = kWalls ? tile_coord(Y0 - 2 + l / AX, ny, g.bcy) : wrap_coord(Y0 - 2 + l / AX, ny);
       phi_off[j] = uint32_t(gy * nx + gx);
     }
     auto load_phi = [&](int p) {
-      const S* src = b.PHI + (int64_t)wrap_coord(p, nz) * plane;
+      const int pz = kWalls ? tile_coord(p, nz, g.bcz) : wrap_coord(p, nz);
+      const S* src = b.PHI + (int64_t)pz * plane;
       S v[PHI_PER_THREAD];
 #pragma unroll
       for (int j = 0; j < PHI_PER_THREAD; ++j) v[j] = src[phi_off[j]];
@@ -207,8 +268,11 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
       }
     };
 
-    load_phi(z0 - 2);
-    load_phi(z0 - 1);
+    // first plane: the halo plane below the chunk, or the bottom plane at a
+    // z wall
+    const int pfirst = (wz && z0 == 0) ? 0 : z0 - 1;
+    load_phi(pfirst - 1);
+    load_phi(pfirst);
     C g_old[kRegs ? Q : 1];
 #pragma unroll
     for (int k = 0; k < (kRegs ? Q : 1); ++k) g_old[k] = C(0);
@@ -218,65 +282,101 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     const bool inner = valid && tx >= 1 && tx <= TX && ty >= 1 && ty <= TY;
     double acc_dn = 0.0, acc_mid = 0.0;
 
-    for (int p = z0 - 1; p <= z1; ++p) {
+    for (int p = pfirst; p <= z1; ++p) {
+      // past a top wall: no plane, only the completion of plane nz - 1
+      const bool closing = wz && p == nz;
       load_phi(p + 1);
       __syncthreads();
-      const int zp = wrap_coord(p, nz);
-      S hv[QH], gv[Q];
-      fetch_pops<LH, S>(b.H, zp, nz, plane, xyb, hv);
-      fetch_pops<L, S>(b.G, zp, nz, plane, xyb, gv);
-
-      const bool own_p = p >= z0 && p < z1;
-      C h[QH];
-      C g_new[kRegs ? Q : 1];
-      double c = 0.0, sg = 0.0;
-#pragma unroll
-      for (int k = 0; k < QH; ++k) {
-        h[k] = C(hv[k]);
-        c = k == 0 ? double(hv[k]) : c + double(hv[k]);
-      }
-#pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        if constexpr (kRegs) g_new[k] = C(gv[k]);
-        sg = k == 0 ? double(gv[k]) : sg + double(gv[k]);
-      }
-      if constexpr (!kRegs) {
-        if (out && own_p) {
-#pragma unroll
-          for (int k = 0; k < Q; ++k) gkeep[p & 1][k][ty - 1][tx - 1] = C(gv[k]);
-        }
-      }
+      const int zp = wz ? min(p, nz - 1) : wrap_coord(p, nz);
+      // all e_z = +1 (-1) sources of this plane lie beyond the bottom (top) wall
+      const bool bz_up = wz && p == 0, bz_dn = wz && p == nz - 1;
       const int sA = ring3(p);
-      const C phi = phiA[sA][ty + 1][tx + 1];
-      const C mu = C(closure(K.q, c, double(phi)));
-      auto atA = [&](int dx, int dy, int dz) -> C {
-        return phiA[ring3(p + dz)][ty + 1 + dy][tx + 1 + dx];
-      };
-      C gr[3], n[3];
-      gradient_normal<L, C>(atA, K.eps2, gr, n);
-      const C sbar = source_moment<C>(K, phi, mu);
-      const double phin = sg + 0.5 * double(sbar);
-      const C phin_c = C(phin);
-      if (valid) phiB[sA][ty][tx] = phin_c;
-      const C dtphi = phin_c - phi;
-      C F[3];
-      h_flux<L, C>(K, mu, gr, n, dtphi, K.anti_trapping != 0, F);
-      const C lam = h_lambda<C>(K, phi, mu);
-      const C cc = C(c);
-      C hs[QH];
-#pragma unroll
-      for (int k = 0; k < QH; ++k) hs[k] = C(S(h_update<LH, C>(K, k, h[k], cc, lam, F)));
+      const bool own_p = p >= z0 && p < z1;
 
-      if (out && own_p) {
-        const auto Hw = make_rsrc(reinterpret_cast<char*>(b.Hn) + zp * groupH, uint32_t(groupH));
+      C hs[QH];
+      C g_new[kRegs ? Q : 1];
+      if (!kWalls || (active && !closing)) {
+        S hv[QH], gv[Q];
+        if constexpr (!kWalls) {
+          fetch_pops<LH, S>(b.H, zp, nz, plane, xyb, hv);
+          fetch_pops<L, S>(b.G, zp, nz, plane, xyb, gv);
+        } else {
+          // pulls; a source beyond a wall gives the node's own opposite
+          // population (bounce-back); a plane beyond a z wall is never read
+          const int zs[3] = {wz ? max(zp - 1, 0) : (zp == 0 ? nz - 1 : zp - 1), zp,
+                             wz ? min(zp + 1, nz - 1) : (zp == nz - 1 ? 0 : zp + 1)};
+          __amdgpu_buffer_rsrc_t RH[3], RG[3];
 #pragma unroll
-        for (int k = 0; k < QH; ++k) bstore_nt<S>(S(hs[k]), Hw, selfB, k * planeB);
-        __builtin_nontemporal_store(S(phin_c), &b.PHIn[(int64_t)zp * plane + y * nx + x]);
+          for (int j = 0; j < 3; ++j) {
+            RH[j] = make_rsrc(reinterpret_cast<const char*>(b.H) + zs[j] * groupH, uint32_t(groupH));
+            RG[j] = make_rsrc(reinterpret_cast<const char*>(b.G) + zs[j] * groupB, uint32_t(groupB));
+          }
+#pragma unroll
+          for (int k = 0; k < QH; ++k) {
+            const bool bz = (LH::ez[k] > 0 && bz_up) || (LH::ez[k] < 0 && bz_dn);
+            if (bz || ((bmh >> k) & 1u))
+              hv[k] = bload<S>(RH[1], selfB, LH::opp[k] * planeB);
+            else
+              hv[k] = bload<S>(RH[1 - LH::ez[k]], xyb[1 - LH::ey[k]][1 - LH::ex[k]], k * planeB);
+          }
+#pragma unroll
+          for (int k = 0; k < Q; ++k) {
+            const bool bz = (L::ez[k] > 0 && bz_up) || (L::ez[k] < 0 && bz_dn);
+            if (bz || ((bmg >> k) & 1u))
+              gv[k] = bload<S>(RG[1], selfB, L::opp[k] * planeB);
+            else
+              gv[k] = bload<S>(RG[1 - L::ez[k]], xyb[1 - L::ey[k]][1 - L::ex[k]], k * planeB);
+          }
+        }
+
+        C h[QH];
+        double c = 0.0, sg = 0.0;
+#pragma unroll
+        for (int k = 0; k < QH; ++k) {
+          h[k] = C(hv[k]);
+          c = k == 0 ? double(hv[k]) : c + double(hv[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          if constexpr (kRegs) g_new[k] = C(gv[k]);
+          sg = k == 0 ? double(gv[k]) : sg + double(gv[k]);
+        }
+        if constexpr (!kRegs) {
+          if (out && own_p) {
+#pragma unroll
+            for (int k = 0; k < Q; ++k) gkeep[p & 1][k][ty - 1][tx - 1] = C(gv[k]);
+          }
+        }
+        const C phi = phiA[sA][ty + 1][tx + 1];
+        const C mu = C(closure(K.q, c, double(phi)));
+        auto atA = [&](int dx, int dy, int dz) -> C {
+          return phiA[ring3(p + dz)][ty + 1 + dy][tx + 1 + dx];
+        };
+        C gr[3], n[3];
+        gradient_normal<L, C>(atA, K.eps2, gr, n);
+        const C sbar = source_moment<C>(K, phi, mu);
+        const double phin = sg + 0.5 * double(sbar);
+        const C phin_c = C(phin);
+        if (active) phiB[sA][ty][tx] = phin_c;
+        const C dtphi = phin_c - phi;
+        C F[3];
+        h_flux<L, C>(K, mu, gr, n, dtphi, K.anti_trapping != 0, F);
+        const C lam = h_lambda<C>(K, phi, mu);
+        const C cc = C(c);
+#pragma unroll
+        for (int k = 0; k < QH; ++k) hs[k] = C(S(h_update<LH, C>(K, k, h[k], cc, lam, F)));
+
+        if (out && own_p) {
+          const auto Hw = make_rsrc(reinterpret_cast<char*>(b.Hn) + zp * groupH, uint32_t(groupH));
+#pragma unroll
+          for (int k = 0; k < QH; ++k) bstore_nt<S>(S(hs[k]), Hw, selfB, k * planeB);
+          __builtin_nontemporal_store(S(phin_c), &b.PHIn[(int64_t)zp * plane + y * nx + x]);
+        }
       }
 
       const bool up_ok = p + 1 >= z0 && p + 1 < z1, dn_ok = p - 1 >= z0 && p - 1 < z1;
       double acc_up = 0.0;
-      if constexpr (kGather) {
+      if constexpr (kGather && !kWalls) {
         // every region node publishes its moving h*, then each inner node
         // gathers from x - e_k in population order
         if (valid) {
@@ -296,6 +396,59 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
               acc_mid = acc_mid + v;
             else
               acc_dn = acc_dn + v;
+          }
+        }
+      }
+      if constexpr (kWalls) {
+        // the e_z = +1 layer goes to the parity buffer of plane p, the others
+        // to the exchange; then the node's c^{n+1}(p) through its in-plane
+        // layer (the e_z = +1 layer from plane p - 1, or bounced) and the
+        // e_z = -1 layer of c^{n+1}(p - 1) (from plane p, or bounced: the
+        // node's own e_z = +1 values of plane p - 1), each in population order
+        const int ub = p & 1, pb = ub ^ 1;
+        if (active && !closing) {
+#pragma unroll
+          for (int k = 0; k < QH; ++k) {
+            if (k < NU)
+              hxu[ub][k][ty][tx] = hs[k];
+            else if (k != LH::REST)
+              hx[k][ty][tx] = hs[k];
+          }
+        }
+        __syncthreads();
+        if (inner && active) {
+          if (!closing) {
+            double a = 0.0;
+#pragma unroll
+            for (int k = 0; k < NU; ++k) {
+              const double v = (bz_up || ((bmh >> k) & 1u))
+                                   ? double(hs[LH::opp[k]])
+                                   : double(hxu[pb][k][ty - LH::ey[k]][tx - LH::ex[k]]);
+              a = k == 0 ? v : a + v;
+            }
+#pragma unroll
+            for (int k = NU; k < NU + NM; ++k) {
+              double v;
+              if (k == LH::REST)
+                v = double(hs[k]);
+              else if ((bmh >> k) & 1u)
+                v = double(hs[LH::opp[k]]);
+              else
+                v = double(hx[k][ty - LH::ey[k]][tx - LH::ex[k]]);
+              a = a + v;
+            }
+#pragma unroll
+            for (int k = NU + NM; k < QH; ++k) {
+              const double v = ((bmh >> k) & 1u) ? double(hxu[pb][LH::opp[k]][ty][tx])
+                                                 : double(hx[k][ty - LH::ey[k]][tx - LH::ex[k]]);
+              acc_dn = acc_dn + v;
+            }
+            acc_up = a;
+          } else {
+            // past the top wall every e_z = -1 population of plane nz - 1
+            // bounces
+#pragma unroll
+            for (int k = NU + NM; k < QH; ++k) acc_dn = acc_dn + double(hxu[pb][LH::opp[k]][ty][tx]);
           }
         }
       }
@@ -339,8 +492,16 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
         const double c1 = kGather ? acc_dn : acc[kGather ? 0 : sB][ty][tx];
         const C phi1 = phiB[sB][ty][tx];
         const C mu1 = C(closure(K.q, c1, double(phi1)));
+        const int zm = (wz && p - 1 == 0) ? 0 : -1, zpl = (wz && p - 1 == nz - 1) ? 0 : 1;
         auto atB = [&](int dx, int dy, int dz) -> C {
-          return phiB[ring3(p - 1 + dz)][ty + dy][tx + dx];
+          if constexpr (kWalls) {
+            const int ox = dx < 0 ? xm : (dx > 0 ? xp : 0);
+            const int oy = dy < 0 ? ym : (dy > 0 ? yp : 0);
+            const int oz = dz < 0 ? zm : (dz > 0 ? zpl : 0);
+            return phiB[ring3(p - 1 + oz)][ty + oy][tx + ox];
+          } else {
+            return phiB[ring3(p - 1 + dz)][ty + dy][tx + dx];
+          }
         };
         C gr1[3], n1[3];
         gradient_normal<L, C>(atB, K.eps2, gr1, n1);
@@ -361,7 +522,9 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
 #pragma unroll
         for (int k = 0; k < Q; ++k) g_old[k] = g_new[k];
       }
-      if constexpr (kGather) {
+      if constexpr (kWalls) {
+        acc_dn = acc_up;
+      } else if constexpr (kGather) {
         acc_dn = acc_mid;
         acc_mid = acc_up;
       }
@@ -371,19 +534,29 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
 }
 
 // 32-bit offsets inside a z plane group: Q * nx * ny * 8 bytes must fit
-// (checked for the larger lattice, 19 populations).
-inline bool fused3d_supported(int nx, int ny, int nz, const int* bc) {
-  return bc[0] == 0 && bc[1] == 0 && bc[2] == 0 && (int64_t)nx * ny * 19 * 8 < ((int64_t)1 << 32) &&
-         (int64_t)nx * ny * nz < ((int64_t)1 << 31);
+// (checked for the larger lattice, 19 populations); any boundary.
+inline bool fused3d_supported(int nx, int ny, int nz, const int*) {
+  return (int64_t)nx * ny * 19 * 8 < ((int64_t)1 << 32) && (int64_t)nx * ny * nz < ((int64_t)1 << 31);
 }
+
+// Domains with a zero-flux wall take the gather form of the in-block
+// streaming, so FP64 on D3Q19 carries g in registers there, on 64 x 5 tiles
+// (one 8-wave block per CU).
+template <class L, class S>
+struct Fused3DWallConfig : Fused3DConfig<L, S> {};
+template <>
+struct Fused3DWallConfig<D3Q19, double> {
+  static constexpr int TX = 64, TY = 5, ZC = 32;
+  static constexpr Carry carry = Carry::kRegisters;
+};
 
 template <class L, class LH, class S, class C, bool kGen>
 struct Fused3D {
-  static int launch(const Geo& g, const Coef<C>& K, const StepBufs<S>& b, hipStream_t st) {
-    using Cfg = Fused3DConfig<L, S>;
+  template <class Cfg, bool kWalls>
+  static int run(const Geo& g, const Coef<C>& K, const StepBufs<S>& b, hipStream_t st) {
     constexpr int TX = Cfg::TX, TY = Cfg::TY, ZC = Cfg::ZC;
     constexpr int NT = TileShape<TX, TY>::NT;
-    auto kernel = k_fused3d<TX, TY, ZC, Cfg::carry, L, LH, S, C, kGen>;
+    auto kernel = k_fused3d<TX, TY, ZC, Cfg::carry, L, LH, S, C, kGen, kWalls>;
     const int tiles_x = (g.nx + TX - 1) / TX;
     const int tiles_y = (g.ny + TY - 1) / TY;
     const int chunks = (g.nz + ZC - 1) / ZC;
@@ -394,6 +567,10 @@ struct Fused3D {
     if (grid <= 0) return -1;
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(NT), 0, st, g, K, b, tiles_x, tiles_xy, ntiles);
     return 0;
+  }
+  static int launch(const Geo& g, const Coef<C>& K, const StepBufs<S>& b, hipStream_t st) {
+    if (g.bcx || g.bcy || g.bcz) return run<Fused3DWallConfig<L, S>, true>(g, K, b, st);
+    return run<Fused3DConfig<L, S>, false>(g, K, b, st);
   }
 };
 

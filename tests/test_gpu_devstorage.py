@@ -286,3 +286,30 @@ def test_dev_light_variants_fused_equals_split(gp, prec, case, variant, which):
     assert b.schedule == "fused" and a.schedule == "split"
     for x, y in zip(a.fields(), b.fields()):
         assert np.array_equal(x, y)
+
+
+# zero-flux walls in the deviation z-march: on every lattice combination and
+# in the general instantiation, with several z chunks (32 planes each) and
+# ragged tiles, the fused kernel gives the bits of the split kernels
+WALL_CASES_3D = [((40, 30, 70), (1, 1, 1)), ((33, 20, 130), (1, 0, 1)),
+                 ((20, 27, 64), (0, 1, 0)), ((70, 13, 66), (0, 0, 1)),
+                 ((5, 14, 128), (1, 1, 0))]
+
+
+@pytest.mark.parametrize("variant", ["base", "alt+quad"])
+@pytest.mark.parametrize("which", ["full", "h", "gh"])
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("case", WALL_CASES_3D)
+def test_dev_walls_fused_equals_split(gp, prec, case, which, variant):
+    shape, bc = case
+    p = (wl.base_params(lattice=wl.D3Q19, shape=shape, bc=bc) if which == "full"
+         else _light(shape, bc, which))
+    if variant != "base":
+        p = dict(p, **VARIANTS[variant])
+    phi0, c0 = wl.random_state_fields(shape, seed=37)
+    print(f"case walls {which} {variant} {prec} {shape} bc={bc}", flush=True)
+    a = gp.Simulation(p, prec, "split").init(phi0, c0).step(9)
+    b = gp.Simulation(p, prec, "fused").init(phi0, c0).step(9)
+    assert b.schedule == "fused" and a.schedule == "split"
+    for x, y in zip(a.fields(), b.fields()):
+        assert np.array_equal(x, y)

@@ -158,3 +158,40 @@ def test_tile_shape_and_schedule_invariance(gp, shape):
     assert b.schedule == "fused"
     for x, y in zip(a.fields(), b.fields()):
         assert np.array_equal(x, y)
+
+
+# zero-flux walls in the 3-D z-march (the gather form, FP64 on D3Q19 with the
+# g carry in registers on 64 x 5 tiles): several z chunks of 32 planes,
+# ragged tiles, every lattice combination and the general instantiation;
+# fused = split bit for bit, and FP64 equal to the oracle
+WALL_CASES = [((40, 30, 70), (1, 1, 1)), ((33, 20, 130), (1, 0, 1)),
+              ((20, 27, 64), (0, 1, 0)), ((70, 13, 66), (0, 0, 1)),
+              ((5, 14, 128), (1, 1, 0))]
+WALL_LATTICES = {"full": dict(lattice=wl.D3Q19), "h": dict(lattice=wl.D3Q19, h_lattice=1),
+                 "gh": dict(lattice=wl.D3Q7)}
+QUAD = dict(free_energy=1, eps_s=1.0, eps_l=2.3, m_s=0.9, m_l=0.12, df_min=0.02)
+
+
+@pytest.mark.parametrize("variant", ["base", "alt+quad"])
+@pytest.mark.parametrize("which", sorted(WALL_LATTICES))
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", WALL_CASES)
+def test_walls_fused_equals_split(gp, oracle_mod, prec, case, which, variant):
+    shape, bc = case
+    over = dict(WALL_LATTICES[which])
+    if variant != "base":
+        over.update(QUAD, h_scheme=1)
+    p = wl.base_params(shape=shape, bc=bc, **over)
+    phi0, c0 = wl.random_state_fields(shape, seed=39)
+    print(f"case walls {which} {variant} {prec} {shape} bc={bc}", flush=True)
+    a = gp.Simulation(p, prec, "split").init(phi0, c0).step(9)
+    b = gp.Simulation(p, prec, "fused").init(phi0, c0).step(9)
+    assert b.schedule == "fused" and a.schedule == "split"
+    fa, fb = a.fields(), b.fields()
+    for x, y in zip(fa, fb):
+        assert np.array_equal(x, y)
+    if prec == "fp64" and variant == "base":
+        errs, ndiff = compare(p, fb, oracle_mod.Oracle(p).init(phi0, c0).step(9).fields())
+        print(f"  vs oracle: errs={errs} differing={ndiff}", flush=True)
+        for k, e in errs.items():
+            assert e <= 1e-11, (k, e)
