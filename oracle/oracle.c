@@ -36,7 +36,7 @@
  *       anti-trapping current, Eq. (Anti-trapping_Equilibrium) (general:
  *       Eq. (Anti-Trapping_Quadratic)).
  *   S8  BGK collision of h, Eqs. (LBE_Composition), (Heq_Composition) and
- *       (SourceTerm_LBE_h), with D(phi) = D_l phi + D_s (1 - phi) and
+ *       (SourceTerm_LBE_h), with D(phi) = D_l q + D_s (1 - q), q = phi on [0, 1], and
  *       1/(tau_h + 1/2), tau_h = 1 / (gamma xi_s^2): 3 / gamma on D2Q9,
  *       D3Q19 and D2Q5 (xi_s^2 = 1/3), 4 / gamma on D3Q7 (xi_s^2 = 1/4), so
  *       that the diffusivity is D in every case.  Alternative scheme
@@ -62,6 +62,14 @@
  *     change: g~^0 = w_k phi0 - G^0_k / 2, h~^0 = h^eq_k - H^0_k / 2 with no
  *     anti-trapping current (dphi/dt unknown at t = 0); with h^eq,alt there
  *     is no source, and h~^0 = h^eq,alt_k with the same F (no j_at);
+ *   - the interpolation functions p (in S_phi) and q (in D) are defined by
+ *     the paper on [0, 1], the range of the phase field; the discrete phi
+ *     overshoots that range by ~1e-3 at interfaces, so p'(phi) and q(phi)
+ *     are evaluated at phi limited to [0, 1] (phi itself is never
+ *     limited): outside the range the unlimited q gives a negative
+ *     diffusivity (D_s = 0, phi < 0), which makes the c-equation
+ *     anti-diffusive, and the unlimited p' reverses the sign of the
+ *     coupling source, which then drives phi further out;
  *   - the general free energies keep the paper's h(phi) = phi,
  *     q(phi) = phi + (1 - phi) D_s / D_l and a = a_at: the paper fixes these
  *     choices for eps_s = eps_l and defers eps_s != eps_l, so the same
@@ -247,12 +255,22 @@ static double edot(const orc_state* s, int k, const double* v) {
   return r;
 }
 
+/* phi limited to [0, 1]: the argument of the interpolation functions p' and
+ * q, which the paper defines on the range of the phase field. */
+static double limit01(double phi) {
+  if (phi < 0.0) return 0.0;
+  if (phi > 1.0) return 1.0;
+  return phi;
+}
+
 /* S3: population sources G_k of the phi-LBE and their zeroth moment Sbar. */
 static void phi_sources(const orc_state* s, double phi, double mu,
                         const double* n3, double* G, double* sbar) {
   const orc_params* p = &s->p;
-  /* G^st = -(lambda M / W^2) S_phi */
-  double pprime = 6.0 * (phi * (1.0 - phi));
+  /* G^st = -(lambda M / W^2) S_phi, p'(phi) of the interpolation p on
+   * [0, 1] */
+  double pl = limit01(phi);
+  double pprime = 6.0 * (pl * (1.0 - pl));
   double Sphi;
   if (p->free_energy == ORC_FE_QUADRATIC)
     Sphi = pprime * coupling_bracket(p, mu);
@@ -279,9 +297,11 @@ static double h_equilibrium(const orc_state* s, int k, double c, double lam) {
   return s->wh[k] * lam;
 }
 
-/* Lambda = gamma D(phi) mu, D(phi) = D_l phi + D_s (1 - phi). */
+/* Lambda = gamma D(phi) mu, D(phi) = D_l q + D_s (1 - q), q = phi on
+ * [0, 1] (the interpolation D_l q(phi) of Eq. Mixed-Formulation). */
 static double h_lambda(const orc_params* p, double phi, double mu) {
-  double D = (p->D_l * phi) + (p->D_s * (1.0 - phi));
+  double q = limit01(phi);
+  double D = (p->D_l * q) + (p->D_s * (1.0 - q));
   return (p->gamma * D) * mu;
 }
 

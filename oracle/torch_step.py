@@ -144,9 +144,17 @@ def at_jump(P, mu):
     return P["c_s_co"] - P["c_l_co"]
 
 
+def limit01(phi):
+    """phi limited to [0, 1]: the argument of the interpolation functions p'
+    (of S_phi) and q (of D), defined on the range of the phase field."""
+    return torch.clamp(phi, 0.0, 1.0)
+
+
 def sources(L, P, phi, mu, n):
     pp = phi * (1.0 - phi)
-    Gst = -((P["lam"] * P["M_phi"]) / (P["W"] * P["W"])) * ((6.0 * pp) * coupling(P, mu))
+    pl = limit01(phi)
+    Gst = -((P["lam"] * P["M_phi"]) / (P["W"] * P["W"])) * ((6.0 * (pl * (1.0 - pl)))
+                                                           * coupling(P, mu))
     if P["counter_term"]:
         kphi = (4.0 / P["W"]) * pp
         G = torch.stack([float(L.w[k]) * (Gst + kphi * _edot(L, k, n)) for k in range(L.Q)])
@@ -167,7 +175,8 @@ def h_parts(L, P, c, phi, mu, F):
     """Equilibrium and source of h.  With h^eq,alt (h_scheme = 1) the flux is
     folded into the moving populations, w_k (Lambda + e_k . F / xi_s^2), and
     the source is zero."""
-    D = P["D_l"] * phi + P["D_s"] * (1.0 - phi)
+    q = limit01(phi)
+    D = P["D_l"] * q + P["D_s"] * (1.0 - q)
     lam_ = (P["gamma"] * D) * mu
     alt = int(P.get("h_scheme", 0)) == 1
     heq = []

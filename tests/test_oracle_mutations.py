@@ -48,8 +48,8 @@ MUTANTS = [
      "r = r + (double)s->e[k][a] * v[a];",
      "r = r + (double)s->e[k][a] * v[s->D - 1 - a];"),
     ("p'(phi): factor 6 dropped",
-     "double pprime = 6.0 * (phi * (1.0 - phi));",
-     "double pprime = (phi * (1.0 - phi));"),
+     "double pprime = 6.0 * (pl * (1.0 - pl));",
+     "double pprime = (pl * (1.0 - pl));"),
     ("G^st: sign flipped",
      "double Gst = -((p->lambda * p->M_phi) / (p->W * p->W)) * Sphi;",
      "double Gst = ((p->lambda * p->M_phi) / (p->W * p->W)) * Sphi;"),
@@ -105,8 +105,8 @@ MUTANTS = [
      "F[a] = (mu * (p->D_l - p->D_s)) * s->grad[3 * i + a] + j;",
      "F[a] = j;"),
     ("D(phi): phases swapped",
-     "double D = (p->D_l * phi) + (p->D_s * (1.0 - phi));",
-     "double D = (p->D_s * phi) + (p->D_l * (1.0 - phi));"),
+     "double D = (p->D_l * q) + (p->D_s * (1.0 - q));",
+     "double D = (p->D_s * q) + (p->D_l * (1.0 - q));"),
     ("h source: gamma dropped",
      "return (s->p.gamma * s->wh[k]) * r;",
      "return (s->wh[k]) * r;"),
@@ -196,6 +196,15 @@ MUTANTS = [
     ("D3Q19 table: axis and diagonal weights swapped",
      "    1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,\n    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,\n    1.0 / 18.0,",
      "    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,\n    1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,\n    1.0 / 18.0,"),
+    ("p'(phi): not limited to [0, 1]",
+     "  double pl = limit01(phi);\n  double pprime",
+     "  double pl = phi;\n  double pprime"),
+    ("D(phi): q not limited to [0, 1]",
+     "  double q = limit01(phi);",
+     "  double q = phi;"),
+    ("limit: lower bound dropped",
+     "  if (phi < 0.0) return 0.0;",
+     "  if (phi < -1.0) return 0.0;"),
     ("diagnostics: phi <= 1/2 counted as solid",
      "if (phi < 0.5) count = count + 1.0;",
      "if (phi <= 0.5) count = count + 1.0;"),

@@ -621,6 +621,70 @@ def test_quadratic_stefan_front(oracle_mod, eps_s, eps_l):
 
 
 # --------------------------------------------------------------------------
+# Interpolation functions on [0, 1] (p' of S_phi, q of D)
+
+
+@pytest.mark.parametrize("lattice", [0, 1])
+@pytest.mark.parametrize("phi_u,c_u", [(-0.01, 0.0), (1.01, 1.0)])
+def test_overshoot_is_not_driven_further(oracle_mod, lattice, phi_u, c_u):
+    """A uniform phase field just outside [0, 1] (solid side undersaturated,
+    liquid side supersaturated) with the counter term stays where it is, to
+    the rounding of the weight sums: no gradient, so no counter term and no
+    flux, and the coupling source vanishes because p'(phi) is the derivative
+    of an interpolation function on [0, 1].  The unlimited 6 phi (1 - phi)
+    has there the sign that drives phi further out of the range (by ~3e-3
+    per step here)."""
+    shape = (1, 6, 8) if lattice == 0 else (4, 5, 6)
+    p = wl.base_params(lattice=lattice, shape=shape, bc=(0, 0, 0), counter_term=1)
+    o = oracle_mod.Oracle(p).init(np.full(shape, phi_u), np.full(shape, c_u))
+    phi0, c0, _ = o.fields()
+    o.step(200)
+    phi1, c1, _ = o.fields()
+    assert np.max(np.abs(phi1 - phi0)) < 1e-13
+    assert np.max(np.abs(c1 - c0)) < 1e-13
+
+
+@pytest.mark.parametrize("lattice", [0, 1])
+def test_no_diffusion_in_overshooting_solid(oracle_mod, lattice):
+    """phi = -0.01 everywhere with D_s = 0: the diffusivity D_l q + D_s (1 - q)
+    with q limited to [0, 1] is 0, so a composition mode does not move (the
+    unlimited q would give D = -1e-3, an anti-diffusion that amplifies it)."""
+    L = 32
+    shape = (1, 2, L) if lattice == 0 else (2, 2, L)
+    p = wl.base_params(lattice=lattice, shape=shape, bc=(0, 0, 0), counter_term=1)
+    phi0 = np.full(shape, -0.01)
+    c0 = (1.0 + 0.01 * np.cos(2 * np.pi * np.arange(L) / L))[None, None, :] + 0.0 * phi0
+    o = oracle_mod.Oracle(p).init(phi0, c0)
+    _, ca, _ = o.fields()
+    o.step(400)
+    _, cb, _ = o.fields()
+    assert np.max(np.abs(cb - ca)) < 1e-14
+
+
+def test_liquid_overshoot_diffuses_at_D_l(oracle_mod):
+    """phi = 1.02 everywhere: q limited to 1, so a composition mode decays at
+    exp(-D_l k^2 t) as in the liquid (the unlimited q = 1.02 would decay 2%
+    faster)."""
+    L = 128
+    shape = (1, 2, L)
+    p = wl.base_params(lattice=0, shape=shape, bc=(0, 0, 0))
+    k = 2 * np.pi / L
+    phi0 = np.full(shape, 1.02)
+    c0 = (p["c_l_co"] + 0.01 * np.cos(k * np.arange(L)))[None, None, :] + 0.0 * phi0
+    o = oracle_mod.Oracle(p).init(phi0, c0)
+    o.step(100)
+
+    def amp():
+        line = o.fields()[1][0, 0]
+        return 2 * np.abs(np.fft.rfft(line)[1]) / L
+    a0 = amp()
+    o.step(2000)
+    rate = -math.log(amp() / a0) / 2000
+    assert abs(rate / (p["D_l"] * k * k) - 1.0) < 2e-3, rate
+    assert np.max(np.abs(o.fields()[0] - 1.02)) < 1e-13
+
+
+# --------------------------------------------------------------------------
 # Diagnostics on hand-computed fixtures
 
 
