@@ -183,7 +183,8 @@ Coef<C> make_coef(const gplbm_params& p) {
   Coef<C> K{};
   const double dc = p.c_s_co - p.c_l_co;
   // tau_g = M_phi / xi_s^2 (3 M_phi, or 4 M_phi on D3Q7)
-  K.omega_g = C(1.0 / (lattice_inv_cs2g(p.lattice) * p.M_phi + 0.5));
+  K.omega_g_d = 1.0 / (lattice_inv_cs2g(p.lattice) * p.M_phi + 0.5);
+  K.omega_g = C(K.omega_g_d);
   // tau_h = 1 / (gamma xi_s^2): the diffusivity of the c-LBE is D(phi) on
   // every h lattice
   K.omega_h = C(1.0 / (1.0 / (p.gamma * lattice_cs2h(p)) + 0.5));

@@ -180,6 +180,10 @@ __device__ __forceinline__ double sources_adj(const Coef<double>& K, double lam_
                                               double sbar_b, double& phi_b, double& mu_b,
                                               double nb[3]) {
   const double pp = phi * (1.0 - phi);
+  // p' of the coupling takes phi limited to [0, 1] (zero derivative outside)
+  const double pl = limit01(phi);
+  const double ppl = pl * (1.0 - pl);
+  const bool in01 = phi >= 0.0 && phi <= 1.0;
   double Gst_b = sbar_b, kphi_b = 0.0, Gdw_b = 0.0;
   if (K.counter_term) {
 #pragma unroll
@@ -207,14 +211,16 @@ __device__ __forceinline__ double sources_adj(const Coef<double>& K, double lam_
   }
   double B, Bp;
   bracket_and_slope(K, mu, B, Bp);
-  const double Sphi = (6.0 * pp) * B;
-  double pp_b = (K.kst * 6.0 * B) * Gst_b + K.k4w * kphi_b;
-  mu_b += (K.kst * 6.0 * pp * Bp) * Gst_b;
+  const double Sphi = (6.0 * ppl) * B;
+  const double ppl_b = (K.kst * 6.0 * B) * Gst_b;
+  double pp_b = K.k4w * kphi_b;
+  mu_b += (K.kst * 6.0 * ppl * Bp) * Gst_b;
   if (!K.counter_term) {
     pp_b += K.kdw * 2.0 * (1.0 - 2.0 * phi) * Gdw_b;
     phi_b += K.kdw * 2.0 * pp * (-2.0) * Gdw_b;
   }
   phi_b += (1.0 - 2.0 * phi) * pp_b;
+  if (in01) phi_b += (1.0 - 2.0 * pl) * ppl_b;
   return -lam_M_W2 * Sphi * Gst_b;
 }
 
@@ -342,7 +348,10 @@ __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> Kin, double 
   const double dtphi = phi1 - f.phi;
   const double oh = K.omega_h;
   const double Dp = K.Dp;
-  const double D = (K.Dl * f.phi) + (K.Ds * (1.0 - f.phi));
+  // D = D_l q + D_s (1 - q), q = phi limited to [0, 1]
+  const double qd = limit01(f.phi);
+  const double D = (K.Dl * qd) + (K.Ds * (1.0 - qd));
+  const bool q_in = f.phi >= 0.0 && f.phi <= 1.0;
   // reverse of h* = (1 - oh) h + oh heq + (1 - oh/2) H
   double hb[LH::Q];
   double c_b = 0.0, lam_b = 0.0, Fb[3] = {0.0, 0.0, 0.0};
@@ -368,8 +377,8 @@ __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> Kin, double 
   // Lambda = gamma D mu
   mu_b += K.gamma * D * lam_b;
   const double D_b = K.gamma * f.mu * lam_b;
-  phi_b += (K.Dl - K.Ds) * D_b;
-  dl_b += f.phi * D_b;
+  if (q_in) phi_b += (K.Dl - K.Ds) * D_b;
+  dl_b += qd * D_b;
   // F = mu D' grad + jfac dtphi n
   const double gF = f.g[0] * Fb[0] + f.g[1] * Fb[1] + (L::D == 3 ? f.g[2] * Fb[2] : 0.0);
   mu_b += Dp * gF;
@@ -507,12 +516,13 @@ __global__ void __launch_bounds__(256) k_adj_init_a(Geo g, Coef<double> K, doubl
       if (LH::D == 3 && LH::ez[k]) Fb[2] += (LH::ez[k] > 0 ? HHb : -HHb);
     }
   }
-  const double D = (K.Dl * phi) + (K.Ds * (1.0 - phi));
+  const double qd = limit01(phi);
+  const double D = (K.Dl * qd) + (K.Ds * (1.0 - qd));
   double dl_b = 0.0, gb[3] = {0.0, 0.0, 0.0};
   mu0_b += K.gamma * D * lam_b;
   const double D_b = K.gamma * mu0 * lam_b;
-  phi_b += (K.Dl - K.Ds) * D_b;
-  dl_b += phi * D_b;
+  if (phi >= 0.0 && phi <= 1.0) phi_b += (K.Dl - K.Ds) * D_b;
+  dl_b += qd * D_b;
   const double gF = f.g[0] * Fb[0] + f.g[1] * Fb[1] + (L::D == 3 ? f.g[2] * Fb[2] : 0.0);
   mu0_b += K.Dp * gF;
   dl_b += mu0 * gF;

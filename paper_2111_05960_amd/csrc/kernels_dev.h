@@ -286,14 +286,17 @@ __global__ void __launch_bounds__(256) k_dev_split_g(Geo g, Coef<float> K, DevSt
   gradient_normal<L, float>(DevGlobalPhi{g, b.nxt.PHI, x, y, z}, K.eps2, gr, n);
   float G[L::Q], gs[L::Q];
   phi_sources<L, float>(K, phi, mu, n, G);
+  double sg = 0.0;
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
     const float gk = pull_dev<Codec, L>(g, b.cur.G, b.cur.PHI, k, x, y, z);
+    sg = k == 0 ? double(gk) : sg + double(gk);
     gs[k] = g_collide<L, float>(K, k, gk, phi, G[k]);
   }
   uint16_t enc[L::Q];
   float gdec[L::Q];
   encode_g<Codec, L>(gs, phi, enc, gdec);
+  balance_g_rest<L, float, float>(K, gdec, sg, phi, source_moment<float>(K, phi, mu));
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
     if (k == L::REST)
@@ -370,11 +373,11 @@ __global__ void __launch_bounds__(kDiagThreads) k_dev_diag_partial(Geo g, DevSta
 // node's own opposite population, decoded with the node's own reference; the
 // T+2 tiles are loaded with clamped coordinates (the mirror ghost of the
 // gradient); the phi^{n+1} stencil of the g collision takes mirrored offsets;
-// and the in-block h streaming keeps the index order of the pull sum: the
-// e_z = +1 contributions gathered for the plane above are held apart (they
-// may be replaced by the node's own bounced values of that plane), the node's
-// own e_z = +1 values of a plane are held for the e_z = -1 bounces of the
-// plane below, and a closing plane past a top wall finishes the last plane.
+// and the in-block h streaming keeps the index order of the pull sum: a node
+// gathers the e_z = +1 layer of its c^{n+1} at its own plane, from the
+// exchange of the plane below (kept one plane longer) or its own bounced
+// values, takes the bounced e_z = -1 values from its own entries in that
+// exchange, and a closing plane past a top wall finishes the last plane.
 
 __device__ __forceinline__ uint16_t bload16(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
   return __builtin_bit_cast(uint16_t, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
@@ -404,8 +407,18 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   constexpr int QH = LH::Q;  // h lattice (D3Q19 or D3Q7)
   // e_z layers of the h lattice: +1 at [0, NU), 0 at [NU, NU + NM), -1 after
   constexpr int NU = count_ez<LH>(1), NM = count_ez<LH>(0);
-  __shared__ uint16_t hxe[2][QH - 1][BY][BX];  // h*^n of plane p: 16-bit codes
-  __shared__ float hxl[2][BY][BX];           // and Lambda^n, the reference of the codes
+  // Exchange of plane p: the 16-bit codes of the moving h*^n and Lambda^n,
+  // their reference.  Periodic: every moving population in hxe and Lambda in
+  // hxl, by plane parity.  Walls: the e_z = +1 layer in hxu and Lambda in hxl
+  // by plane modulo 3 (the plane above gathers that layer after its own
+  // barrier, and a node's own entries there are the bounce of its e_z = -1
+  // populations: with one barrier per plane a buffer is rewritten two planes
+  // after it was read), the other moving populations in hxe by parity.
+  static_assert(!kWalls || LH::REST == NU, "the rest vector opens the in-plane layer");
+  constexpr int NXE = kWalls ? QH - 1 - NU : QH - 1;
+  __shared__ uint16_t hxe[2][NXE][BY][BX];
+  __shared__ uint16_t hxu[kWalls ? 3 : 1][kWalls ? NU : 1][kWalls ? BY : 1][kWalls ? BX : 1];
+  __shared__ float hxl[kWalls ? 3 : 2][BY][BX];
 
   int tx, ty;
   bool valid;
@@ -478,11 +491,6 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   // late, each group gathered in ascending k
   const bool inner = valid && tx >= 1 && tx <= TX && ty >= 1 && ty <= TY;
   double acc_dn = 0.0, acc_mid = 0.0;
-  // walls: e_z = +1 contributions gathered for the plane above, and this
-  // node's own e_z = +1 post-collision values of the plane below
-  float up_v[kWalls ? NU : 1], own_prev[kWalls ? NU : 1];
-#pragma unroll
-  for (int k = 0; k < (kWalls ? NU : 1); ++k) up_v[k] = own_prev[k] = 0.0f;
 
   for (int p = pfirst; p <= z1; ++p) {
     // past a top wall: no plane, only the completion of plane nz - 1
@@ -598,11 +606,19 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     // (the same arithmetic as the writer's, so the same values), keeping the
     // population order of a pull without ordered passes
     const int xb = p & 1;
+    // walls: buffers of planes p and p - 1 modulo 3 (p >= -1)
+    const int ub = (p + 3) % 3, pb = (p + 2) % 3;
+    const int lb = kWalls ? ub : xb;
     if (active && !closing) {
 #pragma unroll
-      for (int k = 0; k < QH; ++k)
-        if (k != LH::REST) hxe[xb][mslot<LH>(k)][ty][tx] = enc[k];
-      hxl[xb][ty][tx] = lam;
+      for (int k = 0; k < QH; ++k) {
+        if (k == LH::REST) continue;
+        if (kWalls && k < NU)
+          hxu[kWalls ? ub : 0][kWalls ? k : 0][ty][tx] = enc[k];
+        else
+          hxe[xb][kWalls ? k - NU - 1 : mslot<LH>(k)][ty][tx] = enc[k];
+      }
+      hxl[lb][ty][tx] = lam;
     }
     load_tiles(p + 2);
     // The one barrier of the plane.  Before it: reads of the phi / Lambda
@@ -610,15 +626,23 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     // of the tile p+2.  After it: reads of the exchange (p & 1) and of
     // phi^{n+1}(p-2 .. p).  The slot of tile p+2 was last read before the
     // previous barrier, that of phi^{n+1}(p) after the barrier three planes
-    // back, and the exchange buffer (p & 1) after the barrier two planes back.
+    // back, and the exchange buffer (p & 1) after the barrier two planes back
+    // (with walls the buffers kept modulo 3, read also after the next
+    // barrier, after the barrier three planes back).
     __syncthreads();
     const bool dn_ok = p - 1 >= z0 && p - 1 < z1;
     // decoded h* that population k of this node receives from x - e_k in the
-    // exchange of plane p
+    // exchange of plane p (not the e_z = +1 layer with walls)
     auto xchg = [&](int k) -> double {
       const int sy = ty - LH::ey[k], sx = tx - LH::ex[k];
-      const float ref = float(LH::w[k]) * hxl[xb][sy][sx];
-      return double(dev_decode<Codec>(hxe[xb][mslot<LH>(k)][sy][sx], ref));
+      const float ref = float(LH::w[k]) * hxl[lb][sy][sx];
+      return double(dev_decode<Codec>(hxe[xb][kWalls ? k - NU - 1 : mslot<LH>(k)][sy][sx], ref));
+    };
+    // walls: decoded e_z = +1 population k of plane p - 1 at region node
+    // (sy, sx)
+    auto xup = [&](int k, int sy, int sx) -> double {
+      const float ref = float(LH::w[k]) * hxl[kWalls ? pb : 0][sy][sx];
+      return double(dev_decode<Codec>(hxu[kWalls ? pb : 0][kWalls ? k : 0][sy][sx], ref));
     };
     double acc_up = 0.0;
     if constexpr (!kWalls) {
@@ -642,7 +666,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
 #pragma unroll
         for (int k = 0; k < NU; ++k) {
           const bool bnc = bz_up || ((bmh >> k) & 1u);
-          const double v = bnc ? double(hdec[LH::opp[k]]) : double(up_v[k]);
+          const double v = bnc ? double(hdec[LH::opp[k]]) : xup(k, ty - LH::ey[k], tx - LH::ex[k]);
           a = k == 0 ? v : a + v;
         }
 #pragma unroll
@@ -660,20 +684,14 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
         // (this node's own e_z = +1 values of plane p - 1)
 #pragma unroll
         for (int k = NU + NM; k < QH; ++k) {
-          const double v = ((bmh >> k) & 1u) ? double(own_prev[LH::opp[k]]) : xchg(k);
+          const double v = ((bmh >> k) & 1u) ? xup(LH::opp[k], ty, tx) : xchg(k);
           acc_dn = acc_dn + v;
-        }
-        // the e_z = +1 layer of plane p + 1, and this plane's own values
-#pragma unroll
-        for (int k = 0; k < NU; ++k) {
-          up_v[k] = float(xchg(k));
-          own_prev[k] = hdec[k];
         }
         acc_up = a;
       } else {
         // past the top wall every e_z = -1 population of plane nz - 1 bounces
 #pragma unroll
-        for (int k = NU + NM; k < QH; ++k) acc_dn = acc_dn + double(own_prev[LH::opp[k]]);
+        for (int k = NU + NM; k < QH; ++k) acc_dn = acc_dn + xup(LH::opp[k], ty, tx);
       }
     }
 
@@ -693,11 +711,16 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
       gradient_normal<LG, float>(atB, K.eps2, gr1, n1);
       float G[Q], gs[Q];
       phi_sources<LG, float>(K, phi1, mu1, n1, G);
+      double sg1 = 0.0;
 #pragma unroll
-      for (int k = 0; k < Q; ++k) gs[k] = g_collide<LG, float>(K, k, g_old[k], phi1, G[k]);
+      for (int k = 0; k < Q; ++k) {
+        sg1 = k == 0 ? double(g_old[k]) : sg1 + double(g_old[k]);
+        gs[k] = g_collide<LG, float>(K, k, g_old[k], phi1, G[k]);
+      }
       uint16_t genc[Q];
       float gdec[Q];
       encode_g<Codec, LG>(gs, phi1, genc, gdec);
+      balance_g_rest<LG, float, float>(K, gdec, sg1, phi1, source_moment<float>(K, phi1, mu1));
       const auto Gw = make_rsrc(reinterpret_cast<char*>(b.nxt.G.mov) + zq * groupB, uint32_t(groupB));
 #pragma unroll
       for (int k = 0; k < Q; ++k)
@@ -717,11 +740,19 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
   }
 }
 
+// output rows per tile with walls: the wall bookkeeping (bounce masks,
+// mirror offsets, the third exchange buffer) does not fit the 128 VGPRs of
+// 16 waves per CU, so the walled z-march runs 64 x 9 tiles (12 waves, up to
+// 168 VGPRs) instead of spilling
+#ifndef GPLBM_DEV_WALL_TY
+#define GPLBM_DEV_WALL_TY 9
+#endif
+
 template <class Codec, class LG, class LH, bool kGen>
 struct DevFused3D {
   template <bool kWalls>
   static int run(const Geo& g, const Coef<float>& K, const DevStep& b, hipStream_t st) {
-    constexpr int TX = 64, TY = GPLBM_DEV_TY, ZC = 32;
+    constexpr int TX = 64, TY = kWalls ? GPLBM_DEV_WALL_TY : GPLBM_DEV_TY, ZC = 32;
     constexpr int NT = TileShape<TX, TY>::NT;
     auto kernel = k_dev_fused3d<TX, TY, ZC, Codec, LG, LH, kGen, kWalls>;
     const int tiles_x = (g.nx + TX - 1) / TX;
@@ -907,11 +938,16 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     gradient_normal<L, float>(at1, K.eps2, gr, n);
     float G[Q], gs[Q];
     phi_sources<L, float>(K, phi1, mu1, n, G);
+    double sg1 = 0.0;
 #pragma unroll
-    for (int k = 0; k < Q; ++k) gs[k] = g_collide<L, float>(K, k, gn[k], phi1, G[k]);
+    for (int k = 0; k < Q; ++k) {
+      sg1 = k == 0 ? double(gn[k]) : sg1 + double(gn[k]);
+      gs[k] = g_collide<L, float>(K, k, gn[k], phi1, G[k]);
+    }
     uint16_t genc[Q];
     float gdec[Q];
     encode_g<Codec, L>(gs, phi1, genc, gdec);
+    balance_g_rest<L, float, float>(K, gdec, sg1, phi1, source_moment<float>(K, phi1, mu1));
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       if (k == L::REST)

@@ -104,6 +104,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT), (sizeof(S) == 4 ? 6 :
     const C cc = C(c);
 #pragma unroll
     for (int k = 0; k < LH::Q; ++k) hs[k] = C(S(h_update<LH, C>(K, k, h[k], cc, lam, F)));
+    balance_rest<LH, S, C>(hs, c);
   }
   if (valid) {
     phiB[ty][tx] = phin_c;
@@ -142,9 +143,16 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT), (sizeof(S) == 4 ? 6 :
   gradient_normal<L, C>(at1, K.eps2, gr, n);
   C G[L::Q];
   phi_sources<L, C>(K, phi1, mu1, n, G);
+  C gs[L::Q];
+  double sg1 = 0.0;
 #pragma unroll
-  for (int k = 0; k < L::Q; ++k)
-    b.Gn[pop_index<L>(g, k, x, y, 0)] = S(g_collide<L, C>(K, k, gn[k], phi1, G[k]));
+  for (int k = 0; k < L::Q; ++k) {
+    sg1 = k == 0 ? double(gn[k]) : sg1 + double(gn[k]);
+    gs[k] = C(S(g_collide<L, C>(K, k, gn[k], phi1, G[k])));
+  }
+  balance_g_rest<L, S, C>(K, gs, sg1, phi1, source_moment<C>(K, phi1, mu1));
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) b.Gn[pop_index<L>(g, k, x, y, 0)] = S(gs[k]);
 #pragma unroll
   for (int k = 0; k < LH::Q; ++k) b.Hn[pop_index<LH>(g, k, x, y, 0)] = S(hs[k]);
   b.PHIn[i] = S(phi1);

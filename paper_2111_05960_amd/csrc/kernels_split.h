@@ -82,9 +82,12 @@ __global__ void __launch_bounds__(256) k_split_h(Geo g, Coef<C> Kin, StepBufs<S>
   h_flux<L, C>(K, mu, gr, n, dtphi, K.anti_trapping != 0, F);
   const C lam = h_lambda<C>(K, phi, mu);
   const C cc = C(c);
+  C hs[LH::Q];
 #pragma unroll
-  for (int k = 0; k < LH::Q; ++k)
-    b.Hn[pop_index<LH>(g, k, x, y, z)] = S(h_update<LH, C>(K, k, h[k], cc, lam, F));
+  for (int k = 0; k < LH::Q; ++k) hs[k] = C(S(h_update<LH, C>(K, k, h[k], cc, lam, F)));
+  balance_rest<LH, S, C>(hs, c);
+#pragma unroll
+  for (int k = 0; k < LH::Q; ++k) b.Hn[pop_index<LH>(g, k, x, y, z)] = S(hs[k]);
   b.PHIn[i] = S(phin);
 }
 
@@ -109,11 +112,17 @@ __global__ void __launch_bounds__(256) k_split_g(Geo g, Coef<C> Kin, StepBufs<S>
   gradient_normal<L, C>(GlobalPhi<S, C>{g, b.PHIn, x, y, z}, K.eps2, gr, n);
   C G[L::Q];
   phi_sources<L, C>(K, phi, mu, n, G);
+  C gs[L::Q];
+  double sg = 0.0;
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
-    C gk = C(pull<L>(g, b.G, k, x, y, z));
-    b.Gn[pop_index<L>(g, k, x, y, z)] = S(g_collide<L, C>(K, k, gk, phi, G[k]));
+    const S v = pull<L>(g, b.G, k, x, y, z);
+    sg = k == 0 ? double(v) : sg + double(v);
+    gs[k] = C(S(g_collide<L, C>(K, k, C(v), phi, G[k])));
   }
+  balance_g_rest<L, S, C>(K, gs, sg, phi, source_moment<C>(K, phi, mu));
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) b.Gn[pop_index<L>(g, k, x, y, z)] = S(gs[k]);
 }
 
 // ---------------------------------------------------------------------------

@@ -119,10 +119,15 @@ def test_adjoint_matches_oracle_autograd(adj, case):
         assert e <= 1e-9, (k, e)
 
 
-def test_adjoint_against_finite_differences(adj):
-    """Porous 2-D D2Q9 (periodic, 96^2), K = 200 steps."""
-    p, phi0, c0, _ = wl.config_porous2d(n=96)
-    K = 200
+@pytest.mark.parametrize("n,K", [(96, 200), (512, 4000)])
+def test_adjoint_against_finite_differences(adj, n, K):
+    """Porous 2-D D2Q9 (periodic), at 96^2 with K = 200 steps and at the
+    differentiation workload's own size, 512^2 with K = 4000 (sqrt(K)
+    checkpointing); the phi0 direction is seeded noise times 4 phi0 (1 - phi0)
+    (it vanishes where phi0 is exactly 0 or 1, where p' and q, evaluated on
+    [0, 1], have a kink)."""
+    p, phi0, c0, _ = wl.config_porous2d(n=n)
+    print(f"case finite differences porous2d n={n} K={K}", flush=True)
     rng = np.random.default_rng(7)
     v = rng.standard_normal(phi0.shape) * 4.0 * phi0 * (1.0 - phi0)
     dev = "cuda"
