@@ -198,17 +198,24 @@ def adjoint_bytes_per_node(Q: int, D: int, precision: str) -> int:
     return 8 * adj_values + fwd * fwd_values
 
 
-def time_reverse_steps(n, precision, log, reps=200):
+def time_reverse_steps(n, precision, log, reps=200, dim=2):
     """Mean time of one reverse step (both reverse kernels) on the n^2 D2Q9
-    porous workload, timed with HIP events on the stream the library launches
-    on, between two saved states."""
+    porous workload (dim 2) or the n^3 D3Q19 one (dim 3), timed with HIP
+    events on the stream the library launches on, between two saved states.
+    The working set of a reverse step (adjoint state read and written, two
+    forward states) is compared with the 256 MB last-level cache: where it
+    fits, the rate is partly a cache rate."""
     import torch
     import workloads as wl
     from paper_2111_05960_amd import Simulation
     from paper_2111_05960_amd import binding as B
 
-    p, phi0, c0, _ = wl.config_porous2d(n=n)
+    if dim == 2:
+        p, phi0, c0, _ = wl.config_porous2d(n=n)
+    else:
+        p, phi0, c0 = wl.config_porous3d(n)
     sim = Simulation(p, precision).init(phi0, c0)
+    del phi0, c0
     s0, _ = sim.checkpoint()
     sim.step(1)
     s1, _ = sim.checkpoint()
@@ -228,13 +235,18 @@ def time_reverse_steps(n, precision, log, reps=200):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    balg = adjoint_bytes_per_node(9, 2, precision)
-    res = {"ms_per_reverse_step": round(ms, 5), "mlups": round(sim.N / (ms * 1e-3) / 1e6, 1),
+    balg = adjoint_bytes_per_node(sim.Q, dim, precision)
+    working_set = balg * sim.N
+    res = {"workload": f"porous{dim}d_{n}_{'d2q9' if dim == 2 else 'd3q19'}",
+           "ms_per_reverse_step": round(ms, 5), "mlups": round(sim.N / (ms * 1e-3) / 1e6, 1),
            "bytes_per_node_step": balg,
            "achieved_gbs": round(balg * sim.N / (ms * 1e-3) / 1e9, 1),
-           "hbm_frac": round(balg * sim.N / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-    log(f"reverse step {precision}: {ms:.4f} ms, {res['mlups']} MLUPS, {res['achieved_gbs']} GB/s "
-        f"algorithmic ({balg} B/node)")
+           "hbm_frac": round(balg * sim.N / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "working_set_gb": round(working_set / 1e9, 3),
+           "cache_resident": working_set <= LLC_BYTES}
+    log(f"reverse step {res['workload']} {precision}: {ms:.4f} ms, {res['mlups']} MLUPS, "
+        f"{res['achieved_gbs']} GB/s algorithmic ({balg} B/node), working set "
+        f"{res['working_set_gb']} GB{' (cache-resident)' if res['cache_resident'] else ''}")
     del sim, work
     torch.cuda.empty_cache()
     return res
@@ -287,6 +299,10 @@ def time_adjoint(K, log, n=512, precision="fp64"):
            "J1": J1.item(), "dJ1_dlambda": g_lam.grad.item(), "dJ1_dDl": g_dl.grad.item(),
            "dJ1_dphi0_norm": float(g_phi0.grad.norm().item())}
     res["reverse_step"] = time_reverse_steps(n, precision, log)
+    if precision == "fp64":
+        # the same reverse kernels on a working set far beyond the last-level
+        # cache (256^3 D3Q19, about 12 GB per reverse step): the HBM rate
+        res["reverse_step_hbm"] = time_reverse_steps(256, precision, log, reps=20, dim=3)
     log(f"adjoint {res['workload']} {precision} K={K}: forward {fwd:.3f} s, backward {bwd:.3f} s "
         f"(ratio {bwd / fwd:.2f}), peak {peak / 1e9:.2f} GB")
     return res
@@ -344,29 +360,44 @@ def calibration_copy(log, gib=4):
 
 
 def stream_ceiling(log, gib=4, reps=10):
-    """Rate of a plain read + write stream on this GPU (one elementwise
-    negation, gib GiB in and gib GiB out, FP64), timed with HIP events over
-    reps launches: the practical ceiling for a kernel that reads and writes
-    in similar amounts, beside the 8 TB/s peak."""
+    """Rate of a plain read + write stream on this GPU, gib GiB in and gib GiB
+    out, timed with HIP events over reps launches: the library's own copy
+    kernel (gplbm_stream_copy: one 16-byte vector per thread, non-temporal
+    stores) and, for reference, torch's FP64 negation.  The practical ceiling
+    for a kernel that reads and writes in similar amounts, beside the 8 TB/s
+    peak.  Returns (in-tree copy GB/s, torch negation GB/s)."""
     import torch
-    n = gib * (1 << 30) // 8
-    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    from paper_2111_05960_amd import binding as B
+    nbytes = gib << 30
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
-    torch.neg(a, out=b)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rates = []
+    for kind in ("copy", "neg"):
+        def once():
+            if kind == "copy":
+                B.gplbm_stream_copy(a.data_ptr(), b.data_ptr(), nbytes, stream.cuda_stream)
+            else:
+                torch.neg(a, out=b)
+        once()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            once()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        rates.append(round(2 * nbytes / (ms * 1e-3) / 1e9, 1))
+        log(f"stream ceiling ({kind}): {rates[-1]:.0f} GB/s ({gib} GiB read + {gib} GiB "
+            f"written, {ms:.3f} ms)")
+    assert torch.equal(b, -a)  # the last launches negated a into b
+    B.gplbm_stream_copy(a.data_ptr(), b.data_ptr(), nbytes, stream.cuda_stream)
     torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(reps):
-        torch.neg(a, out=b)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    gbs = 2 * n * 8 / (ms * 1e-3) / 1e9
-    log(f"stream ceiling: {gbs:.0f} GB/s ({gib} GiB read + {gib} GiB written, {ms:.3f} ms)")
+    assert torch.equal(a, b), "gplbm_stream_copy did not copy"
     del a, b
     torch.cuda.empty_cache()
-    return round(gbs, 1)
+    return rates[0], rates[1]
 
 
 def summarize_profile(kind, dbs, out, workload, precision, schedule):
@@ -566,6 +597,8 @@ def main():
     ap.add_argument("--free-energy", default="equal", choices=["equal", "quadratic"],
                     help="equal curvatures, or general quadratic")
     ap.add_argument("--schedule", default="auto", choices=["auto", "split", "fused"])
+    ap.add_argument("--bc", default="periodic", choices=["periodic", "walls"],
+                    help="periodic grid, or zero flux on every face")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-table", action="store_true",
                     help="also time the FP64 oracle (all threads and one) beside the "
@@ -590,7 +623,8 @@ def main():
         PROFILE_CMD = args.profile_cmd
         summarize_profile(args.profile_kind, args.summarize_profile, args.out, args.workload,
                           form_name(args.precision, args.h_lattice, args.h_scheme,
-                                    args.free_energy), args.schedule)
+                                    args.free_energy) + ("_walls" if args.bc == "walls" else ""),
+                          args.schedule)
         return
 
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
@@ -611,7 +645,9 @@ def main():
     log(f"workload {args.workload} generated in {time.perf_counter() - t0:.1f} s")
 
     variant = (args.h_lattice, args.h_scheme, args.free_energy)
-    main_form = form_name(args.precision, *variant)
+    main_form = form_name(args.precision, *variant) + ("_walls" if args.bc == "walls" else "")
+    if args.bc == "walls":
+        p = dict(p, bc=(1, 1, 1))
     keep = args.precision == "fp64" and not args.no_forms
     main_res = time_gpu(p, phi0, c0, args.precision, args.schedule, args.steps, args.warmup, log,
                         *variant, keep_phi=keep, repeats=3)
@@ -646,6 +682,21 @@ def main():
                 "mass_drift_rel": r["mass_drift_rel"]}
             if "vs_fp64" in r:
                 forms[name]["vs_fp64"] = r["vs_fp64"]
+        # the same grid with zero-flux faces (the porous case's boundary in
+        # the paper): the walled instantiation of the z-march
+        for prec in ("fp64", "fp32", "fp16dev"):
+            name = form_name(prec) + "_walls"
+            pw = dict(p, bc=(1, 1, 1))
+            r = time_gpu(pw, phi0, c0, prec, "auto", args.steps, args.warmup, log)
+            t = stored_traffic(args.workload, name, r["schedule"])
+            forms[name] = {
+                "mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                "schedule": r["schedule"], "bc": "zero flux on every face",
+                "bytes_per_node_step": r["bytes_per_node_step"],
+                "achieved_gbs": round(r["achieved_gbs"], 1),
+                "hbm_frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                "traffic_gb_per_step": None if t is None else round(t["bytes_per_step"] / 1e9, 3),
+                "mass_drift_rel": r["mass_drift_rel"]}
     ref_phi = None
     torch.cuda.empty_cache()
     variants = []
@@ -674,7 +725,7 @@ def main():
     traffic = stored_traffic(args.workload, main_form, main_res["schedule"])
     # a profiled counter run (--calibration-copy) keeps its single calibration
     # negation: the stream-ceiling launches would be counted with it
-    ceiling = None if args.calibration_copy else stream_ceiling(log)
+    ceiling, ceiling_neg = (None, None) if args.calibration_copy else stream_ceiling(log)
     # rate of the bytes the step actually moves (the profiled counters), over
     # the stream ceiling measured here
     traffic_rate = None if traffic is None else \
@@ -713,7 +764,7 @@ def main():
                           (0, "light-gh"): "D2Q5"}[(p["lattice"], args.h_lattice)],
             "h_scheme": args.h_scheme, "free_energy": args.free_energy,
             "grid": [nx, ny, nz],
-            "bc": "periodic",
+            "bc": "periodic" if args.bc == "periodic" else "zero flux on every face",
             "precision": args.precision,
             "schedule": main_res["schedule"],
             "counter_term": p["counter_term"], "anti_trapping": p["anti_trapping"],
@@ -735,7 +786,9 @@ def main():
             "cache_resident": working_set <= LLC_BYTES,
             "launches_per_step": main_res["launches_per_step"],
             "stream_ceiling_gbs": ceiling,
-            "stream_ceiling_kernel": "FP64 negation, 4 GiB read + 4 GiB written (torch.neg)",
+            "stream_ceiling_kernel": "gplbm_stream_copy: 4 GiB read + 4 GiB written, one "
+                                     "16-byte vector per thread, non-temporal stores",
+            "stream_torch_neg_gbs": ceiling_neg,
             "traffic_rate_gbs": None if traffic_rate is None else round(traffic_rate, 1),
             "traffic_rate_frac_of_ceiling": None if traffic_rate is None or ceiling is None
             else round(traffic_rate / ceiling, 4),

@@ -254,6 +254,15 @@ int gplbm_adjoint_step(gplbm_ctx* ctx, const void* state_n, const void* state_np
 int gplbm_adjoint_finish(gplbm_ctx* ctx, const double* phi0, const double* c0, double* phi0_bar,
                          double* c0_bar, double* dJ_dparams);
 
+/* Bandwidth reference of the device (not part of the method): copies bytes
+ * (a multiple of 16, at most 2^31 - 1 blocks of 4 KiB) from src to dst
+ * (device, 16-byte aligned, not overlapping), one 16-byte vector per thread
+ * with non-temporal stores, asynchronously on stream.  Its rate is the
+ * practical ceiling of a kernel that reads and writes the same amount, which
+ * the step does.  GPLBM_E_INVALID for null or misaligned pointers or a size
+ * that is not a multiple of 16. */
+int gplbm_stream_copy(const void* src, void* dst, uint64_t bytes, void* stream);
+
 /* Which schedule the context runs (GPLBM_SCHED_SPLIT or GPLBM_SCHED_FUSED). */
 int gplbm_schedule(const gplbm_ctx* ctx);
 

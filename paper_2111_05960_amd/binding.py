@@ -43,7 +43,7 @@ SYMBOLS = ("gplbm_state_bytes", "gplbm_checkpoint_bytes", "gplbm_create", "gplbm
            "gplbm_diagnostics", "gplbm_save_state", "gplbm_load_state", "gplbm_schedule",
            "gplbm_last_error", "gplbm_destroy", "gplbm_adjoint_bytes", "gplbm_adjoint_begin",
            "gplbm_adjoint_step", "gplbm_adjoint_finish", "gplbm_step_to",
-           "gplbm_diagnostics_noalloc")
+           "gplbm_diagnostics_noalloc", "gplbm_stream_copy")
 
 
 class gplbm_params(ctypes.Structure):
@@ -110,6 +110,7 @@ def load():
     lib.gplbm_read_fields.argtypes = [vp, vp, vp, vp]
     lib.gplbm_diagnostics.argtypes = [vp, P(gplbm_diag)]
     lib.gplbm_diagnostics_noalloc.argtypes = [vp, P(gplbm_diag)]
+    lib.gplbm_stream_copy.argtypes = [vp, vp, u64, vp]
     lib.gplbm_save_state.argtypes = [vp, vp]
     lib.gplbm_load_state.argtypes = [vp, vp, i64]
     lib.gplbm_schedule.argtypes = [vp]
@@ -126,7 +127,7 @@ def load():
     for name in ("gplbm_state_bytes", "gplbm_checkpoint_bytes", "gplbm_create",
                  "gplbm_set_stream", "gplbm_init_fields", "gplbm_step", "gplbm_read_fields",
                  "gplbm_diagnostics", "gplbm_diagnostics_noalloc", "gplbm_save_state",
-                 "gplbm_load_state", "gplbm_schedule",
+                 "gplbm_load_state", "gplbm_schedule", "gplbm_stream_copy",
                  "gplbm_adjoint_bytes", "gplbm_adjoint_begin", "gplbm_adjoint_step",
                  "gplbm_adjoint_finish"):
         getattr(lib, name).restype = ctypes.c_int
@@ -243,6 +244,13 @@ def gplbm_diagnostics_noalloc(ctx, allow_nonfinite: bool = False) -> dict:
     return {"step": d.step, "total_mass": d.total_mass, "solid_fraction": d.solid_fraction,
             "solid_fraction_count": d.solid_fraction_count, "sum_phi": d.sum_phi,
             "phi_min": d.phi_min, "phi_max": d.phi_max, "nonfinite": bool(d.nonfinite)}
+
+
+def gplbm_stream_copy(src_ptr: int, dst_ptr: int, nbytes: int, stream: int):
+    rc = load().gplbm_stream_copy(ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr),
+                                  int(nbytes), ctypes.c_void_p(stream))
+    if rc:
+        raise GplbmError(rc, "gplbm_stream_copy rejected the request")
 
 
 def gplbm_save_state(ctx, dst_ptr: int):

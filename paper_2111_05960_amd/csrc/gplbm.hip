@@ -19,6 +19,7 @@
 #include "kernels_fused2d.h"
 #include "kernels_fused3d.h"
 #include "kernels_split.h"
+#include "stream_copy.h"
 
 using namespace gplbm;
 
@@ -766,6 +767,17 @@ int gplbm_load_state(gplbm_ctx* ctx, const void* dev_src, int64_t step) {
 }
 
 int gplbm_schedule(const gplbm_ctx* ctx) { return ctx ? ctx->sched : GPLBM_E_INVALID; }
+
+int gplbm_stream_copy(const void* src, void* dst, uint64_t bytes, void* stream) {
+  if (!src || !dst || bytes % 16 || ((uintptr_t)src) % 16 || ((uintptr_t)dst) % 16)
+    return GPLBM_E_INVALID;
+  if (bytes == 0) return GPLBM_OK;
+  const uint64_t n = bytes / 16, blocks = (n + kStreamThreads - 1) / kStreamThreads;
+  if (blocks > 0x7fffffffull) return GPLBM_E_INVALID;
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(kStreamThreads), 0,
+                     (hipStream_t)stream, (const StreamVec*)src, (StreamVec*)dst, n);
+  return hipGetLastError() == hipSuccess ? GPLBM_OK : GPLBM_E_DEVICE;
+}
 
 const char* gplbm_last_error(const gplbm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
