@@ -851,18 +851,23 @@ struct AdjOps {
     const Coef<double> K = make_coef<double>(ctx->p);
     const int a = ctx->adj_cur, b = 1 - a;
     const FS S0 = FwdFromState<FS>::get(ctx, s0), S1 = FwdFromState<FS>::get(ctx, s1);
-    // the general reverse kernels only for h^eq,alt or eps_s != eps_l
-    if (ctx->p.h_scheme != GPLBM_H_SOURCE || ctx->p.free_energy != GPLBM_FE_EQUAL) {
-      hipLaunchKernelGGL((k_adj_ra<L, LH, FS, true>), grid(ctx), block(), 0, ctx->stream, g, K,
+    // the general reverse kernels only for h^eq,alt or eps_s != eps_l; the
+    // periodic addressing when no axis has walls
+    const bool gen = ctx->p.h_scheme != GPLBM_H_SOURCE || ctx->p.free_energy != GPLBM_FE_EQUAL;
+    const bool per = !ctx->p.bc[0] && !ctx->p.bc[1] && !ctx->p.bc[2];
+    auto launch = [&](auto kgen, auto kper) {
+      constexpr bool G = decltype(kgen)::value, Pr = decltype(kper)::value;
+      hipLaunchKernelGGL((k_adj_ra<L, LH, FS, G, Pr>), grid(ctx), block(), 0, ctx->stream, g, K,
                          lam_M_W2(ctx), S1, ctx->adj.set[a], ctx->adj.set[b], ctx->adj);
-      hipLaunchKernelGGL((k_adj_rb<L, LH, FS, true>), grid(ctx), block(), 0, ctx->stream, g, K,
+      hipLaunchKernelGGL((k_adj_rb<L, LH, FS, G, Pr>), grid(ctx), block(), 0, ctx->stream, g, K,
                          lam_M_W2(ctx), S0, S1, ctx->adj.set[a], ctx->adj.set[b], ctx->adj);
-    } else {
-      hipLaunchKernelGGL((k_adj_ra<L, LH, FS, false>), grid(ctx), block(), 0, ctx->stream, g, K,
-                         lam_M_W2(ctx), S1, ctx->adj.set[a], ctx->adj.set[b], ctx->adj);
-      hipLaunchKernelGGL((k_adj_rb<L, LH, FS, false>), grid(ctx), block(), 0, ctx->stream, g, K,
-                         lam_M_W2(ctx), S0, S1, ctx->adj.set[a], ctx->adj.set[b], ctx->adj);
-    }
+    };
+    using T = std::true_type;
+    using F = std::false_type;
+    if (gen)
+      per ? launch(T{}, T{}) : launch(T{}, F{});
+    else
+      per ? launch(F{}, T{}) : launch(F{}, F{});
     int rc = check_launch(ctx, "adjoint step");
     if (rc) return rc;
     ctx->adj_cur = b;

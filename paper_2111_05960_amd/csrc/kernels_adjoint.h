@@ -27,6 +27,8 @@
 // not follow D_l).
 #pragma once
 
+#include <type_traits>
+
 #include "kernels_dev.h"
 #include "kernels_split.h"
 
@@ -94,11 +96,153 @@ __device__ __forceinline__ int push_dest(const Geo& g, int k, int x, int y, int 
   return k;
 }
 
+// Addressing of the reverse steps.  AdjAddrGeneral takes any boundary, by
+// the rules of geometry.h; AdjAddrPeriodic serves grids periodic on every
+// axis, where each neighbour is the node plus a wrapped offset (precomputed
+// per node, the plane ones uniform over a block), without the per-population
+// wall tests.  Both give the same indices on a periodic grid.
+struct AdjAddrGeneral {
+  const Geo& g;
+  int x, y, z;
+  __device__ AdjAddrGeneral(const Geo& g_, int x_, int y_, int z_) : g(g_), x(x_), y(y_), z(z_) {}
+  __device__ int64_t self() const { return node_index(g, x, y, z); }
+  // slot that population k of lattice P pulls at this node: (k, x - e_k), or
+  // (opp k, x) when x - e_k lies beyond a wall
+  template <class P>
+  __device__ int64_t pull_slot(int k) const {
+    int sx = x, sy = y, sz = z;
+    bool in = pull_axis(sx, P::ex[k], g.nx, g.bcx) && pull_axis(sy, P::ey[k], g.ny, g.bcy);
+    if (P::D == 3) in = in && pull_axis(sz, P::ez[k], g.nz, g.bcz);
+    if (!in) return pop_index<P>(g, P::opp[k], x, y, z);
+    return pop_index<P>(g, k, sx, sy, sz);
+  }
+  // node and population that pull slot k of this node
+  template <class P>
+  __device__ void push(int k, int64_t& dpop, int64_t& dnode) const {
+    int dx, dy, dz;
+    const int kk = push_dest<P>(g, k, x, y, z, dx, dy, dz);
+    dpop = pop_index<P>(g, kk, dx, dy, dz);
+    dnode = node_index(g, dx, dy, dz);
+  }
+  // source node of the value population k of lattice P pulls (the node
+  // itself for a bounced population), and its slot in the deviation layout
+  template <class P>
+  __device__ void pull_dev_slot(int k, int64_t& node, int64_t& slot, int& kk) const {
+    int sx = x, sy = y, sz = z;
+    bool in = pull_axis(sx, P::ex[k], g.nx, g.bcx) && pull_axis(sy, P::ey[k], g.ny, g.bcy);
+    if (P::D == 3) in = in && pull_axis(sz, P::ez[k], g.nz, g.bcz);
+    kk = in ? k : P::opp[k];
+    if (!in) sx = x, sy = y, sz = z;
+    node = node_index(g, sx, sy, sz);
+    slot = mov_index<P>(g, kk, sx, sy, sz);
+  }
+  // node x + (dx, dy, dz) of the gradient stencil (mirror ghost at walls)
+  __device__ int64_t stencil(int dx, int dy, int dz) const {
+    return node_index(g, stencil_axis(x + dx, g.nx, g.bcx), stencil_axis(y + dy, g.ny, g.bcy),
+                      stencil_axis(z + dz, g.nz, g.bcz));
+  }
+};
+
+struct AdjAddrPeriodic {
+  int64_t plane;
+  int z, zm, zp;             // planes z, z - 1, z + 1 (wrapped)
+  int xy;                    // y nx + x
+  int oxm, oxp, oym, oyp;    // in-plane offsets of x - 1, x + 1, y - 1, y + 1 (wrapped)
+  __device__ AdjAddrPeriodic(const Geo& g, int x, int y, int z_) {
+    plane = (int64_t)g.nx * g.ny;
+    z = z_;
+    zm = z == 0 ? g.nz - 1 : z - 1;
+    zp = z == g.nz - 1 ? 0 : z + 1;
+    xy = y * g.nx + x;
+    oxm = x == 0 ? g.nx - 1 : -1;
+    oxp = x == g.nx - 1 ? 1 - g.nx : 1;
+    oym = y == 0 ? (g.ny - 1) * g.nx : -g.nx;
+    oyp = y == g.ny - 1 ? (1 - g.ny) * g.nx : g.nx;
+  }
+  __device__ int xyn(int dx, int dy) const {
+    return xy + (dx < 0 ? oxm : (dx > 0 ? oxp : 0)) + (dy < 0 ? oym : (dy > 0 ? oyp : 0));
+  }
+  __device__ int zn(int dz) const { return dz < 0 ? zm : (dz > 0 ? zp : z); }
+  __device__ int64_t node(int dx, int dy, int dz) const { return (int64_t)zn(dz) * plane + xyn(dx, dy); }
+  __device__ int64_t self() const { return (int64_t)z * plane + xy; }
+  template <class P>
+  __device__ int64_t pull_slot(int k) const {
+    return ((int64_t)zn(-P::ez[k]) * P::Q + k) * plane + xyn(-P::ex[k], -P::ey[k]);
+  }
+  template <class P>
+  __device__ void push(int k, int64_t& dpop, int64_t& dnode) const {
+    dpop = ((int64_t)zn(P::ez[k]) * P::Q + k) * plane + xyn(P::ex[k], P::ey[k]);
+    dnode = node(P::ex[k], P::ey[k], P::ez[k]);
+  }
+  template <class P>
+  __device__ void pull_dev_slot(int k, int64_t& src, int64_t& slot, int& kk) const {
+    kk = k;
+    src = node(-P::ex[k], -P::ey[k], -P::ez[k]);
+    slot = ((int64_t)zn(-P::ez[k]) * (P::Q - 1) + mslot<P>(k)) * plane + xyn(-P::ex[k], -P::ey[k]);
+  }
+  __device__ int64_t stencil(int dx, int dy, int dz) const { return node(dx, dy, dz); }
+};
+
+template <class S, class A>
+struct AddrPhi {
+  const S* __restrict__ f;
+  const A& a;
+  __device__ double operator()(int dx, int dy, int dz) const { return double(f[a.stencil(dx, dy, dz)]); }
+};
+
 // Forward quantities at one node from a state: c, mu, phi, grad phi, normal.
 template <class L>
 struct NodeFwd {
   double c, mu, phi, g[3], n[3], s;  // s = sqrt(|grad|^2 + eps^2)
 };
+
+template <class L, class LH, class S, class A>
+__device__ __forceinline__ NodeFwd<L> node_fwd_at(const Coef<double>& K, const FwdState<S>& F,
+                                                  const A& a) {
+  NodeFwd<L> f;
+  double c = 0.0;
+#pragma unroll
+  for (int k = 0; k < LH::Q; ++k) {
+    const double v = double(F.H[a.template pull_slot<LH>(k)]);
+    c = k == 0 ? v : c + v;
+  }
+  f.c = c;
+  f.phi = double(F.PHI[a.self()]);
+  f.mu = closure(K.q, c, f.phi);
+  gradient_normal<L, double>(AddrPhi<S, A>{F.PHI, a}, K.eps2, f.g, f.n);
+  double nn = f.g[0] * f.g[0] + f.g[1] * f.g[1];
+  if (L::D == 3) nn = nn + f.g[2] * f.g[2];
+  f.s = sqrt(nn + K.eps2);
+  return f;
+}
+
+template <class L, class LH, class Codec, class A>
+__device__ __forceinline__ NodeFwd<L> node_fwd_at(const Coef<double>& K, const DevFwdState<Codec>& F,
+                                                  const A& a) {
+  NodeFwd<L> f;
+  double c = 0.0;
+#pragma unroll
+  for (int k = 0; k < LH::Q; ++k) {
+    float v;
+    if (k == LH::REST) {
+      v = F.H.rest[a.self()];
+    } else {
+      int64_t src, slot;
+      int kk;
+      a.template pull_dev_slot<LH>(k, src, slot, kk);
+      v = dev_decode<Codec>(F.H.mov[slot], float(LH::w[kk]) * F.LAM[src]);
+    }
+    c = k == 0 ? double(v) : c + double(v);
+  }
+  f.c = c;
+  f.phi = double(F.PHI[a.self()]);
+  f.mu = closure(K.q, c, f.phi);
+  gradient_normal<L, double>(AddrPhi<float, A>{F.PHI, a}, K.eps2, f.g, f.n);
+  double nn = f.g[0] * f.g[0] + f.g[1] * f.g[1];
+  if (L::D == 3) nn = nn + f.g[2] * f.g[2];
+  f.s = sqrt(nn + K.eps2);
+  return f;
+}
 
 template <class L, class LH, class S>
 __device__ __forceinline__ NodeFwd<L> node_fwd(const Geo& g, const Coef<double>& K, const FwdState<S>& F,
@@ -278,6 +422,26 @@ __device__ __forceinline__ double stencil_adj_gather(const Geo& g, const double*
 
 // --------------------------------------------------------------------------
 
+// The same gather on a periodic grid: one preimage per population, x - e_k.
+template <class L>
+__device__ __forceinline__ double stencil_adj_gather_at(const Geo& g, const double* gb3,
+                                                        const AdjAddrPeriodic& a) {
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    if (k == L::REST) continue;
+    const int64_t q = a.node(-L::ex[k], -L::ey[k], -L::ez[k]);
+    const double e_g = edot<L, double>(k, gb3[q], gb3[g.N + q], L::D == 3 ? gb3[2 * g.N + q] : 0.0);
+    acc += L::inv_cs2 * L::w[k] * e_g;
+  }
+  return acc;
+}
+template <class L>
+__device__ __forceinline__ double stencil_adj_gather_at(const Geo& g, const double* gb3,
+                                                        const AdjAddrGeneral& a) {
+  return stencil_adj_gather<L>(g, gb3, a.x, a.y, a.z);
+}
+
 // Adjoint of G' in slot (k, x, y, z), gathered from the previous set.
 template <class L>
 __device__ __forceinline__ double gather_Gb(const Geo& g, const AdjSet& P, int k, int x, int y, int z) {
@@ -288,7 +452,8 @@ __device__ __forceinline__ double gather_Gb(const Geo& g, const AdjSet& P, int k
 
 // kGen: the general instantiation keeps the scheme flags (h^eq,alt, general
 // free energies) of the run; the basic one fixes them off at compile time.
-template <class L, class LH, class FS, bool kGen>
+// kPer: every axis periodic (AdjAddrPeriodic), else any boundary.
+template <class L, class LH, class FS, bool kGen, bool kPer>
 __global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> Kin, double lam_M_W2,
                                                 FS S1, AdjSet P, AdjSet C, AdjWork w) {
   const Coef<double> K = variant<kGen>(Kin);
@@ -296,15 +461,19 @@ __global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> Kin, double 
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= g.nx || y >= g.ny) return;
-  const int64_t i = node_index(g, x, y, z);
-  const NodeFwd<L> f = node_fwd<L, LH>(g, K, S1, x, y, z);  // c^{n+1}, mu^{n+1}, ...
+  using Addr = std::conditional_t<kPer, AdjAddrPeriodic, AdjAddrGeneral>;
+  const Addr ad(g, x, y, z);
+  const int64_t i = ad.self();
+  const NodeFwd<L> f = node_fwd_at<L, LH>(K, S1, ad);  // c^{n+1}, mu^{n+1}, ...
   const double om = K.omega_g;
   double Gb[L::Q];
   double phi_b = 0.0, mu_b = 0.0, nb[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
-    const double a = gather_Gb<L>(g, P, k, x, y, z);
-    C.A1[pop_index<L>(g, k, x, y, z)] = (1.0 - om) * a;
+    int64_t dpop, dnode;
+    ad.template push<L>(k, dpop, dnode);
+    const double a = P.A1[dpop] + P.B2[dnode];
+    C.A1[((int64_t)z * L::Q + k) * ((int64_t)g.nx * g.ny) + (i - (int64_t)z * g.nx * g.ny)] = (1.0 - om) * a;
     Gb[k] = (1.0 - 0.5 * om) * a;
     phi_b += om * L::w[k] * a;
   }
@@ -323,7 +492,7 @@ __global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> Kin, double 
   w.lamb[i] += lb;
 }
 
-template <class L, class LH, class FS, bool kGen>
+template <class L, class LH, class FS, bool kGen, bool kPer>
 __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> Kin, double lam_M_W2,
                                                 FS S0, FS S1, AdjSet P, AdjSet C, AdjWork w) {
   const Coef<double> K = variant<kGen>(Kin);
@@ -331,19 +500,21 @@ __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> Kin, double 
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= g.nx || y >= g.ny) return;
-  const int64_t i = node_index(g, x, y, z);
+  using Addr = std::conditional_t<kPer, AdjAddrPeriodic, AdjAddrGeneral>;
+  const Addr ad(g, x, y, z);
+  const int64_t i = ad.self();
   // total adjoint of h~*^n in this node's slots
   double Hb[LH::Q];
 #pragma unroll
   for (int k = 0; k < LH::Q; ++k) {
-    int dx, dy, dz;
-    const int kk = push_dest<LH>(g, k, x, y, z, dx, dy, dz);
-    Hb[k] = P.B1[pop_index<LH>(g, kk, dx, dy, dz)] + w.A3[node_index(g, dx, dy, dz)];
+    int64_t dpop, dnode;
+    ad.template push<LH>(k, dpop, dnode);
+    Hb[k] = P.B1[dpop] + w.A3[dnode];
   }
   // adjoint of phi^{n+1} at this node (A2, A4 hold both collisions' parts)
-  double p1b = w.A4[i] + stencil_adj_gather<L>(g, w.A2, x, y, z);
+  double p1b = w.A4[i] + stencil_adj_gather_at<L>(g, w.A2, ad);
   // forward quantities of step n
-  const NodeFwd<L> f = node_fwd<L, LH>(g, K, S0, x, y, z);
+  const NodeFwd<L> f = node_fwd_at<L, LH>(K, S0, ad);
   const double phi1 = double(S1.PHI[i]);
   const double dtphi = phi1 - f.phi;
   const double oh = K.omega_h;
@@ -405,7 +576,8 @@ __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> Kin, double 
     phi_b += dmu_dphi * mu_b;
   }
 #pragma unroll
-  for (int k = 0; k < LH::Q; ++k) C.B1[pop_index<LH>(g, k, x, y, z)] = hb[k] + c_b;
+  for (int k = 0; k < LH::Q; ++k)
+    C.B1[((int64_t)z * LH::Q + k) * ((int64_t)g.nx * g.ny) + (i - (int64_t)z * g.nx * g.ny)] = hb[k] + c_b;
   C.B2[i] = p1b;
   for (int a = 0; a < 3; ++a) C.B3[a * g.N + i] = gb[a];
   C.B4[i] = phi_b;

@@ -140,11 +140,17 @@ template <>
 struct Fused3DConfig<D3Q19, double> {
   static constexpr int TX = 64, TY = 6, ZC = 32;
   static constexpr Carry carry = Carry::kLds;
+  static constexpr bool prefetch = false;
 };
+// FP32: the phi^n tile of the plane after next is fetched into registers
+// while a plane is computed (512^3: 9.65-10.0 against 10.6-10.8 ms per step,
+// with h on D3Q7 7.28 against 7.52; in FP64 it ran 2% slower, on D3Q7 12%
+// slower in FP32 and level in FP64)
 template <>
 struct Fused3DConfig<D3Q19, float> {
   static constexpr int TX = 64, TY = 12, ZC = 32;
   static constexpr Carry carry = Carry::kRegisters;
+  static constexpr bool prefetch = true;
 };
 // g on D3Q7: 7 populations carried in registers; tile heights measured on
 // the 512^3 step (FP64: 12 rows 7.05 ms, 8 rows 7.79, 6 rows 8.36; FP32: 8
@@ -153,15 +159,17 @@ template <>
 struct Fused3DConfig<D3Q7, double> {
   static constexpr int TX = 64, TY = 12, ZC = 32;
   static constexpr Carry carry = Carry::kRegisters;
+  static constexpr bool prefetch = false;
 };
 template <>
 struct Fused3DConfig<D3Q7, float> {
   static constexpr int TX = 64, TY = 8, ZC = 32;
   static constexpr Carry carry = Carry::kRegisters;
+  static constexpr bool prefetch = false;
 };
 
-template <int TX, int TY, int ZC, Carry kCarryMode, class L, class LH, class S, class C,
-          bool kGen, bool kWalls>
+template <int TX, int TY, int ZC, Carry kCarryMode, bool kPrefetch, class L, class LH, class S,
+          class C, bool kGen, bool kWalls>
 __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     k_fused3d(Geo g, Coef<C> Kin, StepBufs<S> b, int tiles_x, int tiles_xy, int ntiles) {
   const Coef<C> K = variant<kGen>(Kin);
@@ -255,19 +263,24 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
       const int gy = kWalls ? tile_coord(Y0 - 2 + l / AX, ny, g.bcy) : wrap_coord(Y0 - 2 + l / AX, ny);
       phi_off[j] = uint32_t(gy * nx + gx);
     }
-    auto load_phi = [&](int p) {
+    auto fetch_phi = [&](int p, S (&v)[PHI_PER_THREAD]) {
       const int pz = kWalls ? tile_coord(p, nz, g.bcz) : wrap_coord(p, nz);
       const S* src = b.PHI + (int64_t)pz * plane;
-      S v[PHI_PER_THREAD];
 #pragma unroll
       for (int j = 0; j < PHI_PER_THREAD; ++j) v[j] = src[phi_off[j]];
+    };
+    auto put_phi = [&](int p, const S (&v)[PHI_PER_THREAD]) {
 #pragma unroll
       for (int j = 0; j < PHI_PER_THREAD; ++j) {
         const int l = threadIdx.x + j * NT;
         if (l < AX * AY) phiA[ring3(p)][l / AX][l % AX] = C(v[j]);
       }
     };
-
+    auto load_phi = [&](int p) {
+      S v[PHI_PER_THREAD];
+      fetch_phi(p, v);
+      put_phi(p, v);
+    };
     // first plane: the halo plane below the chunk, or the bottom plane at a
     // z wall
     const int pfirst = (wz && z0 == 0) ? 0 : z0 - 1;
@@ -281,21 +294,34 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
     // ones one plane late, each layer in ascending k)
     const bool inner = valid && tx >= 1 && tx <= TX && ty >= 1 && ty <= TY;
     double acc_dn = 0.0, acc_mid = 0.0;
+    double sg_old = 0.0;
+
+    // prefetch: the phi^n tile of the plane after next, in flight in
+    // registers while the current plane is computed
+    S phi_next[kPrefetch ? PHI_PER_THREAD : 1];
+    if constexpr (kPrefetch) fetch_phi(pfirst + 1, phi_next);
 
     for (int p = pfirst; p <= z1; ++p) {
       // past a top wall: no plane, only the completion of plane nz - 1
       const bool closing = wz && p == nz;
-      load_phi(p + 1);
+      const bool work = !kWalls || (active && !closing);
+      if constexpr (kPrefetch) {
+        put_phi(p + 1, phi_next);
+        fetch_phi(p + 2, phi_next);
+      } else {
+        load_phi(p + 1);
+      }
       __syncthreads();
       const int zp = wz ? min(p, nz - 1) : wrap_coord(p, nz);
       // all e_z = +1 (-1) sources of this plane lie beyond the bottom (top) wall
-      const bool bz_up = wz && p == 0, bz_dn = wz && p == nz - 1;
+      const bool bz_up = wz && p == 0;
       const int sA = ring3(p);
       const bool own_p = p >= z0 && p < z1;
 
       C hs[QH];
       C g_new[kRegs ? Q : 1];
-      if (!kWalls || (active && !closing)) {
+      double sg = 0.0;
+      if (work) {
         S hv[QH], gv[Q];
         if constexpr (!kWalls) {
           fetch_pops<LH, S>(b.H, zp, nz, plane, xyb, hv);
@@ -303,6 +329,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
         } else {
           // pulls; a source beyond a wall gives the node's own opposite
           // population (bounce-back); a plane beyond a z wall is never read
+          const bool bz_dn = wz && p == nz - 1;
           const int zs[3] = {wz ? max(zp - 1, 0) : (zp == 0 ? nz - 1 : zp - 1), zp,
                              wz ? min(zp + 1, nz - 1) : (zp == nz - 1 ? 0 : zp + 1)};
           __amdgpu_buffer_rsrc_t RH[3], RG[3];
@@ -330,7 +357,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
         }
 
         C h[QH];
-        double c = 0.0, sg = 0.0;
+        double c = 0.0;
 #pragma unroll
         for (int k = 0; k < QH; ++k) {
           h[k] = C(hv[k]);
@@ -513,7 +540,8 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
           // storage narrower than double: the zeroth moment of the stored g
           // is balanced through the rest population (balance_g_rest), each
           // moving population stored as soon as it is computed
-          double sg1 = 0.0, s = 0.0;
+          // sg_old: the double sum of these g, taken when they were pulled
+          double s = 0.0;
 #pragma unroll
           for (int k = 0; k < Q; ++k) {
             C gk;
@@ -521,14 +549,13 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
               gk = g_old[k];
             else
               gk = gkeep[(p - 1) & 1][k][ty - 1][tx - 1];
-            sg1 = k == 0 ? double(gk) : sg1 + double(gk);
             if (k == L::REST) continue;
             const S v = S(g_collide<L, C>(K, k, gk, phi1, G[k]));
             bstore_nt<S>(v, Gw, selfB, k * planeB);
             s = s + double(v);
           }
           const double wg = K.omega_g_d;
-          const double m0 = ((1.0 - wg) * sg1 + wg * double(phi1)) +
+          const double m0 = ((1.0 - wg) * sg_old + wg * double(phi1)) +
                             (1.0 - 0.5 * wg) * double(source_moment<C>(K, phi1, mu1));
           bstore_nt<S>(S(m0 - s), Gw, selfB, L::REST * planeB);
         } else {
@@ -547,6 +574,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
 #pragma unroll
         for (int k = 0; k < Q; ++k) g_old[k] = g_new[k];
       }
+      sg_old = sg;
       if constexpr (kWalls) {
         acc_dn = acc_up;
       } else if constexpr (kGather) {
@@ -573,10 +601,16 @@ template <>
 struct Fused3DWallConfig<D3Q19, double> {
   static constexpr int TX = 64, TY = 5, ZC = 32;
   static constexpr Carry carry = Carry::kRegisters;
+  static constexpr bool prefetch = false;
 };
 // FP32 on D3Q19 with walls keeps the 64 x 12 tiles of the periodic grid: it
 // spills about 20 VGPRs there but ran 11.95 ms per 512^3 step against 12.43
-// on 64 x 9 tiles (12 waves, no spill)
+// on 64 x 9 tiles (12 waves, no spill); without the prefetch of the periodic
+// grid (which spills 45 VGPRs there: 19.0 against 16.3 ms)
+template <>
+struct Fused3DWallConfig<D3Q19, float> : Fused3DConfig<D3Q19, float> {
+  static constexpr bool prefetch = false;
+};
 
 template <class L, class LH, class S, class C, bool kGen>
 struct Fused3D {
@@ -584,7 +618,7 @@ struct Fused3D {
   static int run(const Geo& g, const Coef<C>& K, const StepBufs<S>& b, hipStream_t st) {
     constexpr int TX = Cfg::TX, TY = Cfg::TY, ZC = Cfg::ZC;
     constexpr int NT = TileShape<TX, TY>::NT;
-    auto kernel = k_fused3d<TX, TY, ZC, Cfg::carry, L, LH, S, C, kGen, kWalls>;
+    auto kernel = k_fused3d<TX, TY, ZC, Cfg::carry, Cfg::prefetch, L, LH, S, C, kGen, kWalls>;
     const int tiles_x = (g.nx + TX - 1) / TX;
     const int tiles_y = (g.ny + TY - 1) / TY;
     const int chunks = (g.nz + ZC - 1) / ZC;
