@@ -270,9 +270,12 @@ def time_adjoint(K, log, n=512, precision="fp64"):
     c0_t = torch.tensor(c0, device=dev)
     g_lam = torch.tensor(p["lam"], dtype=torch.float64, requires_grad=True)
     g_dl = torch.tensor(p["D_l"], dtype=torch.float64, requires_grad=True)
-    # untimed warm-up of both directions on a short run
-    phiK, _ = adjoint.gplbm_run(g_phi0, c0_t, g_lam, g_dl, p, 16, precision=precision)
+    # untimed warm-up of both directions at the same length, so that the
+    # allocator's pool holds the checkpoints and the segment's states (the
+    # timed run then measures the steps, not first-touch allocations)
+    phiK, _ = adjoint.gplbm_run(g_phi0, c0_t, g_lam, g_dl, p, K, precision=precision)
     adjoint.objectives(g_phi0, phiK, p["W"])[0].backward()
+    del phiK
     g_phi0.grad = None
     g_lam.grad = None
     g_dl.grad = None
@@ -301,8 +304,12 @@ def time_adjoint(K, log, n=512, precision="fp64"):
     res["reverse_step"] = time_reverse_steps(n, precision, log)
     if precision == "fp64":
         # the same reverse kernels on a working set far beyond the last-level
-        # cache (256^3 D3Q19, about 12 GB per reverse step): the HBM rate
-        res["reverse_step_hbm"] = time_reverse_steps(256, precision, log, reps=20, dim=3)
+        # cache (256^3 D3Q19, about 19 GB per reverse step): the HBM rate,
+        # with the counted traffic of the committed rocprofv3 summary
+        r = time_reverse_steps(256, precision, log, reps=20, dim=3)
+        t = stored_traffic("porous3d_256_d3q19", precision, "reverse")
+        r["traffic_gb_per_step"] = None if t is None else round(t["bytes_per_step"] / 1e9, 3)
+        res["reverse_step_hbm"] = r
     log(f"adjoint {res['workload']} {precision} K={K}: forward {fwd:.3f} s, backward {bwd:.3f} s "
         f"(ratio {bwd / fwd:.2f}), peak {peak / 1e9:.2f} GB")
     return res
@@ -429,8 +436,12 @@ def summarize_profile(kind, dbs, out, workload, precision, schedule):
         for kname, counter, n, avg, tot in rows(db, "select kernel_name, counter_name, count(*), avg(value), sum(value) from counters_collection group by kernel_name, counter_name"):
             vals[(kname, counter)] = (n, avg)
             sums[(kname, counter)] = tot
-    step = [k for k in vals if any(t in k[0] for t in ("k_fused", "k_split", "k_dev_fused",
-                                                        "k_dev_split"))]
+    # the step kernels, or in a reverse-step run the two reverse kernels (the
+    # run also takes one forward step between its two saved states)
+    step = [k for k in vals if any(t in k[0] for t in ("k_adj_ra", "k_adj_rb"))]
+    if not step:
+        step = [k for k in vals if any(t in k[0] for t in ("k_fused", "k_split", "k_dev_fused",
+                                                            "k_dev_split"))]
     # the calibration is one 4 GiB negation (the only one in a profiled run:
     # --calibration-copy skips the stream-ceiling launches), which torch may
     # split into several dispatches: their counters are summed
@@ -609,6 +620,9 @@ def main():
                     help="also time the other precision and schedule")
     ap.add_argument("--adjoint-steps", type=int, default=4000,
                     help="K of the differentiation workload (0 skips it)")
+    ap.add_argument("--reverse-only", action="store_true",
+                    help="time only the reverse step on the 256^3 D3Q19 instance (--steps of "
+                         "them) and exit: the command profiled for the reverse kernels")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run a 4 GiB device copy after the timed region (counter calibration)")
     ap.add_argument("--summarize-profile", nargs="+", metavar="DB",
@@ -639,6 +653,12 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.reverse_only:
+        r = time_reverse_steps(256, args.precision, log, reps=args.steps, dim=3)
+        if args.calibration_copy:
+            calibration_copy(log)
+        print(json.dumps(r), flush=True)
+        return
 
     t0 = time.perf_counter()
     p, phi0, c0 = make_workload(args.workload)
