@@ -184,6 +184,16 @@ int gplbm_step(gplbm_ctx* ctx, int64_t nsteps);
  * copies.  Asynchronous on the context's stream. */
 int gplbm_step_to(gplbm_ctx* ctx, const void* src_state, void* dst_state);
 
+/* A segment of steps between saved states: states j = 0 .. n lie at
+ * states + j * stride bytes (device; states 256-byte aligned, stride a
+ * multiple of 256 and at least gplbm_checkpoint_bytes); state 0 is given, and the call computes state j+1
+ * from state j for j < n, as n calls of gplbm_step_to would (a checkpointing
+ * driver rebuilds a segment from its checkpoint with one call).  The
+ * context's own state is left unchanged.  Asynchronous on the context's
+ * stream; GPLBM_E_INVALID for a null pointer, n < 0 or a stride that is too
+ * small or misaligned. */
+int gplbm_step_chain(gplbm_ctx* ctx, void* states, uint64_t stride, int64_t n);
+
 /* Current time level n. */
 int64_t gplbm_step_count(const gplbm_ctx* ctx);
 
@@ -251,6 +261,12 @@ int gplbm_adjoint_bytes(const gplbm_params* p, uint64_t* bytes);
 int gplbm_adjoint_begin(gplbm_ctx* ctx, void* work, uint64_t bytes, const double* phi_bar,
                         const double* c_bar);
 int gplbm_adjoint_step(gplbm_ctx* ctx, const void* state_n, const void* state_np1);
+/* gplbm_adjoint_segment: the reverse steps over a segment of forward states
+ *   laid out as in gplbm_step_chain (states j = 0 .. n at states + j * stride):
+ *   gplbm_adjoint_step(state j, state j+1) for j = n-1 down to 0, in one call.
+ *   Asynchronous; GPLBM_E_INVALID for a null pointer, n < 0 or a bad stride,
+ *   GPLBM_E_STATE before gplbm_adjoint_begin. */
+int gplbm_adjoint_segment(gplbm_ctx* ctx, const void* states, uint64_t stride, int64_t n);
 int gplbm_adjoint_finish(gplbm_ctx* ctx, const double* phi0, const double* c0, double* phi0_bar,
                          double* c0_bar, double* dJ_dparams);
 

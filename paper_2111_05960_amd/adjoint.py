@@ -15,8 +15,9 @@ in a deviation storage format and the FP64 reverse sweep at its decoded
 states.
 
 Checkpointing: forward keeps the state every s = ceil(sqrt(K)) steps;
-backward rebuilds each segment from its checkpoint (gplbm_step_to, no copies)
-and runs the reverse steps over it, so memory holds about 2 sqrt(K) states.
+backward rebuilds each segment from its checkpoint (gplbm_step_chain, no
+copies) and runs the reverse steps over it (gplbm_adjoint_segment), one call
+each per segment, so memory holds about 2 sqrt(K) states.
 """
 from __future__ import annotations
 
@@ -66,20 +67,23 @@ class _Run(torch.autograd.Function):
         B.gplbm_adjoint_begin(sim.ctx, _aligned(work), nb, pb.data_ptr() if pb is not None else 0,
                               cb.data_ptr() if cb is not None else 0)
         ck_bytes = B.gplbm_checkpoint_bytes(sim.params)
-        states = [torch.empty(ck_bytes, dtype=torch.uint8, device=dev) for _ in range(s + 1)]
+        # the s + 1 states of a segment, one after the other at a 256-byte stride
+        stride = (ck_bytes + 255) // 256 * 256
+        seg_buf = torch.empty((s + 1) * stride + 256, dtype=torch.uint8, device=dev)
+        base = _aligned(seg_buf)
+        off = base - seg_buf.data_ptr()
+        state0 = seg_buf[off:off + ck_bytes]
         for (ck, n0) in reversed(ctx.ckpts):
             n1 = min(n0 + s, K)
-            states[0].copy_(ck)
-            for j in range(n1 - n0):
-                B.gplbm_step_to(sim.ctx, states[j].data_ptr(), states[j + 1].data_ptr())
-            for j in range(n1 - n0 - 1, -1, -1):
-                B.gplbm_adjoint_step(sim.ctx, states[j].data_ptr(), states[j + 1].data_ptr())
+            state0.copy_(ck)
+            B.gplbm_step_chain(sim.ctx, base, stride, n1 - n0)
+            B.gplbm_adjoint_segment(sim.ctx, base, stride, n1 - n0)
         phi0d, c0d = ctx.inputs
         g_phi0 = torch.empty_like(phi0d)
         g_c0 = torch.empty_like(c0d)
         dlam, ddl = B.gplbm_adjoint_finish(sim.ctx, phi0d.data_ptr(), c0d.data_ptr(),
                                            g_phi0.data_ptr(), g_c0.data_ptr())
-        del states, work
+        del seg_buf, work
         return (g_phi0.reshape(ctx.shape), g_c0.reshape(ctx.shape),
                 torch.tensor(dlam, dtype=torch.float64), torch.tensor(ddl, dtype=torch.float64),
                 None, None, None, None)

@@ -43,7 +43,8 @@ SYMBOLS = ("gplbm_state_bytes", "gplbm_checkpoint_bytes", "gplbm_create", "gplbm
            "gplbm_diagnostics", "gplbm_save_state", "gplbm_load_state", "gplbm_schedule",
            "gplbm_last_error", "gplbm_destroy", "gplbm_adjoint_bytes", "gplbm_adjoint_begin",
            "gplbm_adjoint_step", "gplbm_adjoint_finish", "gplbm_step_to",
-           "gplbm_diagnostics_noalloc", "gplbm_stream_copy")
+           "gplbm_diagnostics_noalloc", "gplbm_stream_copy", "gplbm_step_chain",
+           "gplbm_adjoint_segment")
 
 
 class gplbm_params(ctypes.Structure):
@@ -111,6 +112,8 @@ def load():
     lib.gplbm_diagnostics.argtypes = [vp, P(gplbm_diag)]
     lib.gplbm_diagnostics_noalloc.argtypes = [vp, P(gplbm_diag)]
     lib.gplbm_stream_copy.argtypes = [vp, vp, u64, vp]
+    lib.gplbm_step_chain.argtypes = [vp, vp, u64, i64]
+    lib.gplbm_adjoint_segment.argtypes = [vp, vp, u64, i64]
     lib.gplbm_save_state.argtypes = [vp, vp]
     lib.gplbm_load_state.argtypes = [vp, vp, i64]
     lib.gplbm_schedule.argtypes = [vp]
@@ -275,6 +278,14 @@ def gplbm_destroy(ctx):
 
 def gplbm_step_to(ctx, src_ptr: int, dst_ptr: int):
     _check(ctx, load().gplbm_step_to(ctx, ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr)))
+
+
+def gplbm_step_chain(ctx, states_ptr: int, stride: int, n: int):
+    _check(ctx, load().gplbm_step_chain(ctx, ctypes.c_void_p(states_ptr), stride, n))
+
+
+def gplbm_adjoint_segment(ctx, states_ptr: int, stride: int, n: int):
+    _check(ctx, load().gplbm_adjoint_segment(ctx, ctypes.c_void_p(states_ptr), stride, n))
 
 
 def gplbm_adjoint_bytes(p: gplbm_params) -> int:

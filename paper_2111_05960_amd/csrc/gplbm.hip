@@ -985,6 +985,29 @@ int gplbm_adjoint_begin(gplbm_ctx* ctx, void* work, uint64_t bytes, const double
   return rc;
 }
 
+int gplbm_step_chain(gplbm_ctx* ctx, void* states, uint64_t stride, int64_t n) {
+  if (!ctx || !states || n < 0 || stride % kAlign || (uintptr_t)states % kAlign)
+    return GPLBM_E_INVALID;
+  uint64_t need = 0;
+  if (gplbm_checkpoint_bytes(&ctx->p, &need) || stride < need) return GPLBM_E_INVALID;
+  char* s = (char*)states;
+  for (int64_t j = 0; j < n; ++j)
+    if (int rc = gplbm_step_to(ctx, s + j * stride, s + (j + 1) * stride)) return rc;
+  return GPLBM_OK;
+}
+
+int gplbm_adjoint_segment(gplbm_ctx* ctx, const void* states, uint64_t stride, int64_t n) {
+  if (!ctx || !states || n < 0 || stride % kAlign || (uintptr_t)states % kAlign)
+    return GPLBM_E_INVALID;
+  uint64_t need = 0;
+  if (gplbm_checkpoint_bytes(&ctx->p, &need) || stride < need) return GPLBM_E_INVALID;
+  if (!ctx->adj_ready) return fail(ctx, GPLBM_E_STATE, "adjoint segment before adjoint begin");
+  const char* s = (const char*)states;
+  for (int64_t j = n - 1; j >= 0; --j)
+    if (int rc = gplbm_adjoint_step(ctx, s + j * stride, s + (j + 1) * stride)) return rc;
+  return GPLBM_OK;
+}
+
 int gplbm_adjoint_step(gplbm_ctx* ctx, const void* state_n, const void* state_np1) {
   if (!ctx || !state_n || !state_np1) return GPLBM_E_INVALID;
   if (!ctx->adj_ready) return fail(ctx, GPLBM_E_STATE, "adjoint step before adjoint begin");

@@ -144,6 +144,8 @@ def test_null_context_is_rejected(lib):
     assert lib.gplbm_step(None, 1) == B.GPLBM_E_INVALID
     assert lib.gplbm_init_fields(None, None, None) == B.GPLBM_E_INVALID
     assert lib.gplbm_step_count(None) == -1
+    assert lib.gplbm_step_chain(None, None, 256, 1) == B.GPLBM_E_INVALID
+    assert lib.gplbm_adjoint_segment(None, None, 256, 1) == B.GPLBM_E_INVALID
 
 
 @pytest.mark.parametrize("prec", ["fp16dev", "bf16dev"])
