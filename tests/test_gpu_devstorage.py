@@ -40,8 +40,10 @@ def interface_error(phi_a, phi_b, grad_b, W=2.5):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_dev_fused_equals_split(gp, prec):
-    shape = (40, 30, 70)
+@pytest.mark.parametrize("shape", [(40, 30, 70), (70, 30, 70)])
+def test_dev_fused_equals_split(gp, prec, shape):
+    """Periodic z-march: one z chunk with a ragged tile row, and two chunks
+    (64 planes and a ragged 6)."""
     p = wl.base_params(lattice=wl.D3Q19, shape=shape, bc=(0, 0, 0))
     phi0, c0 = wl.random_state_fields(shape, seed=21)
     a = gp.Simulation(p, prec, "split").init(phi0, c0).step(12)
@@ -204,7 +206,7 @@ def test_dev_light_h_against_oracle(gp, oracle_mod, prec, case, which):
 @pytest.mark.parametrize("which", ["h", "gh"])
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("case", [((24, 30, 70), (0, 0, 0)), ((1, 53, 91), (1, 1, 0)),
-                                  ((1, 70, 150), (0, 0, 0))])
+                                  ((1, 70, 150), (0, 0, 0)), ((70, 14, 64), (0, 0, 0))])
 def test_dev_light_h_fused_equals_split(gp, prec, case, which):
     shape, bc = case
     p = _light(shape, bc, which)
