@@ -34,9 +34,9 @@ def _aligned(t: torch.Tensor) -> int:
 
 class _Run(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, phi0, c0, lam, D_l, cfg, K, seg, precision):
+    def forward(ctx, phi0, c0, lam, D_l, cfg, K, seg, precision, schedule):
         cfg = dict(cfg, lam=float(lam), D_l=float(D_l))
-        sim = B.Simulation(cfg, precision)
+        sim = B.Simulation(cfg, precision, schedule)
         dev = sim.device
         phi0d = phi0.detach().to(dev, torch.float64).contiguous()
         c0d = c0.detach().to(dev, torch.float64).contiguous()
@@ -86,15 +86,18 @@ class _Run(torch.autograd.Function):
         del seg_buf, work
         return (g_phi0.reshape(ctx.shape), g_c0.reshape(ctx.shape),
                 torch.tensor(dlam, dtype=torch.float64), torch.tensor(ddl, dtype=torch.float64),
-                None, None, None, None)
+                None, None, None, None, None)
 
 
-def gplbm_run(phi0, c0, lam, D_l, cfg, K, seg=None, precision="fp64"):
+def gplbm_run(phi0, c0, lam, D_l, cfg, K, seg=None, precision="fp64", schedule="auto"):
     """(phi^K, c^K) after K steps; differentiable in phi0, c0, lam and D_l.
-    precision: "fp64", "fp32", "fp16dev" or "bf16dev" (forward storage)."""
+    precision: "fp64", "fp32", "fp16dev" or "bf16dev" (forward storage).
+    schedule: "auto", "split" or "fused" for the forward steps and their
+    re-computation (the schedules give the same bits, so the gradients do
+    not depend on it)."""
     if precision not in ("fp64", "fp32", "fp16dev", "bf16dev"):
         raise ValueError(f"unknown precision {precision!r}")
-    return _Run.apply(phi0, c0, lam, D_l, cfg, K, seg, precision)
+    return _Run.apply(phi0, c0, lam, D_l, cfg, K, seg, precision, schedule)
 
 
 def objectives(phi0, phiK, W):

@@ -452,17 +452,20 @@ __device__ __forceinline__ double gather_Gb(const Geo& g, const AdjSet& P, int k
 
 // kGen: the general instantiation keeps the scheme flags (h^eq,alt, general
 // free energies) of the run; the basic one fixes them off at compile time.
-// kPer: every axis periodic (AdjAddrPeriodic), else any boundary.
-template <class L, class LH, class FS, bool kGen, bool kPer>
-__global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> Kin, double lam_M_W2,
-                                                FS S1, AdjSet P, AdjSet C, AdjWork w) {
-  const Coef<double> K = variant<kGen>(Kin);
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= g.nx || y >= g.ny) return;
-  using Addr = std::conditional_t<kPer, AdjAddrPeriodic, AdjAddrGeneral>;
-  const Addr ad(g, x, y, z);
+// The two halves of a reverse step at one node (the two kernels below).
+//
+// reverse_g: the reverse of the g collision of step n+1.  Writes the adjoint
+// of the node's pulled g~^{n+1} (C.A1) when write_a1 is set, and returns the
+// adjoint of grad phi^{n+1} with the previous step's B3 added (a2), of c^{n+1}
+// (a3), the local adjoint of phi^{n+1} with the previous step's B4 added (a4),
+// and the lambda adjoint (lb).  The h collision of step n+1 (previous reverse
+// step) also used grad phi^{n+1} and phi^{n+1}: their adjoints are added here,
+// so that the second half applies the transposed stencil once.
+template <class L, class LH, class FS, class Addr>
+__device__ __forceinline__ void reverse_g(const Geo& g, const Coef<double>& K, double lam_M_W2,
+                                          const FS& S1, const AdjSet& P, const AdjSet& C,
+                                          const Addr& ad, int z, bool write_a1, double (&a2)[3],
+                                          double& a3, double& a4, double& lb) {
   const int64_t i = ad.self();
   const NodeFwd<L> f = node_fwd_at<L, LH>(K, S1, ad);  // c^{n+1}, mu^{n+1}, ...
   const double om = K.omega_g;
@@ -473,35 +476,34 @@ __global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> Kin, double 
     int64_t dpop, dnode;
     ad.template push<L>(k, dpop, dnode);
     const double a = P.A1[dpop] + P.B2[dnode];
-    C.A1[((int64_t)z * L::Q + k) * ((int64_t)g.nx * g.ny) + (i - (int64_t)z * g.nx * g.ny)] = (1.0 - om) * a;
+    if (write_a1)
+      C.A1[((int64_t)z * L::Q + k) * ((int64_t)g.nx * g.ny) + (i - (int64_t)z * g.nx * g.ny)] =
+          (1.0 - om) * a;
     Gb[k] = (1.0 - 0.5 * om) * a;
     phi_b += om * L::w[k] * a;
   }
-  const double lb = sources_adj<L>(K, lam_M_W2, f.phi, f.mu, f.n, Gb, 0.0, phi_b, mu_b, nb);
+  lb = sources_adj<L>(K, lam_M_W2, f.phi, f.mu, f.n, Gb, 0.0, phi_b, mu_b, nb);
   double gb[3] = {0.0, 0.0, 0.0};
   normal_adj<L>(f, nb, gb);
-  // the h collision of step n+1 (previous reverse step) also used grad phi^{n+1}
-  // and phi^{n+1}: their adjoints are added here, so that rb applies the
-  // transposed stencil once
-  for (int a = 0; a < L::D; ++a) w.A2[a * g.N + i] = gb[a] + P.B3[a * g.N + i];
+  for (int a = 0; a < 3; ++a) a2[a] = a < L::D ? gb[a] + P.B3[a * g.N + i] : 0.0;
   double dmu_dc, dmu_dphi;
   closure_grad(K, f.c, f.phi, dmu_dc, dmu_dphi);
-  w.A3[i] = dmu_dc * mu_b;             // adjoint of c^{n+1}
-  phi_b += dmu_dphi * mu_b;            // closure
-  w.A4[i] = phi_b + P.B4[i];
-  w.lamb[i] += lb;
+  a3 = dmu_dc * mu_b;   // adjoint of c^{n+1}
+  phi_b += dmu_dphi * mu_b;  // closure
+  a4 = phi_b + P.B4[i];
 }
 
-template <class L, class LH, class FS, bool kGen, bool kPer>
-__global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> Kin, double lam_M_W2,
-                                                FS S0, FS S1, AdjSet P, AdjSet C, AdjWork w) {
-  const Coef<double> K = variant<kGen>(Kin);
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= g.nx || y >= g.ny) return;
-  using Addr = std::conditional_t<kPer, AdjAddrPeriodic, AdjAddrGeneral>;
-  const Addr ad(g, x, y, z);
+// reverse_h: the reverse of the h collision of step n and of phi^{n+1} =
+// sum g~^{n+1} + S^n / 2.  a3_at(k, dnode): the a3 of the node that pulls
+// slot k of this node (dnode its global index); p1b: the adjoint of
+// phi^{n+1} at this node gathered so far (a4 and the transposed stencil of
+// a2).  Writes B1 .. B4 of the node into C and accumulates its parameter
+// adjoints.
+template <class L, class LH, class FS, class Addr, class FA3>
+__device__ __forceinline__ void reverse_h(const Geo& g, const Coef<double>& K, double lam_M_W2,
+                                          const FS& S0, const FS& S1, const AdjSet& P,
+                                          const AdjSet& C, const AdjWork& w, const Addr& ad, int z,
+                                          const FA3& a3_at, double p1b) {
   const int64_t i = ad.self();
   // total adjoint of h~*^n in this node's slots
   double Hb[LH::Q];
@@ -509,10 +511,8 @@ __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> Kin, double 
   for (int k = 0; k < LH::Q; ++k) {
     int64_t dpop, dnode;
     ad.template push<LH>(k, dpop, dnode);
-    Hb[k] = P.B1[dpop] + w.A3[dnode];
+    Hb[k] = P.B1[dpop] + a3_at(k, dnode);
   }
-  // adjoint of phi^{n+1} at this node (A2, A4 hold both collisions' parts)
-  double p1b = w.A4[i] + stencil_adj_gather_at<L>(g, w.A2, ad);
   // forward quantities of step n
   const NodeFwd<L> f = node_fwd_at<L, LH>(K, S0, ad);
   const double phi1 = double(S1.PHI[i]);
@@ -583,6 +583,43 @@ __global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> Kin, double 
   C.B4[i] = phi_b;
   w.lamb[i] += lb;
   w.dlb[i] += dl_b;
+}
+
+// kPer: every axis periodic (AdjAddrPeriodic), else any boundary.
+template <class L, class LH, class FS, bool kGen, bool kPer>
+__global__ void __launch_bounds__(256) k_adj_ra(Geo g, Coef<double> Kin, double lam_M_W2,
+                                                FS S1, AdjSet P, AdjSet C, AdjWork w) {
+  const Coef<double> K = variant<kGen>(Kin);
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  using Addr = std::conditional_t<kPer, AdjAddrPeriodic, AdjAddrGeneral>;
+  const Addr ad(g, x, y, z);
+  const int64_t i = ad.self();
+  double a2[3], a3, a4, lb;
+  reverse_g<L, LH>(g, K, lam_M_W2, S1, P, C, ad, z, true, a2, a3, a4, lb);
+  for (int a = 0; a < L::D; ++a) w.A2[a * g.N + i] = a2[a];
+  w.A3[i] = a3;
+  w.A4[i] = a4;
+  w.lamb[i] += lb;
+}
+
+template <class L, class LH, class FS, bool kGen, bool kPer>
+__global__ void __launch_bounds__(256) k_adj_rb(Geo g, Coef<double> Kin, double lam_M_W2,
+                                                FS S0, FS S1, AdjSet P, AdjSet C, AdjWork w) {
+  const Coef<double> K = variant<kGen>(Kin);
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  using Addr = std::conditional_t<kPer, AdjAddrPeriodic, AdjAddrGeneral>;
+  const Addr ad(g, x, y, z);
+  const int64_t i = ad.self();
+  // adjoint of phi^{n+1} at this node (A2, A4 hold both collisions' parts)
+  const double p1b = w.A4[i] + stencil_adj_gather_at<L>(g, w.A2, ad);
+  auto a3_at = [&](int, int64_t dnode) { return w.A3[dnode]; };
+  reverse_h<L, LH>(g, K, lam_M_W2, S0, S1, P, C, w, ad, z, a3_at, p1b);
 }
 
 // Seed: the adjoint of S_K from dJ/dphi^K and dJ/dc^K (c^K = sum of the
