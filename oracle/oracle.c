@@ -74,6 +74,11 @@
  *     q(phi) = phi + (1 - phi) D_s / D_l and a = a_at: the paper fixes these
  *     choices for eps_s = eps_l and defers eps_s != eps_l, so the same
  *     interpolations are taken there.
+ * Parity unpinned: the source moment of S6, the initial populations and the
+ * value of eps_n are such choices; no value the paper prints fixes them.
+ * The pins check what follows from them (the recurrence of uniform fields,
+ * the moments at t = 0, the Stefan front within its bar), and the GPU is held
+ * to this file on them.
  */
 #include <math.h>
 #include <stdint.h>
