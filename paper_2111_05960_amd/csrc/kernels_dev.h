@@ -59,6 +59,23 @@ constexpr int kMov = 18;  // the most moving populations per node (D3Q19)
 template <class L = LD>
 __device__ __forceinline__ constexpr int mslot(int k) { return k < L::REST ? k : k - 1; }
 
+// populations of lattice L with e_z = v, as bits
+template <class L>
+__host__ __device__ constexpr uint32_t ez_bits(int v) {
+  uint32_t m = 0;
+  for (int k = 0; k < L::Q; ++k) m |= L::ez[k] == v ? (1u << k) : 0u;
+  return m;
+}
+// opposite populations share a weight (a bounced code decodes with w_k)
+template <class L>
+constexpr bool symmetric_weights() {
+  for (int k = 0; k < L::Q; ++k)
+    if (L::w[k] != L::w[L::opp[k]]) return false;
+  return true;
+}
+static_assert(symmetric_weights<D3Q19>() && symmetric_weights<D3Q7>() &&
+              symmetric_weights<D2Q9>() && symmetric_weights<D2Q5>(), "w_opp(k) = w_k");
+
 // slot of plane q in a ring of four planes (q >= -8)
 __device__ __forceinline__ int ring4(int q) { return (q + 8) & 3; }
 
@@ -432,7 +449,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
 
   for (int tile = first_tile(); tile < ntiles; tile += gridDim.x) {
   const int chunk = tile / tiles_xy, txy = tile % tiles_xy;
-  const int X0 = (txy % tiles_x) * TX, Y0 = (txy / tiles_x) * TY;
+  const int X0 = tile_column(txy, tiles_x, chunk, kWalls) * TX, Y0 = (txy / tiles_x) * TY;
   const int z0 = chunk * ZC, z1 = min(z0 + ZC, nz);
   const int ux = X0 - 1 + tx, uy = Y0 - 1 + ty;
   const bool out = valid && ux < nx && uy < ny && tx >= 1 && tx <= TX && ty >= 1 && ty <= TY;
@@ -527,47 +544,96 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
       // of the node itself for a population bounced back at a wall
       float h[QH];
       double c = 0.0, sg = 0.0;
+      // populations bounced at a wall (bits k); a wavefront with none (all but
+      // those of the tiles at a wall) takes the plain pulls
+      uint32_t bh = 0u, bg = 0u;
+      bool plain = true;
+      if constexpr (kWalls) {
+        bh = bmh | (bz_up ? ez_bits<LH>(1) : 0u) | (bz_dn ? ez_bits<LH>(-1) : 0u);
+        bg = bmg | (bz_up ? ez_bits<LG>(1) : 0u) | (bz_dn ? ez_bits<LG>(-1) : 0u);
+        plain = __builtin_amdgcn_ballot_w64((bh | bg) != 0u) == 0u;
+      }
+      if (!plain) {
+        // Every pull first reads its neighbour (a wrapped address where x -
+        // e_k lies beyond a wall: read, never used), then a lane with bounced
+        // populations replaces those codes by its own opposite ones, and each
+        // code decodes against the reference of the node that wrote it
+        // (w_opp(k) = w_k): one batch of loads and no branch per population
+        uint16_t ch[QH], cg[Q];
 #pragma unroll
-      for (int k = 0; k < QH; ++k) {
-        float v;
-        if (k == LH::REST) {
-          v = b.cur.H.rest[selfnode];
-        } else {
-          const bool bz = (LH::ez[k] > 0 && bz_up) || (LH::ez[k] < 0 && bz_dn);
-          const int ko = LH::opp[k];
-          if (kWalls && (bz || ((bmh >> k) & 1u))) {
-            v = dev_decode<Codec>(bload16(Hz[1], selfB, mslot<LH>(ko) * planeB),
-                                  float(LH::w[ko]) * lamA[sA][ty + 1][tx + 1]);
+        for (int k = 0; k < QH; ++k)
+          ch[k] = k == LH::REST ? uint16_t(0)
+                                : bload16(Hz[1 - LH::ez[k]], xyb[1 - LH::ey[k]][1 - LH::ex[k]],
+                                          mslot<LH>(k) * planeB);
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+          cg[k] = k == LG::REST ? uint16_t(0)
+                                : bload16(Gz[1 - LG::ez[k]], xyb[1 - LG::ey[k]][1 - LG::ex[k]],
+                                          mslot<LG>(k) * planeB);
+        if ((bh | bg) != 0u) {
+#pragma unroll
+          for (int k = 0; k < QH; ++k)
+            if (k != LH::REST && ((bh >> k) & 1u))
+              ch[k] = bload16(Hz[1], selfB, mslot<LH>(LH::opp[k]) * planeB);
+#pragma unroll
+          for (int k = 0; k < Q; ++k)
+            if (k != LG::REST && ((bg >> k) & 1u))
+              cg[k] = bload16(Gz[1], selfB, mslot<LG>(LG::opp[k]) * planeB);
+        }
+        const float lam_own = lamA[sA][ty + 1][tx + 1], phi_own = phiA[sA][ty + 1][tx + 1];
+#pragma unroll
+        for (int k = 0; k < QH; ++k) {
+          float v;
+          if (k == LH::REST) {
+            v = b.cur.H.rest[selfnode];
+          } else {
+            const float src = lamA[ring4(p - LH::ez[k])][ty + 1 - LH::ey[k]][tx + 1 - LH::ex[k]];
+            v = dev_decode<Codec>(ch[k], float(LH::w[k]) * (((bh >> k) & 1u) ? lam_own : src));
+          }
+          h[k] = v;
+          c = k == 0 ? double(v) : c + double(v);
+        }
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          float v;
+          if (k == LG::REST) {
+            v = b.cur.G.rest[selfnode];
+          } else {
+            const float src = phiA[ring4(p - LG::ez[k])][ty + 1 - LG::ey[k]][tx + 1 - LG::ex[k]];
+            v = dev_decode<Codec>(cg[k], float(LG::w[k]) * (((bg >> k) & 1u) ? phi_own : src));
+          }
+          g_new[k] = v;
+          sg = k == 0 ? double(v) : sg + double(v);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < QH; ++k) {
+          float v;
+          if (k == LH::REST) {
+            v = b.cur.H.rest[selfnode];
           } else {
             const float ref = float(LH::w[k]) *
                               lamA[ring4(p - LH::ez[k])][ty + 1 - LH::ey[k]][tx + 1 - LH::ex[k]];
             v = dev_decode<Codec>(bload16(Hz[1 - LH::ez[k]], xyb[1 - LH::ey[k]][1 - LH::ex[k]],
                                           mslot<LH>(k) * planeB), ref);
           }
+          h[k] = v;
+          c = k == 0 ? double(v) : c + double(v);
         }
-        h[k] = v;
-        c = k == 0 ? double(v) : c + double(v);
-      }
 #pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        float v;
-        if (k == LG::REST) {
-          v = b.cur.G.rest[selfnode];
-        } else {
-          const bool bz = (LG::ez[k] > 0 && bz_up) || (LG::ez[k] < 0 && bz_dn);
-          const int ko = LG::opp[k];
-          if (kWalls && (bz || ((bmg >> k) & 1u))) {
-            v = dev_decode<Codec>(bload16(Gz[1], selfB, mslot<LG>(ko) * planeB),
-                                  float(LG::w[ko]) * phiA[sA][ty + 1][tx + 1]);
+        for (int k = 0; k < Q; ++k) {
+          float v;
+          if (k == LG::REST) {
+            v = b.cur.G.rest[selfnode];
           } else {
             const float ref = float(LG::w[k]) *
                               phiA[ring4(p - LG::ez[k])][ty + 1 - LG::ey[k]][tx + 1 - LG::ex[k]];
             v = dev_decode<Codec>(bload16(Gz[1 - LG::ez[k]], xyb[1 - LG::ey[k]][1 - LG::ex[k]],
                                           mslot<LG>(k) * planeB), ref);
           }
+          g_new[k] = v;
+          sg = k == 0 ? double(v) : sg + double(v);
         }
-        g_new[k] = v;
-        sg = k == 0 ? double(v) : sg + double(v);
       }
       const float phi = phiA[sA][ty + 1][tx + 1];
       const float mu = float(closure(K.q, c, double(phi)));

@@ -219,7 +219,7 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
 
   for (int tile = first_tile(); tile < ntiles; tile += gridDim.x) {
     const int chunk = tile / tiles_xy, txy = tile % tiles_xy;
-    const int X0 = (txy % tiles_x) * TX, Y0 = (txy / tiles_x) * TY;
+    const int X0 = tile_column(txy, tiles_x, chunk, kWalls) * TX, Y0 = (txy / tiles_x) * TY;
     const int z0 = chunk * ZC, z1 = min(z0 + ZC, nz);
 
     const int ux = X0 - 1 + tx, uy = Y0 - 1 + ty;

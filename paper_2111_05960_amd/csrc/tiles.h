@@ -75,4 +75,13 @@ __device__ __forceinline__ int first_tile() {
   return (blockIdx.x % kNumXcd) * slots + blockIdx.x / kNumXcd;
 }
 
+// x column of the tile txy (x fastest) of z chunk `chunk`.  A resident grid
+// whose size is a multiple of the tiles per row keeps every block on one
+// column; with walls the columns at an x wall are the slow ones, so the
+// columns turn by one per chunk and every block takes its share of them.
+__device__ __forceinline__ int tile_column(int txy, int tiles_x, int chunk, bool turn) {
+  const int c = txy % tiles_x;
+  return turn ? (c + chunk) % tiles_x : c;
+}
+
 }  // namespace gplbm
