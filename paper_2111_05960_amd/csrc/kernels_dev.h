@@ -59,13 +59,6 @@ constexpr int kMov = 18;  // the most moving populations per node (D3Q19)
 template <class L = LD>
 __device__ __forceinline__ constexpr int mslot(int k) { return k < L::REST ? k : k - 1; }
 
-// populations of lattice L with e_z = v, as bits
-template <class L>
-__host__ __device__ constexpr uint32_t ez_bits(int v) {
-  uint32_t m = 0;
-  for (int k = 0; k < L::Q; ++k) m |= L::ez[k] == v ? (1u << k) : 0u;
-  return m;
-}
 // opposite populations share a weight (a bounced code decodes with w_k)
 template <class L>
 constexpr bool symmetric_weights() {
@@ -549,8 +542,8 @@ __global__ void __launch_bounds__((TileShape<TX, TY>::NT))
       uint32_t bh = 0u, bg = 0u;
       bool plain = true;
       if constexpr (kWalls) {
-        bh = bmh | (bz_up ? ez_bits<LH>(1) : 0u) | (bz_dn ? ez_bits<LH>(-1) : 0u);
-        bg = bmg | (bz_up ? ez_bits<LG>(1) : 0u) | (bz_dn ? ez_bits<LG>(-1) : 0u);
+        bh = bmh | (bz_up ? ez_mask<LH>(1) : 0u) | (bz_dn ? ez_mask<LH>(-1) : 0u);
+        bg = bmg | (bz_up ? ez_mask<LG>(1) : 0u) | (bz_dn ? ez_mask<LG>(-1) : 0u);
         plain = __builtin_amdgcn_ballot_w64((bh | bg) != 0u) == 0u;
       }
       if (!plain) {

@@ -98,6 +98,14 @@ constexpr int count_ez(int v) {
   return n;
 }
 
+// The populations of a lattice with the given e_z, as bits k.
+template <class L>
+constexpr uint32_t ez_mask(int v) {
+  uint32_t m = 0;
+  for (int k = 0; k < L::Q; ++k) m |= L::ez[k] == v ? (1u << k) : 0u;
+  return m;
+}
+
 // The light lattice of the same dimension.
 template <class L>
 struct Light;
