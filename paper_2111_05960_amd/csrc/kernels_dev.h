@@ -811,10 +811,11 @@ template <class Codec, class LG, class LH, bool kGen>
 struct DevFused3D {
   template <bool kWalls>
   static int run(const Geo& g, const Coef<float>& K, const DevStep& b, hipStream_t st) {
-    // z chunks of 64 planes on periodic grids: 512^3 FP16 7.37 against 7.52
-    // ms with 32 (2 halo planes per 66 instead of per 34; 2560 tiles, 10
-    // passes of the 256 resident blocks); 32 with walls
-    constexpr int TX = 64, TY = kWalls ? GPLBM_DEV_WALL_TY : GPLBM_DEV_TY, ZC = kWalls ? 32 : 64;
+    // z chunks of 128 planes on periodic grids (2 halo planes per 130; 1280
+    // tiles at 512^3, 5 passes of the 256 resident blocks): FP16 6.98-7.01
+    // against 7.10 ms with 64, which ran 7.37 against 7.52 with 32; 32 with
+    // walls (64 x 9 tiles: 7296 at 512^3, 28.5 passes, against 14.25 with 64)
+    constexpr int TX = 64, TY = kWalls ? GPLBM_DEV_WALL_TY : GPLBM_DEV_TY, ZC = kWalls ? 32 : 128;
     constexpr int NT = TileShape<TX, TY>::NT;
     auto kernel = k_dev_fused3d<TX, TY, ZC, Codec, LG, LH, kGen, kWalls>;
     const int tiles_x = (g.nx + TX - 1) / TX;

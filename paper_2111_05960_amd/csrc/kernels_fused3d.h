@@ -136,9 +136,12 @@ __device__ __forceinline__ uint32_t xy_bounce_mask(const Geo& g, int ux, int uy)
 
 template <class L, class S>
 struct Fused3DConfig;
+// 64-plane z chunks: two halo planes per 66 instead of per 34 (512^3 FP64
+// 20.06-20.10 against 20.20 ms at 32, FP32 9.86-9.88 against 9.97-10.01,
+// though 5504 tiles are 21.5 passes of the 256 resident blocks)
 template <>
 struct Fused3DConfig<D3Q19, double> {
-  static constexpr int TX = 64, TY = 6, ZC = 32;
+  static constexpr int TX = 64, TY = 6, ZC = 64;
   static constexpr Carry carry = Carry::kLds;
   static constexpr bool prefetch = false;
 };
@@ -148,7 +151,7 @@ struct Fused3DConfig<D3Q19, double> {
 // slower in FP32 and level in FP64)
 template <>
 struct Fused3DConfig<D3Q19, float> {
-  static constexpr int TX = 64, TY = 12, ZC = 32;
+  static constexpr int TX = 64, TY = 12, ZC = 64;
   static constexpr Carry carry = Carry::kRegisters;
   static constexpr bool prefetch = true;
 };
@@ -603,12 +606,15 @@ struct Fused3DWallConfig<D3Q19, double> {
   static constexpr Carry carry = Carry::kRegisters;
   static constexpr bool prefetch = false;
 };
-// FP32 on D3Q19 with walls keeps the 64 x 12 tiles of the periodic grid: it
-// spills about 20 VGPRs there but ran 11.95 ms per 512^3 step against 12.43
-// on 64 x 9 tiles (12 waves, no spill); without the prefetch of the periodic
-// grid (which spills 45 VGPRs there: 19.0 against 16.3 ms)
+// FP32 on D3Q19 with walls: 64 x 9 tiles (12 waves, 142 VGPRs, no spill),
+// 11.01 ms per 512^3 step against 11.33 on the 64 x 12 tiles of the
+// periodic grid (which spill about 25 VGPRs with walls; the order was the
+// reverse before the tile columns turned per chunk, 12.43 against 11.95),
+// 32-plane chunks, and without the prefetch of the periodic grid (which
+// spills 45 VGPRs there: 19.0 against 16.3 ms)
 template <>
 struct Fused3DWallConfig<D3Q19, float> : Fused3DConfig<D3Q19, float> {
+  static constexpr int TY = 9, ZC = 32;
   static constexpr bool prefetch = false;
 };
 
