@@ -136,19 +136,21 @@ __device__ __forceinline__ uint32_t xy_bounce_mask(const Geo& g, int ux, int uy)
 
 template <class L, class S>
 struct Fused3DConfig;
-// 64-plane z chunks: two halo planes per 66 instead of per 34 (512^3 FP64
-// 20.06-20.10 against 20.20 ms at 32, FP32 9.86-9.88 against 9.97-10.01,
-// though 5504 tiles are 21.5 passes of the 256 resident blocks)
+// 32-plane z chunks: 11008 tiles at 512^3, 43 passes of the 256 resident
+// blocks; 64-plane chunks (two halo planes per 66 instead of per 34) ran
+// level in the plain FP64 step (20.06-20.26 against 20.20-20.24 ms) and 3%
+// slower in its general instantiation (h^eq,alt 22.1 against 21.3-21.5)
 template <>
 struct Fused3DConfig<D3Q19, double> {
-  static constexpr int TX = 64, TY = 6, ZC = 64;
+  static constexpr int TX = 64, TY = 6, ZC = 32;
   static constexpr Carry carry = Carry::kLds;
   static constexpr bool prefetch = false;
 };
 // FP32: the phi^n tile of the plane after next is fetched into registers
 // while a plane is computed (512^3: 9.65-10.0 against 10.6-10.8 ms per step,
 // with h on D3Q7 7.28 against 7.52; in FP64 it ran 2% slower, on D3Q7 12%
-// slower in FP32 and level in FP64)
+// slower in FP32 and level in FP64); 64-plane z chunks (9.86-9.92 against
+// 9.97-10.01 ms with 32; 2752 tiles at 512^3, 10.75 passes)
 template <>
 struct Fused3DConfig<D3Q19, float> {
   static constexpr int TX = 64, TY = 12, ZC = 64;
