@@ -159,7 +159,9 @@ struct Fused3DConfig<D3Q19, float> {
 };
 // g on D3Q7: 7 populations carried in registers; tile heights measured on
 // the 512^3 step (FP64: 12 rows 7.05 ms, 8 rows 7.79, 6 rows 8.36; FP32: 8
-// rows 4.05 ms, 12 rows 4.40, 6 rows 4.18)
+// rows 4.05 ms, 12 rows 4.40, 6 rows 4.18); FP32 in 64-plane z chunks (4096
+// tiles at 512^3, 16 passes of the 256 resident blocks: 3.97-3.98 against
+// 4.05 ms with 32, with walls 5.17 against 5.29; FP64 gained 0.5%)
 template <>
 struct Fused3DConfig<D3Q7, double> {
   static constexpr int TX = 64, TY = 12, ZC = 32;
@@ -168,7 +170,7 @@ struct Fused3DConfig<D3Q7, double> {
 };
 template <>
 struct Fused3DConfig<D3Q7, float> {
-  static constexpr int TX = 64, TY = 8, ZC = 32;
+  static constexpr int TX = 64, TY = 8, ZC = 64;
   static constexpr Carry carry = Carry::kRegisters;
   static constexpr bool prefetch = false;
 };
