@@ -40,11 +40,14 @@ def interface_error(phi_a, phi_b, grad_b, W=2.5):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("shape", [(40, 30, 70), (70, 30, 70)])
-def test_dev_fused_equals_split(gp, prec, shape):
-    """Periodic z-march: one z chunk with a ragged tile row, and two chunks
-    (64 planes and a ragged 6)."""
-    p = wl.base_params(lattice=wl.D3Q19, shape=shape, bc=(0, 0, 0))
+@pytest.mark.parametrize("shape,lat", [((40, 30, 70), "full"), ((70, 30, 70), "full"),
+                                       ((140, 14, 70), "full"), ((140, 14, 70), "gh")])
+def test_dev_fused_equals_split(gp, prec, shape, lat):
+    """Periodic z-march (z chunks of 128 planes): one chunk with a ragged
+    tile row, and two chunks (128 planes and a ragged 12) over two tile
+    columns, D3Q19 and g and h on D3Q7."""
+    p = wl.base_params(lattice=wl.D3Q19 if lat == "full" else wl.D3Q7, shape=shape, bc=(0, 0, 0))
+    print(f"case dev fused=split {prec} {shape} {lat}", flush=True)
     phi0, c0 = wl.random_state_fields(shape, seed=21)
     a = gp.Simulation(p, prec, "split").init(phi0, c0).step(12)
     b = gp.Simulation(p, prec, "fused").init(phi0, c0).step(12)

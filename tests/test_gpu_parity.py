@@ -169,6 +169,21 @@ WALL_CASES = [((40, 30, 70), (1, 1, 1)), ((33, 20, 130), (1, 0, 1)),
               ((5, 14, 128), (1, 1, 0))]
 WALL_LATTICES = {"full": dict(lattice=wl.D3Q19), "h": dict(lattice=wl.D3Q19, h_lattice=1),
                  "gh": dict(lattice=wl.D3Q7)}
+
+
+@pytest.mark.parametrize("which", sorted(WALL_LATTICES))
+@pytest.mark.parametrize("shape", [(70, 14, 70), (130, 12, 64)])
+def test_fp32_periodic_chunks_fused_equals_split(gp, shape, which):
+    """Periodic FP32 z-march in z chunks of 64 planes: two and three chunks
+    (the last ragged) give the bits of the split kernels."""
+    p = wl.base_params(shape=shape, bc=(0, 0, 0), **WALL_LATTICES[which])
+    phi0, c0 = wl.random_state_fields(shape, seed=41)
+    print(f"case fp32 periodic chunks {which} {shape}", flush=True)
+    a = gp.Simulation(p, "fp32", "split").init(phi0, c0).step(9)
+    b = gp.Simulation(p, "fp32", "fused").init(phi0, c0).step(9)
+    assert b.schedule == "fused" and a.schedule == "split"
+    for x, y in zip(a.fields(), b.fields()):
+        assert np.array_equal(x, y)
 QUAD = dict(free_energy=1, eps_s=1.0, eps_l=2.3, m_s=0.9, m_l=0.12, df_min=0.02)
 
 
